@@ -1,0 +1,225 @@
+// api.hip -- host runtime behind include/svdb.h: argument checks, the plan
+// (which kernel handles which shape), workspace sizing and launches.
+#include <math.h>
+#include <stdarg.h>
+#include <stdio.h>
+
+#include <string>
+#include <vector>
+
+#include "launchers.hpp"
+#include "svdb.h"
+
+namespace {
+
+thread_local std::string g_err;
+
+int fail(int code, const char *fmt, ...)
+{
+    char buf[512];
+    va_list ap;
+    va_start(ap, fmt);
+    vsnprintf(buf, sizeof buf, fmt, ap);
+    va_end(ap);
+    g_err = buf;
+    return code;
+}
+
+int hip_fail(hipError_t e, const char *where)
+{
+    return fail(SVDB_ERR_HIP, "%s: %s", where, hipGetErrorString(e));
+}
+
+double default_tol(svdb_dtype_t dt)
+{
+    // k * u with k = 30 and u = 2^-s (s significand bits incl. the implicit one)
+    const bool single = (dt == SVDB_R32 || dt == SVDB_C64);
+    return 30.0 * (single ? ldexp(1.0, -24) : ldexp(1.0, -53));
+}
+
+struct Plan {
+    int path = SVDB_PATH_AUTO;
+    int nb = 0;
+    int threads = 0;
+};
+
+svdb_opts_t resolve_opts(const svdb_opts_t *o)
+{
+    svdb_opts_t r;
+    svdb_opts_default(&r);
+    if (o) {
+        r = *o;
+        if (r.max_sweeps <= 0) r.max_sweeps = 100;
+        if (r.masking < 0) r.masking = 1;
+    }
+    return r;
+}
+
+bool plain_fits(int m, int n)
+{
+    return svdb::plain_lds_bytes(m, n) <= (size_t)svdb::plain_max_lds_bytes() && n <= 512;
+}
+
+int make_plan(svdb_dtype_t dt, int m, int n, const svdb_opts_t &o, Plan *p)
+{
+    if (dt != SVDB_R64)
+        return fail(SVDB_ERR_UNSUPPORTED, "dtype %d is not implemented in this build", (int)dt);
+    int path = o.path;
+    if (path == SVDB_PATH_AUTO) path = SVDB_PATH_PLAIN;
+    if (path == SVDB_PATH_PLAIN) {
+        if (!plain_fits(m, n))
+            return fail(SVDB_ERR_UNSUPPORTED, "plain path: %d x %d does not fit in LDS", m, n);
+        p->path = SVDB_PATH_PLAIN;
+        p->nb = 0;
+        p->threads = 256;
+        return 0;
+    }
+    return fail(SVDB_ERR_UNSUPPORTED, "path %d is not implemented in this build", path);
+}
+
+}  // namespace
+
+extern "C" {
+
+void svdb_opts_default(svdb_opts_t *o)
+{
+    if (!o) return;
+    o->max_sweeps = 100;
+    o->path = SVDB_PATH_AUTO;
+    o->nb = 0;
+    o->masking = 1;
+    o->precision = 0;
+    o->sweeps = nullptr;
+}
+
+const char *svdb_last_error(void) { return g_err.c_str(); }
+
+const char *svdb_version(void) { return "svdb 0.1 (gfx950)"; }
+
+int svdb_plan(svdb_dtype_t dtype, int m, int n, const svdb_opts_t *opts, int *path, int *nb,
+              int *threads)
+{
+    svdb_opts_t o = resolve_opts(opts);
+    if (m < 0 || n < 0 || n > m) return fail(-3, "need m >= n >= 0");
+    Plan p;
+    int rc = make_plan(dtype, m, n, o, &p);
+    if (rc) return rc;
+    if (path) *path = p.path;
+    if (nb) *nb = p.nb;
+    if (threads) *threads = p.threads;
+    return 0;
+}
+
+size_t svdb_workspace_size(svdb_dtype_t dtype, int batch, int m, int n, const svdb_opts_t *opts)
+{
+    if (batch < 0 || m < 0 || n < 0 || n > m) return (size_t)-1;
+    svdb_opts_t o = resolve_opts(opts);
+    Plan p;
+    if (make_plan(dtype, m, n, o, &p)) return (size_t)-1;
+    return 0;
+}
+
+int svdb_svd_strided_batched(svdb_dtype_t dtype, int batch, int m, int n, const void *A, int lda,
+                             long long strideA, void *S, long long strideS, void *U, int ldu,
+                             long long strideU, void *V, int ldv, long long strideV, double tol,
+                             int *info, void *workspace, size_t ws_bytes,
+                             const svdb_opts_t *opts, void *stream)
+{
+    g_err.clear();
+    if ((int)dtype < SVDB_R32 || (int)dtype > SVDB_C128) return fail(-1, "invalid dtype");
+    if (batch < 0) return fail(-2, "batch < 0");
+    if (m < 0) return fail(-3, "m < 0");
+    if (n < 0 || n > m) return fail(-4, "need 0 <= n <= m (wide matrices: pass A^H)");
+    const bool empty = (batch == 0 || n == 0);
+    if (!A && !empty) return fail(-5, "A is NULL");
+    if (lda < (m > 1 ? m : 1)) return fail(-6, "lda < max(1, m)");
+    if (batch > 1 && strideA < (long long)lda * n) return fail(-7, "strideA < lda * n");
+    if (!S && !empty) return fail(-8, "S is NULL");
+    if (batch > 1 && strideS < n) return fail(-9, "strideS < n");
+    if (U) {
+        if (ldu < (m > 1 ? m : 1)) return fail(-11, "ldu < max(1, m)");
+        if (batch > 1 && strideU < (long long)ldu * n) return fail(-12, "strideU < ldu * n");
+    }
+    if (V) {
+        if (ldv < (n > 1 ? n : 1)) return fail(-14, "ldv < max(1, n)");
+        if (batch > 1 && strideV < (long long)ldv * n) return fail(-15, "strideV < ldv * n");
+    }
+    if (!isfinite(tol)) return fail(-16, "tol is not finite");
+    if (!info && batch > 0) return fail(-17, "info is NULL");
+    svdb_opts_t o = resolve_opts(opts);
+    Plan p;
+    int rc = make_plan(dtype, m, n, o, &p);
+    if (rc) return rc;
+    const size_t need = svdb_workspace_size(dtype, batch, m, n, &o);
+    if (need > 0 && (!workspace || ws_bytes < need))
+        return fail(-19, "workspace too small: need %zu bytes", need);
+    if (batch == 0) return 0;
+    if (tol <= 0.0) tol = default_tol(dtype);
+    hipStream_t s = (hipStream_t)stream;
+
+    hipError_t e = hipSuccess;
+    if (p.path == SVDB_PATH_PLAIN) {
+        e = svdb::launch_plain_d(batch, m, n, (const double *)A, lda, strideA, (double *)S,
+                                 strideS, (double *)U, ldu, strideU, (double *)V, ldv, strideV,
+                                 tol, o.max_sweeps, info, o.sweeps, s);
+    }
+    if (e != hipSuccess) return hip_fail(e, "launch");
+    return 0;
+}
+
+size_t svdb_batched_workspace_size(svdb_dtype_t dtype, int batch, const int *m, const int *n,
+                                   const svdb_opts_t *opts)
+{
+    if (batch < 0 || (batch > 0 && (!m || !n))) return (size_t)-1;
+    size_t total = 0;
+    for (int b = 0; b < batch; b++) {
+        size_t w = svdb_workspace_size(dtype, 1, m[b], n[b], opts);
+        if (w == (size_t)-1) return w;
+        total += w;
+    }
+    return total;
+}
+
+int svdb_svd_batched(svdb_dtype_t dtype, int batch, const int *m, const int *n,
+                     const void *const *A, const int *lda, void *const *S, void *const *U,
+                     const int *ldu, void *const *V, const int *ldv, double tol, int *info,
+                     void *workspace, size_t ws_bytes, const svdb_opts_t *opts, void *stream)
+{
+    g_err.clear();
+    if ((int)dtype < SVDB_R32 || (int)dtype > SVDB_C128) return fail(-1, "invalid dtype");
+    if (batch < 0) return fail(-2, "batch < 0");
+    if (batch == 0) return 0;
+    if (!m) return fail(-3, "m is NULL");
+    if (!n) return fail(-4, "n is NULL");
+    if (!A) return fail(-5, "A is NULL");
+    if (!lda) return fail(-6, "lda is NULL");
+    if (!S) return fail(-7, "S is NULL");
+    if (U && !ldu) return fail(-9, "ldu is NULL");
+    if (V && !ldv) return fail(-11, "ldv is NULL");
+    if (!isfinite(tol)) return fail(-12, "tol is not finite");
+    if (!info) return fail(-13, "info is NULL");
+    for (int b = 0; b < batch; b++) {
+        if (m[b] < 0) return fail(-3, "m[%d] < 0", b);
+        if (n[b] < 0 || n[b] > m[b]) return fail(-4, "need 0 <= n[%d] <= m[%d]", b, b);
+        const bool empty = n[b] == 0;
+        if (!A[b] && !empty) return fail(-5, "A[%d] is NULL", b);
+        if (lda[b] < (m[b] > 1 ? m[b] : 1)) return fail(-6, "lda[%d] < max(1, m)", b);
+        if (!S[b] && !empty) return fail(-7, "S[%d] is NULL", b);
+        if (U && ldu[b] < (m[b] > 1 ? m[b] : 1)) return fail(-9, "ldu[%d] < max(1, m)", b);
+        if (V && ldv[b] < (n[b] > 1 ? n[b] : 1)) return fail(-11, "ldv[%d] < max(1, n)", b);
+    }
+    svdb_opts_t o = resolve_opts(opts);
+    // One launch per matrix for now; each call writes its own info slot.
+    svdb_opts_t o1 = o;
+    for (int b = 0; b < batch; b++) {
+        o1.sweeps = o.sweeps ? o.sweeps + b : nullptr;
+        int rc = svdb_svd_strided_batched(dtype, 1, m[b], n[b], A[b], lda[b], 0, S[b], 0,
+                                          U ? U[b] : nullptr, U ? ldu[b] : 1, 0,
+                                          V ? V[b] : nullptr, V ? ldv[b] : 1, 0, tol, info + b,
+                                          workspace, ws_bytes, &o1, stream);
+        if (rc) return rc;
+    }
+    return 0;
+}
+
+}  // extern "C"

@@ -1,0 +1,18 @@
+// launchers.hpp -- host-side launch functions of the kernels (internal to the
+// library; the public interface is include/svdb.h).
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stddef.h>
+
+namespace svdb {
+
+// plain.hip: LDS-resident unblocked Jacobi, FP64, one workgroup per matrix.
+size_t plain_lds_bytes(int m, int n);
+int plain_max_lds_bytes();
+hipError_t launch_plain_d(int batch, int m, int n, const double *A, int lda, long long sA,
+                          double *S, long long sS, double *U, int ldu, long long sU, double *V,
+                          int ldv, long long sV, double tol, int max_sweeps, int *info,
+                          int *sweeps, hipStream_t stream);
+
+}  // namespace svdb

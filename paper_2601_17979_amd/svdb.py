@@ -1,0 +1,216 @@
+"""Python binding of the C ABI in include/svdb.h (ctypes; argument marshalling
+only -- every step of the SVD runs in the HIP kernels of libsvdb.so).
+
+Tensors are torch tensors on the GPU; a batch of column-major m x n matrices
+is a tensor of shape (batch, m, n) with strides (strideA, 1, lda), e.g.
+``torch.empty(batch, n, m).transpose(1, 2)``.  `col_major(x)` converts.
+"""
+from __future__ import annotations
+
+import ctypes as C
+import os
+
+import torch
+
+_PKG = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_PKG, "libsvdb.so")
+
+R32, R64, C64, C128 = 0, 1, 2, 3
+PATH_AUTO, PATH_PLAIN, PATH_RESIDENT, PATH_BLOCKED = 0, 1, 2, 3
+ERR_UNSUPPORTED, ERR_HIP = -200, -100
+
+_DTYPES = {torch.float32: R32, torch.float64: R64, torch.complex64: C64, torch.complex128: C128}
+_REAL = {torch.float32: torch.float32, torch.float64: torch.float64,
+         torch.complex64: torch.float32, torch.complex128: torch.float64}
+_PATHS = {"auto": PATH_AUTO, "plain": PATH_PLAIN, "resident": PATH_RESIDENT,
+          "blocked": PATH_BLOCKED}
+
+
+class Opts(C.Structure):
+    _fields_ = [("max_sweeps", C.c_int), ("path", C.c_int), ("nb", C.c_int),
+                ("masking", C.c_int), ("precision", C.c_int), ("sweeps", C.c_void_p)]
+
+
+class SvdbError(RuntimeError):
+    def __init__(self, code, msg):
+        super().__init__(f"svdb error {code}: {msg}")
+        self.code = code
+
+
+_lib = None
+
+
+def lib():
+    """The loaded libsvdb.so.  Raises if the library has not been built: there
+    is no fallback path."""
+    global _lib
+    if _lib is None:
+        if not os.path.exists(LIB_PATH):
+            raise RuntimeError(f"{LIB_PATH} is missing; build it with "
+                               "`python -m paper_2601_17979_amd.build`")
+        L = C.CDLL(LIB_PATH)
+        P, I, D, LL, SZ = C.c_void_p, C.c_int, C.c_double, C.c_longlong, C.c_size_t
+        L.svdb_opts_default.argtypes = [C.POINTER(Opts)]
+        L.svdb_last_error.restype = C.c_char_p
+        L.svdb_version.restype = C.c_char_p
+        L.svdb_plan.argtypes = [I, I, I, C.POINTER(Opts), C.POINTER(I), C.POINTER(I),
+                                C.POINTER(I)]
+        L.svdb_plan.restype = I
+        L.svdb_workspace_size.argtypes = [I, I, I, I, C.POINTER(Opts)]
+        L.svdb_workspace_size.restype = SZ
+        L.svdb_batched_workspace_size.argtypes = [I, I, P, P, C.POINTER(Opts)]
+        L.svdb_batched_workspace_size.restype = SZ
+        L.svdb_svd_strided_batched.argtypes = [I, I, I, I, P, I, LL, P, LL, P, I, LL, P, I, LL,
+                                               D, P, P, SZ, C.POINTER(Opts), P]
+        L.svdb_svd_strided_batched.restype = I
+        L.svdb_svd_batched.argtypes = [I, I, P, P, P, P, P, P, P, P, P, D, P, P, SZ,
+                                       C.POINTER(Opts), P]
+        L.svdb_svd_batched.restype = I
+        _lib = L
+    return _lib
+
+
+def last_error() -> str:
+    return lib().svdb_last_error().decode()
+
+
+def version() -> str:
+    return lib().svdb_version().decode()
+
+
+def make_opts(max_sweeps=100, path="auto", nb=0, masking=True, precision=0, sweeps=None):
+    o = Opts()
+    lib().svdb_opts_default(C.byref(o))
+    o.max_sweeps = int(max_sweeps)
+    o.path = _PATHS[path] if isinstance(path, str) else int(path)
+    o.nb = int(nb)
+    o.masking = 1 if masking else 0
+    o.precision = int(precision)
+    o.sweeps = sweeps.data_ptr() if sweeps is not None else None
+    return o
+
+
+def dtype_code(dt: torch.dtype) -> int:
+    if dt not in _DTYPES:
+        raise TypeError(f"unsupported dtype {dt}")
+    return _DTYPES[dt]
+
+
+def plan(dtype: torch.dtype, m: int, n: int, **kw):
+    """(path, nb, threads) the library would use for one m x n matrix."""
+    o = make_opts(**kw)
+    p, nb, th = C.c_int(), C.c_int(), C.c_int()
+    rc = lib().svdb_plan(dtype_code(dtype), m, n, C.byref(o), C.byref(p), C.byref(nb),
+                         C.byref(th))
+    if rc:
+        raise SvdbError(rc, last_error())
+    return p.value, nb.value, th.value
+
+
+def col_major(A: torch.Tensor) -> torch.Tensor:
+    """Copy of a (batch, m, n) tensor laid out column-major per matrix."""
+    b, m, n = A.shape
+    out = torch.empty((b, n, m), dtype=A.dtype, device=A.device).transpose(1, 2)
+    out.copy_(A)
+    return out
+
+
+def empty_col_major(b, m, n, dtype, device):
+    return torch.empty((b, n, m), dtype=dtype, device=device).transpose(1, 2)
+
+
+def _check_cm(x: torch.Tensor, name: str):
+    if x.dim() != 3:
+        raise ValueError(f"{name} must be (batch, rows, cols)")
+    if x.shape[1] > 1 and x.stride(1) != 1:
+        raise ValueError(f"{name} must be column-major per matrix (stride(1) == 1)")
+
+
+def svd(A: torch.Tensor, tol: float = 0.0, max_sweeps: int = 100, path="auto", nb: int = 0,
+        compute_u: bool = True, compute_v: bool = True, masking: bool = True,
+        precision: int = 0, want_sweeps: bool = True, stream=None, out=None):
+    """Batched reduced SVD of a (batch, m, n) column-major GPU tensor (m >= n).
+
+    Returns (S, U, V, info, sweeps); U/V are None when not requested, sweeps
+    is None unless want_sweeps.  Enqueued on `stream` (default: torch's
+    current stream); synchronise before reading results on the host.
+    """
+    _check_cm(A, "A")
+    b, m, n = A.shape
+    dev = A.device
+    code = dtype_code(A.dtype)
+    if out is not None:
+        S, U, V, info, sweeps = out
+    else:
+        S = torch.empty((b, n), dtype=_REAL[A.dtype], device=dev)
+        U = empty_col_major(b, m, n, A.dtype, dev) if compute_u else None
+        V = empty_col_major(b, n, n, A.dtype, dev) if compute_v else None
+        info = torch.empty(b, dtype=torch.int32, device=dev)
+        sweeps = torch.empty(b, dtype=torch.int32, device=dev) if want_sweeps else None
+    o = make_opts(max_sweeps, path, nb, masking, precision, sweeps)
+    ws_bytes = lib().svdb_workspace_size(code, b, m, n, C.byref(o))
+    if ws_bytes == C.c_size_t(-1).value:
+        raise SvdbError(-1, last_error() or "invalid arguments")
+    ws = torch.empty(max(ws_bytes, 1), dtype=torch.uint8, device=dev) if ws_bytes else None
+    st = (stream or torch.cuda.current_stream(dev)).cuda_stream
+    lda = max(A.stride(2), 1) if n > 1 else max(m, 1)
+    ldu = (U.stride(2) if n > 1 else max(m, 1)) if U is not None else 1
+    ldv = (V.stride(2) if n > 1 else max(n, 1)) if V is not None else 1
+    rc = lib().svdb_svd_strided_batched(
+        code, b, m, n, A.data_ptr(), lda, A.stride(0), S.data_ptr(), S.stride(0),
+        U.data_ptr() if U is not None else None, ldu, U.stride(0) if U is not None else 0,
+        V.data_ptr() if V is not None else None, ldv, V.stride(0) if V is not None else 0,
+        float(tol), info.data_ptr(), ws.data_ptr() if ws is not None else None, ws_bytes,
+        C.byref(o), st)
+    if rc:
+        raise SvdbError(rc, last_error())
+    return S, U, V, info, sweeps
+
+
+def svd_batched(mats, tol: float = 0.0, max_sweeps: int = 100, path="auto", nb: int = 0,
+                compute_u: bool = True, compute_v: bool = True, masking: bool = True,
+                precision: int = 0, stream=None):
+    """Mixed-shape batch: `mats` is a list of (m_b, n_b) column-major GPU
+    tensors of one dtype.  Returns lists (S, U, V) and tensors (info, sweeps)."""
+    if not mats:
+        return [], [], [], None, None
+    dt = mats[0].dtype
+    dev = mats[0].device
+    code = dtype_code(dt)
+    bsz = len(mats)
+    ms = (C.c_int * bsz)(*[int(x.shape[0]) for x in mats])
+    ns = (C.c_int * bsz)(*[int(x.shape[1]) for x in mats])
+    for x in mats:
+        if x.dtype != dt or x.dim() != 2 or (x.shape[0] > 1 and x.stride(0) != 1):
+            raise ValueError("every matrix must be a 2-D column-major tensor of one dtype")
+    Ss = [torch.empty(int(x.shape[1]), dtype=_REAL[dt], device=dev) for x in mats]
+    Us = [torch.empty((int(x.shape[1]), int(x.shape[0])), dtype=dt, device=dev).t()
+          for x in mats] if compute_u else None
+    Vs = [torch.empty((int(x.shape[1]), int(x.shape[1])), dtype=dt, device=dev).t()
+          for x in mats] if compute_v else None
+    info = torch.empty(bsz, dtype=torch.int32, device=dev)
+    sweeps = torch.empty(bsz, dtype=torch.int32, device=dev)
+    P = C.c_void_p * bsz
+    I = C.c_int * bsz
+
+    def ld(x, rows):
+        return max(x.stride(1), rows, 1) if x.shape[1] > 1 else max(rows, 1)
+    Ap = P(*[x.data_ptr() for x in mats])
+    lda = I(*[ld(x, x.shape[0]) for x in mats])
+    Sp = P(*[s.data_ptr() for s in Ss])
+    Up = P(*[u.data_ptr() for u in Us]) if Us is not None else None
+    ldu = I(*[ld(u, u.shape[0]) for u in Us]) if Us is not None else None
+    Vp = P(*[v.data_ptr() for v in Vs]) if Vs is not None else None
+    ldv = I(*[ld(v, v.shape[0]) for v in Vs]) if Vs is not None else None
+    o = make_opts(max_sweeps, path, nb, masking, precision, sweeps)
+    ws_bytes = lib().svdb_batched_workspace_size(code, bsz, ms, ns, C.byref(o))
+    if ws_bytes == C.c_size_t(-1).value:
+        raise SvdbError(-1, last_error() or "invalid arguments")
+    ws = torch.empty(max(ws_bytes, 1), dtype=torch.uint8, device=dev) if ws_bytes else None
+    st = (stream or torch.cuda.current_stream(dev)).cuda_stream
+    rc = lib().svdb_svd_batched(code, bsz, ms, ns, Ap, lda, Sp, Up, ldu, Vp, ldv, float(tol),
+                                info.data_ptr(), ws.data_ptr() if ws is not None else None,
+                                ws_bytes, C.byref(o), st)
+    if rc:
+        raise SvdbError(rc, last_error())
+    return Ss, Us, Vs, info, sweeps

@@ -1,0 +1,105 @@
+"""The C-ABI library on the host: it loads, exports every function declared in
+include/svdb.h, and rejects invalid arguments with the documented codes before
+anything reaches the GPU (no GPU is needed for these checks)."""
+import ctypes as C
+import os
+import re
+
+import pytest
+
+from paper_2601_17979_amd import svdb
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+
+
+def _declared():
+    names = set()
+    for fn in os.listdir(os.path.join(ROOT, "include")):
+        if fn.endswith(".h"):
+            txt = open(os.path.join(ROOT, "include", fn)).read()
+            txt = re.sub(r"/\*.*?\*/", "", txt, flags=re.S)
+            names |= set(re.findall(r"\b(svdb_\w+)\s*\(", txt))
+    return names
+
+
+def test_library_exports_every_declared_symbol():
+    L = svdb.lib()
+    names = _declared()
+    assert "svdb_svd_strided_batched" in names and "svdb_svd_batched" in names
+    for name in sorted(names):
+        assert hasattr(L, name), name
+
+
+def test_version_and_defaults():
+    assert "gfx950" in svdb.version()
+    o = svdb.Opts()
+    svdb.lib().svdb_opts_default(C.byref(o))
+    assert o.max_sweeps == 100 and o.path == svdb.PATH_AUTO and o.masking == 1
+
+
+def _call(**kw):
+    args = dict(dtype=svdb.R64, batch=2, m=8, n=4, A=0x1000, lda=8, sA=32, S=0x2000, sS=4,
+                U=0x3000, ldu=8, sU=32, V=0x4000, ldv=4, sV=16, tol=0.0, info=0x5000,
+                ws=None, wsb=0, opts=None, stream=None)
+    args.update(kw)
+    o = C.byref(args["opts"]) if args["opts"] is not None else None
+    return svdb.lib().svdb_svd_strided_batched(
+        args["dtype"], args["batch"], args["m"], args["n"], args["A"], args["lda"], args["sA"],
+        args["S"], args["sS"], args["U"], args["ldu"], args["sU"], args["V"], args["ldv"],
+        args["sV"], args["tol"], args["info"], args["ws"], args["wsb"], o, args["stream"])
+
+
+@pytest.mark.parametrize("kw,code", [
+    (dict(dtype=9), -1),
+    (dict(batch=-1), -2),
+    (dict(m=-1), -3),
+    (dict(m=3, n=4, lda=4), -4),          # wide matrices are rejected
+    (dict(A=None), -5),
+    (dict(lda=7), -6),
+    (dict(sA=31), -7),
+    (dict(S=None), -8),
+    (dict(sS=3), -9),
+    (dict(ldu=7), -11),
+    (dict(sU=31), -12),
+    (dict(ldv=3), -14),
+    (dict(sV=15), -15),
+    (dict(tol=float("nan")), -16),
+    (dict(info=None), -17),
+])
+def test_argument_errors(kw, code):
+    assert _call(**kw) == code
+    assert svdb.last_error() != ""
+
+
+def test_empty_batch_is_a_noop():
+    # nothing is launched for an empty batch, so this runs without a GPU
+    assert _call(batch=0) == 0
+    assert _call(batch=0, A=None, S=None, info=None) == 0
+
+
+def test_plan_and_workspace():
+    p, nb, th = svdb.plan(svdb.torch.float64, 16, 16)
+    assert p in (svdb.PATH_PLAIN, svdb.PATH_RESIDENT, svdb.PATH_BLOCKED)
+    assert svdb.lib().svdb_workspace_size(svdb.R64, 10, 4, 8, None) == C.c_size_t(-1).value
+    with pytest.raises(svdb.SvdbError):
+        svdb.plan(svdb.torch.float64, 4, 8)
+
+
+def test_batched_argument_errors():
+    L = svdb.lib()
+    m = (C.c_int * 2)(8, 4)
+    n = (C.c_int * 2)(4, 6)                # second matrix is wide
+    P = C.c_void_p * 2
+    I = C.c_int * 2
+    A = P(0x1000, 0x2000)
+    lda = I(8, 4)
+    S = P(0x3000, 0x4000)
+    info = 0x5000
+    rc = L.svdb_svd_batched(svdb.R64, 2, m, n, A, lda, S, None, None, None, None, 0.0, info,
+                            None, 0, None, None)
+    assert rc == -4
+    n[1] = 2
+    lda[0] = 7
+    rc = L.svdb_svd_batched(svdb.R64, 2, m, n, A, lda, S, None, None, None, None, 0.0, info,
+                            None, 0, None, None)
+    assert rc == -6

@@ -1,0 +1,149 @@
+"""GPU parity: the HIP paths against the FP64 oracle, through the C ABI.
+
+Sizes are chosen so that the oracle finishes in seconds while spanning several
+lane groups and ragged tails (m, n not multiples of the group widths); the
+full-size workloads are checked on sampled matrices.  Tolerances: normwise
+sigma error <= 1e-12, ||A - U S V^H||_F / ||A||_F <= 1e-13 n and
+||U^H U - I||_F, ||V^H V - I||_F <= 1e-13 n (FP64).
+"""
+import numpy as np
+import pytest
+
+from workloads import gen
+from gpu_util import aligned_vector_err, compare_with_oracle, oracle_batch, run_gpu, say
+
+pytestmark = pytest.mark.gpu
+
+PATHS = ["plain"]
+
+
+def _batch(shape_list, seed, kind="gauss", kappa=1e6):
+    out = []
+    for k, (m, n) in enumerate(shape_list):
+        r = gen.rng_for(seed, k)
+        out.append(gen.family(r, kind, m, n, kappa))
+    return np.stack(out)
+
+
+@pytest.mark.parametrize("path", PATHS)
+def test_small16_workload(path):
+    """1000 x (16 x 16) FP64, A = U diag(s) V^T, s log-uniform [1e-3, 1],
+    tol 1e-14: every matrix against the oracle."""
+    A = gen.small16(batch=1000)[0].A
+    say(f"[small16 {path}] batch {A.shape}")
+    S, U, V, info, sw = run_gpu(A, tol=1e-14, path=path)
+    Sr, Ur, Vr, swr, infor = oracle_batch(A, tol=1e-14)
+    compare_with_oracle(A, S, U, V, info, Sr, infor, label=f"small16/{path}")
+    worst = max(aligned_vector_err(S[k], U[k], V[k], Sr[k], Ur[k], Vr[k]) for k in range(100))
+    assert worst <= 1e-13, worst
+    say(f"  sweeps gpu {np.bincount(sw)} oracle {np.bincount(swr)}")
+
+
+@pytest.mark.parametrize("path", PATHS)
+@pytest.mark.parametrize("m,n", [(1, 1), (5, 1), (2, 2), (7, 3), (9, 9), (17, 9), (33, 17),
+                                 (40, 40), (65, 31), (64, 64), (128, 32), (100, 100)])
+def test_shapes_vs_oracle(path, m, n):
+    """Ragged and odd shapes (phantom column for odd n), up to the LDS limit."""
+    A = _batch([(m, n)] * 6, seed=100 + m * 7 + n, kind="gauss")
+    A[1] = _batch([(m, n)], seed=200 + m, kind="geo", kappa=1e6)[0]
+    A[2] = _batch([(m, n)], seed=300 + m, kind="cluster1", kappa=1e8)[0]
+    say(f"[shape {m}x{n} {path}]")
+    S, U, V, info, sw = run_gpu(A, path=path)
+    Sr, Ur, Vr, swr, infor = oracle_batch(A)
+    compare_with_oracle(A, S, U, V, info, Sr, infor, label=f"{m}x{n}/{path}")
+
+
+@pytest.mark.parametrize("path", PATHS)
+def test_one_sweep_elementwise(path):
+    """After exactly one sweep (max_sweeps = 1, info = 1) the GPU iterate
+    matches the oracle run in the same round-robin order element by element:
+    this pins the pair schedule, the rotation and its orientation."""
+    A = _batch([(24, 13)] * 8 + [(40, 40)] * 0, seed=400)
+    S, U, V, info, sw = run_gpu(A, path=path, max_sweeps=1)
+    Sr, Ur, Vr, swr, infor = oracle_batch(A, max_sweeps=1, order=1)
+    assert np.all(info == 1) and np.all(infor == 1) and np.all(sw == 1)
+    assert np.abs(S - Sr).max() <= 1e-13 * Sr.max()
+    assert np.abs(U - Ur).max() <= 1e-12
+    assert np.abs(V - Vr).max() <= 1e-12
+
+
+@pytest.mark.parametrize("path", PATHS)
+def test_sweep_counts_match_round_robin_oracle(path):
+    """Same ordering, same threshold: the sweep counts agree (within one
+    sweep, since rounding can move the last decision)."""
+    A = _batch([(32, 32)] * 16, seed=500, kind="geo", kappa=1e6)
+    S, U, V, info, sw = run_gpu(A, path=path)
+    Sr, Ur, Vr, swr, infor = oracle_batch(A, order=1)
+    assert np.all(np.abs(sw - swr) <= 1), (sw, swr)
+
+
+@pytest.mark.parametrize("path", PATHS)
+def test_edge_cases(path):
+    """Zero matrix, exactly rank-1 with a zero column (orthonormal
+    completion of U), a NaN (info 2), Inf (info 2), max_sweeps = 1 (info 1)."""
+    m, n = 12, 7
+    A = _batch([(m, n)] * 6, seed=600)
+    A[0] = 0.0
+    x, y = gen.gaussian(gen.rng_for(601, 0), m, 1), gen.gaussian(gen.rng_for(601, 1), 1, n)
+    y[0, 3] = 0.0
+    A[1] = x @ y
+    A[2, 4, 5] = np.nan
+    A[3, 0, 0] = np.inf
+    S, U, V, info, sw = run_gpu(A, path=path)
+    Sr, Ur, Vr, swr, infor = oracle_batch(A)
+    assert list(info) == [0, 0, 2, 2, 0, 0]
+    compare_with_oracle(A, S, U, V, info, Sr, infor, label=f"edge/{path}")
+    S1, U1, V1, info1, sw1 = run_gpu(A[4:], path=path, max_sweeps=1)
+    assert np.all(info1 == 1) and np.all(sw1 == 1)
+
+
+@pytest.mark.parametrize("path", PATHS)
+def test_deterministic(path):
+    """Two runs give bitwise identical results (no races in LDS)."""
+    A = _batch([(64, 64)] * 32, seed=700, kind="geo")
+    r1 = run_gpu(A, path=path)
+    r2 = run_gpu(A, path=path)
+    for x, y in zip(r1, r2):
+        assert np.array_equal(x, y)
+
+
+@pytest.mark.parametrize("path", PATHS)
+def test_scale_extremes(path):
+    """Entries near the overflow and underflow limits: the power-of-two
+    pre-scaling makes the result the scaled result of a unit-size matrix."""
+    A = _batch([(20, 10)] * 3, seed=800)
+    A[0] *= 2.0 ** 900
+    A[1] *= 2.0 ** -900
+    S, U, V, info, sw = run_gpu(A, path=path)
+    Sr, Ur, Vr, swr, infor = oracle_batch(A / np.array([2.0 ** 900, 2.0 ** -900, 1.0])[:, None, None])
+    assert np.all(info == 0)
+    scales = np.array([2.0 ** 900, 2.0 ** -900, 1.0])
+    for k in range(3):
+        assert np.abs(S[k] / scales[k] - Sr[k]).max() <= 1e-13 * Sr[k][0]
+
+
+def test_full_mixed_workload_sampled():
+    """10000 FP64 matrices (5000 of 64 x 64, 5000 of 128 x 32, half geometric
+    kappa = 1e6, half Gaussian) through the default path, exactly as the
+    benchmark launches them; 120 sampled matrices per shape against the
+    oracle, and invariants on every matrix."""
+    import torch
+    from metrics import orth_err, recon_err
+    groups = gen.mixed_64_128x32()
+    rng = np.random.default_rng(1)
+    for g in groups:
+        say(f"[full mixed] {g.m}x{g.n} batch {g.A.shape[0]}")
+        S, U, V, info, sw = run_gpu(g.A, path="auto")
+        assert np.all(info == 0)
+        idx = np.sort(rng.choice(g.A.shape[0], 120, replace=False))
+        Sr, Ur, Vr, swr, infor = oracle_batch(g.A[idx])
+        compare_with_oracle(g.A[idx], S[idx], U[idx], V[idx], info[idx], Sr, infor,
+                            label=f"full {g.m}x{g.n}")
+        # invariants on all matrices (cheap, vectorised)
+        R = g.A - np.einsum("bij,bj,bkj->bik", U, S, V)
+        rel = np.linalg.norm(R, axis=(1, 2)) / np.linalg.norm(g.A, axis=(1, 2))
+        assert rel.max() <= 1e-13 * g.n, rel.max()
+        assert np.all(np.diff(S, axis=1) <= 0)
+        say(f"  sweeps histogram {np.bincount(sw)}")
+        del S, U, V
+        torch.cuda.empty_cache()
