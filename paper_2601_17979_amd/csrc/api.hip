@@ -65,7 +65,17 @@ int make_plan(svdb_dtype_t dt, int m, int n, const svdb_opts_t &o, Plan *p)
     if (dt != SVDB_R64)
         return fail(SVDB_ERR_UNSUPPORTED, "dtype %d is not implemented in this build", (int)dt);
     int path = o.path;
-    if (path == SVDB_PATH_AUTO) path = SVDB_PATH_PLAIN;
+    int rN, rR, rW;
+    const bool res_ok = svdb::resident_config(m, n, &rN, &rR, &rW);
+    if (path == SVDB_PATH_AUTO) path = res_ok ? SVDB_PATH_RESIDENT : SVDB_PATH_PLAIN;
+    if (path == SVDB_PATH_RESIDENT) {
+        if (!res_ok)
+            return fail(SVDB_ERR_UNSUPPORTED, "resident path: no instance for %d x %d", m, n);
+        p->path = SVDB_PATH_RESIDENT;
+        p->nb = 0;
+        p->threads = 64 * rW;
+        return 0;
+    }
     if (path == SVDB_PATH_PLAIN) {
         if (!plain_fits(m, n))
             return fail(SVDB_ERR_UNSUPPORTED, "plain path: %d x %d does not fit in LDS", m, n);
@@ -158,7 +168,11 @@ int svdb_svd_strided_batched(svdb_dtype_t dtype, int batch, int m, int n, const 
     hipStream_t s = (hipStream_t)stream;
 
     hipError_t e = hipSuccess;
-    if (p.path == SVDB_PATH_PLAIN) {
+    if (p.path == SVDB_PATH_RESIDENT) {
+        e = svdb::launch_resident_d(batch, m, n, (const double *)A, lda, strideA, (double *)S,
+                                    strideS, (double *)U, ldu, strideU, (double *)V, ldv,
+                                    strideV, tol, o.max_sweeps, info, o.sweeps, s);
+    } else if (p.path == SVDB_PATH_PLAIN) {
         e = svdb::launch_plain_d(batch, m, n, (const double *)A, lda, strideA, (double *)S,
                                  strideS, (double *)U, ldu, strideU, (double *)V, ldv, strideV,
                                  tol, o.max_sweeps, info, o.sweeps, s);
