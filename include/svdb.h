@@ -73,6 +73,8 @@ typedef struct {
     int precision;    /* 0: sweeps in the working precision; 1: FP32 sweeps
                          then FP64 refinement (SVDB_R64 / SVDB_C128 only)      */
     int *sweeps;      /* optional DEVICE int[batch]: sweeps executed          */
+    int waves;        /* SVDB_PATH_RESIDENT: wavefronts per matrix (1, 2, 4);
+                         0 -> tuned                                           */
 } svdb_opts_t;
 
 /* Fills *o with the defaults (AUTO path, 100 sweeps, masking on). */

@@ -51,6 +51,7 @@ svdb_opts_t resolve_opts(const svdb_opts_t *o)
         r = *o;
         if (r.max_sweeps <= 0) r.max_sweeps = 100;
         if (r.masking < 0) r.masking = 1;
+        if (r.waves < 0) r.waves = 0;
     }
     return r;
 }
@@ -66,7 +67,7 @@ int make_plan(svdb_dtype_t dt, int m, int n, const svdb_opts_t &o, Plan *p)
         return fail(SVDB_ERR_UNSUPPORTED, "dtype %d is not implemented in this build", (int)dt);
     int path = o.path;
     int rN, rR, rW;
-    const bool res_ok = svdb::resident_config(m, n, &rN, &rR, &rW);
+    const bool res_ok = svdb::resident_config(m, n, o.waves, &rN, &rR, &rW);
     if (path == SVDB_PATH_AUTO) path = res_ok ? SVDB_PATH_RESIDENT : SVDB_PATH_PLAIN;
     if (path == SVDB_PATH_RESIDENT) {
         if (!res_ok)
@@ -100,6 +101,7 @@ void svdb_opts_default(svdb_opts_t *o)
     o->masking = 1;
     o->precision = 0;
     o->sweeps = nullptr;
+    o->waves = 0;
 }
 
 const char *svdb_last_error(void) { return g_err.c_str(); }
@@ -169,7 +171,8 @@ int svdb_svd_strided_batched(svdb_dtype_t dtype, int batch, int m, int n, const 
 
     hipError_t e = hipSuccess;
     if (p.path == SVDB_PATH_RESIDENT) {
-        e = svdb::launch_resident_d(batch, m, n, (const double *)A, lda, strideA, (double *)S,
+        e = svdb::launch_resident_d(batch, m, n, o.waves, (const double *)A, lda, strideA,
+                                    (double *)S,
                                     strideS, (double *)U, ldu, strideU, (double *)V, ldv,
                                     strideV, tol, o.max_sweeps, info, o.sweeps, s);
     } else if (p.path == SVDB_PATH_PLAIN) {

@@ -16,10 +16,10 @@ hipError_t launch_plain_d(int batch, int m, int n, const double *A, int lda, lon
                           int *sweeps, hipStream_t stream);
 
 // resident.hip: register-resident unblocked Jacobi, FP64, n <= 64.
-bool resident_config(int m, int n, int *N, int *R, int *NW);
-hipError_t launch_resident_d(int batch, int m, int n, const double *A, int lda, long long sA,
-                             double *S, long long sS, double *U, int ldu, long long sU, double *V,
-                             int ldv, long long sV, double tol, int max_sweeps, int *info,
-                             int *sweeps, hipStream_t stream);
+bool resident_config(int m, int n, int ns, int *N, int *R, int *NS);
+hipError_t launch_resident_d(int batch, int m, int n, int ns, const double *A, int lda,
+                             long long sA, double *S, long long sS, double *U, int ldu,
+                             long long sU, double *V, int ldv, long long sV, double tol,
+                             int max_sweeps, int *info, int *sweeps, hipStream_t stream);
 
 }  // namespace svdb

@@ -1,30 +1,40 @@
 // resident.hip -- register-resident unblocked one-sided Jacobi SVD (Alg. 2),
 // FP64, for n <= 64 columns.
 //
-// Layout.  The matrix is held as the stacked (m + N) x N matrix [W; V] (W
-// starts as A, V as I; every rotation acts on whole stacked columns), with one
-// stacked row per lane and slot: lane L of wave w, slot t holds stacked row
-// 64 (R w + t) + L.  All rows of W live in wave 0, so only wave 0 forms Gram
-// entries.  N is n rounded up to 16, 32 or 64 (extra columns are zero and
-// never rotate).
+// Layout.  The matrix is held as the stacked matrix [W; V] (W starts as A, V
+// as I; a rotation acts on whole stacked columns) in registers: lane L holds
+// row 64 t + L of W in slot t < RW and row L of V in slot RW.  N is n rounded
+// up to 16, 32 or 64 (extra columns are zero and never rotate).
 //
-// Ordering.  The round-robin ordering of Sec. 2 / 4.1 is realised as a
-// tournament table of K = N/2 seats per row: seat q of the top row (array T)
-// plays seat q of the bottom row (array B).  After an iteration every column
-// except the one in top seat 0 moves one ring position, which here is only a
-// choice of destination registers for the rotated columns -- no data moves
-// between lanes.  After N-1 iterations (one sweep) the table is back in its
-// initial state, so sweeps always start from columns (2q, 2q+1) in seat q.
+// Ordering.  The round-robin ordering of Sec. 2 / 4.1 is a tournament table
+// of K = N/2 seats per row: top seat q plays bottom seat q.  Between
+// iterations every column except the one in top seat 0 moves one position
+// around the ring top 1 .. top K-1, bottom K-1 .. bottom 0.  The seats are
+// split into NS consecutive groups, one wavefront each; a wave keeps the
+// columns of its seats in registers (arrays T, B), so a move inside a group
+// is only a choice of destination registers, and the two columns that cross
+// each group boundary per iteration go through LDS.  After N-1 iterations
+// (one sweep) the table is back in its initial state: sweeps start with
+// columns (2q, 2q+1) in seat q.
 //
-// Per iteration (wave 0): g_ij of the K pairs (Alg. 2, Gram entries) as one
-// FMA per row, a cross-lane reduction (permlane32/16 swaps, then an LDS
-// transpose inside rows of 16 lanes), the rotate-or-skip test and c, s of
-// eq. (sin-cos) computed by lanes in parallel, published through LDS; then
-// every wave rotates its rows of W and V.  The squared column norms g_ii are
-// tracked through the exact identity g_ii' = g_ii + t |g_ij|,
-// g_jj' = g_jj - t |g_ij| of a Jacobi rotation, and recomputed from the columns
-// at the start of every sweep, so the sweep that finds no pair to rotate --
-// the convergence test -- always uses exact norms.
+// Per iteration each wave forms g_ij of its pairs (Alg. 2, Gram entries) with
+// one FMA per row, reduces them across lanes (permlane32/16 swaps, then an
+// LDS transpose inside rows of 16 lanes), takes the rotate-or-skip test and
+// the rotation of eq. (sin-cos) with lanes working on different pairs, and
+// applies it to its rows of W and V.
+//
+// Rotations are applied in scaled form: the registers hold w_c / d_c with a
+// per-column factor d_c (in LDS).  A Jacobi rotation with cosine c and
+// tangent t then costs two FMAs per element, w_i <- w_i + mu_i w_j and
+// w_j <- w_j + mu_j w_i, with d_i, d_j <- c d_i, c d_j (the scaled, or
+// "fast", plane rotation; LAPACK's xGSVJ0 uses the same device).  Within one
+// sweep the stored columns grow by at most (1/c)^(N-1) <= 2^((N-1)/2); the
+// factors are folded back into the columns at every sweep start.
+//
+// The squared column norms g_ii are tracked with the exact identities
+// g_ii' = g_ii + t |g_ij|, g_jj' = g_jj - t |g_ij| of a Jacobi rotation and
+// recomputed from the columns at every sweep start, so the sweep that finds
+// no pair to rotate -- the convergence test -- always uses exact norms.
 #include "device_common.hpp"
 #include "launchers.hpp"
 
@@ -62,6 +72,13 @@ __device__ __forceinline__ double row_ror(double v)
     return __hiloint2double(hi, lo);
 }
 
+__device__ __forceinline__ void wave_sync_lds()
+{
+    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+    __builtin_amdgcn_wave_barrier();
+    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+}
+
 struct OpSum {
     __device__ static double apply(double a, double b) { return a + b; }
 };
@@ -69,13 +86,14 @@ struct OpMax {
     __device__ static double apply(double a, double b) { return fmax(a, b); }
 };
 
-// Reduces K per-lane values over the 64 lanes of a wave.  On return lane
-// L = 16 rho + x holds the reduction of value q = (x mod K/4) + (K/4) rho.
-// buf: 64 * K/4 doubles of LDS private to the calling wave.
-template <int K, class Op>
-__device__ __forceinline__ double reduce_pairs(double (&g)[K], double *buf)
+// Reduces KG (>= 4, power of two) per-lane values over the 64 lanes of a
+// wave.  On return lane L = 16 rho + x holds the reduction of value
+// (x mod KG/4) + (KG/4) rho, with identical bits in every lane that holds the
+// same value.  buf: 64 * KG/4 doubles of LDS private to the calling wave.
+template <int KG, class Op>
+__device__ __forceinline__ double reduce_pairs(double (&g)[KG], double *buf)
 {
-    constexpr int H = K / 2, Q = K / 4;
+    constexpr int H = KG / 2, Q = KG / 4;
     const int lane = threadIdx.x & 63, rho = lane >> 4, x = lane & 15;
     double h[H];
 #pragma unroll
@@ -95,26 +113,42 @@ __device__ __forceinline__ double reduce_pairs(double (&g)[K], double *buf)
     // four lanes {x, x+16, x+32, x+48}; finish inside the row of 16 lanes.
 #pragma unroll
     for (int v = 0; v < Q; v++) buf[(rho * Q + v) * 16 + x] = f[v];
-    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
-    __builtin_amdgcn_wave_barrier();
-    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+    wave_sync_lds();
     const int v = x % Q, h0 = (x / Q) * Q;
     const double *src = buf + (rho * Q + v) * 16 + h0;
     double s = src[0];
 #pragma unroll
     for (int k = 1; k < Q; k++) s = Op::apply(s, src[k]);
     // Rotations by 8, 4, 2, 1 lanes in this order: after each step the values
-    // repeat with half the period, so every step adds the same two operands in
-    // both lanes of a pair and all lanes of one value end with identical bits
-    // (the rotate-or-skip decision below must agree across those lanes).
+    // repeat with half the period, so every step combines the same two
+    // operands in both lanes of a pair and all lanes of one value end with
+    // identical bits (the rotate-or-skip decision must agree across them).
     s = Op::apply(s, row_ror<8>(s));
     if constexpr (Q < 8) s = Op::apply(s, row_ror<4>(s));
     if constexpr (Q < 4) s = Op::apply(s, row_ror<2>(s));
     if constexpr (Q < 2) s = Op::apply(s, row_ror<1>(s));
-    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
-    __builtin_amdgcn_wave_barrier();
-    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+    wave_sync_lds();
     return s;
+}
+
+// Reciprocal and reciprocal square root: hardware estimate plus two Newton
+// steps, r <- r (2 - x r) and y <- y (3 - x y^2) / 2, which take the estimate
+// to full double precision for normal positive x.
+__device__ __forceinline__ double rcp_nr(double x)
+{
+    double r = __builtin_amdgcn_rcp(x);
+    r = fma(fma(-x, r, 1.0), r, r);
+    r = fma(fma(-x, r, 1.0), r, r);
+    return r;
+}
+
+__device__ __forceinline__ double rsq_nr(double x)
+{
+    double y = __builtin_amdgcn_rsq(x);
+    const double h = 0.5 * x;
+    y = y * fma(-h * y, y, 1.5);
+    y = y * fma(-h * y, y, 1.5);
+    return y;
 }
 
 // Column ids in the top and bottom seat q at iteration `it` (see rr_pair).
@@ -133,336 +167,394 @@ __device__ __forceinline__ void rr_seats(int l, int it, int q, int &ct, int &cb)
     cb = rr_initial(y, k);
 }
 
-template <int N, int R, int NW>
-__global__ __launch_bounds__(64 * NW) void resident_jacobi_d(
+template <int N, int R, int NS>
+struct Shared {
+    static constexpr int K = N / 2, KG = K / NS, Q = KG / 4;
+    double nrm[N];                    // squared column norms, by column id
+    double d[N];                      // column scale factors, by column id
+    double2 cs[NS][KG];               // (mu_top, mu_bot) per pair of each wave
+    double buf[NS][64 * Q];           // reduction transposes
+    double xch[2][NS][2][R][64];      // columns leaving each wave (top, bottom)
+    double sig[N];
+    int rank[N];
+    double amax[NS];
+    int bad[NS];
+    int flag;
+};
+
+// Waves per SIMD the register allocation is asked to allow, from the stored
+// doubles per lane ((RW + 1) N / NS), so that the allocation fits without
+// spilling.
+constexpr int res_waves_per_eu(int N, int RW, int NS)
+{
+    return (RW + 1) * N / NS <= 32 ? 2 : 1;
+}
+
+// W rows live in slots 0..RW-1 (row 64 t + lane), V rows in slot RW (row =
+// lane); padding rows are zero, so Gram entries need no masks.
+template <int N, int RW, int NS>
+__global__ __launch_bounds__(64 * NS, res_waves_per_eu(N, RW, NS)) void resident_jacobi_d(
     int m, int n, const double *__restrict__ A, int lda, long long sA, double *S, long long sS,
     double *U, int ldu, long long sU, double *V, int ldv, long long sV, double tol,
     int max_sweeps, int *info, int *sweeps_out)
 {
-    constexpr int K = N / 2;
-    constexpr int Q = K / 4;
-    static_assert(K >= 8 && (K & (K - 1)) == 0, "N must be 16, 32 or 64");
-
-    __shared__ double s_nrm[N];           // squared column norms, by column id
-    __shared__ double2 s_cs[2][K];        // (c, signed e s) per pair, double buffered
-    __shared__ double s_buf[64 * Q];      // reduction transpose (wave 0)
-    __shared__ double s_sig[N];
-    __shared__ int s_rank[N];
-    __shared__ double s_scale;
-    __shared__ int s_bad, s_flag;
+    constexpr int R = RW + 1;
+    using SH = Shared<N, R, NS>;
+    constexpr int K = SH::K, KG = SH::KG, Q = SH::Q;
+    static_assert(KG >= 4 && (KG & (KG - 1)) == 0, "4 <= pairs per wave, power of two");
+    static_assert(N <= 64, "one V row per lane");
+    __shared__ SH sh;
 
     const int b = blockIdx.x;
-    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+    const int lane = threadIdx.x & 63;
+    // wave index as a scalar, so that per-wave LDS addresses stay in SGPRs
+    const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
+    const int x = lane & 15;
+    const int qloc = (x % Q) + Q * (lane >> 4);   // pair of this lane after a reduction
+    const int q0 = wave * KG;                     // first seat of this wave
+    const bool first = (wave == 0), last = (wave == NS - 1);
     A += (size_t)b * sA;
 
-    // stacked row of slot t, and its class
-    int srow[R];
-#pragma unroll
-    for (int t = 0; t < R; t++) srow[t] = 64 * (R * wave + t) + lane;
-
-    double T[K][R], B[K][R];
+    double T[KG][R], B[KG][R];
     // ---- load W = A (zero padded) and V = I ----------------------------------
     double amax = 0.0;
     int bad = 0;
 #pragma unroll
-    for (int t = 0; t < R; t++) {
-        const int s = srow[t];
+    for (int q = 0; q < KG; q++) {
+        const int ct = 2 * (q0 + q), cb = ct + 1;
 #pragma unroll
-        for (int q = 0; q < K; q++) {
+        for (int t = 0; t < RW; t++) {
+            const int s = 64 * t + lane;
             double xt = 0.0, xb = 0.0;
-            const int ct = 2 * q, cb = 2 * q + 1;
             if (s < m) {
                 if (ct < n) xt = A[(size_t)ct * lda + s];
                 if (cb < n) xb = A[(size_t)cb * lda + s];
-            } else if (s < m + N) {
-                xt = (s - m == ct) ? 1.0 : 0.0;
-                xb = (s - m == cb) ? 1.0 : 0.0;
             }
-            if (s < m) {
-                bad |= !isfinite(xt) | !isfinite(xb);
-                amax = fmax(amax, fmax(fabs(xt), fabs(xb)));
-            }
+            bad |= !isfinite(xt) | !isfinite(xb);
+            amax = fmax(amax, fmax(fabs(xt), fabs(xb)));
             T[q][t] = xt;
             B[q][t] = xb;
         }
+        T[q][RW] = (lane == ct) ? 1.0 : 0.0;
+        B[q][RW] = (lane == cb) ? 1.0 : 0.0;
     }
-    if (threadIdx.x == 0) {
-        s_bad = 0;
-        s_flag = 0;
-    }
-    __syncthreads();
     bad = __any(bad);
     amax = wave_max(amax);
-    if (wave == 0 && lane == 0) {
-        s_scale = pow2_scale(amax);
-        if (bad) s_bad = 1;
+    if (lane == 0) {
+        sh.amax[wave] = amax;
+        sh.bad[wave] = bad;
     }
+    if (threadIdx.x < N) sh.d[threadIdx.x] = 1.0;
+    if (threadIdx.x == 0) sh.flag = 0;
     __syncthreads();
-    if (s_bad) {
+    for (int w = 0; w < NS; w++) {
+        bad |= sh.bad[w];
+        amax = fmax(amax, sh.amax[w]);
+    }
+    if (bad) {
         if (threadIdx.x == 0) {
             info[b] = 2;
             if (sweeps_out) sweeps_out[b] = 0;
         }
         return;
     }
-    const double scale = s_scale;
-    if (wave == 0 && scale != 1.0) {
+    const double scale = pow2_scale(amax);
+    if (scale != 1.0) {
 #pragma unroll
-        for (int t = 0; t < R; t++)
-            if (srow[t] < m) {
+        for (int q = 0; q < KG; q++)
 #pragma unroll
-                for (int q = 0; q < K; q++) {
-                    T[q][t] *= scale;
-                    B[q][t] *= scale;
-                }
+            for (int t = 0; t < RW; t++) {
+                T[q][t] *= scale;
+                B[q][t] *= scale;
             }
     }
+    const double tol2 = tol * tol;
 
-    // slot classes for the Gram entries (wave-uniform): 2 all rows of W,
-    // 1 some rows of W, 0 none
-    int wcls[R];
+    double *buf = sh.buf[wave];
+    double2 *cs = sh.cs[wave];
+    int sweeps = 0, converged = 0, par = 0;
+    while (true) {
+        // ---- fold the scale factors back in; exact squared norms ------------
+        {
+            double pt[KG], pb[KG];
 #pragma unroll
-    for (int t = 0; t < R; t++) {
-        const int base = 64 * (R * wave + t);
-        wcls[t] = (base + 63 < m) ? 2 : (base < m ? 1 : 0);
-    }
-
-    const int l = N;
-    int sweeps = 0, converged = 0;
-    int par = 0;
-    while (!converged && sweeps < max_sweeps) {
-        sweeps++;
-        // exact squared norms at the start of the sweep (seat q holds 2q, 2q+1)
-        if (wave == 0) {
-            double pt[K], pb[K];
-#pragma unroll
-            for (int q = 0; q < K; q++) {
+            for (int q = 0; q < KG; q++) {
+                if (q % 4 == 0) __builtin_amdgcn_sched_barrier(0);
+                const double2 dd = *reinterpret_cast<const double2 *>(&sh.d[2 * (q0 + q)]);
+                const double dt = dd.x, db = dd.y;
                 pt[q] = 0.0;
                 pb[q] = 0.0;
-            }
-#pragma unroll
-            for (int t = 0; t < R; t++) {
-                if (wcls[t] == 0) continue;
-                const double msk = (srow[t] < m) ? 1.0 : 0.0;
-#pragma unroll
-                for (int q = 0; q < K; q++) {
-                    const double xt = T[q][t] * msk, xb = B[q][t] * msk;
-                    pt[q] = fma(xt, xt, pt[q]);
-                    pb[q] = fma(xb, xb, pb[q]);
-                }
-            }
-            const double nt = reduce_pairs<K, OpSum>(pt, s_buf);
-            const double nb = reduce_pairs<K, OpSum>(pb, s_buf);
-            const int x = lane & 15, q = (x % Q) + Q * (lane >> 4);
-            if (x < Q) {
-                s_nrm[2 * q] = nt;
-                s_nrm[2 * q + 1] = nb;
-            }
-        }
-        for (int it = 0; it < l - 1; it++) {
-            if (wave == 0) {
-                double g[K];
-#pragma unroll
-                for (int q = 0; q < K; q++) g[q] = 0.0;
 #pragma unroll
                 for (int t = 0; t < R; t++) {
-                    if (wcls[t] == 2) {
-#pragma unroll
-                        for (int q = 0; q < K; q++) g[q] = fma(T[q][t], B[q][t], g[q]);
-                    } else if (wcls[t] == 1) {
-                        const double msk = (srow[t] < m) ? 1.0 : 0.0;
-#pragma unroll
-                        for (int q = 0; q < K; q++) g[q] = fma(T[q][t] * msk, B[q][t], g[q]);
-                    }
+                    T[q][t] *= dt;
+                    B[q][t] *= db;
                 }
-                const double gq = reduce_pairs<K, OpSum>(g, s_buf);
-                const int x = lane & 15, q = (x % Q) + Q * (lane >> 4);
-                int ct, cb;
-                rr_seats(l, it, q, ct, cb);
-                const double at = s_nrm[ct], ab = s_nrm[cb];
-                // orientation of the paper: pair (i, j) with i < j
-                const bool top_is_i = ct < cb;
-                const double gi = top_is_i ? at : ab, gj = top_is_i ? ab : at;
-                const double ag = fabs(gq);
-                double c = 1.0, es = 0.0;
-                const bool rot = (gq != 0.0) && (ag >= tol * sqrt(gi) * sqrt(gj));
-                if (rot) {
-                    double s;
-                    const double tau = (gi - gj) / (2.0 * ag);
-                    const double atau = fabs(tau);
-                    double tt = (atau > 0x1p500) ? 0.5 / atau : 1.0 / (atau + sqrt(1.0 + atau * atau));
-                    tt = (tau >= 0.0) ? tt : -tt;
-                    c = 1.0 / sqrt(1.0 + tt * tt);
-                    s = tt * c;
-                    es = gq > 0.0 ? s : -s;
-                    const double ni = fma(tt, ag, gi), nj = fma(-tt, ag, gj);
-                    if (x < Q) {
-                        s_nrm[top_is_i ? ct : cb] = ni;
-                        s_nrm[top_is_i ? cb : ct] = nj;
-                    }
+#pragma unroll
+                for (int t = 0; t < RW; t++) {
+                    pt[q] = fma(T[q][t], T[q][t], pt[q]);
+                    pb[q] = fma(B[q][t], B[q][t], pb[q]);
                 }
-                // the top seat's column is a_i when top_is_i; otherwise the
-                // roles swap and the sign of e s flips
-                if (x < Q) s_cs[par][q] = make_double2(c, top_is_i ? es : -es);
-                if (__any(rot && x < Q) && lane == 0) s_flag = 1;
+            }
+            const double nt = reduce_pairs<KG, OpSum>(pt, buf);
+            const double nb = reduce_pairs<KG, OpSum>(pb, buf);
+            if (x < Q) {
+                const int c = 2 * (q0 + qloc);
+                sh.nrm[c] = nt;
+                sh.nrm[c + 1] = nb;
+                sh.d[c] = 1.0;
+                sh.d[c + 1] = 1.0;
             }
             __syncthreads();
-            // ---- rotate every row slot; the destinations realise the seat moves
-            double nT[K][R], nB[K][R];
+        }
+        if (converged || sweeps >= max_sweeps) break;
+        sweeps++;
+#pragma unroll 1
+        for (int it = 0; it < N - 1; it++) {
+            // ---- Gram entries of this wave's pairs --------------------------
+            double g[KG];
 #pragma unroll
-            for (int q = K - 1; q >= 0; q--) {
-                const double2 cs = s_cs[par][q];
+            for (int q = 0; q < KG; q++) {
+                g[q] = 0.0;
 #pragma unroll
-                for (int t = 0; t < R; t++) {
-                    const double a = T[q][t], bb = B[q][t];
-                    const double na = fma(cs.x, a, cs.y * bb);
-                    const double nb = fma(cs.x, bb, -cs.y * a);
-                    if (q == 0) nT[0][t] = na;
-                    else if (q < K - 1) nT[q + 1][t] = na;
-                    else nB[K - 1][t] = na;
-                    if (q == 0) nT[1][t] = nb;
-                    else nB[q - 1][t] = nb;
+                for (int t = 0; t < RW; t++) g[q] = fma(T[q][t], B[q][t], g[q]);
+            }
+            const double gs = reduce_pairs<KG, OpSum>(g, buf);
+            // ---- rotate-or-skip and the rotation, one pair per lane group ---
+            int ct, cb;
+            rr_seats(N, it, q0 + qloc, ct, cb);
+            const double dt = sh.d[ct], db = sh.d[cb];
+            const double gam = gs * dt * db;            // true g_ij
+            const bool top_is_i = ct < cb;              // pair (i, j), i < j
+            const double gt = sh.nrm[ct], gb = sh.nrm[cb];
+            const double gi = top_is_i ? gt : gb, gj = top_is_i ? gb : gt;
+            const double ag = fabs(gam);
+            // |g_ij| >= tol sqrt(g_ii) sqrt(g_jj), squared unless the product
+            // of the norms would underflow
+            const double pij = gi * gj;
+            const bool rot = (gam != 0.0) &&
+                             (pij > 1e-250 ? ag * ag >= tol2 * pij : ag >= tol * sqrt(gi) * sqrt(gj));
+            double mut = 0.0, mub = 0.0;
+            if (rot) {
+                const double tau = (gi - gj) * (0.5 * rcp_nr(ag));
+                const double atau = fabs(tau);
+                double tt;
+                if (atau > 0x1p500) {
+                    tt = 0.5 / atau;
+                } else {
+                    const double q2 = fma(atau, atau, 1.0);
+                    tt = rcp_nr(atau + q2 * rsq_nr(q2));
+                }
+                tt = (tau >= 0.0) ? tt : -tt;           // t of eq. (sin-cos)
+                const double c = rsq_nr(fma(tt, tt, 1.0));
+                // new columns: a_i' = c (a_i + e t a_j), a_j' = c (a_j - e t a_i)
+                const double et = (gam > 0.0) ? tt : -tt;
+                const double sg = top_is_i ? et : -et;
+                const double r = db * rcp_nr(dt);       // d_bottom / d_top
+                mut = sg * r;
+                mub = -sg * rcp_nr(r);
+                if (x < Q) {
+                    sh.nrm[top_is_i ? ct : cb] = fma(tt, ag, gi);
+                    sh.nrm[top_is_i ? cb : ct] = fma(-tt, ag, gj);
+                    sh.d[ct] = c * dt;
+                    sh.d[cb] = c * db;
                 }
             }
+            if (x < Q) cs[qloc] = make_double2(mut, mub);
+            if (__any(rot && x < Q) && lane == 0) sh.flag = 1;
+            wave_sync_lds();
+            // ---- apply to W and V and move the seats -------------------------
+            // top seat q -> top q+1 and bottom seat q -> bottom q-1 inside the
+            // wave; the last top seat leaves for the next wave (the last wave
+            // keeps it as its last bottom seat), bottom seat 0 leaves for the
+            // previous wave (the first wave moves it to top seat 1), and top
+            // seat 0 of the first wave stays.
+            // Pairs are processed from the last seat down: the new top column
+            // of pair q goes straight into top seat q+1 (consumed one step
+            // earlier), the new bottom column waits one step in `prev` until
+            // bottom seat q-1 has been read.
+            double outT[R], keep0[R], prev[R];
+            // (mu_top, mu_bot) are read four pairs at a time, one group ahead,
+            // so that at most eight pairs' parameters occupy registers
+            constexpr int CH = KG < 4 ? KG : 4;
+            double2 mu_nx[CH];
 #pragma unroll
-            for (int q = 0; q < K; q++)
+            for (int k = 0; k < CH; k++) mu_nx[k] = cs[KG - 1 - k];
+#pragma unroll
+            for (int c0 = 0; c0 < KG; c0 += CH) {
+                double2 mu_cu[CH];
+#pragma unroll
+                for (int k = 0; k < CH; k++) mu_cu[k] = mu_nx[k];
+                if (c0 + CH < KG) {
+#pragma unroll
+                    for (int k = 0; k < CH; k++) mu_nx[k] = cs[KG - 1 - (c0 + CH + k)];
+                }
+                __builtin_amdgcn_sched_barrier(0);
+#pragma unroll
+                for (int k = 0; k < CH; k++) {
+                    const int q = KG - 1 - (c0 + k);
+                    const double2 mu = mu_cu[k];
+#pragma unroll
+                    for (int t = 0; t < R; t++) {
+                        const double a = T[q][t], bb = B[q][t];
+                        const double na = fma(mu.x, bb, a);
+                        const double nb = fma(mu.y, a, bb);
+                        if (q == KG - 1) outT[t] = na;
+                        else T[q + 1][t] = na;
+                        if (q == 0) keep0[t] = na;
+                        if (q < KG - 1) B[q][t] = prev[t];
+                        prev[t] = nb;
+                    }
+                }
+                __builtin_amdgcn_sched_barrier(0);
+            }
+            double (&outB)[R] = prev;               // new bottom seat 0
+            if constexpr (NS > 1) {
 #pragma unroll
                 for (int t = 0; t < R; t++) {
-                    T[q][t] = nT[q][t];
-                    B[q][t] = nB[q][t];
+                    sh.xch[par][wave][0][t][lane] = outT[t];
+                    sh.xch[par][wave][1][t][lane] = outB[t];
                 }
+                __syncthreads();
+            }
+            const int wprev = first ? 0 : wave - 1, wnext = last ? wave : wave + 1;
+#pragma unroll
+            for (int t = 0; t < R; t++) {
+                // top seat 0: the first wave keeps its own, the others take the
+                // last top seat of the previous wave
+                T[0][t] = first ? keep0[t] : sh.xch[par][wprev][0][t][lane];
+                // bottom seat 0 of the first wave turns into top seat 1
+                if (first) T[1][t] = outB[t];
+                // last bottom seat: the last wave turns its last top seat, the
+                // others take bottom seat 0 of the next wave
+                B[KG - 1][t] = last ? outT[t] : sh.xch[par][wnext][1][t][lane];
+            }
             par ^= 1;
         }
         __syncthreads();
-        converged = (s_flag == 0);
+        converged = (sh.flag == 0);
         __syncthreads();
-        if (threadIdx.x == 0) s_flag = 0;
+        if (threadIdx.x == 0) sh.flag = 0;
     }
 
-    // ---- finalise: sigma = ||w_c|| (two-pass scaled), stable descending sort
-    if (wave == 0) {
-        double mt[K], mb[K];
-#pragma unroll
-        for (int q = 0; q < K; q++) {
-            mt[q] = 0.0;
-            mb[q] = 0.0;
+    // ---- finalise: sigma_c = ||w_c|| from the exact squared norms of the last
+    // fold.  A column whose squared norm is below 2^-900 (entries below
+    // 2^-450 after the pre-scaling) is first multiplied by 2^600, an exact
+    // power of two that keeps every square representable; its factor 2^-600
+    // is remembered in d_c and divided out of sigma_c and of its V part.
+    {
+        const int c = 2 * (q0 + qloc);
+        int tiny = 0;
+        if (x < Q) {
+            const double nt = sh.nrm[c], nb = sh.nrm[c + 1];
+            const bool tt = nt < 0x1p-900, tb = nb < 0x1p-900;
+            sh.d[c] = tt ? 0x1p-600 : 1.0;
+            sh.d[c + 1] = tb ? 0x1p-600 : 1.0;
+            tiny = tt || tb;
         }
+        tiny = __any(tiny);
+        wave_sync_lds();
+        if (tiny) {
+            double pt[KG], pb[KG];
 #pragma unroll
-        for (int t = 0; t < R; t++) {
-            if (wcls[t] == 0) continue;
-            const double msk = (srow[t] < m) ? 1.0 : 0.0;
+            for (int q = 0; q < KG; q++) {
+                const double ft = sh.d[2 * (q0 + q)] < 1.0 ? 0x1p600 : 1.0;
+                const double fb = sh.d[2 * (q0 + q) + 1] < 1.0 ? 0x1p600 : 1.0;
+                pt[q] = 0.0;
+                pb[q] = 0.0;
 #pragma unroll
-            for (int q = 0; q < K; q++) {
-                mt[q] = fmax(mt[q], fabs(T[q][t]) * msk);
-                mb[q] = fmax(mb[q], fabs(B[q][t]) * msk);
+                for (int t = 0; t < R; t++) {
+                    T[q][t] *= ft;
+                    B[q][t] *= fb;
+                }
+#pragma unroll
+                for (int t = 0; t < RW; t++) {
+                    pt[q] = fma(T[q][t], T[q][t], pt[q]);
+                    pb[q] = fma(B[q][t], B[q][t], pb[q]);
+                }
+            }
+            const double nt = reduce_pairs<KG, OpSum>(pt, buf);
+            const double nb = reduce_pairs<KG, OpSum>(pb, buf);
+            if (x < Q) {
+                sh.nrm[c] = nt;
+                sh.nrm[c + 1] = nb;
             }
         }
-        const double xt = reduce_pairs<K, OpMax>(mt, s_buf);
-        const double xb = reduce_pairs<K, OpMax>(mb, s_buf);
-        const int x = lane & 15, q = (x % Q) + Q * (lane >> 4);
         if (x < Q) {
-            s_sig[2 * q] = xt;          // column maxima, temporarily
-            s_sig[2 * q + 1] = xb;
-        }
-        __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
-        __builtin_amdgcn_wave_barrier();
-        __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
-        double pt[K], pb[K];
-#pragma unroll
-        for (int q2 = 0; q2 < K; q2++) {
-            const double it_ = s_sig[2 * q2] > 0.0 ? 1.0 / s_sig[2 * q2] : 0.0;
-            const double ib_ = s_sig[2 * q2 + 1] > 0.0 ? 1.0 / s_sig[2 * q2 + 1] : 0.0;
-            pt[q2] = 0.0;
-            pb[q2] = 0.0;
-#pragma unroll
-            for (int t = 0; t < R; t++) {
-                if (wcls[t] == 0) continue;
-                const double msk = (srow[t] < m) ? 1.0 : 0.0;
-                const double yt = T[q2][t] * it_ * msk, yb = B[q2][t] * ib_ * msk;
-                pt[q2] = fma(yt, yt, pt[q2]);
-                pb[q2] = fma(yb, yb, pb[q2]);
-            }
-        }
-        const double st = reduce_pairs<K, OpSum>(pt, s_buf);
-        const double sb = reduce_pairs<K, OpSum>(pb, s_buf);
-        __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
-        __builtin_amdgcn_wave_barrier();
-        __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
-        if (x < Q) {
-            const double mxt = s_sig[2 * q], mxb = s_sig[2 * q + 1];
-            s_sig[2 * q] = mxt > 0.0 ? mxt * sqrt(st) : 0.0;
-            s_sig[2 * q + 1] = mxb > 0.0 ? mxb * sqrt(sb) : 0.0;
+            sh.sig[c] = sqrt(sh.nrm[c]) * sh.d[c];
+            sh.sig[c + 1] = sqrt(sh.nrm[c + 1]) * sh.d[c + 1];
         }
     }
     __syncthreads();
     if (threadIdx.x < N) {
         const int c = threadIdx.x;
-        const double sc = s_sig[c];
+        const double sc = sh.sig[c];
         int rk = 0;
         for (int j = 0; j < N; j++) {
-            const double sj = s_sig[j];
+            const double sj = sh.sig[j];
             rk += (sj > sc) || (sj == sc && j < c);
         }
-        s_rank[c] = rk;
+        sh.rank[c] = rk;
     }
     __syncthreads();
     S += (size_t)b * sS;
-    if (threadIdx.x < n) S[s_rank[threadIdx.x]] = s_sig[threadIdx.x] / scale;
+    if (threadIdx.x < n) S[sh.rank[threadIdx.x]] = sh.sig[threadIdx.x] / scale;
     if (U) U += (size_t)b * sU;
     if (V) V += (size_t)b * sV;
-    bool any_zero = false;
 #pragma unroll
-    for (int q = 0; q < K; q++) {
+    for (int q = 0; q < KG; q++) {
+        if (q % 4 == 0) __builtin_amdgcn_sched_barrier(0);
 #pragma unroll
         for (int h = 0; h < 2; h++) {
-            const int c = 2 * q + h;
+            const int c = 2 * (q0 + q) + h;
             if (c >= n) continue;
-            const int rk = s_rank[c];
-            const double sc = s_sig[c];
-            const double inv = sc > 0.0 ? 1.0 / sc : 0.0;
-            any_zero |= !(sc > 0.0);
+            const int rk = sh.rank[c];
+            const double nc = sh.nrm[c];
+            const double inv = nc > 0.0 ? rsq_nr(nc) : 0.0;   // 1 / ||stored column||
+            const double dv = sh.d[c];
 #pragma unroll
-            for (int t = 0; t < R; t++) {
-                const int s = srow[t];
+            for (int t = 0; t < RW; t++) {
                 const double val = h ? B[q][t] : T[q][t];
-                if (s < m) {
-                    if (U) U[(size_t)rk * ldu + s] = val * inv;
-                } else if (s < m + n) {
-                    if (V) V[(size_t)rk * ldv + (s - m)] = val;
-                }
+                const int s = 64 * t + lane;
+                if (U && s < m) U[(size_t)rk * ldu + s] = val * inv;
             }
+            if (V && lane < n) V[(size_t)rk * ldv + lane] = (h ? B[q][RW] : T[q][RW]) * dv;
         }
     }
+    bool any_zero = false;
+    for (int c = 0; c < n; c++) any_zero |= !(sh.sig[c] > 0.0);
     // sigma = 0: complete U by Gram-Schmidt on e_1, e_2, ... (rare; wave 0,
     // on the freshly written columns of U in global memory)
-    if (U && wave == 0 && any_zero) {
+    if (U && any_zero) {
         __threadfence();
-        int cand = 0;
-        for (int i = 0; i < n; i++) {
-            if (s_sig[i] > 0.0) continue;
-            double *u = U + (size_t)s_rank[i] * ldu;
-            for (; cand < m; cand++) {
-                for (int r = lane; r < m; r += 64) u[r] = (r == cand) ? 1.0 : 0.0;
-                __threadfence();
-                for (int pass = 0; pass < 2; pass++)
-                    for (int j = 0; j < n; j++) {
-                        if (j == i || (s_sig[j] == 0.0 && j > i)) continue;
-                        const double *qv = U + (size_t)s_rank[j] * ldu;
-                        double d = 0.0;
-                        for (int r = lane; r < m; r += 64) d += qv[r] * u[r];
-                        d = wave_sum(d);
-                        for (int r = lane; r < m; r += 64) u[r] -= d * qv[r];
-                        __threadfence();
-                    }
-                double nu = 0.0;
-                for (int r = lane; r < m; r += 64) nu += u[r] * u[r];
-                nu = sqrt(wave_sum(nu));
-                if (nu > 0.5) {
-                    const double inv = 1.0 / nu;
-                    for (int r = lane; r < m; r += 64) u[r] *= inv;
+        __syncthreads();
+        if (wave == 0) {
+            int cand = 0;
+            for (int i = 0; i < n; i++) {
+                if (sh.sig[i] > 0.0) continue;
+                double *u = U + (size_t)sh.rank[i] * ldu;
+                for (; cand < m; cand++) {
+                    for (int r = lane; r < m; r += 64) u[r] = (r == cand) ? 1.0 : 0.0;
                     __threadfence();
-                    cand++;
-                    break;
+                    for (int pass = 0; pass < 2; pass++)
+                        for (int j = 0; j < n; j++) {
+                            if (j == i || (sh.sig[j] == 0.0 && j > i)) continue;
+                            const double *qv = U + (size_t)sh.rank[j] * ldu;
+                            double d = 0.0;
+                            for (int r = lane; r < m; r += 64) d += qv[r] * u[r];
+                            d = wave_sum(d);
+                            for (int r = lane; r < m; r += 64) u[r] -= d * qv[r];
+                            __threadfence();
+                        }
+                    double nu = 0.0;
+                    for (int r = lane; r < m; r += 64) nu += u[r] * u[r];
+                    nu = sqrt(wave_sum(nu));
+                    if (nu > 0.5) {
+                        const double inv = 1.0 / nu;
+                        for (int r = lane; r < m; r += 64) u[r] *= inv;
+                        __threadfence();
+                        cand++;
+                        break;
+                    }
                 }
             }
         }
@@ -473,66 +565,76 @@ __global__ __launch_bounds__(64 * NW) void resident_jacobi_d(
     }
 }
 
-template <int N, int R, int NW>
+template <int N, int R, int NS>
 hipError_t launch_one(int batch, int m, int n, const double *A, int lda, long long sA, double *S,
                       long long sS, double *U, int ldu, long long sU, double *V, int ldv,
                       long long sV, double tol, int max_sweeps, int *info, int *sweeps,
                       hipStream_t stream)
 {
-    hipLaunchKernelGGL((resident_jacobi_d<N, R, NW>), dim3(batch), dim3(64 * NW), 0, stream, m,
-                       n, A, lda, sA, S, sS, U, ldu, sU, V, ldv, sV, tol, max_sweeps, info,
+    hipLaunchKernelGGL((resident_jacobi_d<N, R, NS>), dim3(batch), dim3(64 * NS), 0, stream,
+                       m, n, A, lda, sA, S, sS, U, ldu, sU, V, ldv, sV, tol, max_sweeps, info,
                        sweeps);
     return hipGetLastError();
 }
 
 }  // namespace
 
-// Shape classes of the resident kernel: N = n rounded up to 16/32/64, R rows
-// per lane and slot count such that all of W sits in wave 0 (m <= 64 R) and
-// [W; V] fits the NW waves (m + N <= 64 R NW).  Returns false when no
-// instance covers (m, n).
-bool resident_config(int m, int n, int *N, int *R, int *NW)
+// Shape classes: N = n rounded up to 16/32/64; RW = ceil(m/64) slots of W
+// rows per lane (m <= 256) plus one slot of V rows; NS = waves (seat groups)
+// per matrix, with at most 96 stored doubles per lane.  `ns` = 0 picks the
+// tuned default.  Returns false when no instance covers (m, n, ns).
+bool resident_config(int m, int n, int ns, int *N, int *R, int *NS)
 {
     if (n < 1 || m < n) return false;
     const int nn = n <= 16 ? 16 : (n <= 32 ? 32 : (n <= 64 ? 64 : 0));
     if (!nn) return false;
-    int r = (m + 63) / 64;
-    const int rmax = nn == 16 ? 4 : (nn == 32 ? 3 : 1);
-    if (r > rmax) return false;
-    int nw = (m + nn + 64 * r - 1) / (64 * r);
-    if (nw > 2) return false;
-    // prefer one wave with one more slot when that keeps the register budget
-    if (nw == 2 && r + 1 <= rmax && m + nn <= 64 * (r + 1)) {
-        r += 1;
-        nw = 1;
-    }
+    const int rw = (m + 63) / 64;
+    if (rw > 4) return false;
+    if (ns == 0) ns = ((rw + 1) * nn > 96) ? 2 : 1;
+    if (ns != 1 && ns != 2 && ns != 4) return false;
+    if ((nn / 2) / ns < 4) return false;
+    if ((rw + 1) * nn / ns > 96) return false;
     *N = nn;
-    *R = r;
-    *NW = nw;
+    *R = rw;
+    *NS = ns;
     return true;
 }
 
-hipError_t launch_resident_d(int batch, int m, int n, const double *A, int lda, long long sA,
-                             double *S, long long sS, double *U, int ldu, long long sU, double *V,
-                             int ldv, long long sV, double tol, int max_sweeps, int *info,
-                             int *sweeps, hipStream_t stream)
+hipError_t launch_resident_d(int batch, int m, int n, int ns, const double *A, int lda,
+                             long long sA, double *S, long long sS, double *U, int ldu,
+                             long long sU, double *V, int ldv, long long sV, double tol,
+                             int max_sweeps, int *info, int *sweeps, hipStream_t stream)
 {
-    int N, R, NW;
-    if (!resident_config(m, n, &N, &R, &NW)) return hipErrorInvalidValue;
+    int N, RW, NS;
+    if (!resident_config(m, n, ns, &N, &RW, &NS)) return hipErrorInvalidValue;
 #define SVDB_RES(NN, RR, WW)                                                                   \
-    if (N == NN && R == RR && NW == WW)                                                        \
+    if (N == NN && RW == RR && NS == WW)                                                       \
         return launch_one<NN, RR, WW>(batch, m, n, A, lda, sA, S, sS, U, ldu, sU, V, ldv, sV,  \
                                       tol, max_sweeps, info, sweeps, stream);
     SVDB_RES(16, 1, 1)
     SVDB_RES(16, 2, 1)
     SVDB_RES(16, 3, 1)
     SVDB_RES(16, 4, 1)
+    SVDB_RES(16, 1, 2)
+    SVDB_RES(16, 2, 2)
+    SVDB_RES(16, 3, 2)
     SVDB_RES(16, 4, 2)
     SVDB_RES(32, 1, 1)
     SVDB_RES(32, 2, 1)
-    SVDB_RES(32, 3, 1)
+    SVDB_RES(32, 1, 2)
+    SVDB_RES(32, 2, 2)
     SVDB_RES(32, 3, 2)
+    SVDB_RES(32, 4, 2)
+    SVDB_RES(32, 1, 4)
+    SVDB_RES(32, 2, 4)
+    SVDB_RES(32, 3, 4)
+    SVDB_RES(32, 4, 4)
     SVDB_RES(64, 1, 2)
+    SVDB_RES(64, 2, 2)
+    SVDB_RES(64, 1, 4)
+    SVDB_RES(64, 2, 4)
+    SVDB_RES(64, 3, 4)
+    SVDB_RES(64, 4, 4)
 #undef SVDB_RES
     return hipErrorInvalidValue;
 }

@@ -28,7 +28,8 @@ _PATHS = {"auto": PATH_AUTO, "plain": PATH_PLAIN, "resident": PATH_RESIDENT,
 
 class Opts(C.Structure):
     _fields_ = [("max_sweeps", C.c_int), ("path", C.c_int), ("nb", C.c_int),
-                ("masking", C.c_int), ("precision", C.c_int), ("sweeps", C.c_void_p)]
+                ("masking", C.c_int), ("precision", C.c_int), ("sweeps", C.c_void_p),
+                ("waves", C.c_int)]
 
 
 class SvdbError(RuntimeError):
@@ -78,7 +79,8 @@ def version() -> str:
     return lib().svdb_version().decode()
 
 
-def make_opts(max_sweeps=100, path="auto", nb=0, masking=True, precision=0, sweeps=None):
+def make_opts(max_sweeps=100, path="auto", nb=0, masking=True, precision=0, sweeps=None,
+              waves=0):
     o = Opts()
     lib().svdb_opts_default(C.byref(o))
     o.max_sweeps = int(max_sweeps)
@@ -87,6 +89,7 @@ def make_opts(max_sweeps=100, path="auto", nb=0, masking=True, precision=0, swee
     o.masking = 1 if masking else 0
     o.precision = int(precision)
     o.sweeps = sweeps.data_ptr() if sweeps is not None else None
+    o.waves = int(waves)
     return o
 
 
@@ -128,7 +131,7 @@ def _check_cm(x: torch.Tensor, name: str):
 
 def svd(A: torch.Tensor, tol: float = 0.0, max_sweeps: int = 100, path="auto", nb: int = 0,
         compute_u: bool = True, compute_v: bool = True, masking: bool = True,
-        precision: int = 0, want_sweeps: bool = True, stream=None, out=None):
+        precision: int = 0, want_sweeps: bool = True, stream=None, out=None, waves: int = 0):
     """Batched reduced SVD of a (batch, m, n) column-major GPU tensor (m >= n).
 
     Returns (S, U, V, info, sweeps); U/V are None when not requested, sweeps
@@ -147,7 +150,7 @@ def svd(A: torch.Tensor, tol: float = 0.0, max_sweeps: int = 100, path="auto", n
         V = empty_col_major(b, n, n, A.dtype, dev) if compute_v else None
         info = torch.empty(b, dtype=torch.int32, device=dev)
         sweeps = torch.empty(b, dtype=torch.int32, device=dev) if want_sweeps else None
-    o = make_opts(max_sweeps, path, nb, masking, precision, sweeps)
+    o = make_opts(max_sweeps, path, nb, masking, precision, sweeps, waves)
     ws_bytes = lib().svdb_workspace_size(code, b, m, n, C.byref(o))
     if ws_bytes == C.c_size_t(-1).value:
         raise SvdbError(-1, last_error() or "invalid arguments")
