@@ -29,6 +29,24 @@ WORKLOAD = ("10000 FP64 SVDs (S,U,V): 5000 x 64x64 + 5000 x 128x32, half geometr
 FP64_VALU_PEAK = 256 * 4 * 16 * 2 * 2.4e9      # CUs x SIMDs x lanes x FMA x clock
 
 
+def measured_traffic(path: str, shape: str):
+    """HBM bytes per launch from the committed rocprofv3 summary, or None when
+    the kernel source has changed since the counters were taken."""
+    import hashlib
+    if path not in ("auto", "resident"):
+        return None
+    prof = os.path.join(ROOT, "profiles", "resident_mixed_64x64_128x32_traffic.json")
+    src = os.path.join(ROOT, "paper_2601_17979_amd", "csrc", "resident.hip")
+    try:
+        rec = json.load(open(prof))
+        sha = hashlib.sha256(open(src, "rb").read()).hexdigest()
+    except OSError:
+        return None
+    if rec.get("kernel_source_sha256") != sha or shape not in rec.get("launches", {}):
+        return None
+    return rec["launches"][shape]["traffic_bytes"]
+
+
 def flops_unblocked(m, n, sweeps):
     """Alg. 2 work for `sweeps` executed sweeps: every sweep forms 3 dots of
     length m per pair (6m flops); every sweep but the last (clean) one also
@@ -47,6 +65,11 @@ def main():
     ap.add_argument("--batch", type=int, default=10000)
     ap.add_argument("--cpu-sample", type=int, default=1000,
                     help="matrices per shape for the CPU oracle baseline (0 = skip)")
+    ap.add_argument("--no-plain", action="store_true",
+                    help="skip the plain GPU Jacobi comparator run")
+    ap.add_argument("--copy-bytes", type=int, default=0,
+                    help="only run one device-to-device copy of this many bytes (used to "
+                         "calibrate the FETCH_SIZE / WRITE_SIZE counters) and exit")
     args = ap.parse_args()
     if args.gpus != 1:
         print(json.dumps({"error": "this build runs on one GPU; --gpus must be 1"}))
@@ -57,6 +80,14 @@ def main():
     from workloads import gen
 
     dev = torch.device("cuda:0")
+    if args.copy_bytes:
+        x = torch.ones(args.copy_bytes // 8, dtype=torch.float64, device=dev)
+        y = torch.empty_like(x)
+        torch.cuda.synchronize()
+        y.copy_(x)
+        torch.cuda.synchronize()
+        print(json.dumps({"copy_bytes": args.copy_bytes}))
+        return
     groups = gen.mixed_64_128x32(batch=args.batch)
     total = sum(g.A.shape[0] for g in groups)
     stream = torch.cuda.current_stream(dev)
@@ -114,13 +145,14 @@ def main():
     fl = flops_unblocked(gd.m, gd.n, swd)
     achieved = fl / (per_kernel[kdom] * 1e-3)
     roofline = {"bound": "alu", "achieved": achieved / 1e12, "peak": FP64_VALU_PEAK / 1e12,
-                "unit": "TFLOP/s", "frac": achieved / FP64_VALU_PEAK, "traffic": None,
+                "unit": "TFLOP/s", "frac": achieved / FP64_VALU_PEAK,
+                "traffic": measured_traffic(args.path, f"{gd.m}x{gd.n}"),
                 "kernel": f"{gd.m}x{gd.n} launch", "kernel_ms": per_kernel[kdom],
                 "flops_per_launch": fl}
 
     # the plain GPU Jacobi on the same workload (the comparator of the metric)
     plain = None
-    if args.path != "plain":
+    if args.path != "plain" and not args.no_plain:
         _, wall_p, per_p = timed("plain", max(1, args.steps // 2), 1)
         plain = {"value": total * max(1, args.steps // 2) / wall_p, "unit": "SVDs/s",
                  "ms_per_step": wall_p / max(1, args.steps // 2) * 1e3,
