@@ -68,7 +68,16 @@ int make_plan(svdb_dtype_t dt, int m, int n, const svdb_opts_t &o, Plan *p)
     int path = o.path;
     int rN, rR, rW;
     const bool res_ok = svdb::resident_config(m, n, o.waves, &rN, &rR, &rW);
-    if (path == SVDB_PATH_AUTO) path = res_ok ? SVDB_PATH_RESIDENT : SVDB_PATH_PLAIN;
+    if (path == SVDB_PATH_AUTO) path = res_ok ? SVDB_PATH_RESIDENT : SVDB_PATH_BLOCKED;
+    if (path == SVDB_PATH_BLOCKED) {
+        const int nb = svdb::blocked_nb(m, n, o.nb);
+        if (!nb) return fail(SVDB_ERR_UNSUPPORTED, "blocked path: nb must be 16 or 32");
+        if (n < 1) return fail(SVDB_ERR_UNSUPPORTED, "blocked path: n must be >= 1");
+        p->path = SVDB_PATH_BLOCKED;
+        p->nb = nb;
+        p->threads = 256;
+        return 0;
+    }
     if (path == SVDB_PATH_RESIDENT) {
         if (!res_ok)
             return fail(SVDB_ERR_UNSUPPORTED, "resident path: no instance for %d x %d", m, n);
@@ -128,6 +137,7 @@ size_t svdb_workspace_size(svdb_dtype_t dtype, int batch, int m, int n, const sv
     svdb_opts_t o = resolve_opts(opts);
     Plan p;
     if (make_plan(dtype, m, n, o, &p)) return (size_t)-1;
+    if (p.path == SVDB_PATH_BLOCKED) return svdb::blocked_workspace_bytes(batch, m, n, p.nb);
     return 0;
 }
 
@@ -175,6 +185,10 @@ int svdb_svd_strided_batched(svdb_dtype_t dtype, int batch, int m, int n, const 
                                     (double *)S,
                                     strideS, (double *)U, ldu, strideU, (double *)V, ldv,
                                     strideV, tol, o.max_sweeps, info, o.sweeps, s);
+    } else if (p.path == SVDB_PATH_BLOCKED) {
+        e = svdb::launch_blocked_d(batch, m, n, p.nb, (const double *)A, lda, strideA,
+                                   (double *)S, strideS, (double *)U, ldu, strideU, (double *)V,
+                                   ldv, strideV, tol, o.max_sweeps, info, o.sweeps, workspace, s);
     } else if (p.path == SVDB_PATH_PLAIN) {
         e = svdb::launch_plain_d(batch, m, n, (const double *)A, lda, strideA, (double *)S,
                                  strideS, (double *)U, ldu, strideU, (double *)V, ldv, strideV,

@@ -22,4 +22,13 @@ hipError_t launch_resident_d(int batch, int m, int n, int ns, const double *A, i
                              long long sU, double *V, int ldv, long long sV, double tol,
                              int max_sweeps, int *info, int *sweeps, hipStream_t stream);
 
+// blocked.hip: block one-sided Jacobi with MFMA Gram/updates, FP64.
+int blocked_nb(int m, int n, int nb);
+int blocked_np(int n, int nb);
+size_t blocked_workspace_bytes(int batch, int m, int n, int nb);
+hipError_t launch_blocked_d(int batch, int m, int n, int nb, const double *A, int lda, long long sA,
+                            double *S, long long sS, double *U, int ldu, long long sU, double *V,
+                            int ldv, long long sV, double tol, int max_sweeps, int *info,
+                            int *sweeps, void *ws, hipStream_t stream);
+
 }  // namespace svdb

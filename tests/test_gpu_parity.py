@@ -14,7 +14,7 @@ from gpu_util import aligned_vector_err, compare_with_oracle, oracle_batch, run_
 
 pytestmark = pytest.mark.gpu
 
-PATHS = ["plain", "resident"]
+PATHS = ["plain", "resident", "blocked"]
 
 
 def _supported(path, m, n):
@@ -65,18 +65,34 @@ def test_shapes_vs_oracle(path, m, n):
     compare_with_oracle(A, S, U, V, info, Sr, infor, label=f"{m}x{n}/{path}")
 
 
+def _block_oracle(A, nb, max_sweeps=100, tol=None):
+    import oracle
+    out = [oracle.block_gesvj(A[k], nb, tol=tol, max_sweeps=max_sweeps, inner_sweeps=1)
+           for k in range(A.shape[0])]
+    return (np.stack([o[0] for o in out]), np.stack([o[1] for o in out]),
+            np.stack([o[2] for o in out]), np.array([o[3] for o in out]),
+            np.array([o[4] for o in out]))
+
+
 @pytest.mark.parametrize("path", PATHS)
 def test_one_sweep_elementwise(path):
     """After exactly one sweep (max_sweeps = 1, info = 1) the GPU iterate
     matches the oracle run in the same round-robin order element by element:
-    this pins the pair schedule, the rotation and its orientation."""
+    this pins the pair schedule, the rotation and its orientation (for the
+    block path: the block pairs, the Gram matrix, the inner sweep of Alg. 1
+    and the update by J)."""
     for m, n in [(24, 16), (40, 32), (64, 64)]:
         A = _batch([(m, n)] * 8, seed=400 + n)
         S, U, V, info, sw = run_gpu(A, path=path, max_sweeps=1)
-        Sr, Ur, Vr, swr, infor = oracle_batch(A, max_sweeps=1, order=1)
+        if path == "blocked":
+            Sr, Ur, Vr, swr, infor = _block_oracle(A, 16, max_sweeps=1)
+        else:
+            Sr, Ur, Vr, swr, infor = oracle_batch(A, max_sweeps=1, order=1)
         assert np.all(info == 1) and np.all(infor == 1) and np.all(sw == 1)
         assert np.abs(S - Sr).max() <= 1e-13 * Sr.max(), (m, n)
-        assert np.abs(U - Ur).max() <= 1e-12, (m, n, np.abs(U - Ur).max())
+        # the iterate W = A V = U diag(S), element by element, relative to max|A|
+        W, Wr = U * S[:, None, :], Ur * Sr[:, None, :]
+        assert np.abs(W - Wr).max() <= 1e-13 * np.abs(A).max(), (m, n, np.abs(W - Wr).max())
         assert np.abs(V - Vr).max() <= 1e-12, (m, n)
 
 
@@ -86,7 +102,10 @@ def test_sweep_counts_match_round_robin_oracle(path):
     sweep, since rounding can move the last decision)."""
     A = _batch([(32, 32)] * 16, seed=500, kind="geo", kappa=1e6)
     S, U, V, info, sw = run_gpu(A, path=path)
-    Sr, Ur, Vr, swr, infor = oracle_batch(A, order=1)
+    if path == "blocked":
+        Sr, Ur, Vr, swr, infor = _block_oracle(A, 16)
+    else:
+        Sr, Ur, Vr, swr, infor = oracle_batch(A, order=1)
     assert np.all(np.abs(sw - swr) <= 1), (sw, swr)
 
 
@@ -160,3 +179,18 @@ def test_full_mixed_workload_sampled():
         say(f"  sweeps histogram {np.bincount(sw)}")
         del S, U, V
         torch.cuda.empty_cache()
+
+
+@pytest.mark.parametrize("nb", [16, 32])
+@pytest.mark.parametrize("m,n", [(96, 80), (130, 65), (200, 130), (256, 256)])
+def test_blocked_larger_shapes(nb, m, n):
+    """Block path beyond the register-resident sizes: several block pairs per
+    iteration, padded block columns (n not a multiple of nb), ragged row
+    chunks (m not a multiple of 64)."""
+    A = _batch([(m, n)] * 3, seed=900 + m + n, kind="gauss")
+    A[1] = _batch([(m, n)], seed=950 + m, kind="geo", kappa=1e8)[0]
+    say(f"[blocked {m}x{n} nb {nb}]")
+    S, U, V, info, sw = run_gpu(A, path="blocked", nb=nb)
+    Sr, Ur, Vr, swr, infor = oracle_batch(A)
+    compare_with_oracle(A, S, U, V, info, Sr, infor, label=f"blocked {m}x{n} nb{nb}")
+    say(f"  sweeps gpu {list(sw)} oracle {list(swr)}")
