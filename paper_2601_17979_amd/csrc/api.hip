@@ -63,11 +63,17 @@ bool plain_fits(int m, int n)
 
 int make_plan(svdb_dtype_t dt, int m, int n, const svdb_opts_t &o, Plan *p)
 {
-    if (dt != SVDB_R64)
+    if (dt != SVDB_R64 && dt != SVDB_R32)
         return fail(SVDB_ERR_UNSUPPORTED, "dtype %d is not implemented in this build", (int)dt);
+    if (o.precision != 0 && o.precision != 1)
+        return fail(SVDB_ERR_UNSUPPORTED, "precision must be 0 or 1");
+    if (o.precision == 1 && dt != SVDB_R64)
+        return fail(SVDB_ERR_UNSUPPORTED, "precision mode 1 needs SVDB_R64 input");
     int path = o.path;
-    int rN, rR, rW;
-    const bool res_ok = svdb::resident_config(m, n, o.waves, &rN, &rR, &rW);
+    int rN = 0, rR = 0, rW = 0;
+    // the unblocked kernels are FP64 only; FP32 and the mixed mode use the block method
+    const bool unblocked_ok = dt == SVDB_R64 && o.precision == 0;
+    const bool res_ok = unblocked_ok && svdb::resident_config(m, n, o.waves, &rN, &rR, &rW);
     if (path == SVDB_PATH_AUTO) path = res_ok ? SVDB_PATH_RESIDENT : SVDB_PATH_BLOCKED;
     if (path == SVDB_PATH_BLOCKED) {
         const int nb = svdb::blocked_nb(m, n, o.nb);
@@ -78,6 +84,8 @@ int make_plan(svdb_dtype_t dt, int m, int n, const svdb_opts_t &o, Plan *p)
         p->threads = 256;
         return 0;
     }
+    if (!unblocked_ok)
+        return fail(SVDB_ERR_UNSUPPORTED, "path %d handles FP64 with precision 0 only", path);
     if (path == SVDB_PATH_RESIDENT) {
         if (!res_ok)
             return fail(SVDB_ERR_UNSUPPORTED, "resident path: no instance for %d x %d", m, n);
@@ -137,7 +145,9 @@ size_t svdb_workspace_size(svdb_dtype_t dtype, int batch, int m, int n, const sv
     svdb_opts_t o = resolve_opts(opts);
     Plan p;
     if (make_plan(dtype, m, n, o, &p)) return (size_t)-1;
-    if (p.path == SVDB_PATH_BLOCKED) return svdb::blocked_workspace_bytes(batch, m, n, p.nb);
+    if (p.path == SVDB_PATH_BLOCKED)
+        return svdb::blocked_workspace_bytes(batch, m, n, p.nb, dtype == SVDB_R32 ? 4 : 8,
+                                             o.precision == 1);
     return 0;
 }
 
@@ -185,10 +195,21 @@ int svdb_svd_strided_batched(svdb_dtype_t dtype, int batch, int m, int n, const 
                                     (double *)S,
                                     strideS, (double *)U, ldu, strideU, (double *)V, ldv,
                                     strideV, tol, o.max_sweeps, info, o.sweeps, s);
+    } else if (p.path == SVDB_PATH_BLOCKED && dtype == SVDB_R32) {
+        e = svdb::launch_blocked_s(batch, m, n, p.nb, (const float *)A, lda, strideA, (float *)S,
+                                   strideS, (float *)U, ldu, strideU, (float *)V, ldv, strideV,
+                                   tol, o.max_sweeps, o.masking, info, o.sweeps, workspace, s);
+    } else if (p.path == SVDB_PATH_BLOCKED && o.precision == 1) {
+        const double tol32 = fmax(tol, default_tol(SVDB_R32));
+        e = svdb::launch_blocked_mixed_d(batch, m, n, p.nb, (const double *)A, lda, strideA,
+                                         (double *)S, strideS, (double *)U, ldu, strideU,
+                                         (double *)V, ldv, strideV, tol, tol32, o.max_sweeps,
+                                         o.masking, info, o.sweeps, workspace, s);
     } else if (p.path == SVDB_PATH_BLOCKED) {
         e = svdb::launch_blocked_d(batch, m, n, p.nb, (const double *)A, lda, strideA,
                                    (double *)S, strideS, (double *)U, ldu, strideU, (double *)V,
-                                   ldv, strideV, tol, o.max_sweeps, info, o.sweeps, workspace, s);
+                                   ldv, strideV, tol, o.max_sweeps, o.masking, info, o.sweeps,
+                                   workspace, s);
     } else if (p.path == SVDB_PATH_PLAIN) {
         e = svdb::launch_plain_d(batch, m, n, (const double *)A, lda, strideA, (double *)S,
                                  strideS, (double *)U, ldu, strideU, (double *)V, ldv, strideV,

@@ -22,13 +22,23 @@ hipError_t launch_resident_d(int batch, int m, int n, int ns, const double *A, i
                              long long sU, double *V, int ldv, long long sV, double tol,
                              int max_sweeps, int *info, int *sweeps, hipStream_t stream);
 
-// blocked.hip: block one-sided Jacobi with MFMA Gram/updates, FP64.
+// blocked.hip: block one-sided Jacobi with MFMA Gram/updates (FP64, FP32,
+// and FP32 sweeps followed by an FP64 refinement).
 int blocked_nb(int m, int n, int nb);
 int blocked_np(int n, int nb);
-size_t blocked_workspace_bytes(int batch, int m, int n, int nb);
+size_t blocked_workspace_bytes(int batch, int m, int n, int nb, int elt, bool mixed);
 hipError_t launch_blocked_d(int batch, int m, int n, int nb, const double *A, int lda, long long sA,
                             double *S, long long sS, double *U, int ldu, long long sU, double *V,
-                            int ldv, long long sV, double tol, int max_sweeps, int *info,
-                            int *sweeps, void *ws, hipStream_t stream);
+                            int ldv, long long sV, double tol, int max_sweeps, int masking,
+                            int *info, int *sweeps, void *ws, hipStream_t stream);
+hipError_t launch_blocked_s(int batch, int m, int n, int nb, const float *A, int lda, long long sA,
+                            float *S, long long sS, float *U, int ldu, long long sU, float *V,
+                            int ldv, long long sV, double tol, int max_sweeps, int masking,
+                            int *info, int *sweeps, void *ws, hipStream_t stream);
+hipError_t launch_blocked_mixed_d(int batch, int m, int n, int nb, const double *A, int lda,
+                                  long long sA, double *S, long long sS, double *U, int ldu,
+                                  long long sU, double *V, int ldv, long long sV, double tol,
+                                  double tol32, int max_sweeps, int masking, int *info,
+                                  int *sweeps, void *ws, hipStream_t stream);
 
 }  // namespace svdb

@@ -138,14 +138,18 @@ def mixed_64_128x32(batch: int = 10000, seed: int = BASE_SEED + 1000) -> list:
     return groups
 
 
-def square256(batch: int = 4000, seed: int = BASE_SEED + 2000) -> list:
-    """batch x (256 x 256) FP64 geometric spectra, half kappa = 1e2, half 1e8."""
+def square256(batch: int = 4000, seed: int = BASE_SEED + 2000, indices=None) -> list:
+    """batch x (256 x 256) FP64 geometric spectra, half kappa = 1e2, half 1e8.
+    `indices` selects a subset of the batch (the same matrices as in the
+    full batch)."""
     half = batch // 2
+    ks = list(range(batch)) if indices is None else [int(k) for k in indices]
 
     def make(r, k):
         return from_spectrum(r, 256, 256, spectrum("geo", 256, 1e2 if k < half else 1e8))
-    A = np.stack([make(rng_for(seed, k), k) for k in range(batch)])
-    return [Group(256, 256, A, ["geo1e2"] * half + ["geo1e8"] * (batch - half), (seed, 0))]
+    A = np.stack([make(rng_for(seed, k), k) for k in ks])
+    kinds = ["geo1e2" if k < half else "geo1e8" for k in ks]
+    return [Group(256, 256, A, kinds, (seed, ks[0] if ks else 0))]
 
 
 def uneven_complex(batch: int = 20000, seed: int = BASE_SEED + 3000, nmin: int = 8,
