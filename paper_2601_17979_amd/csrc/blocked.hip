@@ -141,59 +141,118 @@ template <class T, int NB>
 struct IterShared {
     static constexpr int N2 = 2 * NB;
     static constexpr bool kF64 = std::is_same<T, double>::value;
-    T xs[N2][kCH + 1];                 // row chunk of [X_p X_q], column major, padded
-    double G[N2][N2 + 1];              // Gram matrix, G[row][col]
-    double J[N2][N2 + 1];              // accumulated rotation, J[row][col]
-    T Jw[kF64 ? 1 : N2][N2 + 1];       // J rounded to T (FP32 working precision)
-    double2 cs[NB];                    // (c, e s) of the pairs of an inner iteration
+    struct Streaming {                       // live while W or V stream through
+        T xs[N2][kCH + 1];                   // row chunk of [X_p X_q], column major
+        T Jw[kF64 ? 1 : N2][N2 + 1];         // J rounded to T (FP32 working precision)
+    };
+    union {
+        double G[N2][N2 + 1];                // Gram matrix during the inner solve
+        Streaming io;
+    } u;
+    double J[N2][N2 + 1];                    // accumulated rotation, J[row][col]
+    double2 cs[NB];                          // (c, e s) of the pairs of an inner iteration
     int rot;
 };
 
-// Loads rows [r0, r0 + kCH) of the 2nb block columns p, q of the rows x np
-// matrix X into s.xs (zero beyond `rows`).
+// Per-thread share of one chunk (kCH rows x 2nb columns) held in registers so
+// that the next chunk's global loads overlap the current chunk's MFMAs.
 template <class T, int NB>
-__device__ __forceinline__ void load_chunk(IterShared<T, NB> &s, const T *X, int rows, int r0,
+struct ChunkRegs {
+    static constexpr int E = 2 * NB * kCH / kBT;
+    T v[E];
+};
+
+// Loads rows [r0, r0 + kCH) of block columns p, q of the rows x np matrix X
+// (zero beyond `rows`).  Element e of thread t is chunk entry
+// idx = t + e kBT: column idx / kCH, row idx % kCH (coalesced columns).
+template <class T, int NB>
+__device__ __forceinline__ void chunk_load(ChunkRegs<T, NB> &R, const T *X, int rows, int r0,
                                            int p, int q)
 {
-    constexpr int N2 = 2 * NB;
     const int tid = threadIdx.x;
-    for (int idx = tid; idx < N2 * kCH; idx += kBT) {
+#pragma unroll
+    for (int e = 0; e < ChunkRegs<T, NB>::E; e++) {
+        const int idx = tid + e * kBT;
         const int c = idx / kCH, r = idx % kCH;
         const int gc = c < NB ? p * NB + c : q * NB + (c - NB);
         const int gr = r0 + r;
-        s.xs[c][r] = gr < rows ? X[(size_t)gc * rows + gr] : T(0);
+        R.v[e] = gr < rows ? X[(size_t)gc * rows + gr] : T(0);
     }
 }
 
-// X_chunk (kCH x 2nb) <- X_chunk J, written back to global rows [r0, r0+kCH).
 template <class T, int NB>
-__device__ __forceinline__ void update_chunk(IterShared<T, NB> &s, T *X, int rows, int r0, int p,
-                                             int q)
+__device__ __forceinline__ void chunk_to_lds(IterShared<T, NB> &s, const ChunkRegs<T, NB> &R)
+{
+    const int tid = threadIdx.x;
+#pragma unroll
+    for (int e = 0; e < ChunkRegs<T, NB>::E; e++) {
+        const int idx = tid + e * kBT;
+        s.u.io.xs[idx / kCH][idx % kCH] = R.v[e];
+    }
+}
+
+// Stores the chunk held in s.u.io.xs to rows [r0, r0 + kCH) of X.
+template <class T, int NB>
+__device__ __forceinline__ void chunk_store(const IterShared<T, NB> &s, T *X, int rows, int r0,
+                                            int p, int q)
+{
+    const int tid = threadIdx.x;
+#pragma unroll
+    for (int e = 0; e < ChunkRegs<T, NB>::E; e++) {
+        const int idx = tid + e * kBT;
+        const int c = idx / kCH, r = idx % kCH;
+        const int gc = c < NB ? p * NB + c : q * NB + (c - NB);
+        if (r0 + r < rows) X[(size_t)gc * rows + r0 + r] = s.u.io.xs[c][r];
+    }
+}
+
+// [X_p X_q] <- [X_p X_q] J for a rows x np matrix X, chunk by chunk: MFMA
+// tiles of 16 x 16 from the chunk in LDS and J, results staged back through
+// LDS and written with coalesced stores.
+template <class T, int NB>
+__device__ __forceinline__ void update_block_columns(IterShared<T, NB> &s, T *X, int rows, int p,
+                                                     int q)
 {
     constexpr int N2 = 2 * NB;
-    constexpr int TR = kCH / 16, TC = N2 / 16, TILES = TR * TC;
+    constexpr int TR = kCH / 16, TC = N2 / 16, TILES = TR * TC, TPW = TILES / 4;
+    static_assert(TILES % 4 == 0, "tiles per wave");
     const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
     const int li = lane & 15, lk = lane >> 4;
-    for (int tile = wave; tile < TILES; tile += kBT / 64) {
-        const int ti = tile / TC, tj = tile % TC;
-        typename Mfma<T>::acc_t acc = {0, 0, 0, 0};
+    ChunkRegs<T, NB> R;
+    chunk_load<T, NB>(R, X, rows, 0, p, q);
+    for (int r0 = 0; r0 < rows; r0 += kCH) {
+        __syncthreads();                      // xs free (previous chunk stored)
+        chunk_to_lds<T, NB>(s, R);
+        __syncthreads();
+        if (r0 + kCH < rows) chunk_load<T, NB>(R, X, rows, r0 + kCH, p, q);
+        typename Mfma<T>::acc_t acc[TPW];
 #pragma unroll
-        for (int k0 = 0; k0 < N2; k0 += 4) {
-            const T a = s.xs[k0 + lk][16 * ti + li];   // X[r][k]
-            T bb;                                      // J[k][c]
-            if constexpr (IterShared<T, NB>::kF64)
-                bb = s.J[k0 + lk][16 * tj + li];
-            else
-                bb = s.Jw[k0 + lk][16 * tj + li];
-            acc = Mfma<T>::op(a, bb, acc);
-        }
-        const int c = 16 * tj + li;
-        const int gc = c < NB ? p * NB + c : q * NB + (c - NB);
+        for (int u = 0; u < TPW; u++) {
+            const int tile = wave + 4 * u;
+            const int ti = tile % TR, tj = tile / TR;
+            acc[u] = typename Mfma<T>::acc_t{0, 0, 0, 0};
 #pragma unroll
-        for (int v = 0; v < 4; v++) {
-            const int gr = r0 + 16 * ti + Mfma<T>::row(lane, v);
-            if (gr < rows) X[(size_t)gc * rows + gr] = acc[v];
+            for (int k0 = 0; k0 < N2; k0 += 4) {
+                const T a = s.u.io.xs[k0 + lk][16 * ti + li];   // X[r][k]
+                T bb;                                           // J[k][c]
+                if constexpr (IterShared<T, NB>::kF64)
+                    bb = s.J[k0 + lk][16 * tj + li];
+                else
+                    bb = s.u.io.Jw[k0 + lk][16 * tj + li];
+                acc[u] = Mfma<T>::op(a, bb, acc[u]);
+            }
         }
+        __syncthreads();                      // every wave has read xs
+#pragma unroll
+        for (int u = 0; u < TPW; u++) {
+            const int tile = wave + 4 * u;
+            const int ti = tile % TR, tj = tile / TR;
+#pragma unroll
+            for (int v = 0; v < 4; v++)
+                s.u.io.xs[16 * tj + li][16 * ti + Mfma<T>::row(lane, v)] = acc[u][v];
+        }
+        __syncthreads();
+        chunk_store<T, NB>(s, X, rows, r0, p, q);
     }
 }
 
@@ -209,7 +268,7 @@ __global__ __launch_bounds__(kBT) void blk_iter(int m, int np, int l, int it, T 
     const int b = blockIdx.x / (l / 2), pair = blockIdx.x % (l / 2);
     if (!st[b].active) return;
     const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
-    const int li = lane & 15;
+    const int li = lane & 15, lk = lane >> 4;
     int p, q;
     rr_pair(l, it, pair, p, q);
     W += (size_t)b * m * np;
@@ -219,25 +278,30 @@ __global__ __launch_bounds__(kBT) void blk_iter(int m, int np, int l, int it, T 
     typename Mfma<T>::acc_t acc[GPW];
 #pragma unroll
     for (int g = 0; g < GPW; g++) acc[g] = typename Mfma<T>::acc_t{0, 0, 0, 0};
-    const int lk = lane >> 4;
-    for (int r0 = 0; r0 < m; r0 += kCH) {
-        __syncthreads();
-        load_chunk<T, NB>(s, W, m, r0, p, q);
-        __syncthreads();
+    {
+        ChunkRegs<T, NB> R;
+        chunk_load<T, NB>(R, W, m, 0, p, q);
+        for (int r0 = 0; r0 < m; r0 += kCH) {
+            __syncthreads();
+            chunk_to_lds<T, NB>(s, R);
+            __syncthreads();
+            if (r0 + kCH < m) chunk_load<T, NB>(R, W, m, r0 + kCH, p, q);
 #pragma unroll
-        for (int g = 0; g < GPW; g++) {
-            const int tile = wave + 4 * g;
-            if (tile < GT) {
-                const int ti = tile / TC, tj = tile % TC;
+            for (int g = 0; g < GPW; g++) {
+                const int tile = wave + 4 * g;
+                if (tile < GT) {
+                    const int ti = tile / TC, tj = tile % TC;
 #pragma unroll
-                for (int k0 = 0; k0 < kCH; k0 += 4) {
-                    const T a = s.xs[16 * ti + li][k0 + lk];    // X^T[i][k] = X[k][i]
-                    const T bb = s.xs[16 * tj + li][k0 + lk];   // X[k][j]
-                    acc[g] = Mfma<T>::op(a, bb, acc[g]);
+                    for (int k0 = 0; k0 < kCH; k0 += 4) {
+                        const T a = s.u.io.xs[16 * ti + li][k0 + lk];    // X^T[i][k]
+                        const T bb = s.u.io.xs[16 * tj + li][k0 + lk];   // X[k][j]
+                        acc[g] = Mfma<T>::op(a, bb, acc[g]);
+                    }
                 }
             }
         }
     }
+    __syncthreads();                            // xs is dead, G takes its place
 #pragma unroll
     for (int g = 0; g < GPW; g++) {
         const int tile = wave + 4 * g;
@@ -245,7 +309,7 @@ __global__ __launch_bounds__(kBT) void blk_iter(int m, int np, int l, int it, T 
             const int ti = tile / TC, tj = tile % TC;
 #pragma unroll
             for (int v = 0; v < 4; v++)
-                s.G[16 * ti + Mfma<T>::row(lane, v)][16 * tj + li] = (double)acc[g][v];
+                s.u.G[16 * ti + Mfma<T>::row(lane, v)][16 * tj + li] = (double)acc[g][v];
         }
     }
     for (int idx = tid; idx < N2 * N2; idx += kBT) s.J[idx / N2][idx % N2] = (idx / N2 == idx % N2);
@@ -258,7 +322,7 @@ __global__ __launch_bounds__(kBT) void blk_iter(int m, int np, int l, int it, T 
         if (tid < NB) {
             int i, j;
             rr_pair(N2, r, tid, i, j);
-            const double gii = s.G[i][i], gjj = s.G[j][j], gij = s.G[i][j];
+            const double gii = s.u.G[i][i], gjj = s.u.G[j][j], gij = s.u.G[i][j];
             double c = 1.0, es = 0.0;
             const double ag = fabs(gij);
             const double si = sqrt(fabs(gii)), sj = sqrt(fabs(gjj));
@@ -273,23 +337,38 @@ __global__ __launch_bounds__(kBT) void blk_iter(int m, int np, int l, int it, T 
             s.cs[tid] = make_double2(c, es);
         }
         __syncthreads();
-        // G <- J_r^T G J_r on 2x2 blocks {i_a, j_a} x {i_b, j_b}; J <- J J_r.
-        // The rotation of a pair maps column i to c col_i + es col_j and
-        // column j to -es col_i + c col_j.
-        for (int idx = tid; idx < NB * NB; idx += kBT) {
-            const int ka = idx / NB, kb = idx % NB;
+        // G <- J_r^T G J_r on the 2x2 blocks {i_a, j_a} x {i_b, j_b} with
+        // ka <= kb (G stays symmetric: the block (kb, ka) is the transpose);
+        // J <- J J_r.  The rotation of a pair maps column i to
+        // c col_i + es col_j and column j to -es col_i + c col_j.
+        for (int idx = tid; idx < NB * (NB + 1) / 2; idx += kBT) {
+            // idx -> (ka, kb), ka <= kb, row-major over the upper triangle
+            int ka = 0, rem = idx;
+            while (rem >= NB - ka) {
+                rem -= NB - ka;
+                ka++;
+            }
+            const int kb = ka + rem;
             int ia, ja, ib, jb;
             rr_pair(N2, r, ka, ia, ja);
             rr_pair(N2, r, kb, ib, jb);
             const double2 ra = s.cs[ka], rb = s.cs[kb];
-            const double g00 = s.G[ia][ib], g01 = s.G[ia][jb];
-            const double g10 = s.G[ja][ib], g11 = s.G[ja][jb];
+            const double g00 = s.u.G[ia][ib], g01 = s.u.G[ia][jb];
+            const double g10 = s.u.G[ja][ib], g11 = s.u.G[ja][jb];
             const double h00 = rb.x * g00 + rb.y * g01, h01 = -rb.y * g00 + rb.x * g01;
             const double h10 = rb.x * g10 + rb.y * g11, h11 = -rb.y * g10 + rb.x * g11;
-            s.G[ia][ib] = ra.x * h00 + ra.y * h10;
-            s.G[ia][jb] = ra.x * h01 + ra.y * h11;
-            s.G[ja][ib] = -ra.y * h00 + ra.x * h10;
-            s.G[ja][jb] = -ra.y * h01 + ra.x * h11;
+            const double n00 = ra.x * h00 + ra.y * h10, n01 = ra.x * h01 + ra.y * h11;
+            const double n10 = -ra.y * h00 + ra.x * h10, n11 = -ra.y * h01 + ra.x * h11;
+            s.u.G[ia][ib] = n00;
+            s.u.G[ia][jb] = n01;
+            s.u.G[ja][ib] = n10;
+            s.u.G[ja][jb] = n11;
+            if (ka != kb) {
+                s.u.G[ib][ia] = n00;
+                s.u.G[jb][ia] = n01;
+                s.u.G[ib][ja] = n10;
+                s.u.G[jb][ja] = n11;
+            }
         }
         for (int idx = tid; idx < N2 * NB; idx += kBT) {
             const int row = idx / NB, kb = idx % NB;
@@ -310,22 +389,13 @@ __global__ __launch_bounds__(kBT) void blk_iter(int m, int np, int l, int it, T 
 
     // ---- 3. fused update of the block columns of W and V --------------------
     if (s.rot != 0) {
+        __syncthreads();                        // G is dead, the chunk buffers take its place
         if constexpr (!IterShared<T, NB>::kF64) {
             for (int idx = tid; idx < N2 * N2; idx += kBT)
-                s.Jw[idx / N2][idx % N2] = (T)s.J[idx / N2][idx % N2];
+                s.u.io.Jw[idx / N2][idx % N2] = (T)s.J[idx / N2][idx % N2];
         }
-        for (int r0 = 0; r0 < m; r0 += kCH) {
-            __syncthreads();
-            load_chunk<T, NB>(s, W, m, r0, p, q);
-            __syncthreads();
-            update_chunk<T, NB>(s, W, m, r0, p, q);
-        }
-        for (int r0 = 0; r0 < np; r0 += kCH) {
-            __syncthreads();
-            load_chunk<T, NB>(s, Vw, np, r0, p, q);
-            __syncthreads();
-            update_chunk<T, NB>(s, Vw, np, r0, p, q);
-        }
+        update_block_columns<T, NB>(s, W, m, p, q);
+        update_block_columns<T, NB>(s, Vw, np, p, q);
         if (tid == 0) atomicOr(&st[b].rotated, 1);
     }
 }
