@@ -56,6 +56,69 @@ def flops_unblocked(m, n, sweeps):
     return float(np.sum(pairs * (6 * m * s + 6 * (m + n) * np.maximum(s - 1, 0))))
 
 
+def serve_leg(args, dev):
+    """Serving workload: requests from 12 shape classes (n in {16..512} x
+    {square, m = 2n}), FP64/FP32 alternating, kappa log-uniform in [1, 1e8].
+    Saturation = a closed batch of requests submitted at once; then Poisson
+    arrivals at `serve_load` x saturation for `serve_seconds`; latency =
+    completion - arrival (server clock)."""
+    import torch
+    from paper_2601_17979_amd import svdb
+    from workloads import gen
+    pool = gen.serving_pool(per_class=4)
+    tdt = {"f64": torch.float64, "f32": torch.float32}
+    dev_pool = [svdb.col_major(torch.from_numpy(A)[None].to(tdt[d]).to(dev))[0]
+                for A, d in pool]
+    torch.cuda.synchronize()
+    budget = 8 << 30
+    srv = svdb.Server(budget_bytes=budget, max_requests=2048)
+
+    def drain(n, t_limit):
+        lat, t0 = [], time.time()
+        while len(lat) < n and time.time() - t0 < t_limit:
+            for rid, ts, td, out in srv.poll(timeout_ms=100):
+                lat.append(td - ts)
+        return lat
+
+    # warm-up and saturation: closed batches of the whole pool
+    for x in dev_pool:
+        srv.submit(x)
+    drain(len(dev_pool), 120)
+    reps = 8
+    t0 = svdb.Server.clock()
+    for _ in range(reps):
+        for x in dev_pool:
+            srv.submit(x)
+    drain(reps * len(dev_pool), 300)
+    sat = reps * len(dev_pool) / (svdb.Server.clock() - t0)
+    # open loop: Poisson arrivals
+    rate = args.serve_load * sat
+    rng = np.random.default_rng(17979 + 4000)
+    lat, n_sub = [], 0
+    t_start = svdb.Server.clock()
+    t_next = t_start
+    while t_next - t_start < args.serve_seconds:
+        now = svdb.Server.clock()
+        if now < t_next:
+            for rid, ts, td, out in srv.poll(timeout_ms=0):
+                lat.append(td - ts)
+            time.sleep(max(0.0, min(t_next - svdb.Server.clock(), 0.002)))
+            continue
+        srv.submit(dev_pool[int(rng.integers(len(dev_pool)))])
+        n_sub += 1
+        t_next += rng.exponential(1.0 / rate)
+    lat += drain(n_sub - len(lat), 120)
+    srv.close()
+    lat = np.sort(np.asarray(lat))
+    return {"workload": "12 shape classes n in {16,...,512} x {square, 2n x n}, FP64/FP32 "
+                        "alternating, geometric spectrum kappa log-uniform [1, 1e8]",
+            "saturation_svds_per_s": sat, "offered_load": args.serve_load,
+            "offered_rate_per_s": rate, "requests": int(n_sub), "completed": int(lat.size),
+            "p50_ms": float(np.percentile(lat, 50) * 1e3) if lat.size else None,
+            "p99_ms": float(np.percentile(lat, 99) * 1e3) if lat.size else None,
+            "budget_bytes": budget}
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -67,6 +130,10 @@ def main():
                     help="matrices per shape for the CPU oracle baseline (0 = skip)")
     ap.add_argument("--no-plain", action="store_true",
                     help="skip the plain GPU Jacobi comparator run")
+    ap.add_argument("--serve-seconds", type=float, default=8.0,
+                    help="length of the Poisson serving run (0 = skip the serving leg)")
+    ap.add_argument("--serve-load", type=float, default=0.5,
+                    help="offered load as a fraction of the measured saturation rate")
     ap.add_argument("--copy-bytes", type=int, default=0,
                     help="only run one device-to-device copy of this many bytes (used to "
                          "calibrate the FETCH_SIZE / WRITE_SIZE counters) and exit")
@@ -181,6 +248,8 @@ def main():
                "oracle_sweeps_per_gpu_sweep": sw_ratio}
         sig_err = max(errs)
 
+    serve = serve_leg(args, dev) if args.serve_seconds > 0 else None
+
     line = {
         "metric": METRIC, "value": value, "unit": "SVDs/s", "n_gpus": 1, "steps": args.steps,
         "warmup": args.warmup, "ms_per_step": ms_per_step, "higher_is_better": True,
@@ -194,6 +263,7 @@ def main():
         "speedup_vs_plain": (value / plain["value"]) if plain else 1.0,
         "roofline": roofline,
         "cpu_baseline": cpu,
+        "serve": serve,
     }
     print(json.dumps(line), flush=True)
 

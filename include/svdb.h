@@ -51,7 +51,10 @@ typedef enum {
     SVDB_C128 = 3   /* double complex, (re, im)    */
 } svdb_dtype_t;
 
-/* Execution paths.  AUTO chooses from the tuned plan table. */
+/* Execution paths.  AUTO chooses from the tuned plan table: RESIDENT where
+ * an instance covers the shape (SVDB_R64), else BLOCKED.  PLAIN and
+ * RESIDENT handle SVDB_R64 only; BLOCKED handles every dtype (complex with
+ * nb = 16). */
 typedef enum {
     SVDB_PATH_AUTO = 0,
     SVDB_PATH_PLAIN = 1,     /* LDS-resident unblocked kernel, one workgroup
@@ -71,7 +74,8 @@ typedef struct {
     int masking;      /* blocked path: skip converged matrices (Sec. 7);
                          < 0 -> default (on)                                   */
     int precision;    /* 0: sweeps in the working precision; 1: FP32 sweeps
-                         then FP64 refinement (SVDB_R64 / SVDB_C128 only)      */
+                         then FP64 refinement (SVDB_R64, block method; the
+                         sweeps count covers both phases)                      */
     int *sweeps;      /* optional DEVICE int[batch]: sweeps executed          */
     int waves;        /* SVDB_PATH_RESIDENT: wavefronts per matrix (1, 2, 4);
                          0 -> tuned                                           */
@@ -116,8 +120,15 @@ int svdb_svd_strided_batched(svdb_dtype_t dtype, int batch, int m, int n,
 /*
  * Mixed-shape batch (uneven batching): host arrays m[b], n[b], lda[b],
  * ldu[b], ldv[b] and host arrays of device pointers A[b], S[b], U[b], V[b]
- * (U or V may be NULL as a whole).  Requires m[b] >= n[b] >= 0.  Matrices of
- * one shape class are launched together; the whole batch is one call.
+ * (U or V may be NULL as a whole).  Requires m[b] >= n[b] >= 0; A[b] is
+ * not modified.  Every matrix runs the block method (Sec. 3-7, nb = 16, any
+ * dtype) on its own round-robin schedule over l_b = n_b / 16 (rounded up to
+ * even) block columns: one launch per round-robin step covers the block
+ * pairs of every unconverged matrix of the batch, and a small matrix
+ * completes several sweeps while a large one completes one.  opts->path and
+ * opts->nb are ignored; opts->precision must be 0.  The workspace (at least
+ * svdb_batched_workspace_size() bytes) holds per-matrix descriptors, the
+ * work table and every matrix's working copies of A and V.
  * Arguments, 1-based: dtype 1, batch 2, m 3, n 4, A 5, lda 6, S 7, U 8,
  * ldu 9, V 10, ldv 11, tol 12, info 13, workspace 14, ws_bytes 15, opts 16,
  * stream 17.
@@ -131,7 +142,8 @@ int svdb_svd_batched(svdb_dtype_t dtype, int batch, const int *m, const int *n,
                      void *workspace, size_t ws_bytes,
                      const svdb_opts_t *opts, void *stream);
 
-/* Bytes of device workspace svdb_svd_batched needs for these shapes. */
+/* Bytes of device workspace svdb_svd_batched needs for these shapes
+ * (host arrays m[], n[]); (size_t)-1 on invalid arguments. */
 size_t svdb_batched_workspace_size(svdb_dtype_t dtype, int batch, const int *m,
                                    const int *n, const svdb_opts_t *opts);
 
@@ -143,6 +155,54 @@ size_t svdb_batched_workspace_size(svdb_dtype_t dtype, int batch, const int *m,
  */
 int svdb_plan(svdb_dtype_t dtype, int m, int n, const svdb_opts_t *opts,
               int *path, int *nb, int *threads);
+
+/*
+ * Serving runtime: continuous batching of independent requests on one GPU.
+ *
+ * A server owns a device arena of budget_bytes (allocated at creation, freed
+ * at destruction), its own HIP stream (default priority) and a worker
+ * thread.  Each request runs the block method (nb = 16, any dtype, n <= 512)
+ * on its own schedule; requests are admitted first come, first served while
+ * a slot (max_requests per dtype) is free and the arena holds their working
+ * copies of A and V ((m np + np^2) elements, np = n rounded up to an even
+ * number of 16-column blocks).  A request leaves as soon as it has
+ * converged (or reached opts->max_sweeps), so new requests take its place
+ * between any two launches: the paper's masks (Sec. 7) retire converged
+ * matrices inside a static batch, the server also refills the batch.
+ *
+ *  svdb_server_create: opts may be NULL (defaults; precision must be 0).
+ *     Returns 0, -k for invalid argument k, SVDB_ERR_HIP.
+ *  svdb_server_submit: device pointers as svdb_svd_batched; A must hold its
+ *     values when the call is made (the server reads it on its own stream)
+ *     and every buffer must stay valid until the request completes.  The
+ *     rotation threshold is 30 u of the dtype (tol is reserved).  Thread
+ *     safe.  Returns the request id (>= 0), -k for invalid argument k,
+ *     SVDB_ERR_UNSUPPORTED when n > 512 or the request exceeds the budget,
+ *     SVDB_ERR_HIP after a device failure.
+ *  svdb_server_poll: waits up to timeout_ms (< 0: forever, 0: no wait) for
+ *     completions and returns up to cap of them: id, submission and
+ *     completion times (svdb_server_clock seconds; outputs and *info are
+ *     valid at completion).  Returns the count, or SVDB_ERR_HIP.
+ *  svdb_server_destroy: finishes every submitted request, then frees all.
+ */
+typedef struct svdb_server svdb_server_t;
+
+int svdb_server_create(svdb_server_t **srv, size_t budget_bytes, int max_requests,
+                       const svdb_opts_t *opts);
+long long svdb_server_submit(svdb_server_t *srv, svdb_dtype_t dtype, int m, int n,
+                             const void *A, int lda, void *S, void *U, int ldu,
+                             void *V, int ldv, double tol, int *info, int *sweeps);
+int svdb_server_poll(svdb_server_t *srv, long long *ids, double *t_submit,
+                     double *t_done, int cap, int timeout_ms);
+/* Counters: submitted, completed, active (admitted, running), queued, and
+ * arena bytes in use.  Returns 0 or SVDB_ERR_HIP after a device failure. */
+int svdb_server_stats(svdb_server_t *srv, long long *submitted, long long *completed,
+                      int *active, int *queued, size_t *bytes_in_use);
+/* Text of the server's device failure ("" if none). */
+const char *svdb_server_error(svdb_server_t *srv);
+int svdb_server_destroy(svdb_server_t *srv);
+/* Monotonic clock of the server's timestamps, in seconds. */
+double svdb_server_clock(void);
 
 /* Text of the last failure in the calling thread ("" if none). */
 const char *svdb_last_error(void);

@@ -37,6 +37,11 @@ double default_tol(svdb_dtype_t dt)
     return 30.0 * (single ? ldexp(1.0, -24) : ldexp(1.0, -53));
 }
 
+int elt_bytes(svdb_dtype_t dt)
+{
+    return dt == SVDB_R32 ? 4 : dt == SVDB_C128 ? 16 : 8;
+}
+
 struct Plan {
     int path = SVDB_PATH_AUTO;
     int nb = 0;
@@ -63,8 +68,6 @@ bool plain_fits(int m, int n)
 
 int make_plan(svdb_dtype_t dt, int m, int n, const svdb_opts_t &o, Plan *p)
 {
-    if (dt != SVDB_R64 && dt != SVDB_R32)
-        return fail(SVDB_ERR_UNSUPPORTED, "dtype %d is not implemented in this build", (int)dt);
     if (o.precision != 0 && o.precision != 1)
         return fail(SVDB_ERR_UNSUPPORTED, "precision must be 0 or 1");
     if (o.precision == 1 && dt != SVDB_R64)
@@ -76,8 +79,11 @@ int make_plan(svdb_dtype_t dt, int m, int n, const svdb_opts_t &o, Plan *p)
     const bool res_ok = unblocked_ok && svdb::resident_config(m, n, o.waves, &rN, &rR, &rW);
     if (path == SVDB_PATH_AUTO) path = res_ok ? SVDB_PATH_RESIDENT : SVDB_PATH_BLOCKED;
     if (path == SVDB_PATH_BLOCKED) {
-        const int nb = svdb::blocked_nb(m, n, o.nb);
-        if (!nb) return fail(SVDB_ERR_UNSUPPORTED, "blocked path: nb must be 16 or 32");
+        const bool cx = dt == SVDB_C64 || dt == SVDB_C128;
+        const int nb = svdb::blocked_nb(m, n, o.nb, cx);
+        if (!nb)
+            return fail(SVDB_ERR_UNSUPPORTED, cx ? "blocked path: complex needs nb = 16"
+                                                 : "blocked path: nb must be 16 or 32");
         if (n < 1) return fail(SVDB_ERR_UNSUPPORTED, "blocked path: n must be >= 1");
         p->path = SVDB_PATH_BLOCKED;
         p->nb = nb;
@@ -146,7 +152,7 @@ size_t svdb_workspace_size(svdb_dtype_t dtype, int batch, int m, int n, const sv
     Plan p;
     if (make_plan(dtype, m, n, o, &p)) return (size_t)-1;
     if (p.path == SVDB_PATH_BLOCKED)
-        return svdb::blocked_workspace_bytes(batch, m, n, p.nb, dtype == SVDB_R32 ? 4 : 8,
+        return svdb::blocked_workspace_bytes(batch, m, n, p.nb, elt_bytes(dtype),
                                              o.precision == 1);
     return 0;
 }
@@ -199,6 +205,14 @@ int svdb_svd_strided_batched(svdb_dtype_t dtype, int batch, int m, int n, const 
         e = svdb::launch_blocked_s(batch, m, n, p.nb, (const float *)A, lda, strideA, (float *)S,
                                    strideS, (float *)U, ldu, strideU, (float *)V, ldv, strideV,
                                    tol, o.max_sweeps, o.masking, info, o.sweeps, workspace, s);
+    } else if (p.path == SVDB_PATH_BLOCKED && dtype == SVDB_C128) {
+        e = svdb::launch_blocked_z(batch, m, n, p.nb, A, lda, strideA, (double *)S, strideS, U,
+                                   ldu, strideU, V, ldv, strideV, tol, o.max_sweeps, o.masking,
+                                   info, o.sweeps, workspace, s);
+    } else if (p.path == SVDB_PATH_BLOCKED && dtype == SVDB_C64) {
+        e = svdb::launch_blocked_c(batch, m, n, p.nb, A, lda, strideA, (float *)S, strideS, U,
+                                   ldu, strideU, V, ldv, strideV, tol, o.max_sweeps, o.masking,
+                                   info, o.sweeps, workspace, s);
     } else if (p.path == SVDB_PATH_BLOCKED && o.precision == 1) {
         const double tol32 = fmax(tol, default_tol(SVDB_R32));
         e = svdb::launch_blocked_mixed_d(batch, m, n, p.nb, (const double *)A, lda, strideA,
@@ -222,14 +236,13 @@ int svdb_svd_strided_batched(svdb_dtype_t dtype, int batch, int m, int n, const 
 size_t svdb_batched_workspace_size(svdb_dtype_t dtype, int batch, const int *m, const int *n,
                                    const svdb_opts_t *opts)
 {
+    if ((int)dtype < SVDB_R32 || (int)dtype > SVDB_C128) return (size_t)-1;
     if (batch < 0 || (batch > 0 && (!m || !n))) return (size_t)-1;
-    size_t total = 0;
-    for (int b = 0; b < batch; b++) {
-        size_t w = svdb_workspace_size(dtype, 1, m[b], n[b], opts);
-        if (w == (size_t)-1) return w;
-        total += w;
-    }
-    return total;
+    svdb_opts_t o = resolve_opts(opts);
+    if (o.precision != 0) return (size_t)-1;
+    for (int b = 0; b < batch; b++)
+        if (m[b] < 0 || n[b] < 0 || n[b] > m[b]) return (size_t)-1;
+    return svdb::vbatched_workspace_bytes(batch, m, n, elt_bytes(dtype));
 }
 
 int svdb_svd_batched(svdb_dtype_t dtype, int batch, const int *m, const int *n,
@@ -259,18 +272,20 @@ int svdb_svd_batched(svdb_dtype_t dtype, int batch, const int *m, const int *n,
         if (!S[b] && !empty) return fail(-7, "S[%d] is NULL", b);
         if (U && ldu[b] < (m[b] > 1 ? m[b] : 1)) return fail(-9, "ldu[%d] < max(1, m)", b);
         if (V && ldv[b] < (n[b] > 1 ? n[b] : 1)) return fail(-11, "ldv[%d] < max(1, n)", b);
+        if (U && !U[b] && !empty) return fail(-8, "U[%d] is NULL", b);
+        if (V && !V[b] && !empty) return fail(-10, "V[%d] is NULL", b);
     }
     svdb_opts_t o = resolve_opts(opts);
-    // One launch per matrix for now; each call writes its own info slot.
-    svdb_opts_t o1 = o;
-    for (int b = 0; b < batch; b++) {
-        o1.sweeps = o.sweeps ? o.sweeps + b : nullptr;
-        int rc = svdb_svd_strided_batched(dtype, 1, m[b], n[b], A[b], lda[b], 0, S[b], 0,
-                                          U ? U[b] : nullptr, U ? ldu[b] : 1, 0,
-                                          V ? V[b] : nullptr, V ? ldv[b] : 1, 0, tol, info + b,
-                                          workspace, ws_bytes, &o1, stream);
-        if (rc) return rc;
-    }
+    if (o.precision != 0)
+        return fail(SVDB_ERR_UNSUPPORTED, "uneven batches run in the working precision only");
+    const size_t need = svdb_batched_workspace_size(dtype, batch, m, n, &o);
+    if (!workspace || ws_bytes < need)
+        return fail(-14, "workspace too small: need %zu bytes", need);
+    if (tol <= 0.0) tol = default_tol(dtype);
+    hipError_t e = svdb::launch_vbatched((int)dtype, batch, m, n, A, lda, S, U, ldu, V, ldv, tol,
+                                         o.max_sweeps, o.masking, info, o.sweeps, workspace,
+                                         (hipStream_t)stream);
+    if (e != hipSuccess) return hip_fail(e, "launch");
     return 0;
 }
 

@@ -1,20 +1,24 @@
 // blocked.hip -- the block one-sided Jacobi SVD (Sec. 3, eq. block-gram and
 // eq. right-sv) with a one-sweep inner eigensolver (Sec. 5, "Design 2"),
-// fused vector updates (Sec. 6) and batch masks (Sec. 7), in FP64 or FP32
-// working precision, plus the mixed mode (FP32 sweeps, FP64 refinement).
+// fused vector updates (Sec. 6) and batch masks (Sec. 7), for real and
+// complex matrices in FP64 or FP32 working precision, plus the mixed mode
+// (FP32 sweeps, FP64 refinement) for real FP64 input.
 //
 // Working storage (device workspace, column major): W (m x np) starts as the
 // pre-scaled A, V (np x np) as I; np = l nb with l even.  A sweep is l - 1
 // round-robin iterations (Sec. 4.1) over block columns; each iteration is one
 // launch of blk_iter with one workgroup per (block pair, matrix):
-//   1. G = [W_p W_q]^T [W_p W_q] (2nb x 2nb) on the matrix cores (FP64 MFMA,
+//   1. G = [W_p W_q]^H [W_p W_q] (2nb x 2nb) on the matrix cores (FP64 MFMA,
 //      or FP32 MFMA with FP32 accumulation), streaming the pair's rows
-//      through LDS in chunks of 64 rows;
+//      through LDS in chunks of 64 rows.  A complex chunk X = Xr + i Xi is
+//      held as the real chunk [Xr Xi]; its real Gram matrix R gives
+//      Re G = R_rr + R_ii and Im G = R_ri - R_ir;
 //   2. one sweep of the two-sided Jacobi eigensolver (Alg. 1) on G in LDS,
 //      always in FP64, in round-robin order over the 2nb indices,
 //      accumulating J;
 //   3. [W_p W_q] <- [W_p W_q] J and [V_p V_q] <- [V_p V_q] J on the matrix
-//      cores, reading every element once and writing it once.
+//      cores (complex: [Xr Xi] [[Jr, Ji], [-Ji, Jr]]), reading every element
+//      once and writing it once.
 // A matrix whose inner solves applied no rotation during a whole sweep has
 // orthogonal columns.  With masking (Sec. 7) it is retired at once and
 // skipped by every later launch; without, it keeps being swept until the
@@ -22,7 +26,9 @@
 // sorted outputs.
 #include <hip/hip_runtime.h>
 
+#include <algorithm>
 #include <type_traits>
+#include <vector>
 
 #include "device_common.hpp"
 #include "launchers.hpp"
@@ -36,11 +42,13 @@ typedef float float4v __attribute__((ext_vector_type(4)));
 
 constexpr int kBT = 256;   // threads per workgroup
 constexpr int kCH = 64;    // rows per streamed chunk
+constexpr int kVbNb = 16;  // block width of uneven batches
 
-// The FP32 phase of the mixed mode ends once the largest pair cosine of a
-// sweep is below this and no longer halves from sweep to sweep: FP32
-// rounding then dominates what is left.
-constexpr double kStallCos = 0x1p-10;
+// The FP32 phase of the mixed mode hands over to FP64 once the largest pair
+// cosine of a sweep is at most this: FP32 sweeps cannot resolve directions
+// whose singular values are below about u32 sigma_1, so further FP32 sweeps
+// would be redone in FP64 anyway.
+constexpr double kSwitchCos = 0x1p-7;
 
 // per-matrix state in the workspace
 struct BlkState {
@@ -48,11 +56,50 @@ struct BlkState {
     int rotated;                 // an inner rotation happened in this sweep
     int sweeps;                  // sweeps until convergence
     int bad;                     // non-finite input
-    int done;                    // converged (or, FP32 phase: stalled)
+    int done;                    // converged (FP32 phase: ready to switch)
     int pad;
     double scale;                // power-of-two pre-scaling of A
     unsigned long long maxcos;   // bits of the largest pair cosine this sweep
     double prevcos;              // the previous sweep's
+};
+
+// ---------------------------------------------------------------------------
+// Element types: T real scalar of the working precision; E = T (real) or the
+// two-component vector (re, im) of T (complex) as stored in HBM.
+// ---------------------------------------------------------------------------
+template <class T, bool CX>
+struct Elem {
+    using type = T;
+};
+template <>
+struct Elem<double, true> {
+    using type = double2;
+};
+template <>
+struct Elem<float, true> {
+    using type = float2;
+};
+
+template <class E>
+struct EOps {   // real
+    static constexpr bool cx = false;
+    __device__ static double re(E x) { return (double)x; }
+    __device__ static double im(E) { return 0.0; }
+    __device__ static E make(double r, double) { return (E)r; }
+};
+template <>
+struct EOps<double2> {
+    static constexpr bool cx = true;
+    __device__ static double re(double2 x) { return x.x; }
+    __device__ static double im(double2 x) { return x.y; }
+    __device__ static double2 make(double r, double i) { return make_double2(r, i); }
+};
+template <>
+struct EOps<float2> {
+    static constexpr bool cx = true;
+    __device__ static double re(float2 x) { return (double)x.x; }
+    __device__ static double im(float2 x) { return (double)x.y; }
+    __device__ static float2 make(double r, double i) { return make_float2((float)r, (float)i); }
 };
 
 // 16x16x4 matrix-core products.  Operands: lane l supplies A[l%16][l/16]
@@ -92,24 +139,25 @@ __device__ __forceinline__ void state_reset(BlkState &s, int bad)
 }
 
 // W <- scale * A (zero columns beyond n), V <- I; non-finite input marks the
-// matrix bad.  TA: element type of A, T: working type.
-template <class TA, class T>
-__global__ __launch_bounds__(kBT) void blk_init(int m, int n, int np, const TA *__restrict__ A,
-                                                int lda, long long sA, T *W, T *Vw, BlkState *st)
+// matrix bad.  EA: element type of A, EW: working element type.  One
+// workgroup, pointers of this matrix.
+template <class EA, class EW>
+__device__ __forceinline__ void init_body(int m, int n, int np, const EA *__restrict__ A, int lda,
+                                          EW *W, EW *Vw, BlkState *stb)
 {
-    const int b = blockIdx.x, tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+    using OA = EOps<EA>;
+    using OW = EOps<EW>;
+    const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
     __shared__ double s_max[kBT / 64];
     __shared__ int s_bad[kBT / 64];
-    A += (size_t)b * sA;
-    W += (size_t)b * m * np;
-    Vw += (size_t)b * np * np;
     double amax = 0.0;
     int bad = 0;
     for (int c = wave; c < n; c += kBT / 64)
         for (int r = lane; r < m; r += 64) {
-            const double a = (double)A[(size_t)c * lda + r];
-            bad |= !isfinite(a);
-            amax = fmax(amax, fabs(a));
+            const EA a = A[(size_t)c * lda + r];
+            const double ar = OA::re(a), ai = OA::im(a);
+            bad |= !isfinite(ar) || !isfinite(ai);
+            amax = fmax(amax, fmax(fabs(ar), fabs(ai)));
         }
     amax = wave_max(amax);
     bad = __any(bad);
@@ -126,203 +174,198 @@ __global__ __launch_bounds__(kBT) void blk_init(int m, int n, int np, const TA *
     }
     const double scale = pow2_scale(amax);
     for (int c = wave; c < np; c += kBT / 64)
-        for (int r = lane; r < m; r += 64)
-            W[(size_t)c * m + r] =
-                (c < n && !bad) ? (T)((double)A[(size_t)c * lda + r] * scale) : T(0);
+        for (int r = lane; r < m; r += 64) {
+            EW w = OW::make(0.0, 0.0);
+            if (c < n && !bad) {
+                const EA a = A[(size_t)c * lda + r];
+                w = OW::make(OA::re(a) * scale, OA::im(a) * scale);
+            }
+            W[(size_t)c * m + r] = w;
+        }
     for (size_t idx = tid; idx < (size_t)np * np; idx += kBT)
-        Vw[idx] = (idx % (np + 1) == 0) ? T(1) : T(0);
+        Vw[idx] = OW::make((idx % (np + 1) == 0) ? 1.0 : 0.0, 0.0);
     if (tid == 0) {
-        state_reset(st[b], bad);
-        st[b].scale = scale;
+        state_reset(*stb, bad);
+        stb->scale = scale;
     }
 }
 
-template <class T, int NB>
+template <class EA, class EW>
+__global__ __launch_bounds__(kBT) void blk_init(int m, int n, int np, const EA *__restrict__ A,
+                                                int lda, long long sA, EW *W, EW *Vw, BlkState *st)
+{
+    const int b = blockIdx.x;
+    init_body<EA, EW>(m, n, np, A + (size_t)b * sA, lda, W + (size_t)b * m * np,
+                      Vw + (size_t)b * np * np, st + b);
+}
+
+// ---------------------------------------------------------------------------
+// LDS of one workgroup of blk_iter.  N2 = 2nb complex (or real) columns, NR
+// real columns of the streamed chunk.  The chunk and the real Gram matrix
+// share storage (never live together); a complex G has its own arrays.
+// ---------------------------------------------------------------------------
+template <class T, bool CX, int NB>
 struct IterShared {
-    static constexpr int N2 = 2 * NB;
-    static constexpr bool kF64 = std::is_same<T, double>::value;
-    struct Streaming {                       // live while W or V stream through
-        T xs[N2][kCH + 1];                   // row chunk of [X_p X_q], column major
-        T Jw[kF64 ? 1 : N2][N2 + 1];         // J rounded to T (FP32 working precision)
-    };
+    static constexpr int N2 = 2 * NB, NR = (CX ? 2 : 1) * N2;
     union {
-        double G[N2][N2 + 1];                // Gram matrix during the inner solve
-        Streaming io;
+        T xs[NR][kCH + 1];            // row chunk [Xr (Xi)], column major
+        double R[NR][NR + 1];         // real Gram matrix (the real G itself)
     } u;
-    double J[N2][N2 + 1];                    // accumulated rotation, J[row][col]
-    double2 cs[NB];                          // (c, e s) of the pairs of an inner iteration
+    double Gr[CX ? N2 : 1][N2 + 1];   // complex G: real and imaginary parts
+    double Gi[CX ? N2 : 1][N2 + 1];
+    double Jr[N2][N2 + 1];            // accumulated rotation J[row][col]
+    double Ji[CX ? N2 : 1][N2 + 1];
+    double csc[NB];                   // c of the pairs of an inner iteration
+    double cser[NB], csei[NB];        // e s (complex) or sign(g_ij) s
     int rot;
 };
 
 // Per-thread share of one chunk (kCH rows x 2nb columns) held in registers so
 // that the next chunk's global loads overlap the current chunk's MFMAs.
-template <class T, int NB>
+template <class E, int NB>
 struct ChunkRegs {
-    static constexpr int E = 2 * NB * kCH / kBT;
-    T v[E];
+    static constexpr int K = 2 * NB * kCH / kBT;
+    E v[K];
 };
 
 // Loads rows [r0, r0 + kCH) of block columns p, q of the rows x np matrix X
-// (zero beyond `rows`).  Element e of thread t is chunk entry
-// idx = t + e kBT: column idx / kCH, row idx % kCH (coalesced columns).
-template <class T, int NB>
-__device__ __forceinline__ void chunk_load(ChunkRegs<T, NB> &R, const T *X, int rows, int r0,
+// (zero beyond `rows`).  Element k of thread t is chunk entry
+// idx = t + k kBT: column idx / kCH, row idx % kCH (coalesced columns).
+template <class E, int NB>
+__device__ __forceinline__ void chunk_load(ChunkRegs<E, NB> &Rg, const E *X, int rows, int r0,
                                            int p, int q)
 {
     const int tid = threadIdx.x;
 #pragma unroll
-    for (int e = 0; e < ChunkRegs<T, NB>::E; e++) {
-        const int idx = tid + e * kBT;
+    for (int k = 0; k < ChunkRegs<E, NB>::K; k++) {
+        const int idx = tid + k * kBT;
         const int c = idx / kCH, r = idx % kCH;
         const int gc = c < NB ? p * NB + c : q * NB + (c - NB);
         const int gr = r0 + r;
-        R.v[e] = gr < rows ? X[(size_t)gc * rows + gr] : T(0);
+        Rg.v[k] = gr < rows ? X[(size_t)gc * rows + gr] : EOps<E>::make(0.0, 0.0);
     }
 }
 
-template <class T, int NB>
-__device__ __forceinline__ void chunk_to_lds(IterShared<T, NB> &s, const ChunkRegs<T, NB> &R)
+template <class T, bool CX, int NB, class E>
+__device__ __forceinline__ void chunk_to_lds(IterShared<T, CX, NB> &s, const ChunkRegs<E, NB> &Rg)
 {
+    constexpr int N2 = 2 * NB;
     const int tid = threadIdx.x;
 #pragma unroll
-    for (int e = 0; e < ChunkRegs<T, NB>::E; e++) {
-        const int idx = tid + e * kBT;
-        s.u.io.xs[idx / kCH][idx % kCH] = R.v[e];
+    for (int k = 0; k < ChunkRegs<E, NB>::K; k++) {
+        const int idx = tid + k * kBT;
+        const int c = idx / kCH, r = idx % kCH;
+        if constexpr (CX) {
+            s.u.xs[c][r] = Rg.v[k].x;
+            s.u.xs[c + N2][r] = Rg.v[k].y;
+        } else {
+            s.u.xs[c][r] = Rg.v[k];
+        }
     }
 }
 
-// Stores the chunk held in s.u.io.xs to rows [r0, r0 + kCH) of X.
-template <class T, int NB>
-__device__ __forceinline__ void chunk_store(const IterShared<T, NB> &s, T *X, int rows, int r0,
+// Stores the chunk held in s.u.xs to rows [r0, r0 + kCH) of X.
+template <class T, bool CX, int NB, class E>
+__device__ __forceinline__ void chunk_store(const IterShared<T, CX, NB> &s, E *X, int rows, int r0,
                                             int p, int q)
 {
+    constexpr int N2 = 2 * NB;
     const int tid = threadIdx.x;
 #pragma unroll
-    for (int e = 0; e < ChunkRegs<T, NB>::E; e++) {
-        const int idx = tid + e * kBT;
+    for (int k = 0; k < ChunkRegs<E, NB>::K; k++) {
+        const int idx = tid + k * kBT;
         const int c = idx / kCH, r = idx % kCH;
         const int gc = c < NB ? p * NB + c : q * NB + (c - NB);
-        if (r0 + r < rows) X[(size_t)gc * rows + r0 + r] = s.u.io.xs[c][r];
+        if (r0 + r < rows) {
+            E y;
+            if constexpr (CX) {
+                y.x = s.u.xs[c][r];
+                y.y = s.u.xs[c + N2][r];
+            } else {
+                y = s.u.xs[c][r];
+            }
+            X[(size_t)gc * rows + r0 + r] = y;
+        }
+    }
+}
+
+// Entry (k, c) of the real form of J: J itself (real), or
+// [[Jr, Ji], [-Ji, Jr]] (complex), rounded to the working precision.
+template <class T, bool CX, int NB>
+__device__ __forceinline__ T jreal(const IterShared<T, CX, NB> &s, int k, int c)
+{
+    constexpr int N2 = 2 * NB;
+    if constexpr (!CX) {
+        return (T)s.Jr[k][c];
+    } else {
+        const bool top = k < N2, left = c < N2;
+        const int kk = top ? k : k - N2, cc = left ? c : c - N2;
+        if (top == left) return (T)s.Jr[kk][cc];
+        const double v = s.Ji[kk][cc];
+        return (T)(top ? v : -v);
     }
 }
 
 // [X_p X_q] <- [X_p X_q] J for a rows x np matrix X, chunk by chunk: MFMA
-// tiles of 16 x 16 from the chunk in LDS and J, results staged back through
-// LDS and written with coalesced stores.
-template <class T, int NB>
-__device__ __forceinline__ void update_block_columns(IterShared<T, NB> &s, T *X, int rows, int p,
-                                                     int q)
+// tiles of 16 x 16 from the real chunk in LDS and the real form of J,
+// results staged back through LDS and written with coalesced stores.
+template <class T, bool CX, int NB, class E>
+__device__ __forceinline__ void update_block_columns(IterShared<T, CX, NB> &s, E *X, int rows,
+                                                     int p, int q)
 {
-    constexpr int N2 = 2 * NB;
-    constexpr int TR = kCH / 16, TC = N2 / 16, TILES = TR * TC, TPW = TILES / 4;
+    constexpr int NR = IterShared<T, CX, NB>::NR;
+    constexpr int TR = kCH / 16, TC = NR / 16, TILES = TR * TC, TPW = TILES / 4;
     static_assert(TILES % 4 == 0, "tiles per wave");
     const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
     const int li = lane & 15, lk = lane >> 4;
-    ChunkRegs<T, NB> R;
-    chunk_load<T, NB>(R, X, rows, 0, p, q);
+    ChunkRegs<E, NB> Rg;
+    chunk_load<E, NB>(Rg, X, rows, 0, p, q);
     for (int r0 = 0; r0 < rows; r0 += kCH) {
         __syncthreads();                      // xs free (previous chunk stored)
-        chunk_to_lds<T, NB>(s, R);
+        chunk_to_lds<T, CX, NB, E>(s, Rg);
         __syncthreads();
-        if (r0 + kCH < rows) chunk_load<T, NB>(R, X, rows, r0 + kCH, p, q);
+        if (r0 + kCH < rows) chunk_load<E, NB>(Rg, X, rows, r0 + kCH, p, q);
         typename Mfma<T>::acc_t acc[TPW];
 #pragma unroll
-        for (int u = 0; u < TPW; u++) {
-            const int tile = wave + 4 * u;
+        for (int t = 0; t < TPW; t++) {
+            const int tile = wave + 4 * t;
             const int ti = tile % TR, tj = tile / TR;
-            acc[u] = typename Mfma<T>::acc_t{0, 0, 0, 0};
+            acc[t] = typename Mfma<T>::acc_t{0, 0, 0, 0};
 #pragma unroll
-            for (int k0 = 0; k0 < N2; k0 += 4) {
-                const T a = s.u.io.xs[k0 + lk][16 * ti + li];   // X[r][k]
-                T bb;                                           // J[k][c]
-                if constexpr (IterShared<T, NB>::kF64)
-                    bb = s.J[k0 + lk][16 * tj + li];
-                else
-                    bb = s.u.io.Jw[k0 + lk][16 * tj + li];
-                acc[u] = Mfma<T>::op(a, bb, acc[u]);
+            for (int k0 = 0; k0 < NR; k0 += 4) {
+                const T a = s.u.xs[k0 + lk][16 * ti + li];                 // X[r][k]
+                const T bb = jreal<T, CX, NB>(s, k0 + lk, 16 * tj + li);    // J[k][c]
+                acc[t] = Mfma<T>::op(a, bb, acc[t]);
             }
         }
         __syncthreads();                      // every wave has read xs
 #pragma unroll
-        for (int u = 0; u < TPW; u++) {
-            const int tile = wave + 4 * u;
+        for (int t = 0; t < TPW; t++) {
+            const int tile = wave + 4 * t;
             const int ti = tile % TR, tj = tile / TR;
 #pragma unroll
             for (int v = 0; v < 4; v++)
-                s.u.io.xs[16 * tj + li][16 * ti + Mfma<T>::row(lane, v)] = acc[u][v];
+                s.u.xs[16 * tj + li][16 * ti + Mfma<T>::row(lane, v)] = acc[t][v];
         }
         __syncthreads();
-        chunk_store<T, NB>(s, X, rows, r0, p, q);
+        chunk_store<T, CX, NB, E>(s, X, rows, r0, p, q);
     }
 }
 
+// One inner sweep of Alg. 1 on the real symmetric G (in s.u.R), round robin
+// over the 2nb indices, accumulating J.  Returns this thread's largest pair
+// cosine.
 template <class T, int NB>
-__global__ __launch_bounds__(kBT) void blk_iter(int m, int np, int l, int it, T *W, T *Vw,
-                                                BlkState *st, double tol)
+__device__ __forceinline__ double inner_sweep_real(IterShared<T, false, NB> &s, double tol)
 {
     constexpr int N2 = 2 * NB;
-    constexpr int TC = N2 / 16, GT = TC * TC;   // Gram output tiles
-    constexpr int GPW = (GT + 3) / 4;           // tiles per wave
-    __shared__ IterShared<T, NB> s;
-
-    const int b = blockIdx.x / (l / 2), pair = blockIdx.x % (l / 2);
-    if (!st[b].active) return;
-    const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
-    const int li = lane & 15, lk = lane >> 4;
-    int p, q;
-    rr_pair(l, it, pair, p, q);
-    W += (size_t)b * m * np;
-    Vw += (size_t)b * np * np;
-
-    // ---- 1. Gram matrix on the matrix cores --------------------------------
-    typename Mfma<T>::acc_t acc[GPW];
-#pragma unroll
-    for (int g = 0; g < GPW; g++) acc[g] = typename Mfma<T>::acc_t{0, 0, 0, 0};
-    {
-        ChunkRegs<T, NB> R;
-        chunk_load<T, NB>(R, W, m, 0, p, q);
-        for (int r0 = 0; r0 < m; r0 += kCH) {
-            __syncthreads();
-            chunk_to_lds<T, NB>(s, R);
-            __syncthreads();
-            if (r0 + kCH < m) chunk_load<T, NB>(R, W, m, r0 + kCH, p, q);
-#pragma unroll
-            for (int g = 0; g < GPW; g++) {
-                const int tile = wave + 4 * g;
-                if (tile < GT) {
-                    const int ti = tile / TC, tj = tile % TC;
-#pragma unroll
-                    for (int k0 = 0; k0 < kCH; k0 += 4) {
-                        const T a = s.u.io.xs[16 * ti + li][k0 + lk];    // X^T[i][k]
-                        const T bb = s.u.io.xs[16 * tj + li][k0 + lk];   // X[k][j]
-                        acc[g] = Mfma<T>::op(a, bb, acc[g]);
-                    }
-                }
-            }
-        }
-    }
-    __syncthreads();                            // xs is dead, G takes its place
-#pragma unroll
-    for (int g = 0; g < GPW; g++) {
-        const int tile = wave + 4 * g;
-        if (tile < GT) {
-            const int ti = tile / TC, tj = tile % TC;
-#pragma unroll
-            for (int v = 0; v < 4; v++)
-                s.u.G[16 * ti + Mfma<T>::row(lane, v)][16 * tj + li] = (double)acc[g][v];
-        }
-    }
-    for (int idx = tid; idx < N2 * N2; idx += kBT) s.J[idx / N2][idx % N2] = (idx / N2 == idx % N2);
-    if (tid == 0) s.rot = 0;
-    __syncthreads();
-
-    // ---- 2. one inner sweep of Alg. 1 on G (FP64), round robin -------------
-    double mc = 0.0;   // largest pair cosine seen by this thread
+    const int tid = threadIdx.x;
+    double mc = 0.0;
     for (int r = 0; r < N2 - 1; r++) {
         if (tid < NB) {
             int i, j;
             rr_pair(N2, r, tid, i, j);
-            const double gii = s.u.G[i][i], gjj = s.u.G[j][j], gij = s.u.G[i][j];
+            const double gii = s.u.R[i][i], gjj = s.u.R[j][j], gij = s.u.R[i][j];
             double c = 1.0, es = 0.0;
             const double ag = fabs(gij);
             const double si = sqrt(fabs(gii)), sj = sqrt(fabs(gjj));
@@ -334,7 +377,8 @@ __global__ __launch_bounds__(kBT) void blk_iter(int m, int np, int l, int it, T 
                 es = gij > 0.0 ? sn : -sn;
                 s.rot = 1;
             }
-            s.cs[tid] = make_double2(c, es);
+            s.csc[tid] = c;
+            s.cser[tid] = es;
         }
         __syncthreads();
         // G <- J_r^T G J_r on the 2x2 blocks {i_a, j_a} x {i_b, j_b} with
@@ -342,7 +386,96 @@ __global__ __launch_bounds__(kBT) void blk_iter(int m, int np, int l, int it, T 
         // J <- J J_r.  The rotation of a pair maps column i to
         // c col_i + es col_j and column j to -es col_i + c col_j.
         for (int idx = tid; idx < NB * (NB + 1) / 2; idx += kBT) {
-            // idx -> (ka, kb), ka <= kb, row-major over the upper triangle
+            int ka = 0, rem = idx;   // idx -> (ka, kb), ka <= kb, row-major upper triangle
+            while (rem >= NB - ka) {
+                rem -= NB - ka;
+                ka++;
+            }
+            const int kb = ka + rem;
+            int ia, ja, ib, jb;
+            rr_pair(N2, r, ka, ia, ja);
+            rr_pair(N2, r, kb, ib, jb);
+            const double ca = s.csc[ka], ea = s.cser[ka], cb = s.csc[kb], eb = s.cser[kb];
+            const double g00 = s.u.R[ia][ib], g01 = s.u.R[ia][jb];
+            const double g10 = s.u.R[ja][ib], g11 = s.u.R[ja][jb];
+            const double h00 = cb * g00 + eb * g01, h01 = -eb * g00 + cb * g01;
+            const double h10 = cb * g10 + eb * g11, h11 = -eb * g10 + cb * g11;
+            const double n00 = ca * h00 + ea * h10, n01 = ca * h01 + ea * h11;
+            const double n10 = -ea * h00 + ca * h10, n11 = -ea * h01 + ca * h11;
+            s.u.R[ia][ib] = n00;
+            s.u.R[ia][jb] = n01;
+            s.u.R[ja][ib] = n10;
+            s.u.R[ja][jb] = n11;
+            if (ka != kb) {
+                s.u.R[ib][ia] = n00;
+                s.u.R[jb][ia] = n01;
+                s.u.R[ib][ja] = n10;
+                s.u.R[jb][ja] = n11;
+            }
+        }
+        for (int idx = tid; idx < N2 * NB; idx += kBT) {
+            const int row = idx / NB, kb = idx % NB;
+            int ib, jb;
+            rr_pair(N2, r, kb, ib, jb);
+            const double cb = s.csc[kb], eb = s.cser[kb];
+            const double x = s.Jr[row][ib], y = s.Jr[row][jb];
+            s.Jr[row][ib] = cb * x + eb * y;
+            s.Jr[row][jb] = -eb * x + cb * y;
+        }
+        __syncthreads();
+    }
+    return mc;
+}
+
+// complex helpers (FP64)
+struct cd {
+    double r, i;
+};
+__device__ __forceinline__ cd cmul(cd a, cd b) { return {a.r * b.r - a.i * b.i, a.r * b.i + a.i * b.r}; }
+__device__ __forceinline__ cd cmulc(cd a, cd b)   // a * conj(b)
+{
+    return {a.r * b.r + a.i * b.i, a.i * b.r - a.r * b.i};
+}
+__device__ __forceinline__ cd cadd(cd a, cd b) { return {a.r + b.r, a.i + b.i}; }
+__device__ __forceinline__ cd csub(cd a, cd b) { return {a.r - b.r, a.i - b.i}; }
+__device__ __forceinline__ cd cscale(double c, cd a) { return {c * a.r, c * a.i}; }
+__device__ __forceinline__ cd cconj(cd a) { return {a.r, -a.i}; }
+
+// One inner sweep of Alg. 1 on the Hermitian G (s.Gr + i s.Gi).  The
+// rotation of a pair (R1): with g_ij = |g_ij| e, column i' = c col_i +
+// conj(e) s col_j and column j' = -e s col_i + c col_j.
+template <class T, int NB>
+__device__ __forceinline__ double inner_sweep_cx(IterShared<T, true, NB> &s, double tol)
+{
+    constexpr int N2 = 2 * NB;
+    const int tid = threadIdx.x;
+    double mc = 0.0;
+    for (int r = 0; r < N2 - 1; r++) {
+        if (tid < NB) {
+            int i, j;
+            rr_pair(N2, r, tid, i, j);
+            const double gii = s.Gr[i][i], gjj = s.Gr[j][j];
+            const double gr = s.Gr[i][j], gim = s.Gi[i][j];
+            double c = 1.0, er = 0.0, ei = 0.0;
+            const double ag = hypot(gr, gim);
+            const double si = sqrt(fabs(gii)), sj = sqrt(fabs(gjj));
+            const double den = si * sj;
+            mc = fmax(mc, den > 0.0 ? ag / den : (ag != 0.0 ? 1.0 : 0.0));
+            if (ag != 0.0 && ag >= tol * si * sj) {
+                double sn;
+                jacobi_cs(gii, gjj, ag, c, sn);
+                er = gr / ag * sn;
+                ei = gim / ag * sn;
+                s.rot = 1;
+            }
+            s.csc[tid] = c;
+            s.cser[tid] = er;
+            s.csei[tid] = ei;
+        }
+        __syncthreads();
+        // G <- J_r^H G J_r on the blocks with ka <= kb (the block (kb, ka)
+        // is the conjugate transpose); J <- J J_r.
+        for (int idx = tid; idx < NB * (NB + 1) / 2; idx += kBT) {
             int ka = 0, rem = idx;
             while (rem >= NB - ka) {
                 rem -= NB - ka;
@@ -352,60 +485,166 @@ __global__ __launch_bounds__(kBT) void blk_iter(int m, int np, int l, int it, T 
             int ia, ja, ib, jb;
             rr_pair(N2, r, ka, ia, ja);
             rr_pair(N2, r, kb, ib, jb);
-            const double2 ra = s.cs[ka], rb = s.cs[kb];
-            const double g00 = s.u.G[ia][ib], g01 = s.u.G[ia][jb];
-            const double g10 = s.u.G[ja][ib], g11 = s.u.G[ja][jb];
-            const double h00 = rb.x * g00 + rb.y * g01, h01 = -rb.y * g00 + rb.x * g01;
-            const double h10 = rb.x * g10 + rb.y * g11, h11 = -rb.y * g10 + rb.x * g11;
-            const double n00 = ra.x * h00 + ra.y * h10, n01 = ra.x * h01 + ra.y * h11;
-            const double n10 = -ra.y * h00 + ra.x * h10, n11 = -ra.y * h01 + ra.x * h11;
-            s.u.G[ia][ib] = n00;
-            s.u.G[ia][jb] = n01;
-            s.u.G[ja][ib] = n10;
-            s.u.G[ja][jb] = n11;
+            const double ca = s.csc[ka], cb = s.csc[kb];
+            const cd ea = {s.cser[ka], s.csei[ka]}, eb = {s.cser[kb], s.csei[kb]};
+            const cd g00 = {s.Gr[ia][ib], s.Gi[ia][ib]}, g01 = {s.Gr[ia][jb], s.Gi[ia][jb]};
+            const cd g10 = {s.Gr[ja][ib], s.Gi[ja][ib]}, g11 = {s.Gr[ja][jb], s.Gi[ja][jb]};
+            // h = G_block J_b, J_b = [[c, -e s], [conj(e) s, c]]
+            const cd h00 = cadd(cscale(cb, g00), cmulc(g01, eb));
+            const cd h01 = csub(cscale(cb, g01), cmul(g00, eb));
+            const cd h10 = cadd(cscale(cb, g10), cmulc(g11, eb));
+            const cd h11 = csub(cscale(cb, g11), cmul(g10, eb));
+            // n = J_a^H h, J_a^H = [[c, e s], [-conj(e) s, c]]
+            const cd n00 = cadd(cscale(ca, h00), cmul(ea, h10));
+            const cd n01 = cadd(cscale(ca, h01), cmul(ea, h11));
+            const cd n10 = csub(cscale(ca, h10), cmul(cconj(ea), h00));
+            const cd n11 = csub(cscale(ca, h11), cmul(cconj(ea), h01));
+            s.Gr[ia][ib] = n00.r;
+            s.Gi[ia][ib] = n00.i;
+            s.Gr[ia][jb] = n01.r;
+            s.Gi[ia][jb] = n01.i;
+            s.Gr[ja][ib] = n10.r;
+            s.Gi[ja][ib] = n10.i;
+            s.Gr[ja][jb] = n11.r;
+            s.Gi[ja][jb] = n11.i;
             if (ka != kb) {
-                s.u.G[ib][ia] = n00;
-                s.u.G[jb][ia] = n01;
-                s.u.G[ib][ja] = n10;
-                s.u.G[jb][ja] = n11;
+                s.Gr[ib][ia] = n00.r;
+                s.Gi[ib][ia] = -n00.i;
+                s.Gr[jb][ia] = n01.r;
+                s.Gi[jb][ia] = -n01.i;
+                s.Gr[ib][ja] = n10.r;
+                s.Gi[ib][ja] = -n10.i;
+                s.Gr[jb][ja] = n11.r;
+                s.Gi[jb][ja] = -n11.i;
             }
         }
         for (int idx = tid; idx < N2 * NB; idx += kBT) {
             const int row = idx / NB, kb = idx % NB;
             int ib, jb;
             rr_pair(N2, r, kb, ib, jb);
-            const double2 rb = s.cs[kb];
-            const double x = s.J[row][ib], y = s.J[row][jb];
-            s.J[row][ib] = rb.x * x + rb.y * y;
-            s.J[row][jb] = -rb.y * x + rb.x * y;
+            const double cb = s.csc[kb];
+            const cd eb = {s.cser[kb], s.csei[kb]};
+            const cd x = {s.Jr[row][ib], s.Ji[row][ib]}, y = {s.Jr[row][jb], s.Ji[row][jb]};
+            const cd xn = cadd(cscale(cb, x), cmulc(y, eb));
+            const cd yn = csub(cscale(cb, y), cmul(x, eb));
+            s.Jr[row][ib] = xn.r;
+            s.Ji[row][ib] = xn.i;
+            s.Jr[row][jb] = yn.r;
+            s.Ji[row][jb] = yn.i;
         }
         __syncthreads();
     }
+    return mc;
+}
+
+// One block pair (pair `pair` of round-robin iteration `it` over l block
+// columns) of one matrix: steps 1-3 above.  W, Vw, stb: this matrix's.
+template <class T, bool CX, int NB>
+__device__ __forceinline__ void iter_body(IterShared<T, CX, NB> &s, int m, int np, int l, int it,
+                                          int pair, typename Elem<T, CX>::type *W,
+                                          typename Elem<T, CX>::type *Vw, BlkState *stb,
+                                          double tol)
+{
+    using E = typename Elem<T, CX>::type;
+    using Sh = IterShared<T, CX, NB>;
+    constexpr int N2 = Sh::N2, NR = Sh::NR;
+    constexpr int TC = NR / 16, GT = TC * TC;   // real Gram output tiles
+    constexpr int GPW = (GT + 3) / 4;           // tiles per wave
+    const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+    const int li = lane & 15, lk = lane >> 4;
+    int p, q;
+    rr_pair(l, it, pair, p, q);
+
+    // ---- 1. Gram matrix on the matrix cores --------------------------------
+    typename Mfma<T>::acc_t acc[GPW];
+#pragma unroll
+    for (int g = 0; g < GPW; g++) acc[g] = typename Mfma<T>::acc_t{0, 0, 0, 0};
+    {
+        ChunkRegs<E, NB> Rg;
+        chunk_load<E, NB>(Rg, W, m, 0, p, q);
+        for (int r0 = 0; r0 < m; r0 += kCH) {
+            __syncthreads();
+            chunk_to_lds<T, CX, NB, E>(s, Rg);
+            __syncthreads();
+            if (r0 + kCH < m) chunk_load<E, NB>(Rg, W, m, r0 + kCH, p, q);
+#pragma unroll
+            for (int g = 0; g < GPW; g++) {
+                const int tile = wave + 4 * g;
+                if (tile < GT) {
+                    const int ti = tile / TC, tj = tile % TC;
+#pragma unroll
+                    for (int k0 = 0; k0 < kCH; k0 += 4) {
+                        const T a = s.u.xs[16 * ti + li][k0 + lk];    // X^T[i][k]
+                        const T bb = s.u.xs[16 * tj + li][k0 + lk];   // X[k][j]
+                        acc[g] = Mfma<T>::op(a, bb, acc[g]);
+                    }
+                }
+            }
+        }
+    }
+    __syncthreads();                            // xs is dead, R takes its place
+#pragma unroll
+    for (int g = 0; g < GPW; g++) {
+        const int tile = wave + 4 * g;
+        if (tile < GT) {
+            const int ti = tile / TC, tj = tile % TC;
+#pragma unroll
+            for (int v = 0; v < 4; v++)
+                s.u.R[16 * ti + Mfma<T>::row(lane, v)][16 * tj + li] = (double)acc[g][v];
+        }
+    }
+    if constexpr (CX) {
+        __syncthreads();
+        for (int idx = tid; idx < N2 * N2; idx += kBT) {
+            const int a = idx / N2, c = idx % N2;
+            s.Gr[a][c] = s.u.R[a][c] + s.u.R[a + N2][c + N2];
+            s.Gi[a][c] = s.u.R[a][c + N2] - s.u.R[a + N2][c];
+            s.Ji[a][c] = 0.0;
+        }
+    }
+    for (int idx = tid; idx < N2 * N2; idx += kBT) s.Jr[idx / N2][idx % N2] = (idx / N2 == idx % N2);
+    if (tid == 0) s.rot = 0;
+    __syncthreads();
+
+    // ---- 2. one inner sweep of Alg. 1 on G (FP64), round robin -------------
+    double mc;
+    if constexpr (CX)
+        mc = inner_sweep_cx<T, NB>(s, tol);
+    else
+        mc = inner_sweep_real<T, NB>(s, tol);
     if (wave == 0) {
         mc = wave_max(mc);
         if (lane == 0 && mc > 0.0)
-            atomicMax(&st[b].maxcos, (unsigned long long)__double_as_longlong(mc));
+            atomicMax(&stb->maxcos, (unsigned long long)__double_as_longlong(mc));
     }
 
     // ---- 3. fused update of the block columns of W and V --------------------
     if (s.rot != 0) {
-        __syncthreads();                        // G is dead, the chunk buffers take its place
-        if constexpr (!IterShared<T, NB>::kF64) {
-            for (int idx = tid; idx < N2 * N2; idx += kBT)
-                s.u.io.Jw[idx / N2][idx % N2] = (T)s.J[idx / N2][idx % N2];
-        }
-        update_block_columns<T, NB>(s, W, m, p, q);
-        update_block_columns<T, NB>(s, Vw, np, p, q);
-        if (tid == 0) atomicOr(&st[b].rotated, 1);
+        update_block_columns<T, CX, NB, E>(s, W, m, p, q);
+        update_block_columns<T, CX, NB, E>(s, Vw, np, p, q);
+        if (tid == 0) atomicOr(&stb->rotated, 1);
     }
 }
 
+template <class T, bool CX, int NB>
+__global__ __launch_bounds__(kBT) void blk_iter(int m, int np, int l, int it,
+                                                typename Elem<T, CX>::type *W,
+                                                typename Elem<T, CX>::type *Vw, BlkState *st,
+                                                double tol)
+{
+    __shared__ IterShared<T, CX, NB> s;
+    const int b = blockIdx.x / (l / 2), pair = blockIdx.x % (l / 2);
+    if (!st[b].active) return;
+    iter_body<T, CX, NB>(s, m, np, l, it, pair, W + (size_t)b * m * np, Vw + (size_t)b * np * np,
+                         st + b, tol);
+}
+
 // End of a sweep: a matrix with no rotation is converged (done); with
-// `stall` (FP32 phase of the mixed mode) one whose largest cosine is small
-// and did not halve is done too.  With masking a done matrix is retired;
+// `phase32` (FP32 phase of the mixed mode) one whose largest cosine is at
+// most kSwitchCos is done too.  With masking a done matrix is retired;
 // without, every matrix stays active until the whole batch is done.
 // *pending counts the matrices not done.
-__global__ void blk_sweep_end(int batch, BlkState *st, int *pending, int masking, int stall)
+__global__ void blk_sweep_end(int batch, BlkState *st, int *pending, int masking, int phase32)
 {
     const int b = blockIdx.x * blockDim.x + threadIdx.x;
     if (b >= batch) return;
@@ -415,7 +654,7 @@ __global__ void blk_sweep_end(int batch, BlkState *st, int *pending, int masking
         s.sweeps += 1;
         const double mc = __longlong_as_double((long long)s.maxcos);
         bool fin = !s.rotated;
-        if (stall && mc <= kStallCos && mc > 0.5 * s.prevcos) fin = true;
+        if (phase32 && mc <= kSwitchCos) fin = true;
         s.prevcos = mc;
         if (fin) s.done = 1;
     }
@@ -437,43 +676,45 @@ __global__ void blk_rearm(int batch, BlkState *st, int *sweeps32)
 
 // sigma_c = ||w_c|| (FP64 sums, power-of-two scaling), stable descending
 // rank, U = W diag(sigma)^-1 (sigma = 0: Gram-Schmidt completion), outputs
-// permuted.  T: working type, TO: output type.
-template <class T, class TO>
-__global__ __launch_bounds__(kBT) void blk_finalize(int m, int n, int np, const T *W, const T *Vw,
-                                                    const BlkState *st, const int *sweeps_extra,
-                                                    TO *S, long long sS, TO *U, int ldu,
-                                                    long long sU, TO *V, int ldv, long long sV,
-                                                    int *info, int *sweeps_out)
+// permuted.  EW: working element type, EO: output element type.
+template <class EO>
+using RealOf = typename std::conditional<std::is_same<EO, float2>::value ||
+                                             std::is_same<EO, float>::value,
+                                         float, double>::type;
+
+// One matrix per workgroup; pointers of this matrix; dynamic LDS
+// n (sizeof(double) + sizeof(int)).  info_b, sweeps_b: this matrix's slots.
+template <class EW, class EO>
+__device__ __forceinline__ void finalize_body(int m, int n, int np, const EW *W, const EW *Vw,
+                                              const BlkState &sb, int extra, RealOf<EO> *S,
+                                              EO *U, int ldu, EO *V, int ldv, int *info_b,
+                                              int *sweeps_b)
 {
+    using OW = EOps<EW>;
+    using OO = EOps<EO>;
+    using SR = RealOf<EO>;
     extern __shared__ double dyn[];
     double *sig = dyn;                     // n
     int *rank = (int *)(sig + n);          // n
-    const int b = blockIdx.x, tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
-    const BlkState sb = st[b];
-    const int extra = sweeps_extra ? sweeps_extra[b] : 0;
+    const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
     if (sb.bad) {
         if (tid == 0) {
-            info[b] = 2;
-            if (sweeps_out) sweeps_out[b] = 0;
+            *info_b = 2;
+            if (sweeps_b) *sweeps_b = 0;
         }
         return;
     }
-    W += (size_t)b * m * np;
-    Vw += (size_t)b * np * np;
-    S += (size_t)b * sS;
-    if (U) U += (size_t)b * sU;
-    if (V) V += (size_t)b * sV;
     for (int c = wave; c < n; c += kBT / 64) {
-        const T *w = W + (size_t)c * m;
+        const EW *w = W + (size_t)c * m;
         double mx = 0.0;
-        for (int r = lane; r < m; r += 64) mx = fmax(mx, fabs((double)w[r]));
+        for (int r = lane; r < m; r += 64) mx = fmax(mx, fmax(fabs(OW::re(w[r])), fabs(OW::im(w[r]))));
         mx = wave_max(mx);
         double ss = 0.0;
         if (mx > 0.0) {
             const double sc = ldexp(1.0, -ilogb(mx));
             for (int r = lane; r < m; r += 64) {
-                const double y = (double)w[r] * sc;
-                ss += y * y;
+                const double yr = OW::re(w[r]) * sc, yi = OW::im(w[r]) * sc;
+                ss += yr * yr + yi * yi;
             }
         }
         ss = wave_sum(ss);
@@ -493,14 +734,18 @@ __global__ __launch_bounds__(kBT) void blk_finalize(int m, int n, int np, const 
     for (int c = wave; c < n; c += kBT / 64) {
         const int rk = rank[c];
         const double sc = sig[c];
-        if (lane == 0) S[rk] = (TO)(sc / sb.scale);
+        if (lane == 0) S[rk] = (SR)(sc / sb.scale);
         const double inv = sc > 0.0 ? 1.0 / sc : 0.0;
         if (U)
-            for (int r = lane; r < m; r += 64)
-                U[(size_t)rk * ldu + r] = (TO)((double)W[(size_t)c * m + r] * inv);
+            for (int r = lane; r < m; r += 64) {
+                const EW w = W[(size_t)c * m + r];
+                U[(size_t)rk * ldu + r] = OO::make(OW::re(w) * inv, OW::im(w) * inv);
+            }
         if (V)
-            for (int r = lane; r < n; r += 64)
-                V[(size_t)rk * ldv + r] = (TO)Vw[(size_t)c * np + r];
+            for (int r = lane; r < n; r += 64) {
+                const EW v = Vw[(size_t)c * np + r];
+                V[(size_t)rk * ldv + r] = OO::make(OW::re(v), OW::im(v));
+            }
     }
     // sigma = 0: complete U by Gram-Schmidt on e_1, e_2, ... (wave 0, global U)
     bool any_zero = false;
@@ -512,28 +757,38 @@ __global__ __launch_bounds__(kBT) void blk_finalize(int m, int n, int np, const 
             int cand = 0;
             for (int i = 0; i < n; i++) {
                 if (sig[i] > 0.0) continue;
-                TO *u = U + (size_t)rank[i] * ldu;
+                EO *u = U + (size_t)rank[i] * ldu;
                 for (; cand < m; cand++) {
-                    for (int r = lane; r < m; r += 64) u[r] = (r == cand) ? TO(1) : TO(0);
+                    for (int r = lane; r < m; r += 64) u[r] = OO::make(r == cand ? 1.0 : 0.0, 0.0);
                     __threadfence();
                     for (int pass = 0; pass < 2; pass++)
                         for (int j = 0; j < n; j++) {
                             if (j == i || (sig[j] == 0.0 && j > i)) continue;
-                            const TO *qv = U + (size_t)rank[j] * ldu;
-                            double d = 0.0;
-                            for (int r = lane; r < m; r += 64)
-                                d += (double)qv[r] * (double)u[r];
-                            d = wave_sum(d);
-                            for (int r = lane; r < m; r += 64)
-                                u[r] = (TO)((double)u[r] - d * (double)qv[r]);
+                            const EO *qv = U + (size_t)rank[j] * ldu;
+                            double dr = 0.0, di = 0.0;   // d = q^H u
+                            for (int r = lane; r < m; r += 64) {
+                                const double qr = OO::re(qv[r]), qi = OO::im(qv[r]);
+                                const double ur = OO::re(u[r]), ui = OO::im(u[r]);
+                                dr += qr * ur + qi * ui;
+                                di += qr * ui - qi * ur;
+                            }
+                            dr = wave_sum(dr);
+                            di = wave_sum(di);
+                            for (int r = lane; r < m; r += 64) {
+                                const double qr = OO::re(qv[r]), qi = OO::im(qv[r]);
+                                u[r] = OO::make(OO::re(u[r]) - (dr * qr - di * qi),
+                                                OO::im(u[r]) - (dr * qi + di * qr));
+                            }
                             __threadfence();
                         }
                     double nu = 0.0;
-                    for (int r = lane; r < m; r += 64) nu += (double)u[r] * (double)u[r];
+                    for (int r = lane; r < m; r += 64)
+                        nu += OO::re(u[r]) * OO::re(u[r]) + OO::im(u[r]) * OO::im(u[r]);
                     nu = sqrt(wave_sum(nu));
                     if (nu > 0.5) {
                         const double inv = 1.0 / nu;
-                        for (int r = lane; r < m; r += 64) u[r] = (TO)((double)u[r] * inv);
+                        for (int r = lane; r < m; r += 64)
+                            u[r] = OO::make(OO::re(u[r]) * inv, OO::im(u[r]) * inv);
                         __threadfence();
                         cand++;
                         break;
@@ -543,9 +798,24 @@ __global__ __launch_bounds__(kBT) void blk_finalize(int m, int n, int np, const 
         }
     }
     if (tid == 0) {
-        info[b] = sb.done ? 0 : 1;
-        if (sweeps_out) sweeps_out[b] = sb.sweeps + extra;
+        *info_b = sb.done ? 0 : 1;
+        if (sweeps_b) *sweeps_b = sb.sweeps + extra;
     }
+}
+
+template <class EW, class EO>
+__global__ __launch_bounds__(kBT) void blk_finalize(int m, int n, int np, const EW *W,
+                                                    const EW *Vw, const BlkState *st,
+                                                    const int *sweeps_extra, RealOf<EO> *S,
+                                                    long long sS, EO *U, int ldu, long long sU,
+                                                    EO *V, int ldv, long long sV, int *info,
+                                                    int *sweeps_out)
+{
+    const int b = blockIdx.x;
+    finalize_body<EW, EO>(m, n, np, W + (size_t)b * m * np, Vw + (size_t)b * np * np, st[b],
+                          sweeps_extra ? sweeps_extra[b] : 0, S + (size_t)b * sS,
+                          U ? U + (size_t)b * sU : nullptr, ldu, V ? V + (size_t)b * sV : nullptr,
+                          ldv, info + b, sweeps_out ? sweeps_out + b : nullptr);
 }
 
 // ---------------------------------------------------------------------------
@@ -674,10 +944,30 @@ hipError_t pinned_counter(int **out)
     return hipSuccess;
 }
 
+template <class T, bool CX>
+void launch_iter(int nb, unsigned grid, hipStream_t stream, int m, int np, int l, int it,
+                 typename Elem<T, CX>::type *W, typename Elem<T, CX>::type *Vw, BlkState *st,
+                 double tol)
+{
+    if constexpr (CX) {
+        hipLaunchKernelGGL((blk_iter<T, true, 16>), dim3(grid), dim3(kBT), 0, stream, m, np, l,
+                           it, W, Vw, st, tol);
+        (void)nb;
+    } else {
+        if (nb == 16)
+            hipLaunchKernelGGL((blk_iter<T, false, 16>), dim3(grid), dim3(kBT), 0, stream, m, np,
+                               l, it, W, Vw, st, tol);
+        else
+            hipLaunchKernelGGL((blk_iter<T, false, 32>), dim3(grid), dim3(kBT), 0, stream, m, np,
+                               l, it, W, Vw, st, tol);
+    }
+}
+
 // Sweeps until no matrix is pending or max_sweeps.
-template <class T>
-hipError_t run_sweeps(int batch, int m, int np, int nb, T *W, T *Vw, BlkState *st, int *pending,
-                      double tol, int max_sweeps, int masking, int stall, hipStream_t stream)
+template <class T, bool CX>
+hipError_t run_sweeps(int batch, int m, int np, int nb, typename Elem<T, CX>::type *W,
+                      typename Elem<T, CX>::type *Vw, BlkState *st, int *pending, double tol,
+                      int max_sweeps, int masking, int phase32, hipStream_t stream)
 {
     const int l = np / nb;
     int *host_count;
@@ -685,18 +975,12 @@ hipError_t run_sweeps(int batch, int m, int np, int nb, T *W, T *Vw, BlkState *s
     if (e != hipSuccess) return e;
     const unsigned grid = (unsigned)batch * (unsigned)(l / 2);
     for (int sw = 0; sw < max_sweeps; sw++) {
-        for (int it = 0; it < l - 1; it++) {
-            if (nb == 16)
-                hipLaunchKernelGGL((blk_iter<T, 16>), dim3(grid), dim3(kBT), 0, stream, m, np, l,
-                                   it, W, Vw, st, tol);
-            else
-                hipLaunchKernelGGL((blk_iter<T, 32>), dim3(grid), dim3(kBT), 0, stream, m, np, l,
-                                   it, W, Vw, st, tol);
-        }
+        for (int it = 0; it < l - 1; it++)
+            launch_iter<T, CX>(nb, grid, stream, m, np, l, it, W, Vw, st, tol);
         e = hipMemsetAsync(pending, 0, sizeof(int), stream);
         if (e != hipSuccess) return e;
         hipLaunchKernelGGL(blk_sweep_end, dim3((batch + 255) / 256), dim3(256), 0, stream, batch,
-                           st, pending, masking, stall);
+                           st, pending, masking, phase32);
         e = hipMemcpyAsync(host_count, pending, sizeof(int), hipMemcpyDeviceToHost, stream);
         if (e != hipSuccess) return e;
         e = hipStreamSynchronize(stream);
@@ -746,33 +1030,354 @@ unsigned elementwise_grid(size_t total)
     return (unsigned)(g < 65536 ? (g ? g : 1) : 65536);
 }
 
-template <class TA, class T>
-hipError_t launch_blocked(int batch, int m, int n, int nb, const TA *A, int lda, long long sA, T *S,
-                          long long sS, T *U, int ldu, long long sU, T *V, int ldv, long long sV,
-                          double tol, int max_sweeps, int masking, int *info, int *sweeps,
-                          void *ws, hipStream_t stream)
+template <class T, bool CX>
+hipError_t launch_blocked(int batch, int m, int n, int nb, const typename Elem<T, CX>::type *A,
+                          int lda, long long sA, T *S, long long sS,
+                          typename Elem<T, CX>::type *U, int ldu, long long sU,
+                          typename Elem<T, CX>::type *V, int ldv, long long sV, double tol,
+                          int max_sweeps, int masking, int *info, int *sweeps, void *ws,
+                          hipStream_t stream)
 {
+    using E = typename Elem<T, CX>::type;
     const int np = blocked_np(n, nb);
-    WsLayout L = carve(ws, batch, m, n, np, sizeof(T), false);
-    T *W = (T *)L.W, *Vw = (T *)L.Vw;
-    hipLaunchKernelGGL((blk_init<TA, T>), dim3(batch), dim3(kBT), 0, stream, m, n, np, A, lda, sA,
+    WsLayout L = carve(ws, batch, m, n, np, sizeof(E), false);
+    E *W = (E *)L.W, *Vw = (E *)L.Vw;
+    hipLaunchKernelGGL((blk_init<E, E>), dim3(batch), dim3(kBT), 0, stream, m, n, np, A, lda, sA,
                        W, Vw, L.st);
     hipError_t e = hipGetLastError();
     if (e != hipSuccess) return e;
-    e = run_sweeps<T>(batch, m, np, nb, W, Vw, L.st, L.pending, tol, max_sweeps, masking, 0,
-                      stream);
+    e = run_sweeps<T, CX>(batch, m, np, nb, W, Vw, L.st, L.pending, tol, max_sweeps, masking, 0,
+                          stream);
     if (e != hipSuccess) return e;
     const size_t lds = (size_t)n * (sizeof(double) + sizeof(int));
-    hipLaunchKernelGGL((blk_finalize<T, T>), dim3(batch), dim3(kBT), lds, stream, m, n, np, W, Vw,
-                       L.st, (const int *)nullptr, S, sS, U, ldu, sU, V, ldv, sV, info, sweeps);
+    hipLaunchKernelGGL((blk_finalize<E, E>), dim3(batch), dim3(kBT), lds, stream, m, n, np,
+                       (const E *)W, (const E *)Vw, (const BlkState *)L.st, (const int *)nullptr,
+                       S, sS, U, ldu, sU, V, ldv, sV, info, sweeps);
+    return hipGetLastError();
+}
+
+// ---------------------------------------------------------------------------
+// Uneven batches (one pointer per matrix, any shape mix) and the serving
+// runtime.  Every matrix has its own descriptor (VbDesc) and its own
+// round-robin schedule over l_b block columns (nb = 16).  One launch of
+// vb_iter covers every block pair of every listed matrix; matrix b runs
+// iteration (itg - it0_b) mod (l_b - 1) of its current sweep, so a small
+// matrix completes several sweeps while a large one completes one, and a
+// matrix admitted later (it0_b > 0) joins the running launches.
+// vb_sweep_end closes the sweeps that end at launch itg.
+// ---------------------------------------------------------------------------
+template <class E>
+__global__ __launch_bounds__(kBT) void vb_init(const VbDesc *d, const int *idx, void *base,
+                                               BlkState *st)
+{
+    const int b = idx ? idx[blockIdx.x] : (int)blockIdx.x;
+    const VbDesc D = d[b];
+    E *Wb = (E *)base;
+    init_body<E, E>(D.m, D.n, D.np, (const E *)D.A, D.lda, Wb + D.woff, Wb + D.voff, st + b);
+}
+
+template <class T, bool CX>
+__global__ __launch_bounds__(kBT) void vb_iter(const VbDesc *d, const int2 *work, int itg,
+                                               void *base, BlkState *st, double tol)
+{
+    using E = typename Elem<T, CX>::type;
+    __shared__ IterShared<T, CX, kVbNb> s;
+    const int2 w = work[blockIdx.x];
+    if (!st[w.x].active) return;
+    const VbDesc &D = d[w.x];
+    const int m = D.m, np = D.np, l = D.l;
+    E *Wb = (E *)base;
+    iter_body<T, CX, kVbNb>(s, m, np, l, (itg - D.it0) % (l - 1), w.y, Wb + D.woff, Wb + D.voff,
+                            st + w.x, tol);
+}
+
+// Closes the sweeps of the matrices whose sweep ends at launch itg; a matrix
+// that reaches max_sweeps unconverged stops (info 1).  With `pending`, counts
+// the matrices still sweeping.
+__global__ void vb_sweep_end(int count, const VbDesc *d, int itg, BlkState *st, int max_sweeps,
+                             int masking, int *pending)
+{
+    const int b = blockIdx.x * blockDim.x + threadIdx.x;
+    if (b >= count) return;
+    BlkState &s = st[b];
+    if (s.active && (itg - d[b].it0 + 1) % (d[b].l - 1) == 0) {
+        if (!s.done) {
+            s.sweeps += 1;
+            if (!s.rotated)
+                s.done = 1;
+            else if (s.sweeps >= max_sweeps)
+                s.active = 0;
+        }
+        s.rotated = 0;
+        s.maxcos = 0ull;
+        if (masking && s.done) s.active = 0;
+    }
+    if (pending && s.active && !s.done) atomicAdd(pending, 1);
+}
+
+// flags[b] = 1 once matrix b has stopped sweeping (converged or capped).
+__global__ void vb_collect(int count, const BlkState *st, int *flags)
+{
+    const int b = blockIdx.x * blockDim.x + threadIdx.x;
+    if (b < count) flags[b] = st[b].active ? 0 : 1;
+}
+
+__global__ void vb_mark_empty(int count, BlkState *st)
+{
+    const int b = blockIdx.x * blockDim.x + threadIdx.x;
+    if (b < count) {
+        state_reset(st[b], 0);
+        st[b].active = 0;
+        st[b].done = 1;
+    }
+}
+
+template <class E>
+__global__ __launch_bounds__(kBT) void vb_finalize(const VbDesc *d, const int *idx,
+                                                   const void *base, const BlkState *st)
+{
+    const int b = idx ? idx[blockIdx.x] : (int)blockIdx.x;
+    const VbDesc D = d[b];
+    const E *Wb = (const E *)base;
+    finalize_body<E, E>(D.m, D.n, D.np, Wb + D.woff, Wb + D.voff, st[b], 0, (RealOf<E> *)D.S,
+                        (E *)D.U, D.ldu, (E *)D.V, D.ldv, D.info, D.sweeps);
+}
+
+struct VbLayout {
+    VbDesc *desc;
+    int2 *work;
+    BlkState *st;
+    int *pending;
+    void *base;   // every matrix's W, then V
+    size_t bytes;
+};
+
+VbLayout vb_layout(void *ws, int batch, const int *m, const int *n, size_t elt)
+{
+    size_t nwork = 0, elts = 0;
+    for (int b = 0; b < batch; b++) {
+        if (n[b] == 0) continue;
+        const int np = blocked_np(n[b], kVbNb);
+        nwork += np / kVbNb / 2;
+        elts += (size_t)m[b] * np + (size_t)np * np;
+    }
+    size_t off[5], o = 0;
+    off[0] = o;
+    o += align256((size_t)batch * sizeof(VbDesc));
+    off[1] = o;
+    o += align256(nwork * sizeof(int2));
+    off[2] = o;
+    o += align256((size_t)batch * sizeof(BlkState));
+    off[3] = o;
+    o += 256;
+    off[4] = o;
+    o += align256(elts * elt);
+    VbLayout L{};
+    L.bytes = o;
+    if (ws) {
+        char *p = (char *)ws;
+        L.desc = (VbDesc *)(p + off[0]);
+        L.work = (int2 *)(p + off[1]);
+        L.st = (BlkState *)(p + off[2]);
+        L.pending = (int *)(p + off[3]);
+        L.base = p + off[4];
+    }
+    return L;
+}
+
+// host staging for descriptors and the work table; one per process and host
+// thread, reused once the previous call has synchronised
+hipError_t vb_staging(size_t bytes, char **out)
+{
+    static thread_local char *buf = nullptr;
+    static thread_local size_t cap = 0;
+    if (bytes > cap) {
+        if (buf) (void)hipHostFree(buf);
+        buf = nullptr;
+        cap = 0;
+        hipError_t e = hipHostMalloc((void **)&buf, bytes, hipHostMallocDefault);
+        if (e != hipSuccess) return e;
+        cap = bytes;
+    }
+    *out = buf;
+    return hipSuccess;
+}
+
+template <class T, bool CX>
+void vb_launch_iter_t(const VbDesc *d, const int2 *work, int nwork, int itg, void *base,
+                      BlkState *st, double tol, hipStream_t stream)
+{
+    hipLaunchKernelGGL((vb_iter<T, CX>), dim3((unsigned)nwork), dim3(kBT), 0, stream, d, work, itg,
+                       base, st, tol);
+}
+
+template <class E>
+void vb_launch_init_t(const VbDesc *d, const int *idx, int count, void *base, BlkState *st,
+                      hipStream_t stream)
+{
+    hipLaunchKernelGGL((vb_init<E>), dim3((unsigned)count), dim3(kBT), 0, stream, d, idx, base,
+                       st);
+}
+
+template <class E>
+void vb_launch_finalize_t(const VbDesc *d, const int *idx, int count, int maxn, const void *base,
+                          const BlkState *st, hipStream_t stream)
+{
+    const size_t lds = (size_t)(maxn > 0 ? maxn : 1) * (sizeof(double) + sizeof(int));
+    hipLaunchKernelGGL((vb_finalize<E>), dim3((unsigned)count), dim3(kBT), lds, stream, d, idx,
+                       base, st);
+}
+
+}  // namespace
+
+// dtype-dispatched launchers of the uneven-batch kernels (svdb_dtype_t codes)
+void vb_launch_init(int dtype, const VbDesc *d, const int *idx, int count, void *base,
+                    void *st, hipStream_t stream)
+{
+    BlkState *S = (BlkState *)st;
+    switch (dtype) {
+    case 0: vb_launch_init_t<float>(d, idx, count, base, S, stream); break;
+    case 1: vb_launch_init_t<double>(d, idx, count, base, S, stream); break;
+    case 2: vb_launch_init_t<float2>(d, idx, count, base, S, stream); break;
+    default: vb_launch_init_t<double2>(d, idx, count, base, S, stream); break;
+    }
+}
+
+void vb_launch_iter(int dtype, const VbDesc *d, const int2 *work, int nwork, int itg, void *base,
+                    void *st, double tol, hipStream_t stream)
+{
+    BlkState *S = (BlkState *)st;
+    switch (dtype) {
+    case 0: vb_launch_iter_t<float, false>(d, work, nwork, itg, base, S, tol, stream); break;
+    case 1: vb_launch_iter_t<double, false>(d, work, nwork, itg, base, S, tol, stream); break;
+    case 2: vb_launch_iter_t<float, true>(d, work, nwork, itg, base, S, tol, stream); break;
+    default: vb_launch_iter_t<double, true>(d, work, nwork, itg, base, S, tol, stream); break;
+    }
+}
+
+void vb_launch_sweep_end(int count, const VbDesc *d, int itg, void *st, int max_sweeps,
+                         int masking, int *pending, hipStream_t stream)
+{
+    hipLaunchKernelGGL(vb_sweep_end, dim3((unsigned)((count + 255) / 256)), dim3(256), 0, stream,
+                       count, d, itg, (BlkState *)st, max_sweeps, masking, pending);
+}
+
+void vb_launch_collect(int count, const void *st, int *flags, hipStream_t stream)
+{
+    hipLaunchKernelGGL(vb_collect, dim3((unsigned)((count + 255) / 256)), dim3(256), 0, stream,
+                       count, (const BlkState *)st, flags);
+}
+
+void vb_launch_mark_empty(int count, void *st, hipStream_t stream)
+{
+    hipLaunchKernelGGL(vb_mark_empty, dim3((unsigned)((count + 255) / 256)), dim3(256), 0, stream,
+                       count, (BlkState *)st);
+}
+
+void vb_launch_finalize(int dtype, const VbDesc *d, const int *idx, int count, int maxn,
+                        const void *base, const void *st, hipStream_t stream)
+{
+    const BlkState *S = (const BlkState *)st;
+    switch (dtype) {
+    case 0: vb_launch_finalize_t<float>(d, idx, count, maxn, base, S, stream); break;
+    case 1: vb_launch_finalize_t<double>(d, idx, count, maxn, base, S, stream); break;
+    case 2: vb_launch_finalize_t<float2>(d, idx, count, maxn, base, S, stream); break;
+    default: vb_launch_finalize_t<double2>(d, idx, count, maxn, base, S, stream); break;
+    }
+}
+
+size_t vb_state_bytes() { return sizeof(BlkState); }
+
+int vb_nb() { return kVbNb; }
+
+namespace {
+
+hipError_t launch_vb(int dtype, size_t elt, int batch, const int *m, const int *n,
+                     const void *const *A, const int *lda, void *const *S, void *const *U,
+                     const int *ldu, void *const *V, const int *ldv, double tol, int max_sweeps,
+                     int masking, int *info, int *sweeps, void *ws, hipStream_t stream)
+{
+    VbLayout L = vb_layout(ws, batch, m, n, elt);
+    // descriptors, then the work table with the largest matrices first
+    std::vector<int> order(batch);
+    for (int b = 0; b < batch; b++) order[b] = b;
+    std::stable_sort(order.begin(), order.end(), [&](int x, int y) { return n[x] > n[y]; });
+    const size_t dbytes = (size_t)batch * sizeof(VbDesc);
+    size_t nwork = 0;
+    for (int b = 0; b < batch; b++)
+        if (n[b] > 0) nwork += blocked_np(n[b], kVbNb) / kVbNb / 2;
+    char *host;
+    hipError_t e = vb_staging(dbytes + nwork * sizeof(int2) + 16, &host);
+    if (e != hipSuccess) return e;
+    VbDesc *hd = (VbDesc *)host;
+    int2 *hw = (int2 *)(host + dbytes);
+    long long off = 0;   // elements
+    int lmax = 2, maxn = 0;
+    for (int b = 0; b < batch; b++) {
+        VbDesc D{};
+        D.A = A[b];
+        D.S = S[b];
+        D.U = U ? U[b] : nullptr;
+        D.V = V ? V[b] : nullptr;
+        D.info = info + b;
+        D.sweeps = sweeps ? sweeps + b : nullptr;
+        D.m = m[b];
+        D.n = n[b];
+        D.lda = lda[b];
+        D.ldu = U ? ldu[b] : 1;
+        D.ldv = V ? ldv[b] : 1;
+        D.np = n[b] > 0 ? blocked_np(n[b], kVbNb) : 0;
+        D.l = n[b] > 0 ? D.np / kVbNb : 2;
+        D.it0 = 0;
+        D.woff = off;
+        off += (long long)D.m * D.np;
+        D.voff = off;
+        off += (long long)D.np * D.np;
+        hd[b] = D;
+        lmax = D.l > lmax ? D.l : lmax;
+        maxn = n[b] > maxn ? n[b] : maxn;
+    }
+    size_t w = 0;
+    for (int b : order)
+        for (int q = 0; n[b] > 0 && q < hd[b].l / 2; q++) hw[w++] = make_int2(b, q);
+    e = hipMemcpyAsync(L.desc, hd, dbytes, hipMemcpyHostToDevice, stream);
+    if (e != hipSuccess) return e;
+    if (nwork) {
+        e = hipMemcpyAsync(L.work, hw, nwork * sizeof(int2), hipMemcpyHostToDevice, stream);
+        if (e != hipSuccess) return e;
+    }
+    vb_launch_init(dtype, L.desc, nullptr, batch, L.base, L.st, stream);
+    e = hipGetLastError();
+    if (e != hipSuccess) return e;
+    int *host_count;
+    e = pinned_counter(&host_count);
+    if (e != hipSuccess) return e;
+    int itg = 0;
+    for (int round = 0; round < max_sweeps; round++) {
+        e = hipMemsetAsync(L.pending, 0, sizeof(int), stream);
+        if (e != hipSuccess) return e;
+        for (int k = 0; k < lmax - 1; k++, itg++) {
+            if (nwork)
+                vb_launch_iter(dtype, L.desc, L.work, (int)nwork, itg, L.base, L.st, tol, stream);
+            vb_launch_sweep_end(batch, L.desc, itg, L.st, max_sweeps, masking,
+                                k == lmax - 2 ? L.pending : (int *)nullptr, stream);
+        }
+        e = hipMemcpyAsync(host_count, L.pending, sizeof(int), hipMemcpyDeviceToHost, stream);
+        if (e != hipSuccess) return e;
+        e = hipStreamSynchronize(stream);
+        if (e != hipSuccess) return e;
+        if (*host_count == 0) break;
+    }
+    vb_launch_finalize(dtype, L.desc, nullptr, batch, maxn, L.base, L.st, stream);
     return hipGetLastError();
 }
 
 }  // namespace
 
-int blocked_nb(int m, int n, int nb)
+int blocked_nb(int m, int n, int nb, bool complex_)
 {
     (void)m;
+    if (complex_) return (nb == 0 || nb == 16) ? 16 : 0;
     if (nb == 16 || nb == 32) return nb;
     if (nb != 0) return 0;
     return n <= 96 ? 16 : 32;
@@ -803,8 +1408,8 @@ hipError_t launch_blocked_d(int batch, int m, int n, int nb, const double *A, in
                             int ldv, long long sV, double tol, int max_sweeps, int masking,
                             int *info, int *sweeps, void *ws, hipStream_t stream)
 {
-    return launch_blocked<double, double>(batch, m, n, nb, A, lda, sA, S, sS, U, ldu, sU, V, ldv,
-                                          sV, tol, max_sweeps, masking, info, sweeps, ws, stream);
+    return launch_blocked<double, false>(batch, m, n, nb, A, lda, sA, S, sS, U, ldu, sU, V, ldv,
+                                         sV, tol, max_sweeps, masking, info, sweeps, ws, stream);
 }
 
 hipError_t launch_blocked_s(int batch, int m, int n, int nb, const float *A, int lda, long long sA,
@@ -812,14 +1417,35 @@ hipError_t launch_blocked_s(int batch, int m, int n, int nb, const float *A, int
                             int ldv, long long sV, double tol, int max_sweeps, int masking,
                             int *info, int *sweeps, void *ws, hipStream_t stream)
 {
-    return launch_blocked<float, float>(batch, m, n, nb, A, lda, sA, S, sS, U, ldu, sU, V, ldv, sV,
+    return launch_blocked<float, false>(batch, m, n, nb, A, lda, sA, S, sS, U, ldu, sU, V, ldv, sV,
                                         tol, max_sweeps, masking, info, sweeps, ws, stream);
 }
 
+hipError_t launch_blocked_z(int batch, int m, int n, int nb, const void *A, int lda, long long sA,
+                            double *S, long long sS, void *U, int ldu, long long sU, void *V,
+                            int ldv, long long sV, double tol, int max_sweeps, int masking,
+                            int *info, int *sweeps, void *ws, hipStream_t stream)
+{
+    return launch_blocked<double, true>(batch, m, n, nb, (const double2 *)A, lda, sA, S, sS,
+                                        (double2 *)U, ldu, sU, (double2 *)V, ldv, sV, tol,
+                                        max_sweeps, masking, info, sweeps, ws, stream);
+}
+
+hipError_t launch_blocked_c(int batch, int m, int n, int nb, const void *A, int lda, long long sA,
+                            float *S, long long sS, void *U, int ldu, long long sU, void *V,
+                            int ldv, long long sV, double tol, int max_sweeps, int masking,
+                            int *info, int *sweeps, void *ws, hipStream_t stream)
+{
+    return launch_blocked<float, true>(batch, m, n, nb, (const float2 *)A, lda, sA, S, sS,
+                                       (float2 *)U, ldu, sU, (float2 *)V, ldv, sV, tol, max_sweeps,
+                                       masking, info, sweeps, ws, stream);
+}
+
 // Mixed mode: FP32 sweeps (FP32 matrix cores, FP64 inner solves) with
-// threshold tol32 until each matrix converges or stalls; then Q = orth(V32)
-// in FP64 by two Newton-Schulz steps towards the polar factor,
-// Q <- Q (3 I - Q^T Q) / 2; W = scale A Q, V = Q; FP64 sweeps to tol.
+// threshold tol32 until each matrix converges or its largest cosine reaches
+// kSwitchCos; then Q = orth(V32) in FP64 by two Newton-Schulz steps towards
+// the polar factor, Q <- Q (3 I - Q^T Q) / 2; W = scale A Q, V = Q; FP64
+// sweeps to tol.
 hipError_t launch_blocked_mixed_d(int batch, int m, int n, int nb, const double *A, int lda,
                                   long long sA, double *S, long long sS, double *U, int ldu,
                                   long long sU, double *V, int ldv, long long sV, double tol,
@@ -834,15 +1460,15 @@ hipError_t launch_blocked_mixed_d(int batch, int m, int n, int nb, const double 
                        lda, sA, W32, V32, L.st);
     hipError_t e = hipGetLastError();
     if (e != hipSuccess) return e;
-    e = run_sweeps<float>(batch, m, np, nb, W32, V32, L.st, L.pending, tol32, max_sweeps, 1, 1,
-                          stream);
+    e = run_sweeps<float, false>(batch, m, np, nb, W32, V32, L.st, L.pending, tol32, max_sweeps,
+                                 1, 1, stream);
     if (e != hipSuccess) return e;
 
     // Newton-Schulz on Q; Q1 lives in the (not yet used) FP64 V area, ld n
     const long long nn = (long long)n * n, vv = (long long)np * np;
     double *Q0 = L.Q, *X = L.X, *Q1 = Vw;
     hipLaunchKernelGGL(v32_to_q, dim3(elementwise_grid((size_t)batch * nn)), dim3(256), 0, stream,
-                       batch, n, np, V32, Q0);
+                       batch, n, np, (const float *)V32, Q0);
     const int tn = (n + 63) / 64, tm = (m + 63) / 64;
     const dim3 gnn((unsigned)(batch * tn * tn));
     for (int step = 0; step < 2; step++) {
@@ -868,14 +1494,33 @@ hipError_t launch_blocked_mixed_d(int batch, int m, int n, int nb, const double 
                        L.sw32);
     e = hipGetLastError();
     if (e != hipSuccess) return e;
-    e = run_sweeps<double>(batch, m, np, nb, W, Vw, L.st, L.pending, tol, max_sweeps, masking, 0,
-                           stream);
+    e = run_sweeps<double, false>(batch, m, np, nb, W, Vw, L.st, L.pending, tol, max_sweeps,
+                                  masking, 0, stream);
     if (e != hipSuccess) return e;
     const size_t lds = (size_t)n * (sizeof(double) + sizeof(int));
     hipLaunchKernelGGL((blk_finalize<double, double>), dim3(batch), dim3(kBT), lds, stream, m, n,
-                       np, (const double *)W, (const double *)Vw, L.st, (const int *)L.sw32, S, sS,
-                       U, ldu, sU, V, ldv, sV, info, sweeps);
+                       np, (const double *)W, (const double *)Vw, (const BlkState *)L.st,
+                       (const int *)L.sw32, S, sS, U, ldu, sU, V, ldv, sV, info, sweeps);
     return hipGetLastError();
+}
+
+}  // namespace svdb
+
+namespace svdb {
+
+size_t vbatched_workspace_bytes(int batch, const int *m, const int *n, int elt)
+{
+    return vb_layout(nullptr, batch, m, n, (size_t)elt).bytes + 256;
+}
+
+hipError_t launch_vbatched(int dtype, int batch, const int *m, const int *n, const void *const *A,
+                           const int *lda, void *const *S, void *const *U, const int *ldu,
+                           void *const *V, const int *ldv, double tol, int max_sweeps,
+                           int masking, int *info, int *sweeps, void *ws, hipStream_t stream)
+{
+    const size_t elt = dtype == 0 ? 4 : dtype == 3 ? 16 : 8;
+    return launch_vb(dtype, elt, batch, m, n, A, lda, S, U, ldu, V, ldv, tol, max_sweeps, masking,
+                     info, sweeps, ws, stream);
 }
 
 }  // namespace svdb

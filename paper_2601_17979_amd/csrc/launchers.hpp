@@ -22,9 +22,10 @@ hipError_t launch_resident_d(int batch, int m, int n, int ns, const double *A, i
                              long long sU, double *V, int ldv, long long sV, double tol,
                              int max_sweeps, int *info, int *sweeps, hipStream_t stream);
 
-// blocked.hip: block one-sided Jacobi with MFMA Gram/updates (FP64, FP32,
-// and FP32 sweeps followed by an FP64 refinement).
-int blocked_nb(int m, int n, int nb);
+// blocked.hip: block one-sided Jacobi with MFMA Gram/updates (real and
+// complex, FP64 and FP32, and FP32 sweeps followed by an FP64 refinement).
+// blocked_nb returns the block width for a request (0: not supported).
+int blocked_nb(int m, int n, int nb, bool complex_);
 int blocked_np(int n, int nb);
 size_t blocked_workspace_bytes(int batch, int m, int n, int nb, int elt, bool mixed);
 hipError_t launch_blocked_d(int batch, int m, int n, int nb, const double *A, int lda, long long sA,
@@ -35,10 +36,52 @@ hipError_t launch_blocked_s(int batch, int m, int n, int nb, const float *A, int
                             float *S, long long sS, float *U, int ldu, long long sU, float *V,
                             int ldv, long long sV, double tol, int max_sweeps, int masking,
                             int *info, int *sweeps, void *ws, hipStream_t stream);
+hipError_t launch_blocked_z(int batch, int m, int n, int nb, const void *A, int lda, long long sA,
+                            double *S, long long sS, void *U, int ldu, long long sU, void *V,
+                            int ldv, long long sV, double tol, int max_sweeps, int masking,
+                            int *info, int *sweeps, void *ws, hipStream_t stream);
+hipError_t launch_blocked_c(int batch, int m, int n, int nb, const void *A, int lda, long long sA,
+                            float *S, long long sS, void *U, int ldu, long long sU, void *V,
+                            int ldv, long long sV, double tol, int max_sweeps, int masking,
+                            int *info, int *sweeps, void *ws, hipStream_t stream);
 hipError_t launch_blocked_mixed_d(int batch, int m, int n, int nb, const double *A, int lda,
                                   long long sA, double *S, long long sS, double *U, int ldu,
                                   long long sU, double *V, int ldv, long long sV, double tol,
                                   double tol32, int max_sweeps, int masking, int *info,
                                   int *sweeps, void *ws, hipStream_t stream);
+
+// Per-matrix descriptor of the uneven-batch kernels (device memory).
+struct VbDesc {
+    const void *A;          // input, lda
+    void *S, *U, *V;        // outputs (U, V may be NULL), ldu, ldv
+    int *info, *sweeps;     // this matrix's status slots (sweeps may be NULL)
+    long long woff, voff;   // element offsets of W (m x np) and V (np x np) from the base
+    int m, n, np, l, lda, ldu, ldv, it0;   // it0: launch index of its first iteration
+};
+
+// Launchers of the uneven-batch kernels; dtype as svdb_dtype_t, st points to
+// per-matrix state of vb_state_bytes() each; idx (device) selects matrices,
+// NULL = 0 .. count-1.
+void vb_launch_init(int dtype, const VbDesc *d, const int *idx, int count, void *base, void *st,
+                    hipStream_t stream);
+void vb_launch_iter(int dtype, const VbDesc *d, const int2 *work, int nwork, int itg, void *base,
+                    void *st, double tol, hipStream_t stream);
+void vb_launch_sweep_end(int count, const VbDesc *d, int itg, void *st, int max_sweeps,
+                         int masking, int *pending, hipStream_t stream);
+void vb_launch_collect(int count, const void *st, int *flags, hipStream_t stream);
+void vb_launch_mark_empty(int count, void *st, hipStream_t stream);
+void vb_launch_finalize(int dtype, const VbDesc *d, const int *idx, int count, int maxn,
+                        const void *base, const void *st, hipStream_t stream);
+size_t vb_state_bytes();
+int vb_nb();
+
+// Uneven batches on the block method (nb = 16): per-matrix pointers and
+// shapes; dtype as svdb_dtype_t.  The workspace holds descriptors, the work
+// table, per-matrix state and every matrix's W and V.
+size_t vbatched_workspace_bytes(int batch, const int *m, const int *n, int elt);
+hipError_t launch_vbatched(int dtype, int batch, const int *m, const int *n, const void *const *A,
+                           const int *lda, void *const *S, void *const *U, const int *ldu,
+                           void *const *V, const int *ldv, double tol, int max_sweeps,
+                           int masking, int *info, int *sweeps, void *ws, hipStream_t stream);
 
 }  // namespace svdb

@@ -1,0 +1,507 @@
+// serve.hip -- the serving runtime behind svdb_server_* (include/svdb.h):
+// continuous batching of independent SVD requests on one GPU.
+//
+// Requests arrive one at a time (any thread).  A worker thread owns the GPU
+// stream and repeats rounds:
+//   1. admit queued requests (first come, first served) while a slot is free
+//      and the device arena (the HBM budget) holds the request's working
+//      copies W (m x np) and V (np x np); initialise them;
+//   2. run a few launches of the uneven-batch block kernels over every
+//      admitted request: each request runs its own round-robin schedule from
+//      the launch at which it was admitted (VbDesc::it0), so requests join
+//      and leave between any two launches;
+//   3. collect the requests that stopped sweeping (converged, or capped at
+//      max_sweeps), finalise them into the caller's buffers, free their
+//      slots and arena ranges, and report completion times.
+// The paper's batches are static (Sec. 7 masks converged matrices but keeps
+// the batch); retiring them and admitting new work in their place is what
+// a serving workload needs.
+#include <hip/hip_runtime.h>
+
+#include <chrono>
+#include <condition_variable>
+#include <deque>
+#include <map>
+#include <mutex>
+#include <string>
+#include <thread>
+#include <vector>
+
+#include "launchers.hpp"
+#include "svdb.h"
+
+namespace {
+
+double now_seconds()
+{
+    using namespace std::chrono;
+    return duration<double>(steady_clock::now().time_since_epoch()).count();
+}
+
+size_t al256(size_t x) { return (x + 255) & ~(size_t)255; }
+
+// First-fit range allocator over the device arena, with coalescing.
+class Arena {
+public:
+    void reset(size_t bytes)
+    {
+        free_.clear();
+        if (bytes) free_[0] = bytes;
+        in_use_ = 0;
+    }
+    bool alloc(size_t bytes, size_t *off)
+    {
+        if (bytes == 0) {
+            *off = 0;
+            return true;
+        }
+        for (auto it = free_.begin(); it != free_.end(); ++it) {
+            if (it->second >= bytes) {
+                *off = it->first;
+                const size_t rest = it->second - bytes, start = it->first + bytes;
+                free_.erase(it);
+                if (rest) free_[start] = rest;
+                in_use_ += bytes;
+                return true;
+            }
+        }
+        return false;
+    }
+    void release(size_t off, size_t bytes)
+    {
+        if (bytes == 0) return;
+        in_use_ -= bytes;
+        auto it = free_.emplace(off, bytes).first;
+        auto nx = std::next(it);
+        if (nx != free_.end() && it->first + it->second == nx->first) {
+            it->second += nx->second;
+            free_.erase(nx);
+        }
+        if (it != free_.begin()) {
+            auto pv = std::prev(it);
+            if (pv->first + pv->second == it->first) {
+                pv->second += it->second;
+                free_.erase(it);
+            }
+        }
+    }
+    size_t in_use() const { return in_use_; }
+
+private:
+    std::map<size_t, size_t> free_;   // offset -> length
+    size_t in_use_ = 0;
+};
+
+struct Request {
+    long long id = 0;
+    int dtype = 1, m = 0, n = 0, lda = 1, ldu = 1, ldv = 1;
+    const void *A = nullptr;
+    void *S = nullptr, *U = nullptr, *V = nullptr;
+    int *info = nullptr, *sweeps = nullptr;
+    double tol = 0.0;
+    size_t bytes = 0, off = 0;
+    double t_submit = 0.0;
+};
+
+struct Completion {
+    long long id;
+    double t_submit, t_done;
+};
+
+int elt_of(int dtype) { return dtype == 0 ? 4 : dtype == 3 ? 16 : 8; }
+
+// One dtype: the kernels are compiled per element type.
+struct Group {
+    int dtype = 1;
+    int cap = 0;
+    svdb::VbDesc *d_desc = nullptr, *h_desc = nullptr;
+    void *d_st = nullptr;
+    int *d_flags = nullptr, *h_flags = nullptr;
+    int2 *d_work = nullptr, *h_work = nullptr;
+    int *d_idx = nullptr, *h_idx = nullptr;
+    std::vector<Request> slot;
+    std::vector<char> used;
+    std::vector<int> fresh;   // slots admitted this round
+    int nused = 0, nwork = 0, lmax = 2, maxn = 0;
+    bool dirty = false;
+    int max_pairs = 0;        // work-table entries per slot
+    double tol = 0.0;
+};
+
+}  // namespace
+
+struct svdb_server {
+    hipStream_t stream = nullptr;
+    void *arena = nullptr;
+    size_t budget = 0;
+    Arena alloc;
+    Group g[4];
+    int max_sweeps = 100;
+    int max_n = 512;
+    std::mutex mu;
+    std::condition_variable cv_work, cv_done;
+    std::deque<Request> queue;
+    std::deque<Completion> done;
+    std::thread worker;
+    bool stop = false;
+    int failed = 0;
+    std::string err;
+    long long next_id = 0, submitted = 0, completed = 0;
+    int itg = 0;
+};
+
+namespace {
+
+#define SRV_CHECK(expr)                                                                  \
+    do {                                                                                 \
+        hipError_t e_ = (expr);                                                          \
+        if (e_ != hipSuccess) {                                                          \
+            std::lock_guard<std::mutex> lk(s->mu);                                       \
+            s->failed = 1;                                                               \
+            s->err = std::string(#expr) + ": " + hipGetErrorString(e_);                  \
+            s->cv_done.notify_all();                                                     \
+            return;                                                                      \
+        }                                                                                \
+    } while (0)
+
+void rebuild_work(Group &G)
+{
+    // largest matrices first; only slots still sweeping
+    std::vector<int> order;
+    for (int b = 0; b < G.cap; b++)
+        if (G.used[b]) order.push_back(b);
+    std::stable_sort(order.begin(), order.end(),
+                     [&](int x, int y) { return G.slot[x].n > G.slot[y].n; });
+    int w = 0, lmax = 2, maxn = 0;
+    for (int b : order) {
+        const svdb::VbDesc &D = G.h_desc[b];
+        for (int q = 0; G.slot[b].n > 0 && q < D.l / 2; q++) G.h_work[w++] = make_int2(b, q);
+        lmax = D.l > lmax ? D.l : lmax;
+        maxn = D.n > maxn ? D.n : maxn;
+    }
+    G.nwork = w;
+    G.lmax = lmax;
+    G.maxn = maxn;
+}
+
+void worker_main(svdb_server *s)
+{
+    const int nb = svdb::vb_nb();
+    for (;;) {
+        // ---- 1. admission ----------------------------------------------------
+        {
+            std::unique_lock<std::mutex> lk(s->mu);
+            auto active = [&] {
+                for (auto &G : s->g)
+                    if (G.nused) return true;
+                return false;
+            };
+            s->cv_work.wait(lk, [&] { return s->stop || !s->queue.empty() || active(); });
+            if (s->stop && s->queue.empty() && !active()) return;
+            while (!s->queue.empty()) {
+                Request &r = s->queue.front();
+                Group &G = s->g[r.dtype];
+                int b = -1;
+                for (int k = 0; k < G.cap; k++)
+                    if (!G.used[k]) {
+                        b = k;
+                        break;
+                    }
+                size_t off = 0;
+                if (b < 0 || !s->alloc.alloc(r.bytes, &off)) break;   // wait for retirements
+                r.off = off;
+                G.slot[b] = r;
+                G.used[b] = 1;
+                G.nused++;
+                G.fresh.push_back(b);
+                G.dirty = true;
+                s->queue.pop_front();
+            }
+        }
+        // ---- initialise the admitted requests ----------------------------------
+        for (auto &G : s->g) {
+            if (G.fresh.empty()) continue;
+            const size_t elt = (size_t)elt_of(G.dtype);
+            int lo = G.cap, hi = -1;
+            for (size_t k = 0; k < G.fresh.size(); k++) {
+                const int b = G.fresh[k];
+                const Request &r = G.slot[b];
+                svdb::VbDesc D{};
+                D.A = r.A;
+                D.S = r.S;
+                D.U = r.U;
+                D.V = r.V;
+                D.info = r.info;
+                D.sweeps = r.sweeps;
+                D.m = r.m;
+                D.n = r.n;
+                D.lda = r.lda;
+                D.ldu = r.ldu;
+                D.ldv = r.ldv;
+                D.np = r.n > 0 ? svdb::blocked_np(r.n, nb) : 0;
+                D.l = r.n > 0 ? D.np / nb : 2;
+                D.it0 = s->itg;
+                D.woff = (long long)(r.off / elt);
+                D.voff = D.woff + (long long)D.m * D.np;
+                G.h_desc[b] = D;
+                G.h_idx[k] = b;
+                lo = b < lo ? b : lo;
+                hi = b > hi ? b : hi;
+            }
+            SRV_CHECK(hipMemcpyAsync(G.d_desc + lo, G.h_desc + lo,
+                                     (size_t)(hi - lo + 1) * sizeof(svdb::VbDesc),
+                                     hipMemcpyHostToDevice, s->stream));
+            SRV_CHECK(hipMemcpyAsync(G.d_idx, G.h_idx, G.fresh.size() * sizeof(int),
+                                     hipMemcpyHostToDevice, s->stream));
+            svdb::vb_launch_init(G.dtype, G.d_desc, G.d_idx, (int)G.fresh.size(), s->arena,
+                                 G.d_st, s->stream);
+            SRV_CHECK(hipGetLastError());
+            G.fresh.clear();
+        }
+        // ---- 2. a few launches over everything admitted -----------------------------
+        int K = 1;
+        for (auto &G : s->g) {
+            if (!G.nused) continue;
+            if (G.dirty) {
+                rebuild_work(G);
+                if (G.nwork)
+                    SRV_CHECK(hipMemcpyAsync(G.d_work, G.h_work, (size_t)G.nwork * sizeof(int2),
+                                             hipMemcpyHostToDevice, s->stream));
+                G.dirty = false;
+            }
+            K = G.lmax - 1 > K ? G.lmax - 1 : K;
+        }
+        K = K < 8 ? K : 8;
+        for (int k = 0; k < K; k++, s->itg++)
+            for (auto &G : s->g) {
+                if (!G.nused) continue;
+                if (G.nwork)
+                    svdb::vb_launch_iter(G.dtype, G.d_desc, G.d_work, G.nwork, s->itg, s->arena,
+                                         G.d_st, G.tol, s->stream);
+                svdb::vb_launch_sweep_end(G.cap, G.d_desc, s->itg, G.d_st, s->max_sweeps, 1,
+                                          nullptr, s->stream);
+            }
+        SRV_CHECK(hipGetLastError());
+        // ---- 3. retire what stopped ---------------------------------------------------
+        for (auto &G : s->g) {
+            if (!G.nused) continue;
+            svdb::vb_launch_collect(G.cap, G.d_st, G.d_flags, s->stream);
+            SRV_CHECK(hipMemcpyAsync(G.h_flags, G.d_flags, (size_t)G.cap * sizeof(int),
+                                     hipMemcpyDeviceToHost, s->stream));
+        }
+        SRV_CHECK(hipStreamSynchronize(s->stream));
+        std::vector<std::pair<int, int>> retired;   // (group, slot)
+        for (int gi = 0; gi < 4; gi++) {
+            Group &G = s->g[gi];
+            if (!G.nused) continue;
+            int cnt = 0, maxn = 0;
+            for (int b = 0; b < G.cap; b++)
+                if (G.used[b] && G.h_flags[b]) {
+                    G.h_idx[cnt++] = b;
+                    maxn = G.slot[b].n > maxn ? G.slot[b].n : maxn;
+                    retired.push_back({gi, b});
+                }
+            if (!cnt) continue;
+            SRV_CHECK(hipMemcpyAsync(G.d_idx, G.h_idx, (size_t)cnt * sizeof(int),
+                                     hipMemcpyHostToDevice, s->stream));
+            svdb::vb_launch_finalize(G.dtype, G.d_desc, G.d_idx, cnt, maxn, s->arena, G.d_st,
+                                     s->stream);
+            SRV_CHECK(hipGetLastError());
+        }
+        if (retired.empty()) continue;
+        SRV_CHECK(hipStreamSynchronize(s->stream));
+        const double t = now_seconds();
+        {
+            std::lock_guard<std::mutex> lk(s->mu);
+            for (auto &gb : retired) {
+                Group &G = s->g[gb.first];
+                Request &r = G.slot[gb.second];
+                s->done.push_back({r.id, r.t_submit, t});
+                s->alloc.release(r.off, r.bytes);
+                G.used[gb.second] = 0;
+                G.nused--;
+                G.dirty = true;
+                s->completed++;
+            }
+        }
+        s->cv_done.notify_all();
+    }
+}
+
+void destroy_resources(svdb_server *s)
+{
+    for (auto &G : s->g) {
+        if (G.d_desc) (void)hipFree(G.d_desc);
+        if (G.d_st) (void)hipFree(G.d_st);
+        if (G.d_flags) (void)hipFree(G.d_flags);
+        if (G.d_work) (void)hipFree(G.d_work);
+        if (G.d_idx) (void)hipFree(G.d_idx);
+        if (G.h_desc) (void)hipHostFree(G.h_desc);
+        if (G.h_flags) (void)hipHostFree(G.h_flags);
+        if (G.h_work) (void)hipHostFree(G.h_work);
+        if (G.h_idx) (void)hipHostFree(G.h_idx);
+    }
+    if (s->arena) (void)hipFree(s->arena);
+    if (s->stream) (void)hipStreamDestroy(s->stream);
+}
+
+}  // namespace
+
+extern "C" {
+
+double svdb_server_clock(void) { return now_seconds(); }
+
+int svdb_server_create(svdb_server_t **out, size_t budget_bytes, int max_requests,
+                       const svdb_opts_t *opts)
+{
+    if (!out) return -1;
+    *out = nullptr;
+    if (budget_bytes == 0) return -2;
+    if (max_requests <= 0) return -3;
+    svdb_opts_t o;
+    svdb_opts_default(&o);
+    if (opts) o = *opts;
+    if (o.precision != 0) return SVDB_ERR_UNSUPPORTED;
+    svdb_server *s = new svdb_server();
+    s->budget = al256(budget_bytes);
+    s->max_sweeps = o.max_sweeps > 0 ? o.max_sweeps : 100;
+    hipError_t e = hipStreamCreateWithFlags(&s->stream, hipStreamNonBlocking);
+    if (e == hipSuccess) e = hipMalloc(&s->arena, s->budget);
+    const int pairs = s->max_n / svdb::vb_nb() / 2;   // block pairs of the widest request
+    for (int gi = 0; gi < 4 && e == hipSuccess; gi++) {
+        Group &G = s->g[gi];
+        G.dtype = gi;
+        G.cap = max_requests;
+        G.max_pairs = pairs;
+        G.tol = 30.0 * ldexp(1.0, (gi == 0 || gi == 2) ? -24 : -53);
+        G.slot.assign(G.cap, Request());
+        G.used.assign(G.cap, 0);
+        const size_t nc = (size_t)G.cap;
+        if (e == hipSuccess) e = hipMalloc((void **)&G.d_desc, nc * sizeof(svdb::VbDesc));
+        if (e == hipSuccess) e = hipMalloc(&G.d_st, nc * svdb::vb_state_bytes());
+        if (e == hipSuccess) e = hipMalloc((void **)&G.d_flags, nc * sizeof(int));
+        if (e == hipSuccess) e = hipMalloc((void **)&G.d_work, nc * pairs * sizeof(int2));
+        if (e == hipSuccess) e = hipMalloc((void **)&G.d_idx, nc * sizeof(int));
+        if (e == hipSuccess) e = hipHostMalloc((void **)&G.h_desc, nc * sizeof(svdb::VbDesc), 0);
+        if (e == hipSuccess) e = hipHostMalloc((void **)&G.h_flags, nc * sizeof(int), 0);
+        if (e == hipSuccess) e = hipHostMalloc((void **)&G.h_work, nc * pairs * sizeof(int2), 0);
+        if (e == hipSuccess) e = hipHostMalloc((void **)&G.h_idx, nc * sizeof(int), 0);
+        if (e == hipSuccess) svdb::vb_launch_mark_empty(G.cap, G.d_st, s->stream);
+    }
+    if (e == hipSuccess) e = hipStreamSynchronize(s->stream);
+    if (e != hipSuccess) {
+        destroy_resources(s);
+        delete s;
+        return SVDB_ERR_HIP;
+    }
+    s->alloc.reset(s->budget);
+    s->worker = std::thread(worker_main, s);
+    *out = s;
+    return 0;
+}
+
+long long svdb_server_submit(svdb_server_t *s, svdb_dtype_t dtype, int m, int n, const void *A,
+                             int lda, void *S, void *U, int ldu, void *V, int ldv, double tol,
+                             int *info, int *sweeps)
+{
+    if (!s) return -1;
+    if ((int)dtype < SVDB_R32 || (int)dtype > SVDB_C128) return -2;
+    if (m < 0) return -3;
+    if (n < 0 || n > m) return -4;
+    if (n > s->max_n) return SVDB_ERR_UNSUPPORTED;
+    if (!A && n > 0) return -5;
+    if (lda < (m > 1 ? m : 1)) return -6;
+    if (!S && n > 0) return -7;
+    if (U && ldu < (m > 1 ? m : 1)) return -9;
+    if (V && ldv < (n > 1 ? n : 1)) return -11;
+    if (!info) return -13;
+    Request r;
+    r.dtype = (int)dtype;
+    r.m = m;
+    r.n = n;
+    r.A = A;
+    r.lda = lda;
+    r.S = S;
+    r.U = U;
+    r.ldu = U ? ldu : 1;
+    r.V = V;
+    r.ldv = V ? ldv : 1;
+    r.info = info;
+    r.sweeps = sweeps;
+    const int np = n > 0 ? svdb::blocked_np(n, svdb::vb_nb()) : 0;
+    r.bytes = al256(((size_t)m * np + (size_t)np * np) * (size_t)elt_of(r.dtype));
+    if (r.bytes > s->budget) return SVDB_ERR_UNSUPPORTED;
+    (void)tol;   // per-dtype default threshold (30 u)
+    std::lock_guard<std::mutex> lk(s->mu);
+    if (s->failed) return SVDB_ERR_HIP;
+    r.id = s->next_id++;
+    r.t_submit = now_seconds();
+    s->queue.push_back(r);
+    s->submitted++;
+    s->cv_work.notify_one();
+    return r.id;
+}
+
+int svdb_server_poll(svdb_server_t *s, long long *ids, double *t_submit, double *t_done, int cap,
+                     int timeout_ms)
+{
+    if (!s || cap < 0) return -1;
+    std::unique_lock<std::mutex> lk(s->mu);
+    if (s->done.empty() && timeout_ms != 0 && !s->failed) {
+        auto pred = [&] { return !s->done.empty() || s->failed; };
+        if (timeout_ms < 0)
+            s->cv_done.wait(lk, pred);
+        else
+            s->cv_done.wait_for(lk, std::chrono::milliseconds(timeout_ms), pred);
+    }
+    if (s->failed && s->done.empty()) return SVDB_ERR_HIP;
+    int k = 0;
+    while (k < cap && !s->done.empty()) {
+        const Completion c = s->done.front();
+        s->done.pop_front();
+        if (ids) ids[k] = c.id;
+        if (t_submit) t_submit[k] = c.t_submit;
+        if (t_done) t_done[k] = c.t_done;
+        k++;
+    }
+    return k;
+}
+
+int svdb_server_stats(svdb_server_t *s, long long *submitted, long long *completed, int *active,
+                      int *queued, size_t *bytes_in_use)
+{
+    if (!s) return -1;
+    std::lock_guard<std::mutex> lk(s->mu);
+    int a = 0;
+    for (auto &G : s->g) a += G.nused;
+    if (submitted) *submitted = s->submitted;
+    if (completed) *completed = s->completed;
+    if (active) *active = a;
+    if (queued) *queued = (int)s->queue.size();
+    if (bytes_in_use) *bytes_in_use = s->alloc.in_use();
+    return s->failed ? SVDB_ERR_HIP : 0;
+}
+
+const char *svdb_server_error(svdb_server_t *s)
+{
+    if (!s) return "";
+    std::lock_guard<std::mutex> lk(s->mu);
+    return s->err.c_str();
+}
+
+int svdb_server_destroy(svdb_server_t *s)
+{
+    if (!s) return -1;
+    {
+        std::lock_guard<std::mutex> lk(s->mu);
+        s->stop = true;
+    }
+    s->cv_work.notify_all();
+    if (s->worker.joinable()) s->worker.join();
+    (void)hipStreamSynchronize(s->stream);
+    destroy_resources(s);
+    delete s;
+    return 0;
+}
+
+}  // extern "C"

@@ -67,6 +67,21 @@ def lib():
         L.svdb_svd_batched.argtypes = [I, I, P, P, P, P, P, P, P, P, P, D, P, P, SZ,
                                        C.POINTER(Opts), P]
         L.svdb_svd_batched.restype = I
+        L.svdb_server_create.argtypes = [C.POINTER(P), SZ, I, C.POINTER(Opts)]
+        L.svdb_server_create.restype = I
+        L.svdb_server_submit.argtypes = [P, I, I, I, P, I, P, P, I, P, I, D, P, P]
+        L.svdb_server_submit.restype = LL
+        L.svdb_server_poll.argtypes = [P, P, P, P, I, I]
+        L.svdb_server_poll.restype = I
+        L.svdb_server_stats.argtypes = [P, C.POINTER(LL), C.POINTER(LL), C.POINTER(I),
+                                        C.POINTER(I), C.POINTER(SZ)]
+        L.svdb_server_stats.restype = I
+        L.svdb_server_error.argtypes = [P]
+        L.svdb_server_error.restype = C.c_char_p
+        L.svdb_server_destroy.argtypes = [P]
+        L.svdb_server_destroy.restype = I
+        L.svdb_server_clock.argtypes = []
+        L.svdb_server_clock.restype = D
         _lib = L
     return _lib
 
@@ -217,3 +232,87 @@ def svd_batched(mats, tol: float = 0.0, max_sweeps: int = 100, path="auto", nb: 
     if rc:
         raise SvdbError(rc, last_error())
     return Ss, Us, Vs, info, sweeps
+
+
+class Server:
+    """Continuous-batching SVD server (svdb_server_* of the C ABI).
+
+    ``submit(A)`` takes one column-major (m, n) GPU tensor whose values are
+    final (synchronise the stream that produced it first: the server reads
+    it on its own stream), allocates the outputs
+    and returns a request id; ``poll()`` returns completed requests as
+    (id, t_submit, t_done, (S, U, V, info, sweeps)).  The server keeps every
+    tensor of a request alive until it completes."""
+
+    def __init__(self, budget_bytes: int, max_requests: int = 1024, max_sweeps: int = 100,
+                 device=None):
+        self._dev = torch.device(device or "cuda")
+        o = make_opts(max_sweeps=max_sweeps)
+        h = C.c_void_p()
+        rc = lib().svdb_server_create(C.byref(h), int(budget_bytes), int(max_requests),
+                                      C.byref(o))
+        if rc:
+            raise SvdbError(rc, "svdb_server_create failed")
+        self._h = h
+        self._live = {}
+
+    def submit(self, A: torch.Tensor, compute_u: bool = True, compute_v: bool = True):
+        if A.dim() != 2 or (A.shape[0] > 1 and A.stride(0) != 1):
+            raise ValueError("A must be a 2-D column-major tensor")
+        m, n = int(A.shape[0]), int(A.shape[1])
+        dt = A.dtype
+        S = torch.empty(n, dtype=_REAL[dt], device=A.device)
+        U = torch.empty((n, m), dtype=dt, device=A.device).t() if compute_u else None
+        V = torch.empty((n, n), dtype=dt, device=A.device).t() if compute_v else None
+        info = torch.empty(1, dtype=torch.int32, device=A.device)
+        sweeps = torch.empty(1, dtype=torch.int32, device=A.device)
+        lda = max(A.stride(1), m, 1) if n > 1 else max(m, 1)
+        rid = lib().svdb_server_submit(
+            self._h, dtype_code(dt), m, n, A.data_ptr() if n else None, lda,
+            S.data_ptr() if n else None, U.data_ptr() if U is not None and n else None,
+            max(m, 1), V.data_ptr() if V is not None and n else None, max(n, 1), 0.0,
+            info.data_ptr(), sweeps.data_ptr())
+        if rid < 0:
+            raise SvdbError(int(rid), self.error() or "svdb_server_submit failed")
+        self._live[int(rid)] = (A, S, U, V, info, sweeps)
+        return int(rid)
+
+    def poll(self, timeout_ms: int = 0, cap: int = 4096):
+        ids = (C.c_longlong * cap)()
+        ts = (C.c_double * cap)()
+        td = (C.c_double * cap)()
+        k = lib().svdb_server_poll(self._h, ids, ts, td, cap, int(timeout_ms))
+        if k < 0:
+            raise SvdbError(k, self.error())
+        out = []
+        for i in range(k):
+            A, S, U, V, info, sweeps = self._live.pop(int(ids[i]))
+            out.append((int(ids[i]), ts[i], td[i], (S, U, V, info, sweeps)))
+        return out
+
+    def stats(self):
+        sub, com, act, q, used = C.c_longlong(), C.c_longlong(), C.c_int(), C.c_int(), C.c_size_t()
+        rc = lib().svdb_server_stats(self._h, C.byref(sub), C.byref(com), C.byref(act),
+                                     C.byref(q), C.byref(used))
+        if rc:
+            raise SvdbError(rc, self.error())
+        return {"submitted": sub.value, "completed": com.value, "active": act.value,
+                "queued": q.value, "bytes_in_use": used.value}
+
+    def error(self) -> str:
+        return lib().svdb_server_error(self._h).decode() if self._h else ""
+
+    @staticmethod
+    def clock() -> float:
+        return lib().svdb_server_clock()
+
+    def close(self):
+        if self._h:
+            lib().svdb_server_destroy(self._h)
+            self._h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass

@@ -1,0 +1,127 @@
+"""GPU tests of the serving runtime (svdb_server_*): continuous batching
+with admission by an HBM budget, early retirement and mixed dtypes.  Every
+completed request is checked against the oracle."""
+import time
+
+import numpy as np
+import pytest
+
+import oracle
+from workloads import gen
+from gpu_util import compare_with_oracle, say
+
+pytestmark = pytest.mark.gpu
+
+
+def _mat(seed, k, m, n, dtype, kappa=1e4):
+    A = gen.from_spectrum(gen.rng_for(seed, k), m, n, gen.spectrum("geo", n, kappa))
+    return A.astype(dtype)
+
+
+def _to_dev(A):
+    import torch
+    return torch.from_numpy(np.asfortranarray(A)).cuda().t().contiguous().t()
+
+
+def _drain(srv, count, timeout_s=120.0):
+    got = {}
+    t0 = time.time()
+    while len(got) < count:
+        assert time.time() - t0 < timeout_s, f"only {len(got)} of {count} completed"
+        for rid, ts, td, out in srv.poll(timeout_ms=200):
+            got[rid] = (ts, td, out)
+    return got
+
+
+def _check(A, out, label):
+    S, U, V, info, sw = (x.cpu().numpy() if x is not None else None for x in out)
+    A64 = A.astype(np.float64)
+    dt = np.float32 if A.dtype == np.float32 else np.float64
+    Sr, _, _, _, infor = oracle.gesvj(A64)
+    compare_with_oracle(A64[None], S[None].astype(np.float64), U[None].astype(np.float64),
+                        V[None].astype(np.float64), info, Sr[None], np.array([infor]), dtype=dt,
+                        label=label)
+
+
+def test_server_mixed_requests_vs_oracle():
+    import torch
+    from paper_2601_17979_amd import svdb
+    shapes = [(16, 16), (32, 16), (32, 32), (64, 32), (64, 64), (128, 64), (128, 128),
+              (256, 128)]
+    reqs = []
+    for k in range(48):
+        m, n = shapes[k % len(shapes)]
+        dt = np.float64 if k % 2 == 0 else np.float32
+        reqs.append(_mat(9500, k, m, n, dt))
+    dev = [_to_dev(A) for A in reqs]
+    torch.cuda.synchronize()
+    srv = svdb.Server(budget_bytes=256 << 20, max_requests=64)
+    ids = {srv.submit(x): k for k, x in enumerate(dev)}
+    got = _drain(srv, len(reqs))
+    st = srv.stats()
+    srv.close()
+    assert st["completed"] == len(reqs) and st["active"] == 0 and st["bytes_in_use"] == 0
+    lat = sorted(td - ts for ts, td, _ in got.values())
+    say(f"[serve mix] {len(reqs)} requests, latency p50 {lat[len(lat) // 2] * 1e3:.2f} ms "
+        f"max {lat[-1] * 1e3:.2f} ms")
+    for rid, (ts, td, out) in got.items():
+        k = ids[rid]
+        _check(reqs[k], out, f"serve #{k} {reqs[k].shape} {reqs[k].dtype}")
+
+
+def test_server_alone_equals_in_mix():
+    """A request's outputs do not depend on what else is being served."""
+    import torch
+    from paper_2601_17979_amd import svdb
+    probe = _mat(9600, 0, 96, 80, np.float64)
+    others = [_mat(9600, k, 200, 150, np.float64) for k in range(1, 9)]
+    torch.cuda.synchronize()
+
+    def run(mats):
+        dev = [_to_dev(A) for A in mats]
+        torch.cuda.synchronize()
+        srv = svdb.Server(budget_bytes=128 << 20, max_requests=16)
+        ids = [srv.submit(x) for x in dev]
+        got = _drain(srv, len(mats))
+        srv.close()
+        return [tuple(t.cpu().numpy() for t in got[i][2][:3]) for i in ids]
+
+    alone = run([probe])[0]
+    mixed = run(others[:4] + [probe] + others[4:])[4]
+    for a, b in zip(alone, mixed):
+        assert np.array_equal(a, b)
+
+
+def test_server_budget_admission():
+    """A budget that holds only two working sets at a time still serves a
+    longer queue; the arena never exceeds the budget."""
+    import torch
+    from paper_2601_17979_amd import svdb
+    m, n = 128, 96
+    need = (m * 96 + 96 * 96) * 8            # np = 96 for nb = 16 (l = 6)
+    budget = 2 * need + 1024
+    mats = [_mat(9700, k, m, n, np.float64) for k in range(10)]
+    dev = [_to_dev(A) for A in mats]
+    torch.cuda.synchronize()
+    srv = svdb.Server(budget_bytes=budget, max_requests=8)
+    ids = {srv.submit(x): k for k, x in enumerate(dev)}
+    got = {}
+    peak = 0
+    t0 = time.time()
+    while len(got) < len(mats):
+        assert time.time() - t0 < 120
+        st = srv.stats()
+        peak = max(peak, st["bytes_in_use"])
+        for rid, ts, td, out in srv.poll(timeout_ms=5):
+            got[rid] = out
+    srv.close()
+    say(f"[serve budget] peak arena {peak} of {budget} bytes")
+    assert 0 < peak <= budget
+    for rid, out in got.items():
+        _check(mats[ids[rid]], out, f"budget #{ids[rid]}")
+    with pytest.raises(svdb.SvdbError):
+        srv2 = svdb.Server(budget_bytes=4096, max_requests=2)
+        try:
+            srv2.submit(dev[0])
+        finally:
+            srv2.close()

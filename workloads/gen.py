@@ -170,3 +170,25 @@ def uneven_complex(batch: int = 20000, seed: int = BASE_SEED + 3000, nmin: int =
         A = np.stack([gaussian(rng_for(seed + 1, k), m, n, True) for k in ks])
         groups.append(Group(m, n, A, ["cgauss"] * len(ks), (seed, ks[0])))
     return groups
+
+
+SERVE_CLASSES = [(n * r, n) for n in (16, 32, 64, 128, 256, 512) for r in (1, 2)]
+
+
+def serving_pool(per_class: int = 4, seed: int = BASE_SEED + 4000, max_n: int = 512) -> list:
+    """Request pool of the serving workload: shape classes n in {16, ..., 512}
+    x {square, m = 2n}, dtype alternating FP64 / FP32, kappa log-uniform in
+    [1, 1e8] with a geometric spectrum.  Returns a list of (A, dtype name)
+    with A in FP64 (cast on use)."""
+    pool = []
+    k = 0
+    for m, n in SERVE_CLASSES:
+        if n > max_n:
+            continue
+        for j in range(per_class):
+            r = rng_for(seed, k)
+            kappa = float(np.exp(r.uniform(0.0, np.log(1e8))))
+            A = from_spectrum(r, m, n, spectrum("geo", n, kappa))
+            pool.append((A, "f64" if k % 2 == 0 else "f32"))
+            k += 1
+    return pool
