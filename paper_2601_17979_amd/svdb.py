@@ -185,53 +185,74 @@ def svd(A: torch.Tensor, tol: float = 0.0, max_sweeps: int = 100, path="auto", n
     return S, U, V, info, sweeps
 
 
+class BatchedCall:
+    """A prepared svdb_svd_batched call: outputs, pointer arrays and the
+    workspace are built once; calling the object enqueues the SVD of every
+    matrix of `mats` (a list of column-major (m_b, n_b) GPU tensors of one
+    dtype) and returns (S, U, V, info, sweeps) (lists for S, U, V)."""
+
+    def __init__(self, mats, tol: float = 0.0, max_sweeps: int = 100, compute_u: bool = True,
+                 compute_v: bool = True, masking: bool = True, precision: int = 0):
+        dt = mats[0].dtype
+        dev = mats[0].device
+        self.code = dtype_code(dt)
+        bsz = len(mats)
+        self.bsz = bsz
+        for x in mats:
+            if x.dtype != dt or x.dim() != 2 or (x.shape[0] > 1 and x.stride(0) != 1):
+                raise ValueError("every matrix must be a 2-D column-major tensor of one dtype")
+        self.ms = (C.c_int * bsz)(*[int(x.shape[0]) for x in mats])
+        self.ns = (C.c_int * bsz)(*[int(x.shape[1]) for x in mats])
+        self.S = [torch.empty(int(x.shape[1]), dtype=_REAL[dt], device=dev) for x in mats]
+        self.U = [torch.empty((int(x.shape[1]), int(x.shape[0])), dtype=dt, device=dev).t()
+                  for x in mats] if compute_u else None
+        self.V = [torch.empty((int(x.shape[1]), int(x.shape[1])), dtype=dt, device=dev).t()
+                  for x in mats] if compute_v else None
+        self.info = torch.empty(bsz, dtype=torch.int32, device=dev)
+        self.sweeps = torch.empty(bsz, dtype=torch.int32, device=dev)
+        P = C.c_void_p * bsz
+        I = C.c_int * bsz
+
+        def ld(x, rows):
+            return max(x.stride(1), rows, 1) if x.shape[1] > 1 else max(rows, 1)
+        self.mats = mats
+        self.Ap = P(*[x.data_ptr() for x in mats])
+        self.lda = I(*[ld(x, x.shape[0]) for x in mats])
+        self.Sp = P(*[t.data_ptr() for t in self.S])
+        self.Up = P(*[u.data_ptr() for u in self.U]) if self.U is not None else None
+        self.ldu = I(*[ld(u, u.shape[0]) for u in self.U]) if self.U is not None else None
+        self.Vp = P(*[v.data_ptr() for v in self.V]) if self.V is not None else None
+        self.ldv = I(*[ld(v, v.shape[0]) for v in self.V]) if self.V is not None else None
+        self.opts = make_opts(max_sweeps, "auto", 0, masking, precision, self.sweeps)
+        self.tol = float(tol)
+        self.ws_bytes = lib().svdb_batched_workspace_size(self.code, bsz, self.ms, self.ns,
+                                                          C.byref(self.opts))
+        if self.ws_bytes == C.c_size_t(-1).value:
+            raise SvdbError(-1, last_error() or "invalid arguments")
+        self.ws = torch.empty(max(self.ws_bytes, 1), dtype=torch.uint8, device=dev)
+
+    def __call__(self, stream=None):
+        st = (stream or torch.cuda.current_stream(self.info.device)).cuda_stream
+        rc = lib().svdb_svd_batched(self.code, self.bsz, self.ms, self.ns, self.Ap, self.lda,
+                                    self.Sp, self.Up, self.ldu, self.Vp, self.ldv, self.tol,
+                                    self.info.data_ptr(), self.ws.data_ptr(), self.ws_bytes,
+                                    C.byref(self.opts), st)
+        if rc:
+            raise SvdbError(rc, last_error())
+        return self.S, self.U, self.V, self.info, self.sweeps
+
+
 def svd_batched(mats, tol: float = 0.0, max_sweeps: int = 100, path="auto", nb: int = 0,
                 compute_u: bool = True, compute_v: bool = True, masking: bool = True,
                 precision: int = 0, stream=None):
     """Mixed-shape batch: `mats` is a list of (m_b, n_b) column-major GPU
-    tensors of one dtype.  Returns lists (S, U, V) and tensors (info, sweeps)."""
+    tensors of one dtype.  Returns lists (S, U, V) and tensors (info, sweeps).
+    (path and nb are accepted for symmetry with svd(); uneven batches always
+    run the block method with nb = 16.)"""
     if not mats:
         return [], [], [], None, None
-    dt = mats[0].dtype
-    dev = mats[0].device
-    code = dtype_code(dt)
-    bsz = len(mats)
-    ms = (C.c_int * bsz)(*[int(x.shape[0]) for x in mats])
-    ns = (C.c_int * bsz)(*[int(x.shape[1]) for x in mats])
-    for x in mats:
-        if x.dtype != dt or x.dim() != 2 or (x.shape[0] > 1 and x.stride(0) != 1):
-            raise ValueError("every matrix must be a 2-D column-major tensor of one dtype")
-    Ss = [torch.empty(int(x.shape[1]), dtype=_REAL[dt], device=dev) for x in mats]
-    Us = [torch.empty((int(x.shape[1]), int(x.shape[0])), dtype=dt, device=dev).t()
-          for x in mats] if compute_u else None
-    Vs = [torch.empty((int(x.shape[1]), int(x.shape[1])), dtype=dt, device=dev).t()
-          for x in mats] if compute_v else None
-    info = torch.empty(bsz, dtype=torch.int32, device=dev)
-    sweeps = torch.empty(bsz, dtype=torch.int32, device=dev)
-    P = C.c_void_p * bsz
-    I = C.c_int * bsz
-
-    def ld(x, rows):
-        return max(x.stride(1), rows, 1) if x.shape[1] > 1 else max(rows, 1)
-    Ap = P(*[x.data_ptr() for x in mats])
-    lda = I(*[ld(x, x.shape[0]) for x in mats])
-    Sp = P(*[s.data_ptr() for s in Ss])
-    Up = P(*[u.data_ptr() for u in Us]) if Us is not None else None
-    ldu = I(*[ld(u, u.shape[0]) for u in Us]) if Us is not None else None
-    Vp = P(*[v.data_ptr() for v in Vs]) if Vs is not None else None
-    ldv = I(*[ld(v, v.shape[0]) for v in Vs]) if Vs is not None else None
-    o = make_opts(max_sweeps, path, nb, masking, precision, sweeps)
-    ws_bytes = lib().svdb_batched_workspace_size(code, bsz, ms, ns, C.byref(o))
-    if ws_bytes == C.c_size_t(-1).value:
-        raise SvdbError(-1, last_error() or "invalid arguments")
-    ws = torch.empty(max(ws_bytes, 1), dtype=torch.uint8, device=dev) if ws_bytes else None
-    st = (stream or torch.cuda.current_stream(dev)).cuda_stream
-    rc = lib().svdb_svd_batched(code, bsz, ms, ns, Ap, lda, Sp, Up, ldu, Vp, ldv, float(tol),
-                                info.data_ptr(), ws.data_ptr() if ws is not None else None,
-                                ws_bytes, C.byref(o), st)
-    if rc:
-        raise SvdbError(rc, last_error())
-    return Ss, Us, Vs, info, sweeps
+    call = BatchedCall(mats, tol, max_sweeps, compute_u, compute_v, masking, precision)
+    return call(stream)
 
 
 class Server:
