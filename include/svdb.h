@@ -79,9 +79,17 @@ typedef struct {
     int *sweeps;      /* optional DEVICE int[batch]: sweeps executed          */
     int waves;        /* SVDB_PATH_RESIDENT: wavefronts per matrix (1, 2, 4);
                          0 -> tuned                                           */
+    int precondition; /* QR pre-processing (SVDB_R64, n <= 64, m n <= 8192):
+                         A = Q R, the resident Jacobi on R^T, U = Q J, V from
+                         the Jacobi's left vectors.  -1 (default): on for the
+                         AUTO path where it applies; 0: off; 1: on for the
+                         AUTO and RESIDENT paths (SVDB_ERR_UNSUPPORTED where
+                         it does not apply).  The sweeps count is that of
+                         the iteration on R^T.                                */
 } svdb_opts_t;
 
-/* Fills *o with the defaults (AUTO path, 100 sweeps, masking on). */
+/* Fills *o with the defaults (AUTO path, 100 sweeps, masking on,
+ * precondition -1). */
 void svdb_opts_default(svdb_opts_t *o);
 
 /*

@@ -46,6 +46,7 @@ struct Plan {
     int path = SVDB_PATH_AUTO;
     int nb = 0;
     int threads = 0;
+    bool precond = false;   // QR pre-processing, resident Jacobi on R^T
 };
 
 svdb_opts_t resolve_opts(const svdb_opts_t *o)
@@ -72,8 +73,24 @@ int make_plan(svdb_dtype_t dt, int m, int n, const svdb_opts_t &o, Plan *p)
         return fail(SVDB_ERR_UNSUPPORTED, "precision must be 0 or 1");
     if (o.precision == 1 && dt != SVDB_R64)
         return fail(SVDB_ERR_UNSUPPORTED, "precision mode 1 needs SVDB_R64 input");
+    if (o.precondition < -1 || o.precondition > 1)
+        return fail(SVDB_ERR_UNSUPPORTED, "precondition must be -1, 0 or 1");
     int path = o.path;
     int rN = 0, rR = 0, rW = 0;
+    // QR preconditioning: AUTO (precondition -1 or 1) and RESIDENT (1)
+    const bool pc_ok = dt == SVDB_R64 && o.precision == 0 && svdb::precond_supported(m, n);
+    const bool pc_req = (path == SVDB_PATH_AUTO && o.precondition != 0) ||
+                        (path == SVDB_PATH_RESIDENT && o.precondition == 1);
+    if (pc_req && pc_ok) {
+        svdb::resident_config(n, n, o.waves, &rN, &rR, &rW);
+        p->path = SVDB_PATH_RESIDENT;
+        p->nb = 0;
+        p->threads = 64 * rW;
+        p->precond = true;
+        return 0;
+    }
+    if (o.precondition == 1 && (path == SVDB_PATH_AUTO || path == SVDB_PATH_RESIDENT))
+        return fail(SVDB_ERR_UNSUPPORTED, "QR preconditioning does not apply to this request");
     // the unblocked kernels are FP64 only; FP32 and the mixed mode use the block method
     const bool unblocked_ok = dt == SVDB_R64 && o.precision == 0;
     const bool res_ok = unblocked_ok && svdb::resident_config(m, n, o.waves, &rN, &rR, &rW);
@@ -125,6 +142,7 @@ void svdb_opts_default(svdb_opts_t *o)
     o->precision = 0;
     o->sweeps = nullptr;
     o->waves = 0;
+    o->precondition = -1;
 }
 
 const char *svdb_last_error(void) { return g_err.c_str(); }
@@ -154,6 +172,7 @@ size_t svdb_workspace_size(svdb_dtype_t dtype, int batch, int m, int n, const sv
     if (p.path == SVDB_PATH_BLOCKED)
         return svdb::blocked_workspace_bytes(batch, m, n, p.nb, elt_bytes(dtype),
                                              o.precision == 1);
+    if (p.precond) return svdb::precond_workspace_bytes(batch, m, n);
     return 0;
 }
 
@@ -196,7 +215,11 @@ int svdb_svd_strided_batched(svdb_dtype_t dtype, int batch, int m, int n, const 
     hipStream_t s = (hipStream_t)stream;
 
     hipError_t e = hipSuccess;
-    if (p.path == SVDB_PATH_RESIDENT) {
+    if (p.precond) {
+        e = svdb::launch_precond_d(batch, m, n, o.waves, (const double *)A, lda, strideA,
+                                   (double *)S, strideS, (double *)U, ldu, strideU, (double *)V,
+                                   ldv, strideV, tol, o.max_sweeps, info, o.sweeps, workspace, s);
+    } else if (p.path == SVDB_PATH_RESIDENT) {
         e = svdb::launch_resident_d(batch, m, n, o.waves, (const double *)A, lda, strideA,
                                     (double *)S,
                                     strideS, (double *)U, ldu, strideU, (double *)V, ldv,

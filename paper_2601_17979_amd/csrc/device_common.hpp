@@ -86,6 +86,16 @@ __device__ __forceinline__ double group_max(double v, int width)
 __device__ __forceinline__ double wave_sum(double v) { return group_sum(v, kWave); }
 __device__ __forceinline__ double wave_max(double v) { return group_max(v, kWave); }
 
+// Value of lane (x + ROR) mod 16 of the same row of 16 lanes (DPP row_ror).
+template <int ROR>
+__device__ __forceinline__ double row_ror16(double v)
+{
+    constexpr int ctrl = 0x120 + ROR;
+    const int lo = __builtin_amdgcn_update_dpp(0, __double2loint(v), ctrl, 0xF, 0xF, false);
+    const int hi = __builtin_amdgcn_update_dpp(0, __double2hiint(v), ctrl, 0xF, 0xF, false);
+    return __hiloint2double(hi, lo);
+}
+
 // Power-of-two scale that brings max|a| into [1, 2): multiplying by it is
 // exact, so the iteration on the scaled matrix is the iteration on A with
 // every quantity scaled by a power of two (no overflow in the Gram sums).

@@ -22,6 +22,14 @@ hipError_t launch_resident_d(int batch, int m, int n, int ns, const double *A, i
                              long long sU, double *V, int ldv, long long sV, double tol,
                              int max_sweeps, int *info, int *sweeps, hipStream_t stream);
 
+// qr.hip: QR preconditioning (A = Q R, the resident Jacobi on R^T, U = Q J).
+bool precond_supported(int m, int n);
+size_t precond_workspace_bytes(int batch, int m, int n);
+hipError_t launch_precond_d(int batch, int m, int n, int ns, const double *A, int lda,
+                            long long sA, double *S, long long sS, double *U, int ldu,
+                            long long sU, double *V, int ldv, long long sV, double tol,
+                            int max_sweeps, int *info, int *sweeps, void *ws, hipStream_t stream);
+
 // blocked.hip: block one-sided Jacobi with MFMA Gram/updates (real and
 // complex, FP64 and FP32, and FP32 sweeps followed by an FP64 refinement).
 // blocked_nb returns the block width for a request (0: not supported).

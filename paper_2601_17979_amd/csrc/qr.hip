@@ -1,0 +1,314 @@
+// qr.hip -- QR preconditioning of the one-sided Jacobi method for real FP64
+// matrices: the QR pre-processing of the section "Other Performance
+// Considerations" (subsection on pre-processing with a QR factorization),
+// with the iteration run on R^T rather than on R, the variant of Drmac and
+// Veselic that the same subsection cites for its faster convergence.
+//
+//   A = Q R                    Householder QR (qr_house_d), Q = H_0 ... H_{n-1}
+//   R^T = U_x diag(S) J^T      one-sided Jacobi on X = R^T (resident kernel):
+//                              U_x = X J diag(S)^-1, J the accumulated rotations
+//   A = (Q J) diag(S) U_x^T    so U = Q [J; 0] (apply_q_d) and V = U_x.
+//
+// The columns of R^T carry the row scaling of R, which is graded after the
+// QR step, so the iteration on R^T needs markedly fewer sweeps than on A for
+// graded or ill-conditioned matrices; for m > n every sweep is also cheaper
+// (n x n instead of m x n).
+//
+// Both kernels run one 256-thread workgroup per matrix (m <= 256, n <= 64,
+// m n <= 8192).
+#include <hip/hip_runtime.h>
+
+#include "device_common.hpp"
+#include "launchers.hpp"
+
+namespace svdb {
+
+namespace {
+
+constexpr int kQT = 256;
+constexpr int kQrMaxElems = 8192;   // m n doubles in LDS
+
+// Sum over a row of 16 lanes by DPP rotations 8, 4, 2, 1: every lane of the
+// row ends with the same bits.
+__device__ __forceinline__ double row_sum16(double v)
+{
+    v += row_ror16<8>(v);
+    v += row_ror16<4>(v);
+    v += row_ror16<2>(v);
+    v += row_ror16<1>(v);
+    return v;
+}
+
+// Layout of both kernels: the 256 threads form 16 groups of 16 lanes; group
+// g owns columns g, g + 16, ... (CPG of them) and lane x of a group holds
+// rows x, x + 16, ... (RPL of them) of its columns in registers, so column
+// dot products are 16-lane DPP reductions and up to 16 columns are in
+// flight at once.
+
+// Householder QR.  Column j's group forms the reflector (v_j(j) = 1, as in
+// LAPACK's xGEQRF) and publishes it in LDS; after one barrier every group
+// applies it to its own trailing columns.  A is pre-scaled by a power of two
+// (max |a| in [1, 2)) so that no square overflows.  Outputs: X = R^T
+// (unscaled, n x n), and for the application of Q the reflectors as full
+// columns V (m x n: zeros above the diagonal, ones on it) with tau.
+template <int RPL, int CPG>
+__global__ __launch_bounds__(kQT) void qr_house_d(int m, int n, const double *__restrict__ A,
+                                                  int lda, long long sA, double *X, double *Vq,
+                                                  double *tau_out)
+{
+    __shared__ double vbuf[2][16 * RPL];
+    __shared__ double s_tau[64];
+    __shared__ double s_max[kQT / 64];
+    __shared__ int s_bad[kQT / 64];
+    const int b = blockIdx.x, tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+    const int grp = tid >> 4, gl = tid & 15;
+    A += (size_t)b * sA;
+    double h[CPG][RPL];
+    double amax = 0.0;
+    int bad = 0;
+#pragma unroll
+    for (int c = 0; c < CPG; c++)
+#pragma unroll
+        for (int r = 0; r < RPL; r++) {
+            const int row = gl + 16 * r, col = grp + 16 * c;
+            const double a = (row < m && col < n) ? A[(size_t)col * lda + row] : 0.0;
+            bad |= !isfinite(a);
+            amax = fmax(amax, fabs(a));
+            h[c][r] = a;
+        }
+    amax = wave_max(amax);
+    bad = __any(bad);
+    if (lane == 0) {
+        s_max[wave] = amax;
+        s_bad[wave] = bad;
+    }
+    __syncthreads();
+    amax = fmax(fmax(s_max[0], s_max[1]), fmax(s_max[2], s_max[3]));
+    // a non-finite input turns X into NaN, which the Jacobi kernel reports
+    // (info 2)
+    const bool finite = !(s_bad[0] | s_bad[1] | s_bad[2] | s_bad[3]);
+    const double scale = finite ? pow2_scale(amax) : 1.0;
+#pragma unroll
+    for (int c = 0; c < CPG; c++)
+#pragma unroll
+        for (int r = 0; r < RPL; r++) h[c][r] *= scale;
+    for (int j = 0; j < n && finite; j++) {
+        double *vb = vbuf[j & 1];
+        if (grp == (j & 15)) {
+            const int cj = j >> 4;
+            double s = 0.0, a = 0.0;
+#pragma unroll
+            for (int r = 0; r < RPL; r++) {
+                const int row = gl + 16 * r;
+                const double x = h[cj][r];
+                s = row > j ? fma(x, x, s) : s;
+                a = row == j ? x : a;
+            }
+            s = row_sum16(s);
+            const double alpha = row_sum16(a);   // one nonzero term: exact
+            double beta = alpha, tau = 0.0, scal = 0.0;
+            if (s > 0.0) {
+                const double nrm = sqrt(fma(alpha, alpha, s));
+                beta = alpha >= 0.0 ? -nrm : nrm;
+                tau = (beta - alpha) / beta;
+                scal = 1.0 / (alpha - beta);
+            }
+#pragma unroll
+            for (int r = 0; r < RPL; r++) {
+                const int row = gl + 16 * r;
+                const double x = h[cj][r];
+                const double v = row == j ? 1.0 : (row > j ? x * scal : 0.0);
+                vb[row] = v;
+                h[cj][r] = row == j ? beta : (row > j ? v : x);
+            }
+            if (gl == 0) s_tau[j] = tau;
+        }
+        __syncthreads();
+        const double tau = s_tau[j];
+        if (tau != 0.0) {
+            double v[RPL];
+#pragma unroll
+            for (int r = 0; r < RPL; r++) v[r] = vb[gl + 16 * r];
+#pragma unroll
+            for (int c = 0; c < CPG; c++) {
+                const int col = grp + 16 * c;
+                if (col > j && col < n) {   // uniform in the group
+                    double w = 0.0;
+#pragma unroll
+                    for (int r = 0; r < RPL; r++) w = fma(v[r], h[c][r], w);
+                    w = row_sum16(w) * tau;
+#pragma unroll
+                    for (int r = 0; r < RPL; r++) h[c][r] = fma(-w, v[r], h[c][r]);
+                }
+            }
+        }
+    }
+    // X = R^T / scale: X(col, row) = R(row, col) for row <= col, zero above
+    // the diagonal of X; the reflectors as full columns
+    X += (size_t)b * n * n;
+    const double inv = 1.0 / scale;
+    if (Vq) Vq += (size_t)b * m * n;
+#pragma unroll
+    for (int c = 0; c < CPG; c++)
+#pragma unroll
+        for (int r = 0; r < RPL; r++) {
+            const int row = gl + 16 * r, col = grp + 16 * c;
+            if (col >= n || row >= m) continue;
+            const double x = h[c][r];
+            if (row < n)
+                X[(size_t)row * n + col] =
+                    !finite ? __builtin_nan("") : (row <= col ? x * inv : 0.0);
+            if (Vq)
+                Vq[(size_t)col * m + row] = row > col ? x : (row == col ? 1.0 : 0.0);
+        }
+    if (Vq && tid < n) tau_out[(size_t)b * n + tid] = finite ? s_tau[tid] : 0.0;
+}
+
+// U = Q [Y; 0] = H_0 ... H_{n-1} [Y; 0] (Y n x n, ld n), the reflectors
+// (full columns, in LDS) applied last to first to the register-held U; no
+// barrier after the reflectors are loaded.  Matrices with info 2
+// (non-finite input) are left untouched.
+template <int RPL, int CPG>
+__global__ __launch_bounds__(kQT) void apply_q_d(int m, int n, const double *__restrict__ Vq,
+                                                 const double *__restrict__ tau,
+                                                 const double *__restrict__ Y, double *U, int ldu,
+                                                 long long sU, const int *info)
+{
+    extern __shared__ double Vl[];   // m x n, ld m
+    __shared__ double s_tau[64];
+    const int b = blockIdx.x, tid = threadIdx.x;
+    const int grp = tid >> 4, gl = tid & 15;
+    if (info[b] == 2) return;
+    Vq += (size_t)b * m * n;
+    Y += (size_t)b * n * n;
+    U += (size_t)b * sU;
+    for (int idx = tid; idx < m * n; idx += kQT) Vl[idx] = Vq[idx];
+    if (tid < n) s_tau[tid] = tau[(size_t)b * n + tid];
+    double u[CPG][RPL];
+#pragma unroll
+    for (int c = 0; c < CPG; c++)
+#pragma unroll
+        for (int r = 0; r < RPL; r++) {
+            const int row = gl + 16 * r, col = grp + 16 * c;
+            u[c][r] = (row < n && col < n) ? Y[(size_t)col * n + row] : 0.0;
+        }
+    __syncthreads();
+    for (int j = n - 1; j >= 0; j--) {
+        const double t = s_tau[j];
+        if (t == 0.0) continue;
+        double v[RPL];
+#pragma unroll
+        for (int r = 0; r < RPL; r++) {
+            const int row = gl + 16 * r;
+            v[r] = row < m ? Vl[(size_t)j * m + row] : 0.0;
+        }
+#pragma unroll
+        for (int c = 0; c < CPG; c++) {
+            double w = 0.0;
+#pragma unroll
+            for (int r = 0; r < RPL; r++) w = fma(v[r], u[c][r], w);
+            w = row_sum16(w) * t;
+#pragma unroll
+            for (int r = 0; r < RPL; r++) u[c][r] = fma(-w, v[r], u[c][r]);
+        }
+    }
+#pragma unroll
+    for (int c = 0; c < CPG; c++)
+#pragma unroll
+        for (int r = 0; r < RPL; r++) {
+            const int row = gl + 16 * r, col = grp + 16 * c;
+            if (row < m && col < n) U[(size_t)col * ldu + row] = u[c][r];
+        }
+}
+
+// rows per lane (power of two) and columns per group for an m x n matrix
+bool qr_shape(int m, int n, int *rpl, int *cpg)
+{
+    const int r = (m + 15) / 16;
+    const int rp = r <= 1 ? 1 : r <= 2 ? 2 : r <= 4 ? 4 : r <= 8 ? 8 : r <= 16 ? 16 : 0;
+    const int cp = (n + 15) / 16;
+    if (!rp || cp < 1 || cp > 4) return false;
+    *rpl = rp;
+    *cpg = cp;
+    return true;
+}
+
+size_t al256(size_t x) { return (x + 255) & ~(size_t)255; }
+
+}  // namespace
+
+bool precond_supported(int m, int n)
+{
+    int N, R, NS, rpl, cpg;
+    return n >= 1 && m >= n && (size_t)m * n <= (size_t)kQrMaxElems && n <= 64 &&
+           qr_shape(m, n, &rpl, &cpg) && resident_config(n, n, 0, &N, &R, &NS);
+}
+
+size_t precond_workspace_bytes(int batch, int m, int n)
+{
+    // X = R^T, reflectors, tau, J (Jacobi V), and U_x when V is not wanted
+    return al256((size_t)batch * n * n * 8) + al256((size_t)batch * m * n * 8) +
+           al256((size_t)batch * n * 8) + 2 * al256((size_t)batch * n * n * 8);
+}
+
+hipError_t launch_precond_d(int batch, int m, int n, int ns, const double *A, int lda,
+                            long long sA, double *S, long long sS, double *U, int ldu,
+                            long long sU, double *V, int ldv, long long sV, double tol,
+                            int max_sweeps, int *info, int *sweeps, void *ws, hipStream_t stream)
+{
+    int rpl, cpg;
+    if (!qr_shape(m, n, &rpl, &cpg)) return hipErrorInvalidValue;
+    char *p = (char *)ws;
+    double *X = (double *)p;
+    p += al256((size_t)batch * n * n * 8);
+    double *Vq = (double *)p;
+    p += al256((size_t)batch * m * n * 8);
+    double *tau = (double *)p;
+    p += al256((size_t)batch * n * 8);
+    double *J = (double *)p;
+    p += al256((size_t)batch * n * n * 8);
+    double *Ux = (double *)p;
+    double *vq = U ? Vq : nullptr;
+#define SVDB_QR(RP, CP)                                                                        \
+    if (rpl == RP && cpg == CP)                                                                \
+        hipLaunchKernelGGL((qr_house_d<RP, CP>), dim3(batch), dim3(kQT), 0, stream, m, n, A,   \
+                           lda, sA, X, vq, tau);
+#define SVDB_QR_ROW(RP) SVDB_QR(RP, 1) SVDB_QR(RP, 2) SVDB_QR(RP, 3) SVDB_QR(RP, 4)
+    SVDB_QR_ROW(1)
+    SVDB_QR_ROW(2)
+    SVDB_QR_ROW(4)
+    SVDB_QR_ROW(8)
+    SVDB_QR_ROW(16)
+#undef SVDB_QR_ROW
+#undef SVDB_QR
+    hipError_t e = hipGetLastError();
+    if (e != hipSuccess) return e;
+    // Jacobi on X = R^T: its U is our V, its V (the rotations J) feeds U
+    double *vx = V ? V : Ux;
+    const int ldvx = V ? ldv : n;
+    const long long svx = V ? sV : (long long)n * n;
+    e = launch_resident_d(batch, n, n, ns, X, n, (long long)n * n, S, sS, vx, ldvx, svx,
+                          U ? J : nullptr, n, (long long)n * n, tol, max_sweeps, info, sweeps,
+                          stream);
+    if (e != hipSuccess) return e;
+    if (U) {
+        const size_t lds = (size_t)m * n * sizeof(double);
+#define SVDB_AQ(RP, CP)                                                                        \
+    if (rpl == RP && cpg == CP)                                                                \
+        hipLaunchKernelGGL((apply_q_d<RP, CP>), dim3(batch), dim3(kQT), lds, stream, m, n,     \
+                           (const double *)Vq, (const double *)tau, (const double *)J, U, ldu,  \
+                           sU, (const int *)info);
+#define SVDB_AQ_ROW(RP) SVDB_AQ(RP, 1) SVDB_AQ(RP, 2) SVDB_AQ(RP, 3) SVDB_AQ(RP, 4)
+        SVDB_AQ_ROW(1)
+        SVDB_AQ_ROW(2)
+        SVDB_AQ_ROW(4)
+        SVDB_AQ_ROW(8)
+        SVDB_AQ_ROW(16)
+#undef SVDB_AQ_ROW
+#undef SVDB_AQ
+        e = hipGetLastError();
+    }
+    return e;
+}
+
+}  // namespace svdb

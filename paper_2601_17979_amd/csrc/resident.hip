@@ -42,6 +42,10 @@ namespace svdb {
 
 namespace {
 
+// Squared column norm below which a column of the pre-scaled matrix counts
+// as zero (see the fold at the sweep start).
+constexpr double kNegligible = 0x1p-960;
+
 // ---- cross-lane helpers (gfx950) ------------------------------------------
 
 __device__ __forceinline__ void swap32(double &a, double &b)
@@ -297,12 +301,31 @@ __global__ __launch_bounds__(64 * NS, res_waves_per_eu(N, RW, NS)) void resident
             }
             const double nt = reduce_pairs<KG, OpSum>(pt, buf);
             const double nb = reduce_pairs<KG, OpSum>(pb, buf);
+            // a column whose squared norm is below kNegligible (a norm below
+            // 2^-480 of the pre-scaled matrix, whose largest entry is about
+            // 1) is set to zero in W: rotating it further would only push
+            // rounding noise towards underflow
+            int dead = 0;
             if (x < Q) {
                 const int c = 2 * (q0 + qloc);
-                sh.nrm[c] = nt;
-                sh.nrm[c + 1] = nb;
+                const bool zt = nt < kNegligible, zb = nb < kNegligible;
+                dead = (zt && nt != 0.0) || (zb && nb != 0.0);
+                sh.nrm[c] = zt ? 0.0 : nt;
+                sh.nrm[c + 1] = zb ? 0.0 : nb;
                 sh.d[c] = 1.0;
                 sh.d[c + 1] = 1.0;
+            }
+            if (__any(dead)) {
+                wave_sync_lds();
+#pragma unroll
+                for (int q = 0; q < KG; q++) {
+                    const double2 nn = *reinterpret_cast<const double2 *>(&sh.nrm[2 * (q0 + q)]);
+#pragma unroll
+                    for (int t = 0; t < RW; t++) {
+                        T[q][t] = nn.x == 0.0 ? 0.0 : T[q][t];
+                        B[q][t] = nn.y == 0.0 ? 0.0 : B[q][t];
+                    }
+                }
             }
             __syncthreads();
         }
@@ -331,7 +354,7 @@ __global__ __launch_bounds__(64 * NS, res_waves_per_eu(N, RW, NS)) void resident
             // |g_ij| >= tol sqrt(g_ii) sqrt(g_jj), squared unless the product
             // of the norms would underflow
             const double pij = gi * gj;
-            const bool rot = (gam != 0.0) &&
+            const bool rot = (gam != 0.0) && gi >= kNegligible && gj >= kNegligible &&
                              (pij > 1e-250 ? ag * ag >= tol2 * pij : ag >= tol * sqrt(gi) * sqrt(gj));
             double mut = 0.0, mub = 0.0;
             if (rot) {

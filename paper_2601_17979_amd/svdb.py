@@ -29,7 +29,7 @@ _PATHS = {"auto": PATH_AUTO, "plain": PATH_PLAIN, "resident": PATH_RESIDENT,
 class Opts(C.Structure):
     _fields_ = [("max_sweeps", C.c_int), ("path", C.c_int), ("nb", C.c_int),
                 ("masking", C.c_int), ("precision", C.c_int), ("sweeps", C.c_void_p),
-                ("waves", C.c_int)]
+                ("waves", C.c_int), ("precondition", C.c_int)]
 
 
 class SvdbError(RuntimeError):
@@ -95,7 +95,7 @@ def version() -> str:
 
 
 def make_opts(max_sweeps=100, path="auto", nb=0, masking=True, precision=0, sweeps=None,
-              waves=0):
+              waves=0, precondition=-1):
     o = Opts()
     lib().svdb_opts_default(C.byref(o))
     o.max_sweeps = int(max_sweeps)
@@ -105,6 +105,7 @@ def make_opts(max_sweeps=100, path="auto", nb=0, masking=True, precision=0, swee
     o.precision = int(precision)
     o.sweeps = sweeps.data_ptr() if sweeps is not None else None
     o.waves = int(waves)
+    o.precondition = int(precondition)
     return o
 
 
@@ -146,7 +147,8 @@ def _check_cm(x: torch.Tensor, name: str):
 
 def svd(A: torch.Tensor, tol: float = 0.0, max_sweeps: int = 100, path="auto", nb: int = 0,
         compute_u: bool = True, compute_v: bool = True, masking: bool = True,
-        precision: int = 0, want_sweeps: bool = True, stream=None, out=None, waves: int = 0):
+        precision: int = 0, want_sweeps: bool = True, stream=None, out=None, waves: int = 0,
+        precondition: int = -1):
     """Batched reduced SVD of a (batch, m, n) column-major GPU tensor (m >= n).
 
     Returns (S, U, V, info, sweeps); U/V are None when not requested, sweeps
@@ -165,7 +167,7 @@ def svd(A: torch.Tensor, tol: float = 0.0, max_sweeps: int = 100, path="auto", n
         V = empty_col_major(b, n, n, A.dtype, dev) if compute_v else None
         info = torch.empty(b, dtype=torch.int32, device=dev)
         sweeps = torch.empty(b, dtype=torch.int32, device=dev) if want_sweeps else None
-    o = make_opts(max_sweeps, path, nb, masking, precision, sweeps, waves)
+    o = make_opts(max_sweeps, path, nb, masking, precision, sweeps, waves, precondition)
     ws_bytes = lib().svdb_workspace_size(code, b, m, n, C.byref(o))
     if ws_bytes == C.c_size_t(-1).value:
         raise SvdbError(-1, last_error() or "invalid arguments")
