@@ -1,15 +1,16 @@
 /*
  * svdb.h -- C ABI of the MI355X batched one-sided Jacobi SVD library.
  *
- * Problem (paper Sec. 1, eq. "svd"): for each m x n matrix A of a batch, with
+ * Problem (section "Computing the Singular Value Decomposition", eq. svd): for each m x n matrix A of a batch, with
  * m >= n, compute the reduced SVD A = U diag(S) V^H: U is m x n with
  * orthonormal columns, V is n x n unitary, S is real, non-negative and sorted
- * in descending order (Alg. 2, last step; accuracy check T4 in Sec. 4.5).
+ * in descending order (Alg. 2, last step; accuracy check T4 of "Performance of the Baseline
+ * Implementation").
  * The method is the one-sided (Hestenes) Jacobi iteration of Alg. 2 with the
- * rotation of eq. (sin-cos), the round-robin parallel ordering of Sec. 2/4.1,
- * and, for wider matrices, the block method of Sec. 3 (eq. block-gram,
- * eq. right-sv) with a one-sweep inner eigensolver (Sec. 5) and batch masks
- * (Sec. 7).
+ * rotation of eq. (sin-cos), the round-robin parallel ordering (Fig. "rr"),
+ * and, for wider matrices, the block method (eq. block-gram,
+ * eq. right-sv) with a one-sweep inner eigensolver ("Inexact Hermitian
+ * Eigendecomposition") and batch masks ("Masked Batch Operations").
  *
  * Conventions for every entry point:
  *  - Matrices are column major (LAPACK style) with a leading dimension.
@@ -32,7 +33,7 @@
  *  - `tol` is the rotation threshold k*u of Alg. 2: the pair (i, j) is
  *    rotated iff g_ij != 0 and |g_ij| >= tol * sqrt(g_ii) * sqrt(g_jj).
  *    tol <= 0 selects 30 u of the working precision (the paper's k = 30,
- *    Sec. 4.5 / 8.1).
+ *    "Performance of the Baseline Implementation", "Numerical Accuracy").
  */
 #ifndef SVDB_H
 #define SVDB_H
@@ -60,7 +61,7 @@ typedef enum {
     SVDB_PATH_PLAIN = 1,     /* LDS-resident unblocked kernel, one workgroup
                                 per matrix (the plain GPU Jacobi)           */
     SVDB_PATH_RESIDENT = 2,  /* register-resident unblocked kernel (Alg. 2) */
-    SVDB_PATH_BLOCKED = 3    /* block method (Sec. 3-7) with MFMA Gram and
+    SVDB_PATH_BLOCKED = 3    /* block method (eq. block-gram) with MFMA Gram and
                                 updates                                     */
 } svdb_path_t;
 
@@ -71,7 +72,8 @@ typedef struct {
     int max_sweeps;   /* cap on sweeps (Alg. 2 max_nsweeps); <= 0 -> 100       */
     int path;         /* svdb_path_t                                          */
     int nb;           /* block width for SVDB_PATH_BLOCKED; 0 -> tuned         */
-    int masking;      /* blocked path: skip converged matrices (Sec. 7);
+    int masking;      /* blocked path: skip converged matrices ("Masked
+                         Batch Operations");
                          < 0 -> default (on)                                   */
     int precision;    /* 0: sweeps in the working precision; 1: FP32 sweeps
                          then FP64 refinement (SVDB_R64, block method; the
@@ -129,7 +131,7 @@ int svdb_svd_strided_batched(svdb_dtype_t dtype, int batch, int m, int n,
  * Mixed-shape batch (uneven batching): host arrays m[b], n[b], lda[b],
  * ldu[b], ldv[b] and host arrays of device pointers A[b], S[b], U[b], V[b]
  * (U or V may be NULL as a whole).  Requires m[b] >= n[b] >= 0; A[b] is
- * not modified.  Every matrix runs the block method (Sec. 3-7, nb = 16, any
+ * not modified.  Every matrix runs the block method (eq. block-gram, nb = 16, any
  * dtype) on its own round-robin schedule over l_b = n_b / 16 (rounded up to
  * even) block columns: one launch per round-robin step covers the block
  * pairs of every unconverged matrix of the batch, and a small matrix
@@ -175,8 +177,9 @@ int svdb_plan(svdb_dtype_t dtype, int m, int n, const svdb_opts_t *opts,
  * copies of A and V ((m np + np^2) elements, np = n rounded up to an even
  * number of 16-column blocks).  A request leaves as soon as it has
  * converged (or reached opts->max_sweeps), so new requests take its place
- * between any two launches: the paper's masks (Sec. 7) retire converged
- * matrices inside a static batch, the server also refills the batch.
+ * between any two launches: the paper's masks ("Masked Batch Operations")
+ * retire converged matrices inside a static batch, the server also refills
+ * the batch.
  *
  *  svdb_server_create: opts may be NULL (defaults; precision must be 0).
  *     Returns 0, -k for invalid argument k, SVDB_ERR_HIP.

@@ -14,15 +14,16 @@
  * the precision of the caller's data; the caller up-casts FP32 inputs.
  *
  * Functions and the passages they follow:
- *   oracle_round_robin    Sec. 2 (parallel orderings, Brent-Luk round robin,
- *                         Fig. "rr"; pinned by the worked example in Sec. 5.1)
- *   oracle_row_cyclic     Sec. 2 (row-cyclic ordering, Forsythe-Henrici)
+ *   oracle_round_robin    "Algorithmic Background" (parallel orderings, Brent-Luk round robin,
+ *                         Fig. "rr"; pinned by the worked example of "Inexact Hermitian
+ *                         Eigendecomposition", subsection "Motivation")
+ *   oracle_row_cyclic     "Algorithmic Background" (row-cyclic ordering, Forsythe-Henrici)
  *   oracle_gesvj_d/_z     Alg. 2 (unblocked one-sided Jacobi SVD) with the
  *                         rotation of eq. (sin-cos) in its 2x2 form,
  *                         eq. (background-svd-jacobi)
  *   oracle_heevj_z        Alg. 1 (two-sided Jacobi Hermitian eigensolver)
- *   oracle_block_iter_z   Sec. 3 block method, eqs. (block-gram), (right-sv);
- *                         Sec. 4 steps S1-S5; Sec. 5 inexact inner solve
+ *   oracle_block_iter_z   "Algorithmic Background" block method, eqs. (block-gram), (right-sv);
+ *                         "Initial Design" steps S1-S5; "Inexact Hermitian Eigendecomposition" inner solve
  *   oracle_block_gesvj_z  the blocked solver built from the above
  *
  * Readings of the paper taken here (each is also listed in the design notes):
@@ -400,7 +401,7 @@ int oracle_gesvj_z(int m, int n, const zc *A, int lda, double tol,
  * G: n x n Hermitian (column major, ldg = n), overwritten by J^H G J.
  * J: n x n, set to the accumulated product of the rotations.
  * order: 0 row-cyclic, 1 round robin (the order used by the paper's batch
- * eigensolver, Sec. 4 "Hermitian Eigenvalue Problem").  Runs at most
+ * eigensolver, "Initial Design", subsection "Hermitian Eigenvalue Problem").  Runs at most
  * max_sweeps sweeps.  Returns the number of rotations applied; *sweeps_out
  * receives the sweeps executed and *conv_out whether the last sweep applied
  * no rotation.
@@ -457,7 +458,8 @@ long oracle_heevj_z(int n, zc *G, zc *J, double tol, int max_sweeps, int order,
 }
 
 /* ------------------------------------------------------------------ */
-/* Block one-sided Jacobi (Sec. 3 and 4, inexact inner solve Sec. 5)   */
+/* Block one-sided Jacobi ("Algorithmic Background", "Initial Design";  */
+/* inexact inner solve: "Inexact Hermitian Eigendecomposition")          */
 /* ------------------------------------------------------------------ */
 
 /*
@@ -560,7 +562,7 @@ int oracle_block_gesvj_z(int m, int n, int nb, const zc *A, int lda, double tol,
 
 /* ------------------------------------------------------------------ */
 /* Batch drivers: OpenMP parallel for over the batch (the paper's CPU    */
-/* baseline pattern, Sec. 8.2), one matrix per thread at a time.        */
+/* baseline pattern, "Comparison with Existing Batch SVD Solvers"), one matrix per thread at a time.        */
 /* ------------------------------------------------------------------ */
 
 int oracle_num_threads(void)

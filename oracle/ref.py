@@ -18,12 +18,13 @@ _HERE = os.path.dirname(os.path.abspath(__file__))
 _SRC = os.path.join(_HERE, "jacobi_ref.c")
 _LIB = os.path.join(_HERE, "libjacobi_ref.so")
 
-EPS64 = 2.0 ** -53          # unit roundoff u of FP64 (Sec. 2, u = 2^-s)
+EPS64 = 2.0 ** -53          # unit roundoff u of FP64 ("Algorithmic Background", u = 2^-s)
 EPS32 = 2.0 ** -24
 
 
 def default_tol(dtype) -> float:
-    """k*u with k = 30, the paper's test threshold (Sec. 4.5 and 8.1)."""
+    """k*u with k = 30, the paper's test threshold (subsections "Performance of the
+    Baseline Implementation" and "Numerical Accuracy")."""
     return 30.0 * (EPS32 if np.dtype(dtype) in (np.float32, np.complex64) else EPS64)
 
 
@@ -186,7 +187,8 @@ def block_iter(W, V, l, nb, it, tol=None, inner_sweeps=1):
 
 
 def block_gesvj(A, nb, tol=None, max_sweeps=100, inner_sweeps=1):
-    """Blocked one-sided Jacobi (Sec. 3-5).  Returns (S, U, V, sweeps, info);
+    """Blocked one-sided Jacobi ("Algorithmic Background" to "Inexact Hermitian
+    Eigendecomposition").  Returns (S, U, V, sweeps, info);
     U and V are real when A is real."""
     A = np.asarray(A)
     m, n = A.shape

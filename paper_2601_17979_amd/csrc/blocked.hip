@@ -1,12 +1,14 @@
-// blocked.hip -- the block one-sided Jacobi SVD (Sec. 3, eq. block-gram and
-// eq. right-sv) with a one-sweep inner eigensolver (Sec. 5, "Design 2"),
-// fused vector updates (Sec. 6) and batch masks (Sec. 7), for real and
+// blocked.hip -- the block one-sided Jacobi SVD (section "Algorithmic
+// Background", eq. block-gram and eq. right-sv) with a one-sweep inner
+// eigensolver ("Inexact Hermitian Eigendecomposition", Design 2), fused
+// vector updates ("Optimized Vector Updates", Alg. 3) and batch masks
+// ("Masked Batch Operations"), for real and
 // complex matrices in FP64 or FP32 working precision, plus the mixed mode
 // (FP32 sweeps, FP64 refinement) for real FP64 input.
 //
 // Working storage (device workspace, column major): W (m x np) starts as the
 // pre-scaled A, V (np x np) as I; np = l nb with l even.  A sweep is l - 1
-// round-robin iterations (Sec. 4.1) over block columns; each iteration is one
+// round-robin iterations ("Parallel Ordering") over block columns; each iteration is one
 // launch of blk_iter with one workgroup per (block pair, matrix):
 //   1. G = [W_p W_q]^H [W_p W_q] (2nb x 2nb) on the matrix cores (FP64 MFMA,
 //      or FP32 MFMA with FP32 accumulation), streaming the pair's rows
@@ -20,7 +22,7 @@
 //      cores (complex: [Xr Xi] [[Jr, Ji], [-Ji, Jr]]), reading every element
 //      once and writing it once.
 // A matrix whose inner solves applied no rotation during a whole sweep has
-// orthogonal columns.  With masking (Sec. 7) it is retired at once and
+// orthogonal columns.  With masking ("Masked Batch Operations") it is retired at once and
 // skipped by every later launch; without, it keeps being swept until the
 // whole batch has converged.  blk_finalize forms sigma (FP64 sums), U and the
 // sorted outputs.

@@ -12,7 +12,8 @@ namespace svdb {
 constexpr int kWave = 64;
 
 // ---------------------------------------------------------------------------
-// Round-robin parallel ordering (Sec. 2 and 4.1, Brent-Luk).
+// Round-robin parallel ordering ("Algorithmic Background", Fig. "rr"; "Initial
+// Design", subsection "Parallel Ordering"; Brent-Luk).
 //
 // l (even) indices sit at a two-row table; pair q of an iteration is
 // (top seat q, bottom seat q).  Top seat 0 never moves; the other 2k-1 seats

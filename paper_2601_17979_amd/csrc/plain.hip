@@ -1,6 +1,6 @@
 // plain.hip -- the plain GPU Jacobi: unblocked one-sided Jacobi SVD (Alg. 2)
 // with the whole matrix W (m x n) and V (n x n) resident in LDS, one
-// 256-thread workgroup per matrix, round-robin pairs (Sec. 2), FP64.
+// 256-thread workgroup per matrix, round-robin pairs ("Algorithmic Background"), FP64.
 //
 // This kernel is the simple reference point of the library's fast paths: it
 // is written for clarity and is not tuned.  Every round-robin iteration

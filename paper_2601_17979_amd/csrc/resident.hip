@@ -6,7 +6,8 @@
 // row 64 t + L of W in slot t < RW and row L of V in slot RW.  N is n rounded
 // up to 16, 32 or 64 (extra columns are zero and never rotate).
 //
-// Ordering.  The round-robin ordering of Sec. 2 / 4.1 is a tournament table
+// Ordering.  The round-robin ordering (Fig. "rr"; "Parallel Ordering") is a
+// tournament table
 // of K = N/2 seats per row: top seat q plays bottom seat q.  Between
 // iterations every column except the one in top seat 0 moves one position
 // around the ring top 1 .. top K-1, bottom K-1 .. bottom 0.  The seats are

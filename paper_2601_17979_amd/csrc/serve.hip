@@ -13,9 +13,9 @@
 //   3. collect the requests that stopped sweeping (converged, or capped at
 //      max_sweeps), finalise them into the caller's buffers, free their
 //      slots and arena ranges, and report completion times.
-// The paper's batches are static (Sec. 7 masks converged matrices but keeps
-// the batch); retiring them and admitting new work in their place is what
-// a serving workload needs.
+// The paper's batches are static (its masks, section "Masked Batch
+// Operations", retire converged matrices but keep the batch); retiring them
+// and admitting new work in their place is what a serving workload needs.
 #include <hip/hip_runtime.h>
 
 #include <chrono>

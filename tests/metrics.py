@@ -3,7 +3,7 @@
 The tolerances of the build: normwise sigma error max_i |s_i - s_i^ref| / s_1^ref
 <= 1e-12 (FP64) / 1e-5 (FP32); ||A - U S V^H||_F / ||A||_F <= 1e-13 n and
 ||U^H U - I||_F, ||V^H V - I||_F <= 1e-13 n (FP64); FP32 uses 30 u_32 n.
-The paper's e1-e4 (Sec. 8.1) are computed for reporting.
+The paper's e1-e4 (subsection "Numerical Accuracy") are computed for reporting.
 """
 import numpy as np
 
@@ -32,7 +32,7 @@ def orth_err(Q):
 
 
 def paper_errors(A, S, U, V, Sref):
-    """e1..e4 of Sec. 8.1 (1-norms)."""
+    """e1..e4 of the subsection "Numerical Accuracy" (1-norms)."""
     m, n = A.shape
     e1 = np.linalg.norm(A - (U * S) @ V.conj().T, 1) / (n * max(np.linalg.norm(A, 1), 1e-300))
     e2 = np.linalg.norm(np.eye(n) - U.conj().T @ U, 1) / m

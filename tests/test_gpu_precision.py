@@ -96,7 +96,7 @@ def test_precision_edge_cases(mode):
 
 def test_masking_off_gives_the_same_result():
     """Without masks a converged matrix keeps being swept, but its inner
-    solves rotate nothing, so every output is bitwise the same (Sec. 7)."""
+    solves rotate nothing, so every output is bitwise the same (section "Masked Batch Operations")."""
     A = _batch((96, 80), 8, seed=6200)
     S1, U1, V1, i1, s1 = run_gpu(A, path="blocked", masking=True)
     S0, U0, V0, i0, s0 = run_gpu(A, path="blocked", masking=False)

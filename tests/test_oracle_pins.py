@@ -129,7 +129,7 @@ def _load_golden(name):
 # ---------------------------------------------------------------------------
 
 def pin_round_robin_valid():
-    """Sec. 2 / Sec. 4: a sweep is l-1 iterations of l/2 disjoint pairs that
+    """Round robin ("Algorithmic Background", "Parallel Ordering"): a sweep is l-1 iterations of l/2 disjoint pairs that
     together cover every pair exactly once."""
     for l in list(range(2, 40, 2)) + [64, 128, 256]:
         rr = oracle.round_robin(l)
@@ -145,7 +145,8 @@ def pin_round_robin_valid():
 
 
 def pin_round_robin_worked_example():
-    """Sec. 5.1: with four block columns the first iteration pairs blocks
+    """Worked example ("Inexact Hermitian Eigendecomposition", "Motivation"):
+    with four block columns the first iteration pairs blocks
     (1,2),(3,4) and the second (1,4),(2,3)."""
     rr = oracle.round_robin(4)
     assert sorted(map(tuple, rr[0].tolist())) == [(0, 1), (2, 3)]
@@ -280,7 +281,8 @@ def pin_numpy_svd(complex_):
 
 
 def pin_worked_example():
-    """Sec. 5.1 worked example: block size 2 on the printed 8 x 8 matrix.
+    """Worked example of "Inexact Hermitian Eigendecomposition", subsection
+    "Motivation": block size 2 on the printed 8 x 8 matrix.
     With the inner eigensolver run to convergence in round-robin order and the
     eigenvectors left unsorted, the first two round-robin iterations reproduce
     the printed [A_1 A_2] and G_{1,2} (to the four printed decimals, allowing

@@ -9,7 +9,7 @@ numpy's SeedSequence, so a matrix is identical whether it is drawn alone or as
 part of any batch.
 
 Singular-value families follow the paper's accuracy table (Table "svd_dist",
-Sec. 8.1): random, arith, cluster0, cluster1, logrand, geo; `logu` is a
+section "Numerical Accuracy"): random, arith, cluster0, cluster1, logrand, geo; `logu` is a
 log-uniform spectrum on an interval [lo, hi].
 """
 from __future__ import annotations
@@ -78,7 +78,8 @@ def gaussian(rng: np.random.Generator, m: int, n: int, complex_: bool = False) -
 
 
 def uniform01(rng: np.random.Generator, m: int, n: int) -> np.ndarray:
-    """Uniform [0, 1) entries, the paper's `random` family (Sec. 4.5)."""
+    """Uniform [0, 1) entries, the paper's `random` family (subsection "Performance of the Baseline
+    Implementation")."""
     return rng.uniform(0.0, 1.0, (m, n))
 
 
