@@ -29,22 +29,21 @@ WORKLOAD = ("10000 FP64 SVDs (S,U,V): 5000 x 64x64 + 5000 x 128x32, half geometr
 FP64_VALU_PEAK = 256 * 4 * 16 * 2 * 2.4e9      # CUs x SIMDs x lanes x FMA x clock
 
 
-def measured_traffic(path: str, shape: str):
-    """HBM bytes per launch from the committed rocprofv3 summary, or None when
-    the kernel source has changed since the counters were taken."""
+def measured_traffic(shape: str):
+    """HBM bytes of one QR-preconditioned call of this shape (QR + Jacobi on
+    R^T + applying Q) from the committed rocprofv3 summary, or None when a
+    kernel source has changed since the counters were taken."""
     import hashlib
-    if path not in ("auto", "resident"):
-        return None
-    prof = os.path.join(ROOT, "profiles", "resident_mixed_64x64_128x32_traffic.json")
-    src = os.path.join(ROOT, "paper_2601_17979_amd", "csrc", "resident.hip")
+    prof = os.path.join(ROOT, "profiles", "precond_mixed_64x64_128x32_traffic.json")
     try:
         rec = json.load(open(prof))
-        sha = hashlib.sha256(open(src, "rb").read()).hexdigest()
-    except OSError:
+        for src, sha in rec["kernel_source_sha256"].items():
+            if hashlib.sha256(open(os.path.join(ROOT, src), "rb").read()).hexdigest() != sha:
+                return None
+    except (OSError, KeyError, ValueError):
         return None
-    if rec.get("kernel_source_sha256") != sha or shape not in rec.get("launches", {}):
-        return None
-    return rec["launches"][shape]["traffic_bytes"]
+    call = rec.get("calls", {}).get(shape)
+    return call["traffic_bytes"] if call else None
 
 
 def flops_unblocked(m, n, sweeps):
@@ -367,7 +366,7 @@ def main():
     achieved = fl / (per_kernel[kdom] * 1e-3)
     roofline = {"bound": "alu", "achieved": achieved / 1e12, "peak": FP64_VALU_PEAK / 1e12,
                 "unit": "TFLOP/s", "frac": achieved / FP64_VALU_PEAK,
-                "traffic": None if precond else measured_traffic(args.path, f"{gd.m}x{gd.n}"),
+                "traffic": measured_traffic(f"{gd.m}x{gd.n}") if precond else None,
                 "kernel": f"{gd.m}x{gd.n} call" + (" (QR + Jacobi on R^T + apply Q)"
                                                    if precond else " (resident Jacobi)"),
                 "kernel_ms": per_kernel[kdom], "flops_per_launch": fl}
