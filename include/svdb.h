@@ -81,13 +81,15 @@ typedef struct {
     int *sweeps;      /* optional DEVICE int[batch]: sweeps executed          */
     int waves;        /* SVDB_PATH_RESIDENT: wavefronts per matrix (1, 2, 4);
                          0 -> tuned                                           */
-    int precondition; /* QR pre-processing (SVDB_R64, n <= 64, m n <= 8192):
-                         A = Q R, the resident Jacobi on R^T, U = Q J, V from
-                         the Jacobi's left vectors.  -1 (default): on for the
-                         AUTO path where it applies; 0: off; 1: on for the
-                         AUTO and RESIDENT paths (SVDB_ERR_UNSUPPORTED where
-                         it does not apply).  The sweeps count is that of
-                         the iteration on R^T.                                */
+    int precondition; /* QR pre-processing of real FP64 matrices: A = Q R,
+                         the Jacobi iteration on R^T, U = Q J, V from the
+                         iteration's left vectors.  n <= 64 (m n <= 8192):
+                         the resident kernel on R^T; n > 64 (m <= 1024): the
+                         block method on R^T.  -1 (default): on for the AUTO
+                         path where it applies; 0: off; 1: on (AUTO,
+                         RESIDENT or BLOCKED path; SVDB_ERR_UNSUPPORTED
+                         where it does not apply).  The sweeps count is that
+                         of the iteration on R^T.                            */
 } svdb_opts_t;
 
 /* Fills *o with the defaults (AUTO path, 100 sweeps, masking on,

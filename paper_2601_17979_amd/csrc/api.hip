@@ -47,6 +47,7 @@ struct Plan {
     int nb = 0;
     int threads = 0;
     bool precond = false;   // QR pre-processing, resident Jacobi on R^T
+    bool precond_big = false;   // QR pre-processing, block Jacobi on R^T
 };
 
 svdb_opts_t resolve_opts(const svdb_opts_t *o)
@@ -89,7 +90,21 @@ int make_plan(svdb_dtype_t dt, int m, int n, const svdb_opts_t &o, Plan *p)
         p->precond = true;
         return 0;
     }
-    if (o.precondition == 1 && (path == SVDB_PATH_AUTO || path == SVDB_PATH_RESIDENT))
+    // wide matrices: the block Jacobi on R^T (AUTO, or BLOCKED with 1)
+    const bool pcb_ok = dt == SVDB_R64 && o.precision == 0 && !pc_ok &&
+                        svdb::precond_big_supported(m, n);
+    const bool pcb_req = (path == SVDB_PATH_AUTO && o.precondition != 0) ||
+                         (path == SVDB_PATH_BLOCKED && o.precondition == 1);
+    if (pcb_req && pcb_ok) {
+        const int nb = svdb::blocked_nb(n, n, o.nb, false);
+        if (!nb) return fail(SVDB_ERR_UNSUPPORTED, "blocked path: nb must be 16 or 32");
+        p->path = SVDB_PATH_BLOCKED;
+        p->nb = nb;
+        p->threads = 256;
+        p->precond_big = true;
+        return 0;
+    }
+    if (o.precondition == 1)
         return fail(SVDB_ERR_UNSUPPORTED, "QR preconditioning does not apply to this request");
     // the unblocked kernels are FP64 only; FP32 and the mixed mode use the block method
     const bool unblocked_ok = dt == SVDB_R64 && o.precision == 0;
@@ -169,10 +184,11 @@ size_t svdb_workspace_size(svdb_dtype_t dtype, int batch, int m, int n, const sv
     svdb_opts_t o = resolve_opts(opts);
     Plan p;
     if (make_plan(dtype, m, n, o, &p)) return (size_t)-1;
+    if (p.precond) return svdb::precond_workspace_bytes(batch, m, n);
+    if (p.precond_big) return svdb::precond_big_workspace_bytes(batch, m, n, p.nb);
     if (p.path == SVDB_PATH_BLOCKED)
         return svdb::blocked_workspace_bytes(batch, m, n, p.nb, elt_bytes(dtype),
                                              o.precision == 1);
-    if (p.precond) return svdb::precond_workspace_bytes(batch, m, n);
     return 0;
 }
 
@@ -215,7 +231,12 @@ int svdb_svd_strided_batched(svdb_dtype_t dtype, int batch, int m, int n, const 
     hipStream_t s = (hipStream_t)stream;
 
     hipError_t e = hipSuccess;
-    if (p.precond) {
+    if (p.precond_big) {
+        e = svdb::launch_precond_big_d(batch, m, n, p.nb, (const double *)A, lda, strideA,
+                                       (double *)S, strideS, (double *)U, ldu, strideU,
+                                       (double *)V, ldv, strideV, tol, o.max_sweeps, o.masking,
+                                       info, o.sweeps, workspace, s);
+    } else if (p.precond) {
         e = svdb::launch_precond_d(batch, m, n, o.waves, (const double *)A, lda, strideA,
                                    (double *)S, strideS, (double *)U, ldu, strideU, (double *)V,
                                    ldv, strideV, tol, o.max_sweeps, info, o.sweeps, workspace, s);

@@ -52,6 +52,13 @@ constexpr int kVbNb = 16;  // block width of uneven batches
 // would be redone in FP64 anyway.
 constexpr double kSwitchCos = 0x1p-7;
 
+// A column whose squared norm is below kNegligible (a norm below 2^-480 of
+// the pre-scaled matrix, whose largest entry is about 1) is never rotated,
+// and a singular value below 2^-480 is taken as zero: rotating such columns
+// only pushes rounding noise towards underflow (on exactly rank-deficient
+// input the iteration would otherwise not stop).
+constexpr double kNegligible = 0x1p-960;
+
 // per-matrix state in the workspace
 struct BlkState {
     int active;                  // swept by the next launches
@@ -373,7 +380,7 @@ __device__ __forceinline__ double inner_sweep_real(IterShared<T, false, NB> &s, 
             const double si = sqrt(fabs(gii)), sj = sqrt(fabs(gjj));
             const double den = si * sj;
             mc = fmax(mc, den > 0.0 ? ag / den : (ag != 0.0 ? 1.0 : 0.0));
-            if (gij != 0.0 && ag >= tol * si * sj) {
+            if (gij != 0.0 && gii >= kNegligible && gjj >= kNegligible && ag >= tol * si * sj) {
                 double sn;
                 jacobi_cs(gii, gjj, ag, c, sn);
                 es = gij > 0.0 ? sn : -sn;
@@ -463,7 +470,7 @@ __device__ __forceinline__ double inner_sweep_cx(IterShared<T, true, NB> &s, dou
             const double si = sqrt(fabs(gii)), sj = sqrt(fabs(gjj));
             const double den = si * sj;
             mc = fmax(mc, den > 0.0 ? ag / den : (ag != 0.0 ? 1.0 : 0.0));
-            if (ag != 0.0 && ag >= tol * si * sj) {
+            if (ag != 0.0 && gii >= kNegligible && gjj >= kNegligible && ag >= tol * si * sj) {
                 double sn;
                 jacobi_cs(gii, gjj, ag, c, sn);
                 er = gr / ag * sn;
@@ -720,7 +727,8 @@ __device__ __forceinline__ void finalize_body(int m, int n, int np, const EW *W,
             }
         }
         ss = wave_sum(ss);
-        if (lane == 0) sig[c] = mx > 0.0 ? ldexp(sqrt(ss), ilogb(mx)) : 0.0;
+        const double sc = mx > 0.0 ? ldexp(sqrt(ss), ilogb(mx)) : 0.0;
+        if (lane == 0) sig[c] = sc >= 0x1p-480 ? sc : 0.0;
     }
     __syncthreads();
     for (int c = tid; c < n; c += kBT) {

@@ -29,6 +29,13 @@ hipError_t launch_precond_d(int batch, int m, int n, int ns, const double *A, in
                             long long sA, double *S, long long sS, double *U, int ldu,
                             long long sU, double *V, int ldv, long long sV, double tol,
                             int max_sweeps, int *info, int *sweeps, void *ws, hipStream_t stream);
+bool precond_big_supported(int m, int n);
+size_t precond_big_workspace_bytes(int batch, int m, int n, int nb);
+hipError_t launch_precond_big_d(int batch, int m, int n, int nb, const double *A, int lda,
+                                long long sA, double *S, long long sS, double *U, int ldu,
+                                long long sU, double *V, int ldv, long long sV, double tol,
+                                int max_sweeps, int masking, int *info, int *sweeps, void *ws,
+                                hipStream_t stream);
 
 // blocked.hip: block one-sided Jacobi with MFMA Gram/updates (real and
 // complex, FP64 and FP32, and FP32 sweeps followed by an FP64 refinement).

@@ -233,6 +233,155 @@ bool qr_shape(int m, int n, int *rpl, int *cpg)
     return true;
 }
 
+// ---------------------------------------------------------------------------
+// Wide matrices (n > 64, m <= 1024): the same QR in global memory, for the
+// block path.  qr_house_g factors one matrix per workgroup in place in the
+// workspace (16-lane groups share out the trailing columns, the reflector of
+// the step is staged in LDS, two barriers per column); apply_q_g applies Q to one
+// block of 16 columns of U per workgroup, held in registers.
+// ---------------------------------------------------------------------------
+constexpr int kQrMaxM = 1024;
+
+__global__ __launch_bounds__(kQT) void qr_house_g(int m, int n, const double *__restrict__ A,
+                                                  int lda, long long sA, double *Vq, double *X,
+                                                  double *tau_out)
+{
+    __shared__ double vbuf[2][kQrMaxM];
+    __shared__ double s_tau[2];
+    __shared__ double s_max[kQT / 64];
+    __shared__ int s_bad[kQT / 64];
+    const int b = blockIdx.x, tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+    const int grp = tid >> 4, gl = tid & 15;
+    A += (size_t)b * sA;
+    double *H = Vq + (size_t)b * m * n;
+    double *tau = tau_out + (size_t)b * n;
+    double amax = 0.0;
+    int bad = 0;
+    for (size_t idx = tid; idx < (size_t)m * n; idx += kQT) {
+        const double a = A[(idx / m) * lda + idx % m];
+        bad |= !isfinite(a);
+        amax = fmax(amax, fabs(a));
+    }
+    amax = wave_max(amax);
+    bad = __any(bad);
+    if (lane == 0) {
+        s_max[wave] = amax;
+        s_bad[wave] = bad;
+    }
+    __syncthreads();
+    amax = fmax(fmax(s_max[0], s_max[1]), fmax(s_max[2], s_max[3]));
+    const bool finite = !(s_bad[0] | s_bad[1] | s_bad[2] | s_bad[3]);
+    const double scale = finite ? pow2_scale(amax) : 1.0;
+    for (size_t idx = tid; idx < (size_t)m * n; idx += kQT)
+        H[idx] = A[(idx / m) * lda + idx % m] * scale;
+    __syncthreads();
+    for (int j = 0; j < n && finite; j++) {
+        double *vb = vbuf[j & 1];
+        double *hj = H + (size_t)j * m;
+        if (grp == (j & 15)) {
+            double s = 0.0;
+            for (int i = j + 1 + gl; i < m; i += 16) s = fma(hj[i], hj[i], s);
+            s = row_sum16(s);
+            const double alpha = hj[j];
+            double beta = alpha, tau_j = 0.0, scal = 0.0;
+            if (s > 0.0) {
+                const double nrm = sqrt(fma(alpha, alpha, s));
+                beta = alpha >= 0.0 ? -nrm : nrm;
+                tau_j = (beta - alpha) / beta;
+                scal = 1.0 / (alpha - beta);
+            }
+            for (int i = j + 1 + gl; i < m; i += 16) {
+                const double v = hj[i] * scal;
+                vb[i] = v;
+                hj[i] = v;
+            }
+            if (gl == 0) {
+                vb[j] = 1.0;
+                hj[j] = beta;
+                s_tau[j & 1] = tau_j;
+                tau[j] = tau_j;
+            }
+        }
+        __syncthreads();
+        const double t = s_tau[j & 1];
+        if (t != 0.0) {
+            for (int k = j + 1 + grp; k < n; k += 16) {
+                double *hk = H + (size_t)k * m;
+                double w = 0.0;
+                for (int i = j + gl; i < m; i += 16) w = fma(vb[i], hk[i], w);
+                w = row_sum16(w) * t;
+                for (int i = j + gl; i < m; i += 16) hk[i] = fma(-w, vb[i], hk[i]);
+            }
+        }
+        __syncthreads();   // the trailing columns are final before the next step reads them
+    }
+    __syncthreads();
+    // X = R^T / scale, then the reflectors as full columns
+    X += (size_t)b * n * n;
+    const double inv = 1.0 / scale;
+    for (size_t idx = tid; idx < (size_t)n * n; idx += kQT) {
+        const int r = (int)(idx % n), c = (int)(idx / n);   // X(r, c) = R(c, r)
+        X[idx] = !finite ? __builtin_nan("") : (r >= c ? H[(size_t)r * m + c] * inv : 0.0);
+    }
+    __syncthreads();
+    for (size_t idx = tid; idx < (size_t)m * n; idx += kQT) {
+        const int row = (int)(idx % m), col = (int)(idx / m);
+        if (row <= col) H[idx] = row == col ? 1.0 : 0.0;
+    }
+    if (!finite)
+        for (int j = tid; j < n; j += kQT) tau[j] = 0.0;
+}
+
+// U[:, 16 blk .. 16 blk + 15] = Q [Y; 0] for one block of 16 columns: group g
+// owns column 16 blk + g, lane x rows x, x + 16, ... (RPL of them).  The
+// reflector of each step is staged in LDS (double buffered, one barrier).
+template <int RPL>
+__global__ __launch_bounds__(kQT) void apply_q_g(int m, int n, const double *__restrict__ Vq,
+                                                 const double *__restrict__ tau,
+                                                 const double *__restrict__ Y, double *U, int ldu,
+                                                 long long sU, const int *info)
+{
+    __shared__ double vbuf[2][16 * RPL];
+    const int nblk = (n + 15) / 16;
+    const int b = blockIdx.x / nblk, blk = blockIdx.x % nblk;
+    const int tid = threadIdx.x, grp = tid >> 4, gl = tid & 15;
+    if (info[b] == 2) return;
+    Vq += (size_t)b * m * n;
+    tau += (size_t)b * n;
+    Y += (size_t)b * n * n;
+    U += (size_t)b * sU;
+    const int col = 16 * blk + grp;
+    double u[RPL];
+#pragma unroll
+    for (int r = 0; r < RPL; r++) {
+        const int row = gl + 16 * r;
+        u[r] = (row < n && col < n) ? Y[(size_t)col * n + row] : 0.0;
+    }
+    for (int i = tid; i < 16 * RPL; i += kQT)
+        vbuf[(n - 1) & 1][i] = i < m ? Vq[(size_t)(n - 1) * m + i] : 0.0;
+    for (int j = n - 1; j >= 0; j--) {
+        __syncthreads();
+        if (j > 0)   // stage the next reflector
+            for (int i = tid; i < 16 * RPL; i += kQT)
+                vbuf[(j - 1) & 1][i] = i < m ? Vq[(size_t)(j - 1) * m + i] : 0.0;
+        const double t = tau[j];
+        if (t == 0.0) continue;
+        const double *vb = vbuf[j & 1];
+        double w = 0.0;
+#pragma unroll
+        for (int r = 0; r < RPL; r++) w = fma(vb[gl + 16 * r], u[r], w);
+        w = row_sum16(w) * t;
+#pragma unroll
+        for (int r = 0; r < RPL; r++) u[r] = fma(-w, vb[gl + 16 * r], u[r]);
+    }
+    if (col < n)
+#pragma unroll
+        for (int r = 0; r < RPL; r++) {
+            const int row = gl + 16 * r;
+            if (row < m) U[(size_t)col * ldu + row] = u[r];
+        }
+}
+
 size_t al256(size_t x) { return (x + 255) & ~(size_t)255; }
 
 }  // namespace
@@ -309,6 +458,64 @@ hipError_t launch_precond_d(int batch, int m, int n, int ns, const double *A, in
         e = hipGetLastError();
     }
     return e;
+}
+
+bool precond_big_supported(int m, int n)
+{
+    return n > 64 && m >= n && m <= kQrMaxM;
+}
+
+size_t precond_big_workspace_bytes(int batch, int m, int n, int nb)
+{
+    return precond_workspace_bytes(batch, m, n) + blocked_workspace_bytes(batch, n, n, nb, 8, false);
+}
+
+// Wide FP64 matrices: QR in global memory, the block Jacobi on X = R^T, and
+// U = Q J applied by column blocks.
+hipError_t launch_precond_big_d(int batch, int m, int n, int nb, const double *A, int lda,
+                                long long sA, double *S, long long sS, double *U, int ldu,
+                                long long sU, double *V, int ldv, long long sV, double tol,
+                                int max_sweeps, int masking, int *info, int *sweeps, void *ws,
+                                hipStream_t stream)
+{
+    if (!precond_big_supported(m, n)) return hipErrorInvalidValue;
+    char *p = (char *)ws;
+    double *X = (double *)p;
+    p += al256((size_t)batch * n * n * 8);
+    double *Vq = (double *)p;
+    p += al256((size_t)batch * m * n * 8);
+    double *tau = (double *)p;
+    p += al256((size_t)batch * n * 8);
+    double *J = (double *)p;
+    p += al256((size_t)batch * n * n * 8);
+    double *Ux = (double *)p;
+    p += al256((size_t)batch * n * n * 8);
+    void *bws = p;
+    hipLaunchKernelGGL(qr_house_g, dim3(batch), dim3(kQT), 0, stream, m, n, A, lda, sA, Vq, X, tau);
+    hipError_t e = hipGetLastError();
+    if (e != hipSuccess) return e;
+    double *vx = V ? V : Ux;
+    const int ldvx = V ? ldv : n;
+    const long long svx = V ? sV : (long long)n * n;
+    e = launch_blocked_d(batch, n, n, nb, X, n, (long long)n * n, S, sS, vx, ldvx, svx,
+                         U ? J : nullptr, n, (long long)n * n, tol, max_sweeps, masking, info,
+                         sweeps, bws, stream);
+    if (e != hipSuccess || !U) return e;
+    const int rpl = (m + 15) / 16;
+    const dim3 grid((unsigned)(batch * ((n + 15) / 16)));
+#define SVDB_AQG(RP)                                                                           \
+    if (rpl <= RP) {                                                                           \
+        hipLaunchKernelGGL((apply_q_g<RP>), grid, dim3(kQT), 0, stream, m, n,                  \
+                           (const double *)Vq, (const double *)tau, (const double *)J, U, ldu,  \
+                           sU, (const int *)info);                                             \
+        return hipGetLastError();                                                              \
+    }
+    SVDB_AQG(8)
+    SVDB_AQG(16)
+    SVDB_AQG(32)
+    SVDB_AQG(64)
+#undef SVDB_AQG
+    return hipErrorInvalidValue;
 }
 
 }  // namespace svdb

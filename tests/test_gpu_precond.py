@@ -112,3 +112,44 @@ def test_precond_mixed_workload_sample():
         Sr, _, _, swr, infor = oracle_batch(A)
         compare_with_oracle(A, S, U, V, info, Sr, infor, label=f"auto {g.m}x{g.n}")
         say(f"  {g.m}x{g.n}: sweeps gpu {sw.mean():.2f} oracle on A {swr.mean():.2f}")
+
+
+@pytest.mark.parametrize("m,n,count", [(96, 65, 4), (130, 96, 4), (200, 130, 3), (256, 256, 2),
+                                       (1000, 100, 2)])
+def test_precond_wide_vs_oracle(m, n, count):
+    """n > 64: QR in global memory, the block Jacobi on R^T, U = Q J."""
+    import torch
+    from paper_2601_17979_amd import svdb
+    assert svdb.plan(torch.float64, m, n)[0] == svdb.PATH_BLOCKED
+    A = _batch((m, n), count, seed=8600 + m + n, kinds=("geo", "gauss", "cluster1"), kappa=1e8)
+    say(f"[precond wide {m}x{n}]")
+    S, U, V, info, sw = run_gpu(A)
+    Sr, Ur, Vr, swr, infor = oracle_batch(A)
+    compare_with_oracle(A, S, U, V, info, Sr, infor, label=f"precond wide {m}x{n}")
+    _, _, _, _, sw0 = run_gpu(A, path="blocked", nb=16 if n <= 96 else 32)
+    say(f"  sweeps on R^T {sw.tolist()} on A {sw0.tolist()} oracle {swr.tolist()}")
+
+
+def test_precond_wide_edge_cases():
+    import torch
+    from paper_2601_17979_amd import svdb
+    m, n = 150, 100
+    A = _batch((m, n), 4, seed=8700)
+    A[0] = 0.0
+    A[1][:, 10] = 0.0
+    A[1][:, 20] = A[1][:, 30]
+    A[2][5, 5] = np.nan
+    Ag = svdb.col_major(torch.from_numpy(A).cuda())
+    out = (torch.full((4, n), 7.0, dtype=torch.float64, device="cuda"),
+           svdb.empty_col_major(4, m, n, torch.float64, "cuda").fill_(7.0),
+           svdb.empty_col_major(4, n, n, torch.float64, "cuda").fill_(7.0),
+           torch.empty(4, dtype=torch.int32, device="cuda"),
+           torch.empty(4, dtype=torch.int32, device="cuda"))
+    svdb.svd(Ag, out=out)
+    torch.cuda.synchronize()
+    S, U, V, info, sw = (x.cpu().numpy() for x in out)
+    assert info[2] == 2 and np.all(U[2] == 7.0)
+    keep = [0, 1, 3]
+    Sr, _, _, _, infor = oracle_batch(A[keep])
+    compare_with_oracle(A[keep], S[keep], U[keep], V[keep], info[keep], Sr, infor,
+                        label="precond wide edge")
