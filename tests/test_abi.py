@@ -6,6 +6,7 @@ import os
 import re
 
 import pytest
+import torch
 
 from paper_2601_17979_amd import svdb
 
@@ -103,3 +104,39 @@ def test_batched_argument_errors():
     rc = L.svdb_svd_batched(svdb.R64, 2, m, n, A, lda, S, None, None, None, None, 0.0, info,
                             None, 0, None, None)
     assert rc == -6
+
+
+def test_server_argument_errors():
+    """Argument checks of the serving entry points that run before any
+    device call."""
+    h = C.c_void_p()
+    lib = svdb.lib()
+    assert lib.svdb_server_create(None, 1 << 20, 4, None) == -1
+    assert lib.svdb_server_create(C.byref(h), 0, 4, None) == -2
+    assert lib.svdb_server_create(C.byref(h), 1 << 20, 0, None) == -3
+    o = svdb.make_opts(precision=1)
+    assert lib.svdb_server_create(C.byref(h), 1 << 20, 4, C.byref(o)) == svdb.ERR_UNSUPPORTED
+    assert lib.svdb_server_submit(None, svdb.R64, 8, 4, 0x1000, 8, 0x2000, None, 8, None, 4,
+                                  0.0, 0x3000, None) == -1
+    assert lib.svdb_server_poll(None, None, None, None, 0, 0) == -1
+    assert lib.svdb_server_stats(None, None, None, None, None, None) == -1
+    assert lib.svdb_server_destroy(None) == -1
+    assert lib.svdb_server_clock() > 0.0
+
+
+def test_precondition_option_in_plan():
+    """AUTO plans the QR-preconditioned resident path for FP64 n <= 64 and
+    the preconditioned block path for wider matrices; precondition = 0 turns
+    both off, and 1 is refused where it does not apply."""
+    p_auto = svdb.plan(torch.float64, 64, 64)
+    assert p_auto[0] == svdb.PATH_RESIDENT
+    assert svdb.plan(torch.float64, 256, 256)[0] == svdb.PATH_BLOCKED
+    assert svdb.plan(torch.float64, 64, 64, precondition=0)[0] == svdb.PATH_RESIDENT
+    with pytest.raises(svdb.SvdbError):
+        svdb.plan(torch.complex128, 64, 64, precondition=1)
+    with pytest.raises(svdb.SvdbError):
+        svdb.plan(torch.float64, 2048, 100, precondition=1)
+    ws_pc = svdb.lib().svdb_workspace_size(svdb.R64, 10, 64, 64, C.byref(svdb.make_opts()))
+    ws_no = svdb.lib().svdb_workspace_size(svdb.R64, 10, 64, 64,
+                                           C.byref(svdb.make_opts(precondition=0)))
+    assert ws_pc > 0 and ws_no == 0
