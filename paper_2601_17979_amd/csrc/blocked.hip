@@ -11,18 +11,15 @@
 // round-robin iterations ("Parallel Ordering") over block columns; each iteration is one
 // launch of blk_iter with one workgroup per (block pair, matrix):
 //   1. G = [W_p W_q]^H [W_p W_q] (2nb x 2nb) on the matrix cores (FP64 MFMA,
-//      or FP32 MFMA with FP32 accumulation): every wave streams its own
-//      16-row slabs through a private LDS slab and accumulates the tiles on
-//      and above the diagonal; the four partial sums are added in wave
-//      order.  A complex slab X = Xr + i Xi is held as the real slab
-//      [Xr Xi]; its real Gram matrix R gives Re G = R_rr + R_ii and
-//      Im G = R_ri - R_ir;
+//      or FP32 MFMA with FP32 accumulation), streaming the pair's rows
+//      through LDS in chunks of 64 rows.  A complex chunk X = Xr + i Xi is
+//      held as the real chunk [Xr Xi]; its real Gram matrix R gives
+//      Re G = R_rr + R_ii and Im G = R_ri - R_ir;
 //   2. one sweep of the two-sided Jacobi eigensolver (Alg. 1) on G in LDS,
 //      always in FP64, in round-robin order over the 2nb indices,
 //      accumulating J;
 //   3. [W_p W_q] <- [W_p W_q] J and [V_p V_q] <- [V_p V_q] J on the matrix
-//      cores (complex: [Xr Xi] [[Jr, Ji], [-Ji, Jr]]), every wave streaming
-//      its own 16-row slabs with no workgroup barrier, reading every element
+//      cores (complex: [Xr Xi] [[Jr, Ji], [-Ji, Jr]]), reading every element
 //      once and writing it once.
 // A matrix whose inner solves applied no rotation during a whole sweep has
 // orthogonal columns.  With masking ("Masked Batch Operations") it is retired at once and
@@ -213,16 +210,15 @@ __global__ __launch_bounds__(kBT) void blk_init(int m, int n, int np, const EA *
 
 // ---------------------------------------------------------------------------
 // LDS of one workgroup of blk_iter.  N2 = 2nb complex (or real) columns, NR
-// real columns of [Xr (Xi)].  The per-wave row slabs of the Gram phase and
-// the real Gram matrix share storage (never live together); a complex G has
-// its own arrays.
+// real columns of the streamed chunk.  The chunk and the real Gram matrix
+// share storage (never live together); a complex G has its own arrays.
 // ---------------------------------------------------------------------------
 template <class T, bool CX, int NB>
 struct IterShared {
     static constexpr int N2 = 2 * NB, NR = (CX ? 2 : 1) * N2;
     union {
-        T slab[kBT / 64][NR][16 + 1];  // per-wave 16-row slab of [Xr (Xi)], column major
-        double R[NR][NR + 1];          // real Gram matrix (the real G itself)
+        T xs[NR][kCH + 1];            // row chunk [Xr (Xi)], column major
+        double R[NR][NR + 1];         // real Gram matrix (the real G itself)
     } u;
     double Gr[CX ? N2 : 1][N2 + 1];   // complex G: real and imaginary parts
     double Gi[CX ? N2 : 1][N2 + 1];
@@ -233,99 +229,72 @@ struct IterShared {
     int rot;
 };
 
-__device__ __forceinline__ void wave_lds_sync()
-{
-    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
-    __builtin_amdgcn_wave_barrier();
-    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
-}
-
-// One lane's share of a 16-row slab of the 2nb columns of block pair (p, q):
-// lane l holds rows r0 + l % 16 of columns l / 16, l / 16 + 4, ... (zero
-// beyond `rows`), so every load instruction reads 4 columns x 16 rows.
+// Per-thread share of one chunk (kCH rows x 2nb columns) held in registers so
+// that the next chunk's global loads overlap the current chunk's MFMAs.
 template <class E, int NB>
-struct SlabRegs {
-    static constexpr int K = 2 * NB / 4;
+struct ChunkRegs {
+    static constexpr int K = 2 * NB * kCH / kBT;
     E v[K];
 };
 
+// Loads rows [r0, r0 + kCH) of block columns p, q of the rows x np matrix X
+// (zero beyond `rows`).  Element k of thread t is chunk entry
+// idx = t + k kBT: column idx / kCH, row idx % kCH (coalesced columns).
 template <class E, int NB>
-__device__ __forceinline__ void slab_load(SlabRegs<E, NB> &Rg, const E *X, int rows, int r0, int p,
-                                          int q)
+__device__ __forceinline__ void chunk_load(ChunkRegs<E, NB> &Rg, const E *X, int rows, int r0,
+                                           int p, int q)
 {
-    const int lane = threadIdx.x & 63, li = lane & 15, lk = lane >> 4;
-    const int row = r0 + li;
+    const int tid = threadIdx.x;
 #pragma unroll
-    for (int k = 0; k < SlabRegs<E, NB>::K; k++) {
-        const int c = lk + 4 * k;
+    for (int k = 0; k < ChunkRegs<E, NB>::K; k++) {
+        const int idx = tid + k * kBT;
+        const int c = idx / kCH, r = idx % kCH;
         const int gc = c < NB ? p * NB + c : q * NB + (c - NB);
-        Rg.v[k] = row < rows ? X[(size_t)gc * rows + row] : EOps<E>::make(0.0, 0.0);
+        const int gr = r0 + r;
+        Rg.v[k] = gr < rows ? X[(size_t)gc * rows + gr] : EOps<E>::make(0.0, 0.0);
     }
 }
 
-// Gram matrix of [X_p X_q]: every wave accumulates the tiles on and above
-// the diagonal over its own 16-row slabs (staged in its private LDS slab, no
-// workgroup barrier), then the four partial sums are added into s.u.R in
-// wave order (deterministic).
 template <class T, bool CX, int NB, class E>
-__device__ __forceinline__ void gram_streamed(IterShared<T, CX, NB> &s, const E *X, int rows, int p,
-                                              int q)
+__device__ __forceinline__ void chunk_to_lds(IterShared<T, CX, NB> &s, const ChunkRegs<E, NB> &Rg)
 {
-    constexpr int N2 = 2 * NB, NR = IterShared<T, CX, NB>::NR;
-    constexpr int TC = NR / 16, GTS = TC * (TC + 1) / 2;
-    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
-    const int li = lane & 15, lk = lane >> 4;
-    T(*sl)[16 + 1] = s.u.slab[wave];
-    typename Mfma<T>::acc_t acc[GTS];
+    constexpr int N2 = 2 * NB;
+    const int tid = threadIdx.x;
 #pragma unroll
-    for (int t = 0; t < GTS; t++) acc[t] = typename Mfma<T>::acc_t{0, 0, 0, 0};
-    const int nslab = (rows + 15) / 16;
-    SlabRegs<E, NB> Rg;
-    if (wave < nslab) slab_load<E, NB>(Rg, X, rows, 16 * wave, p, q);
-    for (int sb = wave; sb < nslab; sb += kBT / 64) {
-#pragma unroll
-        for (int k = 0; k < SlabRegs<E, NB>::K; k++) {
-            const int c = lk + 4 * k;
-            if constexpr (CX) {
-                sl[c][li] = Rg.v[k].x;
-                sl[c + N2][li] = Rg.v[k].y;
-            } else {
-                sl[c][li] = Rg.v[k];
-            }
+    for (int k = 0; k < ChunkRegs<E, NB>::K; k++) {
+        const int idx = tid + k * kBT;
+        const int c = idx / kCH, r = idx % kCH;
+        if constexpr (CX) {
+            s.u.xs[c][r] = Rg.v[k].x;
+            s.u.xs[c + N2][r] = Rg.v[k].y;
+        } else {
+            s.u.xs[c][r] = Rg.v[k];
         }
-        wave_lds_sync();
-        if (sb + kBT / 64 < nslab) slab_load<E, NB>(Rg, X, rows, 16 * (sb + kBT / 64), p, q);
-        int t = 0;
-#pragma unroll
-        for (int ti = 0; ti < TC; ti++)
-#pragma unroll
-            for (int tj = ti; tj < TC; tj++, t++)
-#pragma unroll
-                for (int k0 = 0; k0 < 16; k0 += 4) {
-                    const T a = sl[16 * ti + li][k0 + lk];    // X^T[i][k]
-                    const T bb = sl[16 * tj + li][k0 + lk];   // X[k][j]
-                    acc[t] = Mfma<T>::op(a, bb, acc[t]);
-                }
-        wave_lds_sync();   // the slab is read before the next one overwrites it
     }
-    __syncthreads();       // slabs are dead, R takes their place
-#pragma unroll 1
-    for (int w = 0; w < kBT / 64; w++) {
-        if (wave == w) {
-            int t = 0;
+}
+
+// Stores the chunk held in s.u.xs to rows [r0, r0 + kCH) of X.
+template <class T, bool CX, int NB, class E>
+__device__ __forceinline__ void chunk_store(const IterShared<T, CX, NB> &s, E *X, int rows, int r0,
+                                            int p, int q)
+{
+    constexpr int N2 = 2 * NB;
+    const int tid = threadIdx.x;
 #pragma unroll
-            for (int ti = 0; ti < TC; ti++)
-#pragma unroll
-                for (int tj = ti; tj < TC; tj++, t++)
-#pragma unroll
-                    for (int v = 0; v < 4; v++) {
-                        const int r = 16 * ti + Mfma<T>::row(lane, v), c = 16 * tj + li;
-                        const double x = (double)acc[t][v] + (w ? s.u.R[r][c] : 0.0);
-                        s.u.R[r][c] = x;
-                        if (ti != tj) s.u.R[c][r] = x;
-                    }
+    for (int k = 0; k < ChunkRegs<E, NB>::K; k++) {
+        const int idx = tid + k * kBT;
+        const int c = idx / kCH, r = idx % kCH;
+        const int gc = c < NB ? p * NB + c : q * NB + (c - NB);
+        if (r0 + r < rows) {
+            E y;
+            if constexpr (CX) {
+                y.x = s.u.xs[c][r];
+                y.y = s.u.xs[c + N2][r];
+            } else {
+                y = s.u.xs[c][r];
+            }
+            X[(size_t)gc * rows + r0 + r] = y;
         }
-        __syncthreads();
     }
 }
 
@@ -346,73 +315,49 @@ __device__ __forceinline__ T jreal(const IterShared<T, CX, NB> &s, int k, int c)
     }
 }
 
-// [X_p X_q] <- [X_p X_q] J for a rows x np matrix X.  Every wave streams its
-// own 16-row slabs without workgroup barriers: it forms the transposed
-// product (X J)^T = J^T X^T on the matrix cores, A operand J^T from LDS, B
-// operand the slab straight from its registers, and stores each result
-// register as 16 consecutive rows of one column.
+// [X_p X_q] <- [X_p X_q] J for a rows x np matrix X, chunk by chunk: MFMA
+// tiles of 16 x 16 from the real chunk in LDS and the real form of J,
+// results staged back through LDS and written with coalesced stores.
 template <class T, bool CX, int NB, class E>
-__device__ __forceinline__ void update_streamed(IterShared<T, CX, NB> &s, E *X, int rows, int p,
-                                                int q)
+__device__ __forceinline__ void update_block_columns(IterShared<T, CX, NB> &s, E *X, int rows,
+                                                     int p, int q)
 {
-    constexpr int N2 = 2 * NB, NR = IterShared<T, CX, NB>::NR;
-    constexpr int TC = NR / 16, KK = NR / 4, KC = N2 / 4;
+    constexpr int NR = IterShared<T, CX, NB>::NR;
+    constexpr int TR = kCH / 16, TC = NR / 16, TILES = TR * TC, TPW = TILES / 4;
+    static_assert(TILES % 4 == 0, "tiles per wave");
     const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
     const int li = lane & 15, lk = lane >> 4;
-    const int nslab = (rows + 15) / 16;
-    SlabRegs<E, NB> Rg;
-    if (wave < nslab) slab_load<E, NB>(Rg, X, rows, 16 * wave, p, q);
-    for (int sb = wave; sb < nslab; sb += kBT / 64) {
-        // B operands X[r0 + l%16][k], k = 4 kk + l/16 (complex: re, then im)
-        T bx[KK];
+    ChunkRegs<E, NB> Rg;
+    chunk_load<E, NB>(Rg, X, rows, 0, p, q);
+    for (int r0 = 0; r0 < rows; r0 += kCH) {
+        __syncthreads();                      // xs free (previous chunk stored)
+        chunk_to_lds<T, CX, NB, E>(s, Rg);
+        __syncthreads();
+        if (r0 + kCH < rows) chunk_load<E, NB>(Rg, X, rows, r0 + kCH, p, q);
+        typename Mfma<T>::acc_t acc[TPW];
 #pragma unroll
-        for (int k = 0; k < KC; k++) {
-            if constexpr (CX) {
-                bx[k] = Rg.v[k].x;
-                bx[k + KC] = Rg.v[k].y;
-            } else {
-                bx[k] = Rg.v[k];
+        for (int t = 0; t < TPW; t++) {
+            const int tile = wave + 4 * t;
+            const int ti = tile % TR, tj = tile / TR;
+            acc[t] = typename Mfma<T>::acc_t{0, 0, 0, 0};
+#pragma unroll
+            for (int k0 = 0; k0 < NR; k0 += 4) {
+                const T a = s.u.xs[k0 + lk][16 * ti + li];                 // X[r][k]
+                const T bb = jreal<T, CX, NB>(s, k0 + lk, 16 * tj + li);    // J[k][c]
+                acc[t] = Mfma<T>::op(a, bb, acc[t]);
             }
         }
-        if (sb + kBT / 64 < nslab) slab_load<E, NB>(Rg, X, rows, 16 * (sb + kBT / 64), p, q);
-        const int row = 16 * sb + li;
-        if constexpr (!CX) {
+        __syncthreads();                      // every wave has read xs
 #pragma unroll
-            for (int ti = 0; ti < TC; ti++) {
-                typename Mfma<T>::acc_t acc = {0, 0, 0, 0};
+        for (int t = 0; t < TPW; t++) {
+            const int tile = wave + 4 * t;
+            const int ti = tile % TR, tj = tile / TR;
 #pragma unroll
-                for (int kk = 0; kk < KK; kk++)
-                    acc = Mfma<T>::op(jreal<T, CX, NB>(s, 4 * kk + lk, 16 * ti + li), bx[kk], acc);
-                if (row < rows)
-#pragma unroll
-                    for (int v = 0; v < 4; v++) {
-                        const int c = 16 * ti + Mfma<T>::row(lane, v);
-                        const int gc = c < NB ? p * NB + c : q * NB + (c - NB);
-                        X[(size_t)gc * rows + row] = acc[v];
-                    }
-            }
-        } else {
-#pragma unroll
-            for (int ti = 0; ti < TC / 2; ti++) {
-                typename Mfma<T>::acc_t ar = {0, 0, 0, 0}, ai = {0, 0, 0, 0};
-#pragma unroll
-                for (int kk = 0; kk < KK; kk++) {
-                    ar = Mfma<T>::op(jreal<T, CX, NB>(s, 4 * kk + lk, 16 * ti + li), bx[kk], ar);
-                    ai = Mfma<T>::op(jreal<T, CX, NB>(s, 4 * kk + lk, N2 + 16 * ti + li), bx[kk],
-                                     ai);
-                }
-                if (row < rows)
-#pragma unroll
-                    for (int v = 0; v < 4; v++) {
-                        const int c = 16 * ti + Mfma<T>::row(lane, v);
-                        const int gc = c < NB ? p * NB + c : q * NB + (c - NB);
-                        E y;
-                        y.x = ar[v];
-                        y.y = ai[v];
-                        X[(size_t)gc * rows + row] = y;
-                    }
-            }
+            for (int v = 0; v < 4; v++)
+                s.u.xs[16 * tj + li][16 * ti + Mfma<T>::row(lane, v)] = acc[t][v];
         }
+        __syncthreads();
+        chunk_store<T, CX, NB, E>(s, X, rows, r0, p, q);
     }
 }
 
@@ -611,14 +556,54 @@ __device__ __forceinline__ void iter_body(IterShared<T, CX, NB> &s, int m, int n
 {
     using E = typename Elem<T, CX>::type;
     using Sh = IterShared<T, CX, NB>;
-    constexpr int N2 = Sh::N2;
+    constexpr int N2 = Sh::N2, NR = Sh::NR;
+    constexpr int TC = NR / 16, GT = TC * TC;   // real Gram output tiles
+    constexpr int GPW = (GT + 3) / 4;           // tiles per wave
     const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+    const int li = lane & 15, lk = lane >> 4;
     int p, q;
     rr_pair(l, it, pair, p, q);
 
     // ---- 1. Gram matrix on the matrix cores --------------------------------
-    gram_streamed<T, CX, NB, E>(s, W, m, p, q);
+    typename Mfma<T>::acc_t acc[GPW];
+#pragma unroll
+    for (int g = 0; g < GPW; g++) acc[g] = typename Mfma<T>::acc_t{0, 0, 0, 0};
+    {
+        ChunkRegs<E, NB> Rg;
+        chunk_load<E, NB>(Rg, W, m, 0, p, q);
+        for (int r0 = 0; r0 < m; r0 += kCH) {
+            __syncthreads();
+            chunk_to_lds<T, CX, NB, E>(s, Rg);
+            __syncthreads();
+            if (r0 + kCH < m) chunk_load<E, NB>(Rg, W, m, r0 + kCH, p, q);
+#pragma unroll
+            for (int g = 0; g < GPW; g++) {
+                const int tile = wave + 4 * g;
+                if (tile < GT) {
+                    const int ti = tile / TC, tj = tile % TC;
+#pragma unroll
+                    for (int k0 = 0; k0 < kCH; k0 += 4) {
+                        const T a = s.u.xs[16 * ti + li][k0 + lk];    // X^T[i][k]
+                        const T bb = s.u.xs[16 * tj + li][k0 + lk];   // X[k][j]
+                        acc[g] = Mfma<T>::op(a, bb, acc[g]);
+                    }
+                }
+            }
+        }
+    }
+    __syncthreads();                            // xs is dead, R takes its place
+#pragma unroll
+    for (int g = 0; g < GPW; g++) {
+        const int tile = wave + 4 * g;
+        if (tile < GT) {
+            const int ti = tile / TC, tj = tile % TC;
+#pragma unroll
+            for (int v = 0; v < 4; v++)
+                s.u.R[16 * ti + Mfma<T>::row(lane, v)][16 * tj + li] = (double)acc[g][v];
+        }
+    }
     if constexpr (CX) {
+        __syncthreads();
         for (int idx = tid; idx < N2 * N2; idx += kBT) {
             const int a = idx / N2, c = idx % N2;
             s.Gr[a][c] = s.u.R[a][c] + s.u.R[a + N2][c + N2];
@@ -644,8 +629,8 @@ __device__ __forceinline__ void iter_body(IterShared<T, CX, NB> &s, int m, int n
 
     // ---- 3. fused update of the block columns of W and V --------------------
     if (s.rot != 0) {
-        update_streamed<T, CX, NB, E>(s, W, m, p, q);
-        update_streamed<T, CX, NB, E>(s, Vw, np, p, q);
+        update_block_columns<T, CX, NB, E>(s, W, m, p, q);
+        update_block_columns<T, CX, NB, E>(s, Vw, np, p, q);
         if (tid == 0) atomicOr(&stb->rotated, 1);
     }
 }
