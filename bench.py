@@ -93,29 +93,41 @@ def serve_leg(args, dev):
     # open loop: Poisson arrivals
     rate = args.serve_load * sat
     rng = np.random.default_rng(17979 + 4000)
-    lat, n_sub = [], 0
+    lat, n_sub, cls = [], 0, {}
+    by_class = {}
+
+    def collect(items):
+        for rid, ts, td, out in items:
+            lat.append(td - ts)
+            by_class.setdefault(cls.pop(rid), []).append(td - ts)
     t_start = svdb.Server.clock()
     t_next = t_start
     while t_next - t_start < args.serve_seconds:
         now = svdb.Server.clock()
         if now < t_next:
-            for rid, ts, td, out in srv.poll(timeout_ms=0):
-                lat.append(td - ts)
+            collect(srv.poll(timeout_ms=0))
             time.sleep(max(0.0, min(t_next - svdb.Server.clock(), 0.002)))
             continue
-        srv.submit(dev_pool[int(rng.integers(len(dev_pool)))])
+        k = int(rng.integers(len(dev_pool)))
+        rid = srv.submit(dev_pool[k])
+        cls[rid] = f"{pool[k][0].shape[0]}x{pool[k][0].shape[1]}"
         n_sub += 1
         t_next += rng.exponential(1.0 / rate)
-    lat += drain(n_sub - len(lat), 120)
+    t0 = time.time()
+    while len(lat) < n_sub and time.time() - t0 < 120:
+        collect(srv.poll(timeout_ms=100))
     srv.close()
     lat = np.sort(np.asarray(lat))
+    per_class = {c: {"count": len(v), "p50_ms": float(np.percentile(v, 50) * 1e3),
+                     "p99_ms": float(np.percentile(v, 99) * 1e3)}
+                 for c, v in sorted(by_class.items(), key=lambda kv: int(kv[0].split("x")[1]))}
     return {"workload": "12 shape classes n in {16,...,512} x {square, 2n x n}, FP64/FP32 "
                         "alternating, geometric spectrum kappa log-uniform [1, 1e8]",
             "saturation_svds_per_s": sat, "offered_load": args.serve_load,
             "offered_rate_per_s": rate, "requests": int(n_sub), "completed": int(lat.size),
             "p50_ms": float(np.percentile(lat, 50) * 1e3) if lat.size else None,
             "p99_ms": float(np.percentile(lat, 99) * 1e3) if lat.size else None,
-            "budget_bytes": budget}
+            "per_class": per_class, "budget_bytes": budget}
 
 
 def flops_blocked(m, n, nb, sweeps, cf=1):

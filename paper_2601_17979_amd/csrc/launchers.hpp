@@ -30,6 +30,24 @@ hipError_t launch_precond_d(int batch, int m, int n, int ns, const double *A, in
                             long long sU, double *V, int ldv, long long sV, double tol,
                             int max_sweeps, int *info, int *sweeps, void *ws, hipStream_t stream);
 bool precond_big_supported(int m, int n);
+
+// QR preconditioning of single requests (serving runtime): one QrJob per
+// matrix in device memory; list (device) selects the jobs of a launch.
+struct QrJob {
+    const void *A;            // input, lda, m x n (m <= 1024, n <= 512)
+    int lda, m, n, f32;       // f32: A holds floats
+    double *Vq, *X, *tau;     // workspace: reflectors (m x n), X = R^T (n x n), tau (n)
+    const double *Y;          // J from the Jacobi on X (n x n, ld n)
+    void *U;                  // output U (ldu), or NULL
+    int ldu, uf32;            // uf32: U, S and V are floats
+    const double *S64, *Vx64; // FP64 staging of S and V (FP32 requests)
+    void *Sout, *Vout;        // FP32 outputs S and V (V may be NULL), ldv
+    int ldv, pad;
+    const int *info;          // the request's status
+};
+void launch_qr_jobs(const QrJob *jobs, const int *list, int count, hipStream_t stream);
+void launch_apply_q_jobs(const QrJob *jobs, const int *list, int count, int max_m,
+                         hipStream_t stream);
 size_t precond_big_workspace_bytes(int batch, int m, int n, int nb);
 hipError_t launch_precond_big_d(int batch, int m, int n, int nb, const double *A, int lda,
                                 long long sA, double *S, long long sS, double *U, int ldu,

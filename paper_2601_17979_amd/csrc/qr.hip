@@ -241,24 +241,25 @@ bool qr_shape(int m, int n, int *rpl, int *cpg)
 // block of 16 columns of U per workgroup, held in registers.
 // ---------------------------------------------------------------------------
 constexpr int kQrMaxM = 1024;
+constexpr int kQrMaxN = 512;
 
-__global__ __launch_bounds__(kQT) void qr_house_g(int m, int n, const double *__restrict__ A,
-                                                  int lda, long long sA, double *Vq, double *X,
-                                                  double *tau_out)
+// One matrix per workgroup: A (m x n, lda; FP64 or FP32) -> H (the
+// workspace, m x n, ld m): R in the upper triangle, then the reflectors as
+// full columns; X = R^T (unscaled, n x n, ld n); tau (n).
+template <class TA>
+__device__ __forceinline__ void qr_house_body(int m, int n, const TA *__restrict__ A, int lda,
+                                              double *H, double *X, double *tau)
 {
     __shared__ double vbuf[2][kQrMaxM];
     __shared__ double s_tau[2];
     __shared__ double s_max[kQT / 64];
     __shared__ int s_bad[kQT / 64];
-    const int b = blockIdx.x, tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+    const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
     const int grp = tid >> 4, gl = tid & 15;
-    A += (size_t)b * sA;
-    double *H = Vq + (size_t)b * m * n;
-    double *tau = tau_out + (size_t)b * n;
     double amax = 0.0;
     int bad = 0;
     for (size_t idx = tid; idx < (size_t)m * n; idx += kQT) {
-        const double a = A[(idx / m) * lda + idx % m];
+        const double a = (double)A[(idx / m) * lda + idx % m];
         bad |= !isfinite(a);
         amax = fmax(amax, fabs(a));
     }
@@ -273,7 +274,7 @@ __global__ __launch_bounds__(kQT) void qr_house_g(int m, int n, const double *__
     const bool finite = !(s_bad[0] | s_bad[1] | s_bad[2] | s_bad[3]);
     const double scale = finite ? pow2_scale(amax) : 1.0;
     for (size_t idx = tid; idx < (size_t)m * n; idx += kQT)
-        H[idx] = A[(idx / m) * lda + idx % m] * scale;
+        H[idx] = (double)A[(idx / m) * lda + idx % m] * scale;
     __syncthreads();
     for (int j = 0; j < n && finite; j++) {
         double *vb = vbuf[j & 1];
@@ -317,7 +318,6 @@ __global__ __launch_bounds__(kQT) void qr_house_g(int m, int n, const double *__
     }
     __syncthreads();
     // X = R^T / scale, then the reflectors as full columns
-    X += (size_t)b * n * n;
     const double inv = 1.0 / scale;
     for (size_t idx = tid; idx < (size_t)n * n; idx += kQT) {
         const int r = (int)(idx % n), c = (int)(idx / n);   // X(r, c) = R(c, r)
@@ -332,24 +332,26 @@ __global__ __launch_bounds__(kQT) void qr_house_g(int m, int n, const double *__
         for (int j = tid; j < n; j += kQT) tau[j] = 0.0;
 }
 
+__global__ __launch_bounds__(kQT) void qr_house_g(int m, int n, const double *__restrict__ A,
+                                                  int lda, long long sA, double *Vq, double *X,
+                                                  double *tau_out)
+{
+    const int b = blockIdx.x;
+    qr_house_body<double>(m, n, A + (size_t)b * sA, lda, Vq + (size_t)b * m * n,
+                          X + (size_t)b * n * n, tau_out + (size_t)b * n);
+}
+
 // U[:, 16 blk .. 16 blk + 15] = Q [Y; 0] for one block of 16 columns: group g
 // owns column 16 blk + g, lane x rows x, x + 16, ... (RPL of them).  The
 // reflector of each step is staged in LDS (double buffered, one barrier).
-template <int RPL>
-__global__ __launch_bounds__(kQT) void apply_q_g(int m, int n, const double *__restrict__ Vq,
-                                                 const double *__restrict__ tau,
-                                                 const double *__restrict__ Y, double *U, int ldu,
-                                                 long long sU, const int *info)
+// TO: element type of U.
+template <int RPL, class TO>
+__device__ __forceinline__ void apply_q_body(int m, int n, int blk, const double *__restrict__ Vq,
+                                             const double *__restrict__ tau,
+                                             const double *__restrict__ Y, TO *U, int ldu)
 {
     __shared__ double vbuf[2][16 * RPL];
-    const int nblk = (n + 15) / 16;
-    const int b = blockIdx.x / nblk, blk = blockIdx.x % nblk;
     const int tid = threadIdx.x, grp = tid >> 4, gl = tid & 15;
-    if (info[b] == 2) return;
-    Vq += (size_t)b * m * n;
-    tau += (size_t)b * n;
-    Y += (size_t)b * n * n;
-    U += (size_t)b * sU;
     const int col = 16 * blk + grp;
     double u[RPL];
 #pragma unroll
@@ -378,8 +380,57 @@ __global__ __launch_bounds__(kQT) void apply_q_g(int m, int n, const double *__r
 #pragma unroll
         for (int r = 0; r < RPL; r++) {
             const int row = gl + 16 * r;
-            if (row < m) U[(size_t)col * ldu + row] = u[r];
+            if (row < m) U[(size_t)col * ldu + row] = (TO)u[r];
         }
+}
+
+template <int RPL>
+__global__ __launch_bounds__(kQT) void apply_q_g(int m, int n, const double *__restrict__ Vq,
+                                                 const double *__restrict__ tau,
+                                                 const double *__restrict__ Y, double *U, int ldu,
+                                                 long long sU, const int *info)
+{
+    const int nblk = (n + 15) / 16;
+    const int b = blockIdx.x / nblk, blk = blockIdx.x % nblk;
+    if (info[b] == 2) return;
+    apply_q_body<RPL, double>(m, n, blk, Vq + (size_t)b * m * n, tau + (size_t)b * n,
+                              Y + (size_t)b * n * n, U + (size_t)b * sU, ldu);
+}
+
+// ---- descriptor-driven variants for the serving runtime -------------------
+__global__ __launch_bounds__(kQT) void qr_house_job(const QrJob *jobs, const int *list)
+{
+    const QrJob J = jobs[list[blockIdx.x]];
+    if (J.f32)
+        qr_house_body<float>(J.m, J.n, (const float *)J.A, J.lda, J.Vq, J.X, J.tau);
+    else
+        qr_house_body<double>(J.m, J.n, (const double *)J.A, J.lda, J.Vq, J.X, J.tau);
+}
+
+// one workgroup per (job, block of 16 columns); also converts S and V to
+// FP32 for FP32 requests (block 0 of the job)
+template <int RPL>
+__global__ __launch_bounds__(kQT) void apply_q_job(const QrJob *jobs, const int *list)
+{
+    constexpr int kMaxBlk = kQrMaxN / 16;
+    const QrJob J = jobs[list[blockIdx.x / kMaxBlk]];
+    const int blk = blockIdx.x % kMaxBlk;
+    if (16 * blk >= J.n || *J.info == 2) return;
+    if (J.U) {
+        if (J.uf32)
+            apply_q_body<RPL, float>(J.m, J.n, blk, J.Vq, J.tau, J.Y, (float *)J.U, J.ldu);
+        else
+            apply_q_body<RPL, double>(J.m, J.n, blk, J.Vq, J.tau, J.Y, (double *)J.U, J.ldu);
+    }
+    if (J.uf32) {   // S and V from their FP64 staging
+        const int tid = threadIdx.x;
+        for (int c = 16 * blk; c < 16 * blk + 16 && c < J.n; c++) {
+            if (tid == 0) ((float *)J.Sout)[c] = (float)J.S64[c];
+            if (J.Vout)
+                for (int r = tid; r < J.n; r += kQT)
+                    ((float *)J.Vout)[(size_t)c * J.ldv + r] = (float)J.Vx64[(size_t)c * J.n + r];
+        }
+    }
 }
 
 size_t al256(size_t x) { return (x + 255) & ~(size_t)255; }
@@ -458,6 +509,28 @@ hipError_t launch_precond_d(int batch, int m, int n, int ns, const double *A, in
         e = hipGetLastError();
     }
     return e;
+}
+
+void launch_qr_jobs(const QrJob *jobs, const int *list, int count, hipStream_t stream)
+{
+    if (count > 0)
+        hipLaunchKernelGGL(qr_house_job, dim3((unsigned)count), dim3(kQT), 0, stream, jobs, list);
+}
+
+void launch_apply_q_jobs(const QrJob *jobs, const int *list, int count, int max_m,
+                         hipStream_t stream)
+{
+    if (count <= 0) return;
+    const dim3 grid((unsigned)(count * (kQrMaxN / 16)));
+    const int rpl = (max_m + 15) / 16;
+    if (rpl <= 8)
+        hipLaunchKernelGGL(apply_q_job<8>, grid, dim3(kQT), 0, stream, jobs, list);
+    else if (rpl <= 16)
+        hipLaunchKernelGGL(apply_q_job<16>, grid, dim3(kQT), 0, stream, jobs, list);
+    else if (rpl <= 32)
+        hipLaunchKernelGGL(apply_q_job<32>, grid, dim3(kQT), 0, stream, jobs, list);
+    else
+        hipLaunchKernelGGL(apply_q_job<64>, grid, dim3(kQT), 0, stream, jobs, list);
 }
 
 bool precond_big_supported(int m, int n)

@@ -95,6 +95,8 @@ private:
 struct Request {
     long long id = 0;
     int dtype = 1, m = 0, n = 0, lda = 1, ldu = 1, ldv = 1;
+    int group = 1;   // kernel group (dtype of the working copies)
+    int pc = 0;      // QR-preconditioned: FP64 Jacobi on R^T, U = Q J
     const void *A = nullptr;
     void *S = nullptr, *U = nullptr, *V = nullptr;
     int *info = nullptr, *sweeps = nullptr;
@@ -110,6 +112,37 @@ struct Completion {
 
 int elt_of(int dtype) { return dtype == 0 ? 4 : dtype == 3 ? 16 : 8; }
 
+// Arena layout of a QR-preconditioned request (FP64, byte offsets from its
+// range): the Jacobi's W (n x np) and V (np x np), X = R^T, the reflectors
+// (m x n), tau, J, and for FP32 requests the FP64 staging of S and V.
+struct PcLayout {
+    size_t w, v, x, q, tau, j, s64, vx64, bytes;
+};
+
+PcLayout pc_layout(int m, int n, int np, bool f32)
+{
+    PcLayout L{};
+    size_t o = 0;
+    L.w = o;
+    o += al256((size_t)n * np * 8);
+    L.v = o;
+    o += al256((size_t)np * np * 8);
+    L.x = o;
+    o += al256((size_t)n * n * 8);
+    L.q = o;
+    o += al256((size_t)m * n * 8);
+    L.tau = o;
+    o += al256((size_t)n * 8);
+    L.j = o;
+    o += al256((size_t)n * n * 8);
+    L.s64 = o;
+    o += f32 ? al256((size_t)n * 8) : 0;
+    L.vx64 = o;
+    o += f32 ? al256((size_t)n * n * 8) : 0;
+    L.bytes = o;
+    return L;
+}
+
 // One dtype: the kernels are compiled per element type.
 struct Group {
     int dtype = 1;
@@ -119,6 +152,8 @@ struct Group {
     int *d_flags = nullptr, *h_flags = nullptr;
     int2 *d_work = nullptr, *h_work = nullptr;
     int *d_idx = nullptr, *h_idx = nullptr;
+    svdb::QrJob *d_jobs = nullptr, *h_jobs = nullptr;   // QR preconditioning (FP64 group)
+    int *d_idx2 = nullptr, *h_idx2 = nullptr;
     std::vector<Request> slot;
     std::vector<char> used;
     std::vector<int> fresh;   // slots admitted this round
@@ -138,6 +173,7 @@ struct svdb_server {
     Group g[4];
     int max_sweeps = 100;
     int max_n = 512;
+    int precondition = 1;
     std::mutex mu;
     std::condition_variable cv_work, cv_done;
     std::deque<Request> queue;
@@ -200,7 +236,7 @@ void worker_main(svdb_server *s)
             if (s->stop && s->queue.empty() && !active()) return;
             while (!s->queue.empty()) {
                 Request &r = s->queue.front();
-                Group &G = s->g[r.dtype];
+                Group &G = s->g[r.group];
                 int b = -1;
                 for (int k = 0; k < G.cap; k++)
                     if (!G.used[k]) {
@@ -222,27 +258,65 @@ void worker_main(svdb_server *s)
         for (auto &G : s->g) {
             if (G.fresh.empty()) continue;
             const size_t elt = (size_t)elt_of(G.dtype);
-            int lo = G.cap, hi = -1;
+            char *base = (char *)s->arena;
+            int lo = G.cap, hi = -1, npc = 0;
             for (size_t k = 0; k < G.fresh.size(); k++) {
                 const int b = G.fresh[k];
                 const Request &r = G.slot[b];
                 svdb::VbDesc D{};
-                D.A = r.A;
-                D.S = r.S;
-                D.U = r.U;
-                D.V = r.V;
                 D.info = r.info;
                 D.sweeps = r.sweeps;
-                D.m = r.m;
                 D.n = r.n;
-                D.lda = r.lda;
-                D.ldu = r.ldu;
-                D.ldv = r.ldv;
                 D.np = r.n > 0 ? svdb::blocked_np(r.n, nb) : 0;
                 D.l = r.n > 0 ? D.np / nb : 2;
                 D.it0 = s->itg;
-                D.woff = (long long)(r.off / elt);
-                D.voff = D.woff + (long long)D.m * D.np;
+                if (r.pc) {
+                    // the Jacobi runs on X = R^T (n x n); its U is our V, its V is J
+                    const bool f32 = r.dtype == SVDB_R32;
+                    const PcLayout P = pc_layout(r.m, r.n, D.np, f32);
+                    D.A = base + r.off + P.x;
+                    D.lda = r.n;
+                    D.m = r.n;
+                    D.S = f32 ? (void *)(base + r.off + P.s64) : r.S;
+                    D.U = r.V ? (f32 ? (void *)(base + r.off + P.vx64) : r.V) : nullptr;
+                    D.ldu = f32 ? r.n : r.ldv;
+                    D.V = r.U ? (void *)(base + r.off + P.j) : nullptr;
+                    D.ldv = r.n;
+                    D.woff = (long long)((r.off + P.w) / 8);
+                    D.voff = (long long)((r.off + P.v) / 8);
+                    svdb::QrJob J{};
+                    J.A = r.A;
+                    J.lda = r.lda;
+                    J.m = r.m;
+                    J.n = r.n;
+                    J.f32 = f32;
+                    J.Vq = (double *)(base + r.off + P.q);
+                    J.X = (double *)(base + r.off + P.x);
+                    J.tau = (double *)(base + r.off + P.tau);
+                    J.Y = (const double *)(base + r.off + P.j);
+                    J.U = r.U;
+                    J.ldu = r.ldu;
+                    J.uf32 = f32;
+                    J.S64 = (const double *)(base + r.off + P.s64);
+                    J.Vx64 = (const double *)(base + r.off + P.vx64);
+                    J.Sout = r.S;
+                    J.Vout = r.V;
+                    J.ldv = r.ldv;
+                    J.info = r.info;
+                    G.h_jobs[b] = J;
+                    G.h_idx2[npc++] = b;
+                } else {
+                    D.A = r.A;
+                    D.S = r.S;
+                    D.U = r.U;
+                    D.V = r.V;
+                    D.m = r.m;
+                    D.lda = r.lda;
+                    D.ldu = r.ldu;
+                    D.ldv = r.ldv;
+                    D.woff = (long long)(r.off / elt);
+                    D.voff = D.woff + (long long)D.m * D.np;
+                }
                 G.h_desc[b] = D;
                 G.h_idx[k] = b;
                 lo = b < lo ? b : lo;
@@ -253,6 +327,15 @@ void worker_main(svdb_server *s)
                                      hipMemcpyHostToDevice, s->stream));
             SRV_CHECK(hipMemcpyAsync(G.d_idx, G.h_idx, G.fresh.size() * sizeof(int),
                                      hipMemcpyHostToDevice, s->stream));
+            if (npc) {
+                SRV_CHECK(hipMemcpyAsync(G.d_jobs + lo, G.h_jobs + lo,
+                                         (size_t)(hi - lo + 1) * sizeof(svdb::QrJob),
+                                         hipMemcpyHostToDevice, s->stream));
+                SRV_CHECK(hipMemcpyAsync(G.d_idx2, G.h_idx2, (size_t)npc * sizeof(int),
+                                         hipMemcpyHostToDevice, s->stream));
+                svdb::launch_qr_jobs(G.d_jobs, G.d_idx2, npc, s->stream);
+                SRV_CHECK(hipGetLastError());
+            }
             svdb::vb_launch_init(G.dtype, G.d_desc, G.d_idx, (int)G.fresh.size(), s->arena,
                                  G.d_st, s->stream);
             SRV_CHECK(hipGetLastError());
@@ -307,6 +390,19 @@ void worker_main(svdb_server *s)
             svdb::vb_launch_finalize(G.dtype, G.d_desc, G.d_idx, cnt, maxn, s->arena, G.d_st,
                                      s->stream);
             SRV_CHECK(hipGetLastError());
+            int npc = 0, maxm = 0;
+            for (int k = 0; k < cnt; k++) {
+                const Request &r = G.slot[G.h_idx[k]];
+                if (!r.pc) continue;
+                G.h_idx2[npc++] = G.h_idx[k];
+                maxm = r.m > maxm ? r.m : maxm;
+            }
+            if (npc) {
+                SRV_CHECK(hipMemcpyAsync(G.d_idx2, G.h_idx2, (size_t)npc * sizeof(int),
+                                         hipMemcpyHostToDevice, s->stream));
+                svdb::launch_apply_q_jobs(G.d_jobs, G.d_idx2, npc, maxm, s->stream);
+                SRV_CHECK(hipGetLastError());
+            }
         }
         if (retired.empty()) continue;
         SRV_CHECK(hipStreamSynchronize(s->stream));
@@ -340,6 +436,10 @@ void destroy_resources(svdb_server *s)
         if (G.h_flags) (void)hipHostFree(G.h_flags);
         if (G.h_work) (void)hipHostFree(G.h_work);
         if (G.h_idx) (void)hipHostFree(G.h_idx);
+        if (G.d_jobs) (void)hipFree(G.d_jobs);
+        if (G.h_jobs) (void)hipHostFree(G.h_jobs);
+        if (G.d_idx2) (void)hipFree(G.d_idx2);
+        if (G.h_idx2) (void)hipHostFree(G.h_idx2);
     }
     if (s->arena) (void)hipFree(s->arena);
     if (s->stream) (void)hipStreamDestroy(s->stream);
@@ -365,6 +465,7 @@ int svdb_server_create(svdb_server_t **out, size_t budget_bytes, int max_request
     svdb_server *s = new svdb_server();
     s->budget = al256(budget_bytes);
     s->max_sweeps = o.max_sweeps > 0 ? o.max_sweeps : 100;
+    s->precondition = o.precondition == 1;
     hipError_t e = hipStreamCreateWithFlags(&s->stream, hipStreamNonBlocking);
     if (e == hipSuccess) e = hipMalloc(&s->arena, s->budget);
     const int pairs = s->max_n / svdb::vb_nb() / 2;   // block pairs of the widest request
@@ -386,6 +487,10 @@ int svdb_server_create(svdb_server_t **out, size_t budget_bytes, int max_request
         if (e == hipSuccess) e = hipHostMalloc((void **)&G.h_flags, nc * sizeof(int), 0);
         if (e == hipSuccess) e = hipHostMalloc((void **)&G.h_work, nc * pairs * sizeof(int2), 0);
         if (e == hipSuccess) e = hipHostMalloc((void **)&G.h_idx, nc * sizeof(int), 0);
+        if (e == hipSuccess) e = hipMalloc((void **)&G.d_jobs, nc * sizeof(svdb::QrJob));
+        if (e == hipSuccess) e = hipHostMalloc((void **)&G.h_jobs, nc * sizeof(svdb::QrJob), 0);
+        if (e == hipSuccess) e = hipMalloc((void **)&G.d_idx2, nc * sizeof(int));
+        if (e == hipSuccess) e = hipHostMalloc((void **)&G.h_idx2, nc * sizeof(int), 0);
         if (e == hipSuccess) svdb::vb_launch_mark_empty(G.cap, G.d_st, s->stream);
     }
     if (e == hipSuccess) e = hipStreamSynchronize(s->stream);
@@ -429,7 +534,10 @@ long long svdb_server_submit(svdb_server_t *s, svdb_dtype_t dtype, int m, int n,
     r.info = info;
     r.sweeps = sweeps;
     const int np = n > 0 ? svdb::blocked_np(n, svdb::vb_nb()) : 0;
-    r.bytes = al256(((size_t)m * np + (size_t)np * np) * (size_t)elt_of(r.dtype));
+    r.pc = s->precondition && (dtype == SVDB_R32 || dtype == SVDB_R64) && n > 0 && m <= 1024;
+    r.group = r.pc ? SVDB_R64 : r.dtype;
+    r.bytes = r.pc ? pc_layout(m, n, np, dtype == SVDB_R32).bytes
+                   : al256(((size_t)m * np + (size_t)np * np) * (size_t)elt_of(r.dtype));
     if (r.bytes > s->budget) return SVDB_ERR_UNSUPPORTED;
     (void)tol;   // per-dtype default threshold (30 u)
     std::lock_guard<std::mutex> lk(s->mu);

@@ -268,9 +268,9 @@ class Server:
     tensor of a request alive until it completes."""
 
     def __init__(self, budget_bytes: int, max_requests: int = 1024, max_sweeps: int = 100,
-                 device=None):
+                 device=None, precondition: int = -1):
         self._dev = torch.device(device or "cuda")
-        o = make_opts(max_sweeps=max_sweeps)
+        o = make_opts(max_sweeps=max_sweeps, precondition=precondition)
         h = C.c_void_p()
         rc = lib().svdb_server_create(C.byref(h), int(budget_bytes), int(max_requests),
                                       C.byref(o))

@@ -94,7 +94,8 @@ def test_server_alone_equals_in_mix():
 
 def test_server_budget_admission():
     """A budget that holds only two working sets at a time still serves a
-    longer queue; the arena never exceeds the budget."""
+    longer queue; the arena never exceeds the budget.  (Without QR
+    preconditioning, so that a working set is W (m x np) and V (np x np).)"""
     import torch
     from paper_2601_17979_amd import svdb
     m, n = 128, 96
@@ -103,7 +104,7 @@ def test_server_budget_admission():
     mats = [_mat(9700, k, m, n, np.float64) for k in range(10)]
     dev = [_to_dev(A) for A in mats]
     torch.cuda.synchronize()
-    srv = svdb.Server(budget_bytes=budget, max_requests=8)
+    srv = svdb.Server(budget_bytes=budget, max_requests=8, precondition=0)
     ids = {srv.submit(x): k for k, x in enumerate(dev)}
     got = {}
     peak = 0
@@ -120,8 +121,30 @@ def test_server_budget_admission():
     for rid, out in got.items():
         _check(mats[ids[rid]], out, f"budget #{ids[rid]}")
     with pytest.raises(svdb.SvdbError):
-        srv2 = svdb.Server(budget_bytes=4096, max_requests=2)
+        srv2 = svdb.Server(budget_bytes=4096, max_requests=2, precondition=0)
         try:
             srv2.submit(dev[0])
         finally:
             srv2.close()
+
+
+@pytest.mark.parametrize("precondition", [0, 1])
+def test_server_precondition_modes(precondition):
+    """FP64 and FP32 requests with and without QR preconditioning (FP32
+    requests are then solved in FP64 and returned in FP32)."""
+    import torch
+    from paper_2601_17979_amd import svdb
+    shapes = [(48, 40), (130, 96), (300, 200), (64, 64)]
+    reqs = [_mat(9800, k, m, n, np.float64 if k % 2 else np.float32, kappa=1e6)
+            for k, (m, n) in enumerate(shapes * 2)]
+    dev = [_to_dev(A) for A in reqs]
+    torch.cuda.synchronize()
+    srv = svdb.Server(budget_bytes=512 << 20, max_requests=32,
+                      precondition=1 if precondition else 0)
+    ids = {srv.submit(x): k for k, x in enumerate(dev)}
+    got = _drain(srv, len(reqs))
+    srv.close()
+    for rid, (ts, td, out) in got.items():
+        k = ids[rid]
+        assert out[0].dtype == (torch.float64 if reqs[k].dtype == np.float64 else torch.float32)
+        _check(reqs[k], out, f"precondition={precondition} #{k} {reqs[k].shape}")
