@@ -70,7 +70,8 @@ def serve_leg(args, dev):
                 for A, d in pool]
     torch.cuda.synchronize()
     budget = 8 << 30
-    srv = svdb.Server(budget_bytes=budget, max_requests=2048)
+    srv = svdb.Server(budget_bytes=budget, max_requests=2048,
+                      precondition=1 if args.serve_precondition else 0)
 
     def drain(n, t_limit):
         lat, t0 = [], time.time()
@@ -127,7 +128,8 @@ def serve_leg(args, dev):
             "offered_rate_per_s": rate, "requests": int(n_sub), "completed": int(lat.size),
             "p50_ms": float(np.percentile(lat, 50) * 1e3) if lat.size else None,
             "p99_ms": float(np.percentile(lat, 99) * 1e3) if lat.size else None,
-            "per_class": per_class, "budget_bytes": budget}
+            "per_class": per_class, "budget_bytes": budget,
+            "qr_preconditioning": bool(args.serve_precondition)}
 
 
 def flops_blocked(m, n, nb, sweeps, cf=1):
@@ -286,6 +288,8 @@ def main():
                     help="skip the plain GPU Jacobi comparator run")
     ap.add_argument("--serve-seconds", type=float, default=8.0,
                     help="length of the Poisson serving run (0 = skip the serving leg)")
+    ap.add_argument("--serve-precondition", type=int, default=0,
+                    help="1: QR-precondition the real requests of the serving leg")
     ap.add_argument("--serve-load", type=float, default=0.5,
                     help="offered load as a fraction of the measured saturation rate")
     ap.add_argument("--workload", default="mixed", choices=["mixed", "square256", "uneven"],

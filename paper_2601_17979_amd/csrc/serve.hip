@@ -153,9 +153,24 @@ struct Group {
     int2 *d_work = nullptr, *h_work = nullptr;
     int *d_idx = nullptr, *h_idx = nullptr;
     svdb::QrJob *d_jobs = nullptr, *h_jobs = nullptr;   // QR preconditioning (FP64 group)
-    int *d_idx2 = nullptr, *h_idx2 = nullptr;
     std::vector<Request> slot;
     std::vector<char> used;
+    // QR-preconditioned slots: 0 in the launches (or not preconditioned),
+    // 1 waiting for or in the QR, 2 waiting for or in the application of Q
+    std::vector<char> stage;
+    // work on the auxiliary streams: at most one batch in flight per lane, the
+    // requests that arrive meanwhile wait and form the next batch, so batches
+    // grow with the load
+    struct Lane {
+        std::vector<int> wait;   // slots waiting for the lane
+        std::vector<int> cur;    // the batch in flight
+        hipEvent_t ev = nullptr;
+        int pos = 0;             // its slot list in the device ring
+        bool busy = false;
+    };
+    Lane lane[3];   // QR of requests with n <= 64, QR of wider ones, application of Q
+    int *d_ring = nullptr, *h_ring = nullptr;
+    int ring_len = 0, ring_head = 0;
     std::vector<int> fresh;   // slots admitted this round
     int nused = 0, nwork = 0, lmax = 2, maxn = 0;
     bool dirty = false;
@@ -167,6 +182,8 @@ struct Group {
 
 struct svdb_server {
     hipStream_t stream = nullptr;
+    hipStream_t aux[3] = {};       // the lanes of preconditioned requests
+    hipEvent_t ev_fin = nullptr;   // end of the finalisations of a round
     void *arena = nullptr;
     size_t budget = 0;
     Arena alloc;
@@ -205,7 +222,7 @@ void rebuild_work(Group &G)
     // largest matrices first; only slots still sweeping
     std::vector<int> order;
     for (int b = 0; b < G.cap; b++)
-        if (G.used[b]) order.push_back(b);
+        if (G.used[b] && G.stage[b] == 0) order.push_back(b);
     std::stable_sort(order.begin(), order.end(),
                      [&](int x, int y) { return G.slot[x].n > G.slot[y].n; });
     int w = 0, lmax = 2, maxn = 0;
@@ -220,9 +237,112 @@ void rebuild_work(Group &G)
     G.maxn = maxn;
 }
 
-void worker_main(svdb_server *s)
+// Descriptor (and, when preconditioned, QR job) of a request admitted into
+// slot b of group G.
+void describe(svdb_server *s, Group &G, int b)
 {
     const int nb = svdb::vb_nb();
+    const size_t elt = (size_t)elt_of(G.dtype);
+    char *base = (char *)s->arena;
+    const Request &r = G.slot[b];
+    svdb::VbDesc D{};
+    D.info = r.info;
+    D.sweeps = r.sweeps;
+    D.n = r.n;
+    D.np = r.n > 0 ? svdb::blocked_np(r.n, nb) : 0;
+    D.l = r.n > 0 ? D.np / nb : 2;
+    D.it0 = s->itg;
+    if (r.pc) {
+        // the Jacobi runs on X = R^T (n x n); its U is our V, its V is J
+        const bool f32 = r.dtype == SVDB_R32;
+        const PcLayout P = pc_layout(r.m, r.n, D.np, f32);
+        D.A = base + r.off + P.x;
+        D.lda = r.n;
+        D.m = r.n;
+        D.S = f32 ? (void *)(base + r.off + P.s64) : r.S;
+        D.U = r.V ? (f32 ? (void *)(base + r.off + P.vx64) : r.V) : nullptr;
+        D.ldu = f32 ? r.n : r.ldv;
+        D.V = r.U ? (void *)(base + r.off + P.j) : nullptr;
+        D.ldv = r.n;
+        D.woff = (long long)((r.off + P.w) / 8);
+        D.voff = (long long)((r.off + P.v) / 8);
+        svdb::QrJob J{};
+        J.A = r.A;
+        J.lda = r.lda;
+        J.m = r.m;
+        J.n = r.n;
+        J.f32 = f32;
+        J.Vq = (double *)(base + r.off + P.q);
+        J.X = (double *)(base + r.off + P.x);
+        J.tau = (double *)(base + r.off + P.tau);
+        J.Y = (const double *)(base + r.off + P.j);
+        J.U = r.U;
+        J.ldu = r.ldu;
+        J.uf32 = f32;
+        J.S64 = (const double *)(base + r.off + P.s64);
+        J.Vx64 = (const double *)(base + r.off + P.vx64);
+        J.Sout = r.S;
+        J.Vout = r.V;
+        J.ldv = r.ldv;
+        J.info = r.info;
+        G.h_jobs[b] = J;
+    } else {
+        D.A = r.A;
+        D.S = r.S;
+        D.U = r.U;
+        D.V = r.V;
+        D.m = r.m;
+        D.lda = r.lda;
+        D.ldu = r.ldu;
+        D.ldv = r.ldv;
+        D.woff = (long long)(r.off / elt);
+        D.voff = D.woff + (long long)D.m * D.np;
+    }
+    G.h_desc[b] = D;
+}
+
+// Copies the lane's waiting slots into the device ring (on `st`) as its
+// new batch; first waits for any batch in flight whose list would be
+// overwritten.
+hipError_t lane_stage(Group &G, Group::Lane &L, hipStream_t st)
+{
+    const int n = (int)L.wait.size();
+    if (G.ring_head + n > G.ring_len) G.ring_head = 0;
+    const int lo = G.ring_head, hi = G.ring_head + n;
+    for (auto &O : G.lane)
+        if (O.busy && O.pos < hi && lo < O.pos + (int)O.cur.size()) {
+            const hipError_t e = hipEventSynchronize(O.ev);
+            if (e != hipSuccess) return e;
+        }
+    for (int k = 0; k < n; k++) G.h_ring[lo + k] = L.wait[k];
+    G.ring_head = hi;
+    L.pos = lo;
+    L.cur.swap(L.wait);
+    L.wait.clear();
+    if (!L.ev) {
+        const hipError_t e = hipEventCreateWithFlags(&L.ev, hipEventDisableTiming);
+        if (e != hipSuccess) return e;
+    }
+    return hipMemcpyAsync(G.d_ring + lo, G.h_ring + lo, (size_t)n * sizeof(int),
+                          hipMemcpyHostToDevice, st);
+}
+
+// hipSuccess with *done set once the lane's batch has finished
+hipError_t lane_done(Group::Lane &L, bool *done)
+{
+    *done = false;
+    if (!L.busy) return hipSuccess;
+    const hipError_t q = hipEventQuery(L.ev);
+    if (q == hipErrorNotReady) return hipSuccess;
+    if (q != hipSuccess) return q;
+    L.busy = false;
+    *done = true;
+    return hipSuccess;
+}
+
+void worker_main(svdb_server *s)
+{
+    std::vector<int> init;   // slots to initialise this round
     for (;;) {
         // ---- 1. admission ----------------------------------------------------
         {
@@ -248,101 +368,65 @@ void worker_main(svdb_server *s)
                 r.off = off;
                 G.slot[b] = r;
                 G.used[b] = 1;
+                G.stage[b] = r.pc ? 1 : 0;
                 G.nused++;
                 G.fresh.push_back(b);
-                G.dirty = true;
                 s->queue.pop_front();
             }
         }
-        // ---- initialise the admitted requests ----------------------------------
+        // ---- preconditioned requests go to a QR lane; the others are
+        // initialised below, with those whose QR has finished ------------------
         for (auto &G : s->g) {
-            if (G.fresh.empty()) continue;
-            const size_t elt = (size_t)elt_of(G.dtype);
-            char *base = (char *)s->arena;
-            int lo = G.cap, hi = -1, npc = 0;
-            for (size_t k = 0; k < G.fresh.size(); k++) {
-                const int b = G.fresh[k];
-                const Request &r = G.slot[b];
-                svdb::VbDesc D{};
-                D.info = r.info;
-                D.sweeps = r.sweeps;
-                D.n = r.n;
-                D.np = r.n > 0 ? svdb::blocked_np(r.n, nb) : 0;
-                D.l = r.n > 0 ? D.np / nb : 2;
-                D.it0 = s->itg;
-                if (r.pc) {
-                    // the Jacobi runs on X = R^T (n x n); its U is our V, its V is J
-                    const bool f32 = r.dtype == SVDB_R32;
-                    const PcLayout P = pc_layout(r.m, r.n, D.np, f32);
-                    D.A = base + r.off + P.x;
-                    D.lda = r.n;
-                    D.m = r.n;
-                    D.S = f32 ? (void *)(base + r.off + P.s64) : r.S;
-                    D.U = r.V ? (f32 ? (void *)(base + r.off + P.vx64) : r.V) : nullptr;
-                    D.ldu = f32 ? r.n : r.ldv;
-                    D.V = r.U ? (void *)(base + r.off + P.j) : nullptr;
-                    D.ldv = r.n;
-                    D.woff = (long long)((r.off + P.w) / 8);
-                    D.voff = (long long)((r.off + P.v) / 8);
-                    svdb::QrJob J{};
-                    J.A = r.A;
-                    J.lda = r.lda;
-                    J.m = r.m;
-                    J.n = r.n;
-                    J.f32 = f32;
-                    J.Vq = (double *)(base + r.off + P.q);
-                    J.X = (double *)(base + r.off + P.x);
-                    J.tau = (double *)(base + r.off + P.tau);
-                    J.Y = (const double *)(base + r.off + P.j);
-                    J.U = r.U;
-                    J.ldu = r.ldu;
-                    J.uf32 = f32;
-                    J.S64 = (const double *)(base + r.off + P.s64);
-                    J.Vx64 = (const double *)(base + r.off + P.vx64);
-                    J.Sout = r.S;
-                    J.Vout = r.V;
-                    J.ldv = r.ldv;
-                    J.info = r.info;
-                    G.h_jobs[b] = J;
-                    G.h_idx2[npc++] = b;
-                } else {
-                    D.A = r.A;
-                    D.S = r.S;
-                    D.U = r.U;
-                    D.V = r.V;
-                    D.m = r.m;
-                    D.lda = r.lda;
-                    D.ldu = r.ldu;
-                    D.ldv = r.ldv;
-                    D.woff = (long long)(r.off / elt);
-                    D.voff = D.woff + (long long)D.m * D.np;
+            init.clear();
+            for (int b : G.fresh) {
+                describe(s, G, b);
+                if (!G.slot[b].pc) {
+                    init.push_back(b);
+                    continue;
                 }
-                G.h_desc[b] = D;
-                G.h_idx[k] = b;
-                lo = b < lo ? b : lo;
-                hi = b > hi ? b : hi;
+                const int q = G.slot[b].n <= 64 ? 0 : 1;
+                SRV_CHECK(hipMemcpyAsync(G.d_jobs + b, G.h_jobs + b, sizeof(svdb::QrJob),
+                                         hipMemcpyHostToDevice, s->aux[q]));
+                G.lane[q].wait.push_back(b);
+            }
+            G.fresh.clear();
+            for (int q = 0; q < 2; q++) {
+                Group::Lane &L = G.lane[q];
+                bool done;
+                SRV_CHECK(lane_done(L, &done));
+                if (done)
+                    for (int b : L.cur) {
+                        G.stage[b] = 0;
+                        G.h_desc[b].it0 = s->itg;
+                        init.push_back(b);
+                    }
+                if (!L.busy && !L.wait.empty()) {
+                    SRV_CHECK(lane_stage(G, L, s->aux[q]));
+                    svdb::launch_qr_jobs(G.d_jobs, G.d_ring + L.pos, (int)L.cur.size(), s->aux[q]);
+                    SRV_CHECK(hipGetLastError());
+                    SRV_CHECK(hipEventRecord(L.ev, s->aux[q]));
+                    L.busy = true;
+                }
+            }
+            if (init.empty()) continue;
+            int lo = G.cap, hi = -1;
+            for (size_t k = 0; k < init.size(); k++) {
+                G.h_idx[k] = init[k];
+                lo = init[k] < lo ? init[k] : lo;
+                hi = init[k] > hi ? init[k] : hi;
             }
             SRV_CHECK(hipMemcpyAsync(G.d_desc + lo, G.h_desc + lo,
                                      (size_t)(hi - lo + 1) * sizeof(svdb::VbDesc),
                                      hipMemcpyHostToDevice, s->stream));
-            SRV_CHECK(hipMemcpyAsync(G.d_idx, G.h_idx, G.fresh.size() * sizeof(int),
+            SRV_CHECK(hipMemcpyAsync(G.d_idx, G.h_idx, init.size() * sizeof(int),
                                      hipMemcpyHostToDevice, s->stream));
-            if (npc) {
-                SRV_CHECK(hipMemcpyAsync(G.d_jobs + lo, G.h_jobs + lo,
-                                         (size_t)(hi - lo + 1) * sizeof(svdb::QrJob),
-                                         hipMemcpyHostToDevice, s->stream));
-                SRV_CHECK(hipMemcpyAsync(G.d_idx2, G.h_idx2, (size_t)npc * sizeof(int),
-                                         hipMemcpyHostToDevice, s->stream));
-                svdb::launch_qr_jobs(G.d_jobs, G.d_idx2, npc, s->stream);
-                SRV_CHECK(hipGetLastError());
-            }
-            svdb::vb_launch_init(G.dtype, G.d_desc, G.d_idx, (int)G.fresh.size(), s->arena,
-                                 G.d_st, s->stream);
+            svdb::vb_launch_init(G.dtype, G.d_desc, G.d_idx, (int)init.size(), s->arena, G.d_st,
+                                 s->stream);
             SRV_CHECK(hipGetLastError());
-            G.fresh.clear();
+            G.dirty = true;
         }
-        // ---- 2. a few launches over everything admitted -----------------------------
-        int K = 1;
+        // ---- 2. a few launches over every request in the launches ----------------
+        int K = 0;
         for (auto &G : s->g) {
             if (!G.nused) continue;
             if (G.dirty) {
@@ -352,7 +436,7 @@ void worker_main(svdb_server *s)
                                              hipMemcpyHostToDevice, s->stream));
                 G.dirty = false;
             }
-            K = G.lmax - 1 > K ? G.lmax - 1 : K;
+            if (G.nwork) K = G.lmax - 1 > K ? G.lmax - 1 : K;
         }
         K = K < 8 ? K : 8;
         for (int k = 0; k < K; k++, s->itg++)
@@ -373,16 +457,20 @@ void worker_main(svdb_server *s)
                                      hipMemcpyDeviceToHost, s->stream));
         }
         SRV_CHECK(hipStreamSynchronize(s->stream));
-        std::vector<std::pair<int, int>> retired;   // (group, slot)
+        std::vector<std::pair<int, int>> retired;   // (group, slot) complete now
+        bool any_pc = false;
         for (int gi = 0; gi < 4; gi++) {
             Group &G = s->g[gi];
             if (!G.nused) continue;
             int cnt = 0, maxn = 0;
             for (int b = 0; b < G.cap; b++)
-                if (G.used[b] && G.h_flags[b]) {
+                if (G.used[b] && G.stage[b] == 0 && G.h_flags[b]) {
                     G.h_idx[cnt++] = b;
                     maxn = G.slot[b].n > maxn ? G.slot[b].n : maxn;
-                    retired.push_back({gi, b});
+                    if (G.slot[b].pc)
+                        any_pc = true;
+                    else
+                        retired.push_back({gi, b});
                 }
             if (!cnt) continue;
             SRV_CHECK(hipMemcpyAsync(G.d_idx, G.h_idx, (size_t)cnt * sizeof(int),
@@ -390,37 +478,59 @@ void worker_main(svdb_server *s)
             svdb::vb_launch_finalize(G.dtype, G.d_desc, G.d_idx, cnt, maxn, s->arena, G.d_st,
                                      s->stream);
             SRV_CHECK(hipGetLastError());
-            int npc = 0, maxm = 0;
-            for (int k = 0; k < cnt; k++) {
-                const Request &r = G.slot[G.h_idx[k]];
-                if (!r.pc) continue;
-                G.h_idx2[npc++] = G.h_idx[k];
-                maxm = r.m > maxm ? r.m : maxm;
-            }
-            if (npc) {
-                SRV_CHECK(hipMemcpyAsync(G.d_idx2, G.h_idx2, (size_t)npc * sizeof(int),
-                                         hipMemcpyHostToDevice, s->stream));
-                svdb::launch_apply_q_jobs(G.d_jobs, G.d_idx2, npc, maxm, s->stream);
-                SRV_CHECK(hipGetLastError());
-            }
         }
-        if (retired.empty()) continue;
-        SRV_CHECK(hipStreamSynchronize(s->stream));
-        const double t = now_seconds();
-        {
-            std::lock_guard<std::mutex> lk(s->mu);
-            for (auto &gb : retired) {
-                Group &G = s->g[gb.first];
-                Request &r = G.slot[gb.second];
-                s->done.push_back({r.id, r.t_submit, t});
-                s->alloc.release(r.off, r.bytes);
-                G.used[gb.second] = 0;
-                G.nused--;
-                G.dirty = true;
-                s->completed++;
+        // preconditioned requests: U = Q J (and the FP32 outputs) on the third
+        // lane, after the finalisations issued so far
+        bool fin_recorded = false;
+        for (int gi = 0; gi < 4; gi++) {
+            Group &G = s->g[gi];
+            Group::Lane &L = G.lane[2];
+            if (any_pc)
+                for (int b = 0; b < G.cap; b++)
+                    if (G.used[b] && G.stage[b] == 0 && G.h_flags[b] && G.slot[b].pc) {
+                        G.stage[b] = 2;
+                        G.dirty = true;
+                        L.wait.push_back(b);
+                    }
+            bool done;
+            SRV_CHECK(lane_done(L, &done));
+            if (done)
+                for (int b : L.cur) retired.push_back({gi, b});
+            if (L.busy || L.wait.empty()) continue;
+            if (!fin_recorded) {
+                SRV_CHECK(hipEventRecord(s->ev_fin, s->stream));
+                SRV_CHECK(hipStreamWaitEvent(s->aux[2], s->ev_fin, 0));
+                fin_recorded = true;
             }
+            int maxm = 0;
+            for (int b : L.wait) maxm = G.slot[b].m > maxm ? G.slot[b].m : maxm;
+            SRV_CHECK(lane_stage(G, L, s->aux[2]));
+            svdb::launch_apply_q_jobs(G.d_jobs, G.d_ring + L.pos, (int)L.cur.size(), maxm,
+                                      s->aux[2]);
+            SRV_CHECK(hipGetLastError());
+            SRV_CHECK(hipEventRecord(L.ev, s->aux[2]));
+            L.busy = true;
         }
-        s->cv_done.notify_all();
+        if (!retired.empty()) {
+            SRV_CHECK(hipStreamSynchronize(s->stream));
+            const double t = now_seconds();
+            {
+                std::lock_guard<std::mutex> lk(s->mu);
+                for (auto &gb : retired) {
+                    Group &G = s->g[gb.first];
+                    Request &r = G.slot[gb.second];
+                    s->done.push_back({r.id, r.t_submit, t});
+                    s->alloc.release(r.off, r.bytes);
+                    G.used[gb.second] = 0;
+                    G.stage[gb.second] = 0;
+                    G.nused--;
+                    G.dirty = true;
+                    s->completed++;
+                }
+            }
+            s->cv_done.notify_all();
+        }
+        if (K == 0 && retired.empty()) std::this_thread::sleep_for(std::chrono::microseconds(20));
     }
 }
 
@@ -438,10 +548,15 @@ void destroy_resources(svdb_server *s)
         if (G.h_idx) (void)hipHostFree(G.h_idx);
         if (G.d_jobs) (void)hipFree(G.d_jobs);
         if (G.h_jobs) (void)hipHostFree(G.h_jobs);
-        if (G.d_idx2) (void)hipFree(G.d_idx2);
-        if (G.h_idx2) (void)hipHostFree(G.h_idx2);
+        for (auto &L : G.lane)
+            if (L.ev) (void)hipEventDestroy(L.ev);
+        if (G.d_ring) (void)hipFree(G.d_ring);
+        if (G.h_ring) (void)hipHostFree(G.h_ring);
     }
     if (s->arena) (void)hipFree(s->arena);
+    if (s->ev_fin) (void)hipEventDestroy(s->ev_fin);
+    for (hipStream_t a : s->aux)
+        if (a) (void)hipStreamDestroy(a);
     if (s->stream) (void)hipStreamDestroy(s->stream);
 }
 
@@ -467,6 +582,9 @@ int svdb_server_create(svdb_server_t **out, size_t budget_bytes, int max_request
     s->max_sweeps = o.max_sweeps > 0 ? o.max_sweeps : 100;
     s->precondition = o.precondition == 1;
     hipError_t e = hipStreamCreateWithFlags(&s->stream, hipStreamNonBlocking);
+    for (hipStream_t &a : s->aux)
+        if (e == hipSuccess) e = hipStreamCreateWithFlags(&a, hipStreamNonBlocking);
+    if (e == hipSuccess) e = hipEventCreateWithFlags(&s->ev_fin, hipEventDisableTiming);
     if (e == hipSuccess) e = hipMalloc(&s->arena, s->budget);
     const int pairs = s->max_n / svdb::vb_nb() / 2;   // block pairs of the widest request
     for (int gi = 0; gi < 4 && e == hipSuccess; gi++) {
@@ -477,6 +595,11 @@ int svdb_server_create(svdb_server_t **out, size_t budget_bytes, int max_request
         G.tol = 30.0 * ldexp(1.0, (gi == 0 || gi == 2) ? -24 : -53);
         G.slot.assign(G.cap, Request());
         G.used.assign(G.cap, 0);
+        G.stage.assign(G.cap, 0);
+        G.ring_len = 4 * G.cap;
+        if (e == hipSuccess) e = hipMalloc((void **)&G.d_ring, (size_t)G.ring_len * sizeof(int));
+        if (e == hipSuccess)
+            e = hipHostMalloc((void **)&G.h_ring, (size_t)G.ring_len * sizeof(int), 0);
         const size_t nc = (size_t)G.cap;
         if (e == hipSuccess) e = hipMalloc((void **)&G.d_desc, nc * sizeof(svdb::VbDesc));
         if (e == hipSuccess) e = hipMalloc(&G.d_st, nc * svdb::vb_state_bytes());
@@ -489,8 +612,6 @@ int svdb_server_create(svdb_server_t **out, size_t budget_bytes, int max_request
         if (e == hipSuccess) e = hipHostMalloc((void **)&G.h_idx, nc * sizeof(int), 0);
         if (e == hipSuccess) e = hipMalloc((void **)&G.d_jobs, nc * sizeof(svdb::QrJob));
         if (e == hipSuccess) e = hipHostMalloc((void **)&G.h_jobs, nc * sizeof(svdb::QrJob), 0);
-        if (e == hipSuccess) e = hipMalloc((void **)&G.d_idx2, nc * sizeof(int));
-        if (e == hipSuccess) e = hipHostMalloc((void **)&G.h_idx2, nc * sizeof(int), 0);
         if (e == hipSuccess) svdb::vb_launch_mark_empty(G.cap, G.d_st, s->stream);
     }
     if (e == hipSuccess) e = hipStreamSynchronize(s->stream);
@@ -607,6 +728,7 @@ int svdb_server_destroy(svdb_server_t *s)
     s->cv_work.notify_all();
     if (s->worker.joinable()) s->worker.join();
     (void)hipStreamSynchronize(s->stream);
+    for (hipStream_t a : s->aux) (void)hipStreamSynchronize(a);
     destroy_resources(s);
     delete s;
     return 0;
