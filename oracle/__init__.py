@@ -6,4 +6,5 @@ library, and only the test suite, the smoke check and the CPU-baseline leg of
 the benchmark may use it.
 """
 from .ref import (block_gesvj, block_iter, build, default_tol, gesvj, gesvj_batch,  # noqa: F401
-                  heevj, num_threads, round_robin, row_cyclic, set_num_threads)
+                  heevj, num_threads, precond_gesvj, precond_gesvj_batch, round_robin,
+                  row_cyclic, set_num_threads)

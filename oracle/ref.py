@@ -162,6 +162,45 @@ def gesvj_batch(A, tol=None, max_sweeps=100, order=0, threads=None):
     return S, Ut.transpose(0, 2, 1), Vt.transpose(0, 2, 1), sweeps, info
 
 
+def precond_gesvj(A, tol=None, max_sweeps=100, order=1):
+    """Alg. 2 preconditioned after Drmac and Veselic, as the section
+    "Algorithmic Background" (paragraph "Efficient implementations") cites
+    them: the iteration on the transposed triangular factor of a
+    column-pivoted QR, here after a second, unpivoted QR of that factor (one
+    real m x n matrix, m >= n; each factorisation a library step):
+        A P = Q1 R1      column-pivoted QR (LAPACK xGEQP3 through scipy)
+        R1^T = Q2 R2     unpivoted QR (LAPACK xGEQRF through numpy)
+        X = R2^T,  X J = U_x diag(S)   Alg. 2 on X (its U is U_x, its V is J)
+        A = (Q1 U_x) diag(S) (P Q2 J)^T.
+    Returns (S, U, V, sweeps, info), sweeps being those of Alg. 2 on X."""
+    import scipy.linalg as sl
+    A = np.asarray(A, dtype=np.float64)
+    m, n = A.shape
+    if m < n:
+        raise ValueError("oracle requires m >= n")
+    if not np.all(np.isfinite(A)):
+        return np.zeros(n), None, None, 0, 2
+    Q1, R1, piv = sl.qr(A, mode="economic", pivoting=True)   # A[:, piv] = Q1 R1
+    Q2, R2 = np.linalg.qr(R1.T)
+    S, Ux, J, sw, info = gesvj(R2.T, tol, max_sweeps, order)
+    U = Q1 @ Ux
+    V = np.empty_like(J)
+    V[piv, :] = Q2 @ J                                       # P e_k = e_piv[k]
+    return S, U, V, sw, info
+
+
+def precond_gesvj_batch(A, tol=None, max_sweeps=100, order=1):
+    """precond_gesvj over a batch (batch, m, n); same returns as gesvj_batch."""
+    A = np.asarray(A)
+    out = [precond_gesvj(a, tol, max_sweeps, order) for a in A]
+    b, m, n = A.shape
+    S = np.stack([o[0] for o in out])
+    U = np.stack([o[1] if o[1] is not None else np.full((m, n), np.nan) for o in out])
+    V = np.stack([o[2] if o[2] is not None else np.full((n, n), np.nan) for o in out])
+    return (S, U, V, np.array([o[3] for o in out], dtype=np.int32),
+            np.array([o[4] for o in out], dtype=np.int32))
+
+
 def heevj(G, tol=None, max_sweeps=100, order=1):
     """Alg. 1 on a Hermitian G.  Returns (G_out, J, n_rotations, sweeps, converged)."""
     G = np.asfortranarray(np.asarray(G, dtype=np.complex128))
