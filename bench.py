@@ -30,9 +30,10 @@ FP64_VALU_PEAK = 256 * 4 * 16 * 2 * 2.4e9      # CUs x SIMDs x lanes x FMA x clo
 
 
 def measured_traffic(shape: str):
-    """HBM bytes of one QR-preconditioned call of this shape (QR + Jacobi on
-    R^T + applying Q) from the committed rocprofv3 summary, or None when a
-    kernel source has changed since the counters were taken."""
+    """HBM bytes of one QR-preconditioned call of this shape (both QRs, the
+    Jacobi on R2^T, both applications of Q) from the committed rocprofv3
+    summary, or None when a kernel source has changed since the counters were
+    taken."""
     import hashlib
     prof = os.path.join(ROOT, "profiles", "precond_mixed_64x64_128x32_traffic.json")
     try:
@@ -282,8 +283,9 @@ def main():
     ap.add_argument("--warmup", type=int, default=2)
     ap.add_argument("--path", default="auto")
     ap.add_argument("--batch", type=int, default=10000)
-    ap.add_argument("--cpu-sample", type=int, default=1000,
-                    help="matrices per shape for the CPU oracle baseline (0 = skip)")
+    ap.add_argument("--cpu-sample", type=int, default=5000,
+                    help="matrices per shape for the CPU oracle baseline (default: the whole "
+                         "workload, about 20 core-seconds; 0 = skip)")
     ap.add_argument("--no-plain", action="store_true",
                     help="skip the plain GPU Jacobi comparator run")
     ap.add_argument("--serve-seconds", type=float, default=8.0,
@@ -374,8 +376,9 @@ def main():
 
     # dominant call: the launch sequence with the longest average duration.
     # With QR preconditioning (the AUTO default for these shapes) one call is
-    # Householder QR + the Jacobi on R^T (n x n) + applying Q; its work is
-    # counted as all three.
+    # the pivoted QR of A (2n^2(m - n/3)), the QR of R1^T (4n^3/3), the
+    # Jacobi on R2^T (n x n), U = Q1 [U_x; 0] (2n^2(2m - n)) and V = P Q2 J
+    # (2n^3); its work is counted as all five.
     kdom = int(np.argmax(per_kernel))
     gd, Sd, Ud, Vd, infod, swd = results[kdom]
     try:   # AUTO preconditions exactly where precondition = 1 is accepted
@@ -385,15 +388,17 @@ def main():
         precond = False
     if precond:
         m_, n_ = gd.m, gd.n
-        fl = flops_unblocked(n_, n_, swd) + len(swd) * (2.0 * n_ * n_ * (m_ - n_ / 3.0) +
-                                                        2.0 * n_ * n_ * (2 * m_ - n_))
+        fl = flops_unblocked(n_, n_, swd) + len(swd) * (
+            2.0 * n_ * n_ * (m_ - n_ / 3.0) + 4.0 * n_ ** 3 / 3.0 +
+            2.0 * n_ * n_ * (2 * m_ - n_) + 2.0 * n_ ** 3)
     else:
         fl = flops_unblocked(gd.m, gd.n, swd)
     achieved = fl / (per_kernel[kdom] * 1e-3)
     roofline = {"bound": "alu", "achieved": achieved / 1e12, "peak": FP64_VALU_PEAK / 1e12,
                 "unit": "TFLOP/s", "frac": achieved / FP64_VALU_PEAK,
                 "traffic": measured_traffic(f"{gd.m}x{gd.n}") if precond else None,
-                "kernel": f"{gd.m}x{gd.n} call" + (" (QR + Jacobi on R^T + apply Q)"
+                "kernel": f"{gd.m}x{gd.n} call" + (" (pivoted QR, QR of R1^T, Jacobi on R2^T, "
+                                                   "Q1 and Q2 applied)"
                                                    if precond else " (resident Jacobi)"),
                 "kernel_ms": per_kernel[kdom], "flops_per_launch": fl}
 

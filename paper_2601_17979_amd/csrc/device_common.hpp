@@ -97,6 +97,12 @@ __device__ __forceinline__ double row_ror16(double v)
     return __hiloint2double(hi, lo);
 }
 
+template <int ROR>
+__device__ __forceinline__ int row_ror16i(int v)
+{
+    return __builtin_amdgcn_update_dpp(0, v, 0x120 + ROR, 0xF, 0xF, false);
+}
+
 // Power-of-two scale that brings max|a| into [1, 2): multiplying by it is
 // exact, so the iteration on the scaled matrix is the iteration on A with
 // every quantity scaled by a power of two (no overflow in the Gram sums).

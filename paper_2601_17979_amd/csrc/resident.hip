@@ -188,11 +188,14 @@ struct Shared {
 };
 
 // Waves per SIMD the register allocation is asked to allow, from the stored
-// doubles per lane ((RW + 1) N / NS), so that the allocation fits without
-// spilling.
+// doubles per lane d = (RW + 1) N / NS: 3 up to d = 32 (168 VGPRs), 2 up to
+// d = 64 (256), else 1.  With these bounds the iteration loop stays free of
+// spills; what does not fit goes to scratch in the per-sweep fold and the
+// finalisation, which run once per sweep, while a second or third resident
+// wave per SIMD hides the latency of the loop's reduction and rotation chain.
 constexpr int res_waves_per_eu(int N, int RW, int NS)
 {
-    return (RW + 1) * N / NS <= 32 ? 2 : 1;
+    return (RW + 1) * N / NS <= 32 ? 3 : ((RW + 1) * N / NS <= 64 ? 2 : 1);
 }
 
 // W rows live in slots 0..RW-1 (row 64 t + lane), V rows in slot RW (row =
@@ -281,41 +284,41 @@ __global__ __launch_bounds__(64 * NS, res_waves_per_eu(N, RW, NS)) void resident
     while (true) {
         // ---- fold the scale factors back in; exact squared norms ------------
         {
-            double pt[KG], pb[KG];
-#pragma unroll
-            for (int q = 0; q < KG; q++) {
-                if (q % 4 == 0) __builtin_amdgcn_sched_barrier(0);
-                const double2 dd = *reinterpret_cast<const double2 *>(&sh.d[2 * (q0 + q)]);
-                const double dt = dd.x, db = dd.y;
-                pt[q] = 0.0;
-                pb[q] = 0.0;
-#pragma unroll
-                for (int t = 0; t < R; t++) {
-                    T[q][t] *= dt;
-                    B[q][t] *= db;
-                }
-#pragma unroll
-                for (int t = 0; t < RW; t++) {
-                    pt[q] = fma(T[q][t], T[q][t], pt[q]);
-                    pb[q] = fma(B[q][t], B[q][t], pb[q]);
-                }
-            }
-            const double nt = reduce_pairs<KG, OpSum>(pt, buf);
-            const double nb = reduce_pairs<KG, OpSum>(pb, buf);
-            // a column whose squared norm is below kNegligible (a norm below
-            // 2^-480 of the pre-scaled matrix, whose largest entry is about
-            // 1) is set to zero in W: rotating it further would only push
-            // rounding noise towards underflow
+            // top seats, then bottom seats, KC pairs per reduction, so that
+            // few partial sums are live next to the columns
+            constexpr int KC = KG >= 8 ? 8 : KG, QC = KC / 4;
             int dead = 0;
-            if (x < Q) {
-                const int c = 2 * (q0 + qloc);
-                const bool zt = nt < kNegligible, zb = nb < kNegligible;
-                dead = (zt && nt != 0.0) || (zb && nb != 0.0);
-                sh.nrm[c] = zt ? 0.0 : nt;
-                sh.nrm[c + 1] = zb ? 0.0 : nb;
-                sh.d[c] = 1.0;
-                sh.d[c + 1] = 1.0;
-            }
+#pragma unroll
+            for (int side = 0; side < 2; side++)
+#pragma unroll
+                for (int h0 = 0; h0 < KG; h0 += KC) {
+                    double p[KC];
+#pragma unroll
+                    for (int k = 0; k < KC; k++) {
+                        const int q = h0 + k;
+                        const double dq = sh.d[2 * (q0 + q) + side];
+                        double(&X)[R] = side ? B[q] : T[q];
+                        p[k] = 0.0;
+#pragma unroll
+                        for (int t = 0; t < R; t++) X[t] *= dq;
+#pragma unroll
+                        for (int t = 0; t < RW; t++) p[k] = fma(X[t], X[t], p[k]);
+                    }
+                    // lane (rho, x) holds pair h0 + (x mod QC) + QC rho
+                    const double nv = reduce_pairs<KC, OpSum>(p, buf);
+                    // a column whose squared norm is below kNegligible (a
+                    // norm below 2^-480 of the pre-scaled matrix, whose
+                    // largest entry is about 1) is set to zero in W: rotating
+                    // it further would only push rounding noise towards
+                    // underflow
+                    if (x < QC) {
+                        const int c = 2 * (q0 + h0 + x + QC * (lane >> 4)) + side;
+                        const bool z = nv < kNegligible;
+                        dead |= z && nv != 0.0;
+                        sh.nrm[c] = z ? 0.0 : nv;
+                        sh.d[c] = 1.0;
+                    }
+                }
             if (__any(dead)) {
                 wave_sync_lds();
 #pragma unroll

@@ -1,6 +1,8 @@
-"""GPU parity of the QR-preconditioned path (A = Q R, the resident Jacobi on
-R^T, U = Q J) against the FP64 oracle, through the C ABI.  FP64 tolerances:
-normwise sigma error <= 1e-12, reconstruction and orthogonality <= 1e-13 n."""
+"""GPU parity of the QR-preconditioned paths against the FP64 oracle, through
+the C ABI.  Resident path (n <= 64): A P = Q1 R1 (pivoted), R1^T = Q2 R2, the
+Jacobi on R2^T, U = Q1 U_x, V = P Q2 J.  Wide path: A = Q R, the block Jacobi
+on R^T, U = Q J.  FP64 tolerances: normwise sigma error <= 1e-12,
+reconstruction and orthogonality <= 1e-13 n."""
 import numpy as np
 import pytest
 
@@ -112,6 +114,22 @@ def test_precond_mixed_workload_sample():
         Sr, _, _, swr, infor = oracle_batch(A)
         compare_with_oracle(A, S, U, V, info, Sr, infor, label=f"auto {g.m}x{g.n}")
         say(f"  {g.m}x{g.n}: sweeps gpu {sw.mean():.2f} oracle on A {swr.mean():.2f}")
+
+
+def test_precond_sweeps_match_the_oracle_pipeline():
+    """The resident path follows the oracle's preconditioned driver (pivoted
+    QR, second QR, Alg. 2 on R2^T): same SVD, and sweep counts within one of
+    the oracle's on every matrix of a workload sample (rounding can move a
+    pair across the threshold, never the whole schedule)."""
+    import oracle
+    groups = gen.mixed_64_128x32(batch=400)
+    for g in groups:
+        A = g.A[::8]
+        S, U, V, info, sw = run_gpu(A)
+        Sr, Ur, Vr, swr, infor = oracle.precond_gesvj_batch(A)
+        compare_with_oracle(A, S, U, V, info, Sr, infor, label=f"pipeline {g.m}x{g.n}")
+        say(f"  {g.m}x{g.n}: sweeps gpu {sw.mean():.2f} oracle pipeline {swr.mean():.2f}")
+        assert np.all(np.abs(sw - swr) <= 1), (sw.tolist(), swr.tolist())
 
 
 @pytest.mark.parametrize("m,n,count", [(96, 65, 4), (130, 96, 4), (200, 130, 3), (256, 256, 2),
