@@ -1,11 +1,13 @@
 /*
  * svdb.h -- C ABI of the MI355X batched one-sided Jacobi SVD library.
  *
- * Problem (section "Computing the Singular Value Decomposition", eq. svd): for each m x n matrix A of a batch, with
- * m >= n, compute the reduced SVD A = U diag(S) V^H: U is m x n with
- * orthonormal columns, V is n x n unitary, S is real, non-negative and sorted
- * in descending order (Alg. 2, last step; accuracy check T4 of "Performance of the Baseline
- * Implementation").
+ * Problem (section "Computing the Singular Value Decomposition", eq. svd): for each m x n matrix A of a batch,
+ * compute the reduced SVD A = U diag(S) V^H with k = min(m, n): U is m x k
+ * and V is n x k, both with orthonormal columns (V is unitary when m >= n),
+ * S is real, non-negative and sorted in descending order (Alg. 2, last step;
+ * accuracy check T4 of "Performance of the Baseline Implementation").  A
+ * wide matrix (m < n) is solved through its conjugate transpose, A^H =
+ * V S U^H (section "Pre-processing the SVD using a QR Factorization").
  * The method is the one-sided (Hestenes) Jacobi iteration of Alg. 2 with the
  * rotation of eq. (sin-cos), the round-robin parallel ordering (Fig. "rr"),
  * and, for wider matrices, the block method (eq. block-gram,
@@ -81,15 +83,16 @@ typedef struct {
     int *sweeps;      /* optional DEVICE int[batch]: sweeps executed          */
     int waves;        /* SVDB_PATH_RESIDENT: wavefronts per matrix (1, 2, 4);
                          0 -> tuned                                           */
-    int precondition; /* QR pre-processing of real FP64 matrices: A = Q R,
-                         the Jacobi iteration on R^T, U = Q J, V from the
-                         iteration's left vectors.  n <= 64 (m n <= 8192):
-                         the resident kernel on R^T; n > 64 (m <= 1024): the
-                         block method on R^T.  -1 (default): on for the AUTO
-                         path where it applies; 0: off; 1: on (AUTO,
-                         RESIDENT or BLOCKED path; SVDB_ERR_UNSUPPORTED
-                         where it does not apply).  The sweeps count is that
-                         of the iteration on R^T.                            */
+    int precondition; /* QR pre-processing of real FP64 matrices.  n <= 64
+                         (m n <= 8192): A P = Q1 R1 with column pivoting,
+                         R1^T = Q2 R2, the resident kernel on R2^T, U = Q1
+                         U_x, V = P Q2 J.  n > 64 (m <= 1024): A = Q R, the
+                         block method on R^T, U = Q J.  -1 (default): on
+                         for the AUTO path where it applies; 0: off; 1: on
+                         (AUTO, RESIDENT or BLOCKED path;
+                         SVDB_ERR_UNSUPPORTED where it does not apply).  The
+                         sweeps count is that of the iteration on the
+                         triangular factor.                                  */
 } svdb_opts_t;
 
 /* Fills *o with the defaults (AUTO path, 100 sweeps, masking on,
@@ -110,9 +113,12 @@ size_t svdb_workspace_size(svdb_dtype_t dtype, int batch, int m, int n,
  * R64/C128), U and V.
  *
  *  A       in: batch x (m x n), lda >= max(1, m).  Not modified.
- *  S       out: n singular values per matrix, descending.
- *  U       out: m x n left singular vectors (ldu >= m), or NULL.
- *  V       out: n x n right singular vectors (ldv >= n), A = U S V^H, or NULL.
+ *  S       out: k = min(m, n) singular values per matrix, descending.
+ *  U       out: m x k left singular vectors (ldu >= m), or NULL.
+ *  V       out: n x k right singular vectors (ldv >= n), A = U S V^H, or NULL.
+ *  For m < n the call first writes A^H into the workspace (its size
+ *  includes that copy) and runs the m >= n path on it with U and V
+ *  exchanged; the path is the one svdb_plan gives for n x m.
  *  info    out: device int[batch] (see above).  Required.
  *  workspace / ws_bytes: device scratch of at least svdb_workspace_size()
  *          bytes (may be NULL when that is 0).
@@ -132,8 +138,10 @@ int svdb_svd_strided_batched(svdb_dtype_t dtype, int batch, int m, int n,
 /*
  * Mixed-shape batch (uneven batching): host arrays m[b], n[b], lda[b],
  * ldu[b], ldv[b] and host arrays of device pointers A[b], S[b], U[b], V[b]
- * (U or V may be NULL as a whole).  Requires m[b] >= n[b] >= 0; A[b] is
- * not modified.  Every matrix runs the block method (eq. block-gram, nb = 16, any
+ * (U or V may be NULL as a whole).  Any m[b], n[b] >= 0, with outputs as in
+ * svdb_svd_strided_batched (k_b = min(m_b, n_b) columns; a wide matrix is
+ * read transposed into its working copy); A[b] is not modified.  Every
+ * matrix runs the block method (eq. block-gram, nb = 16, any
  * dtype) on its own round-robin schedule over l_b = n_b / 16 (rounded up to
  * even) block columns: one launch per round-robin step covers the block
  * pairs of every unconverged matrix of the batch, and a small matrix
@@ -161,7 +169,7 @@ size_t svdb_batched_workspace_size(svdb_dtype_t dtype, int batch, const int *m,
 
 /*
  * The path and launch shape AUTO (or the forced path in opts) would use for
- * one m x n matrix: *path (svdb_path_t), *nb (block width, 0 if unblocked),
+ * one m x n matrix (for m < n: that of the n x m matrix A^H): *path (svdb_path_t), *nb (block width, 0 if unblocked),
  * *threads (threads per matrix).  Returns 0, or SVDB_ERR_UNSUPPORTED if no
  * path handles the shape.
  */
@@ -192,8 +200,11 @@ int svdb_plan(svdb_dtype_t dtype, int m, int n, const svdb_opts_t *opts,
  *     values when the call is made (the server reads it on its own stream)
  *     and every buffer must stay valid until the request completes.  The
  *     rotation threshold is 30 u of the dtype (tol is reserved).  Thread
- *     safe.  Returns the request id (>= 0), -k for invalid argument k,
- *     SVDB_ERR_UNSUPPORTED when n > 512 or the request exceeds the budget,
+ *     safe.  Any m, n >= 0: outputs as in svdb_svd_strided_batched (a
+ *     wide request runs as A^H, read transposed, without preconditioning).
+ *     Returns the request id (>= 0), -k for invalid argument k,
+ *     SVDB_ERR_UNSUPPORTED when min(m, n) > 512 or the request exceeds the
+ *     budget,
  *     SVDB_ERR_HIP after a device failure.
  *  svdb_server_poll: waits up to timeout_ms (< 0: forever, 0: no wait) for
  *     completions and returns up to cap of them: id, submission and

@@ -42,6 +42,12 @@ int elt_bytes(svdb_dtype_t dt)
     return dt == SVDB_R32 ? 4 : dt == SVDB_C128 ? 16 : 8;
 }
 
+// bytes of the A^H copy of a strided batch of wide matrices
+size_t wide_copy_bytes(svdb_dtype_t dtype, int batch, int m, int n)
+{
+    return ((size_t)batch * m * n * elt_bytes(dtype) + 255) / 256 * 256;
+}
+
 struct Plan {
     int path = SVDB_PATH_AUTO;
     int nb = 0;
@@ -168,9 +174,10 @@ int svdb_plan(svdb_dtype_t dtype, int m, int n, const svdb_opts_t *opts, int *pa
               int *threads)
 {
     svdb_opts_t o = resolve_opts(opts);
-    if (m < 0 || n < 0 || n > m) return fail(-3, "need m >= n >= 0");
+    if (m < 0 || n < 0) return fail(-3, "need m, n >= 0");
     Plan p;
-    int rc = make_plan(dtype, m, n, o, &p);
+    // a wide matrix runs the plan of its conjugate transpose
+    int rc = m >= n ? make_plan(dtype, m, n, o, &p) : make_plan(dtype, n, m, o, &p);
     if (rc) return rc;
     if (path) *path = p.path;
     if (nb) *nb = p.nb;
@@ -180,7 +187,12 @@ int svdb_plan(svdb_dtype_t dtype, int m, int n, const svdb_opts_t *opts, int *pa
 
 size_t svdb_workspace_size(svdb_dtype_t dtype, int batch, int m, int n, const svdb_opts_t *opts)
 {
-    if (batch < 0 || m < 0 || n < 0 || n > m) return (size_t)-1;
+    if (batch < 0 || m < 0 || n < 0) return (size_t)-1;
+    if (n > m) {   // A^H (n x m) in the workspace, then the tall call's own
+        const size_t tall = svdb_workspace_size(dtype, batch, n, m, opts);
+        if (tall == (size_t)-1) return tall;
+        return wide_copy_bytes(dtype, batch, m, n) + tall;
+    }
     svdb_opts_t o = resolve_opts(opts);
     Plan p;
     if (make_plan(dtype, m, n, o, &p)) return (size_t)-1;
@@ -192,44 +204,14 @@ size_t svdb_workspace_size(svdb_dtype_t dtype, int batch, int m, int n, const sv
     return 0;
 }
 
-int svdb_svd_strided_batched(svdb_dtype_t dtype, int batch, int m, int n, const void *A, int lda,
-                             long long strideA, void *S, long long strideS, void *U, int ldu,
-                             long long strideU, void *V, int ldv, long long strideV, double tol,
-                             int *info, void *workspace, size_t ws_bytes,
-                             const svdb_opts_t *opts, void *stream)
-{
-    g_err.clear();
-    if ((int)dtype < SVDB_R32 || (int)dtype > SVDB_C128) return fail(-1, "invalid dtype");
-    if (batch < 0) return fail(-2, "batch < 0");
-    if (m < 0) return fail(-3, "m < 0");
-    if (n < 0 || n > m) return fail(-4, "need 0 <= n <= m (wide matrices: pass A^H)");
-    const bool empty = (batch == 0 || n == 0);
-    if (!A && !empty) return fail(-5, "A is NULL");
-    if (lda < (m > 1 ? m : 1)) return fail(-6, "lda < max(1, m)");
-    if (batch > 1 && strideA < (long long)lda * n) return fail(-7, "strideA < lda * n");
-    if (!S && !empty) return fail(-8, "S is NULL");
-    if (batch > 1 && strideS < n) return fail(-9, "strideS < n");
-    if (U) {
-        if (ldu < (m > 1 ? m : 1)) return fail(-11, "ldu < max(1, m)");
-        if (batch > 1 && strideU < (long long)ldu * n) return fail(-12, "strideU < ldu * n");
-    }
-    if (V) {
-        if (ldv < (n > 1 ? n : 1)) return fail(-14, "ldv < max(1, n)");
-        if (batch > 1 && strideV < (long long)ldv * n) return fail(-15, "strideV < ldv * n");
-    }
-    if (!isfinite(tol)) return fail(-16, "tol is not finite");
-    if (!info && batch > 0) return fail(-17, "info is NULL");
-    svdb_opts_t o = resolve_opts(opts);
-    Plan p;
-    int rc = make_plan(dtype, m, n, o, &p);
-    if (rc) return rc;
-    const size_t need = svdb_workspace_size(dtype, batch, m, n, &o);
-    if (need > 0 && (!workspace || ws_bytes < need))
-        return fail(-19, "workspace too small: need %zu bytes", need);
-    if (batch == 0) return 0;
-    if (tol <= 0.0) tol = default_tol(dtype);
-    hipStream_t s = (hipStream_t)stream;
+namespace {
 
+// The tall (m >= n) call on plan p; outputs as in svdb_svd_strided_batched.
+hipError_t run_tall(svdb_dtype_t dtype, const Plan &p, const svdb_opts_t &o, int batch, int m,
+                    int n, const void *A, int lda, long long strideA, void *S, long long strideS,
+                    void *U, int ldu, long long strideU, void *V, int ldv, long long strideV,
+                    double tol, int *info, void *workspace, hipStream_t s)
+{
     hipError_t e = hipSuccess;
     if (p.precond_big) {
         e = svdb::launch_precond_big_d(batch, m, n, p.nb, (const double *)A, lda, strideA,
@@ -273,6 +255,64 @@ int svdb_svd_strided_batched(svdb_dtype_t dtype, int batch, int m, int n, const 
                                  strideS, (double *)U, ldu, strideU, (double *)V, ldv, strideV,
                                  tol, o.max_sweeps, info, o.sweeps, s);
     }
+    return e;
+}
+
+}  // namespace
+
+int svdb_svd_strided_batched(svdb_dtype_t dtype, int batch, int m, int n, const void *A, int lda,
+                             long long strideA, void *S, long long strideS, void *U, int ldu,
+                             long long strideU, void *V, int ldv, long long strideV, double tol,
+                             int *info, void *workspace, size_t ws_bytes,
+                             const svdb_opts_t *opts, void *stream)
+{
+    g_err.clear();
+    if ((int)dtype < SVDB_R32 || (int)dtype > SVDB_C128) return fail(-1, "invalid dtype");
+    if (batch < 0) return fail(-2, "batch < 0");
+    if (m < 0) return fail(-3, "m < 0");
+    if (n < 0) return fail(-4, "n < 0");
+    const int k = m < n ? m : n;   // singular values per matrix
+    const bool empty = (batch == 0 || k == 0);
+    if (!A && !empty) return fail(-5, "A is NULL");
+    if (lda < (m > 1 ? m : 1)) return fail(-6, "lda < max(1, m)");
+    if (batch > 1 && strideA < (long long)lda * n) return fail(-7, "strideA < lda * n");
+    if (!S && !empty) return fail(-8, "S is NULL");
+    if (batch > 1 && strideS < k) return fail(-9, "strideS < min(m, n)");
+    if (U) {
+        if (ldu < (m > 1 ? m : 1)) return fail(-11, "ldu < max(1, m)");
+        if (batch > 1 && strideU < (long long)ldu * k) return fail(-12, "strideU < ldu * min(m, n)");
+    }
+    if (V) {
+        if (ldv < (n > 1 ? n : 1)) return fail(-14, "ldv < max(1, n)");
+        if (batch > 1 && strideV < (long long)ldv * k) return fail(-15, "strideV < ldv * min(m, n)");
+    }
+    if (!isfinite(tol)) return fail(-16, "tol is not finite");
+    if (!info && batch > 0) return fail(-17, "info is NULL");
+    svdb_opts_t o = resolve_opts(opts);
+    const bool wide = n > m;
+    Plan p;
+    int rc = wide ? make_plan(dtype, n, m, o, &p) : make_plan(dtype, m, n, o, &p);
+    if (rc) return rc;
+    const size_t need = svdb_workspace_size(dtype, batch, m, n, &o);
+    if (need > 0 && (!workspace || ws_bytes < need))
+        return fail(-19, "workspace too small: need %zu bytes", need);
+    if (batch == 0) return 0;
+    if (tol <= 0.0) tol = default_tol(dtype);
+    hipStream_t s = (hipStream_t)stream;
+    hipError_t e;
+    if (!wide) {
+        e = run_tall(dtype, p, o, batch, m, n, A, lda, strideA, S, strideS, U, ldu, strideU, V,
+                     ldv, strideV, tol, info, workspace, s);
+    } else {
+        // A^H = U' diag(S) V'^H (n x m, tall): U = V' and V = U'
+        void *At = workspace;
+        char *rest = (char *)workspace + wide_copy_bytes(dtype, batch, m, n);
+        e = k ? svdb::launch_conj_transpose((int)dtype, batch, m, n, A, lda, strideA, At, s)
+              : hipSuccess;
+        if (e == hipSuccess)
+            e = run_tall(dtype, p, o, batch, n, m, At, n, (long long)n * m, S, strideS, V, ldv,
+                         strideV, U, ldu, strideU, tol, info, rest, s);
+    }
     if (e != hipSuccess) return hip_fail(e, "launch");
     return 0;
 }
@@ -284,9 +324,13 @@ size_t svdb_batched_workspace_size(svdb_dtype_t dtype, int batch, const int *m, 
     if (batch < 0 || (batch > 0 && (!m || !n))) return (size_t)-1;
     svdb_opts_t o = resolve_opts(opts);
     if (o.precision != 0) return (size_t)-1;
-    for (int b = 0; b < batch; b++)
-        if (m[b] < 0 || n[b] < 0 || n[b] > m[b]) return (size_t)-1;
-    return svdb::vbatched_workspace_bytes(batch, m, n, elt_bytes(dtype));
+    std::vector<int> mt(batch), nt(batch);   // wide matrices as their (tall) A^H
+    for (int b = 0; b < batch; b++) {
+        if (m[b] < 0 || n[b] < 0) return (size_t)-1;
+        mt[b] = m[b] >= n[b] ? m[b] : n[b];
+        nt[b] = m[b] >= n[b] ? n[b] : m[b];
+    }
+    return svdb::vbatched_workspace_bytes(batch, mt.data(), nt.data(), elt_bytes(dtype));
 }
 
 int svdb_svd_batched(svdb_dtype_t dtype, int batch, const int *m, const int *n,
@@ -309,8 +353,8 @@ int svdb_svd_batched(svdb_dtype_t dtype, int batch, const int *m, const int *n,
     if (!info) return fail(-13, "info is NULL");
     for (int b = 0; b < batch; b++) {
         if (m[b] < 0) return fail(-3, "m[%d] < 0", b);
-        if (n[b] < 0 || n[b] > m[b]) return fail(-4, "need 0 <= n[%d] <= m[%d]", b, b);
-        const bool empty = n[b] == 0;
+        if (n[b] < 0) return fail(-4, "n[%d] < 0", b);
+        const bool empty = n[b] == 0 || m[b] == 0;
         if (!A[b] && !empty) return fail(-5, "A[%d] is NULL", b);
         if (lda[b] < (m[b] > 1 ? m[b] : 1)) return fail(-6, "lda[%d] < max(1, m)", b);
         if (!S[b] && !empty) return fail(-7, "S[%d] is NULL", b);
@@ -326,9 +370,26 @@ int svdb_svd_batched(svdb_dtype_t dtype, int batch, const int *m, const int *n,
     if (!workspace || ws_bytes < need)
         return fail(-14, "workspace too small: need %zu bytes", need);
     if (tol <= 0.0) tol = default_tol(dtype);
-    hipError_t e = svdb::launch_vbatched((int)dtype, batch, m, n, A, lda, S, U, ldu, V, ldv, tol,
+    // a wide matrix (m < n) runs as its conjugate transpose, read transposed
+    // by the init kernel, with U and V exchanged: A^H = U' S V'^H gives
+    // U = V' and V = U'
+    std::vector<int> mt(batch), nt(batch), tr(batch), ldut(batch), ldvt(batch);
+    std::vector<void *> Ut(batch), Vt(batch);
+    for (int b = 0; b < batch; b++) {
+        void *ub = U ? U[b] : nullptr, *vb = V ? V[b] : nullptr;
+        const int lu = U ? ldu[b] : 1, lv = V ? ldv[b] : 1;
+        tr[b] = n[b] > m[b];
+        mt[b] = tr[b] ? n[b] : m[b];
+        nt[b] = tr[b] ? m[b] : n[b];
+        Ut[b] = tr[b] ? vb : ub;
+        ldut[b] = tr[b] ? lv : lu;
+        Vt[b] = tr[b] ? ub : vb;
+        ldvt[b] = tr[b] ? lu : lv;
+    }
+    hipError_t e = svdb::launch_vbatched((int)dtype, batch, mt.data(), nt.data(), A, lda, S,
+                                         Ut.data(), ldut.data(), Vt.data(), ldvt.data(), tol,
                                          o.max_sweeps, o.masking, info, o.sweeps, workspace,
-                                         (hipStream_t)stream);
+                                         (hipStream_t)stream, tr.data());
     if (e != hipSuccess) return hip_fail(e, "launch");
     return 0;
 }

@@ -152,8 +152,10 @@ __device__ __forceinline__ void state_reset(BlkState &s, int bad)
 // workgroup, pointers of this matrix.
 template <class EA, class EW>
 __device__ __forceinline__ void init_body(int m, int n, int np, const EA *__restrict__ A, int lda,
-                                          EW *W, EW *Vw, BlkState *stb)
+                                          EW *W, EW *Vw, BlkState *stb, bool trans = false)
 {
+    // trans: A is the n x m matrix whose conjugate transpose is read, element
+    // (r, c) being conj(A(c, r)) (wide inputs of the uneven batch)
     using OA = EOps<EA>;
     using OW = EOps<EW>;
     const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
@@ -163,7 +165,7 @@ __device__ __forceinline__ void init_body(int m, int n, int np, const EA *__rest
     int bad = 0;
     for (int c = wave; c < n; c += kBT / 64)
         for (int r = lane; r < m; r += 64) {
-            const EA a = A[(size_t)c * lda + r];
+            const EA a = trans ? A[(size_t)r * lda + c] : A[(size_t)c * lda + r];
             const double ar = OA::re(a), ai = OA::im(a);
             bad |= !isfinite(ar) || !isfinite(ai);
             amax = fmax(amax, fmax(fabs(ar), fabs(ai)));
@@ -186,8 +188,9 @@ __device__ __forceinline__ void init_body(int m, int n, int np, const EA *__rest
         for (int r = lane; r < m; r += 64) {
             EW w = OW::make(0.0, 0.0);
             if (c < n && !bad) {
-                const EA a = A[(size_t)c * lda + r];
-                w = OW::make(OA::re(a) * scale, OA::im(a) * scale);
+                const EA a = trans ? A[(size_t)r * lda + c] : A[(size_t)c * lda + r];
+                const double ai = trans ? -OA::im(a) : OA::im(a);
+                w = OW::make(OA::re(a) * scale, ai * scale);
             }
             W[(size_t)c * m + r] = w;
         }
@@ -1083,7 +1086,8 @@ __global__ __launch_bounds__(kBT) void vb_init(const VbDesc *d, const int *idx, 
     const int b = idx ? idx[blockIdx.x] : (int)blockIdx.x;
     const VbDesc D = d[b];
     E *Wb = (E *)base;
-    init_body<E, E>(D.m, D.n, D.np, (const E *)D.A, D.lda, Wb + D.woff, Wb + D.voff, st + b);
+    init_body<E, E>(D.m, D.n, D.np, (const E *)D.A, D.lda, Wb + D.woff, Wb + D.voff, st + b,
+                    D.trans != 0);
 }
 
 template <class T, bool CX>
@@ -1305,7 +1309,8 @@ namespace {
 hipError_t launch_vb(int dtype, size_t elt, int batch, const int *m, const int *n,
                      const void *const *A, const int *lda, void *const *S, void *const *U,
                      const int *ldu, void *const *V, const int *ldv, double tol, int max_sweeps,
-                     int masking, int *info, int *sweeps, void *ws, hipStream_t stream)
+                     int masking, int *info, int *sweeps, void *ws, hipStream_t stream,
+                     const int *trans)
 {
     VbLayout L = vb_layout(ws, batch, m, n, elt);
     // descriptors, then the work table with the largest matrices first
@@ -1339,6 +1344,7 @@ hipError_t launch_vb(int dtype, size_t elt, int batch, const int *m, const int *
         D.np = n[b] > 0 ? blocked_np(n[b], kVbNb) : 0;
         D.l = n[b] > 0 ? D.np / kVbNb : 2;
         D.it0 = 0;
+        D.trans = trans ? trans[b] : 0;
         D.woff = off;
         off += (long long)D.m * D.np;
         D.voff = off;
@@ -1527,11 +1533,12 @@ size_t vbatched_workspace_bytes(int batch, const int *m, const int *n, int elt)
 hipError_t launch_vbatched(int dtype, int batch, const int *m, const int *n, const void *const *A,
                            const int *lda, void *const *S, void *const *U, const int *ldu,
                            void *const *V, const int *ldv, double tol, int max_sweeps,
-                           int masking, int *info, int *sweeps, void *ws, hipStream_t stream)
+                           int masking, int *info, int *sweeps, void *ws, hipStream_t stream,
+                           const int *trans)
 {
     const size_t elt = dtype == 0 ? 4 : dtype == 3 ? 16 : 8;
     return launch_vb(dtype, elt, batch, m, n, A, lda, S, U, ldu, V, ldv, tol, max_sweeps, masking,
-                     info, sweeps, ws, stream);
+                     info, sweeps, ws, stream, trans);
 }
 
 }  // namespace svdb

@@ -90,6 +90,7 @@ struct VbDesc {
     int *info, *sweeps;     // this matrix's status slots (sweeps may be NULL)
     long long woff, voff;   // element offsets of W (m x np) and V (np x np) from the base
     int m, n, np, l, lda, ldu, ldv, it0;   // it0: launch index of its first iteration
+    int trans;   // 1: A holds the n x m matrix whose conjugate transpose is this m x n one
 };
 
 // Launchers of the uneven-batch kernels; dtype as svdb_dtype_t, st points to
@@ -115,6 +116,12 @@ size_t vbatched_workspace_bytes(int batch, const int *m, const int *n, int elt);
 hipError_t launch_vbatched(int dtype, int batch, const int *m, const int *n, const void *const *A,
                            const int *lda, void *const *S, void *const *U, const int *ldu,
                            void *const *V, const int *ldv, double tol, int max_sweeps,
-                           int masking, int *info, int *sweeps, void *ws, hipStream_t stream);
+                           int masking, int *info, int *sweeps, void *ws, hipStream_t stream,
+                           const int *trans = nullptr);
+
+// layout.hip: At (n x m, ld n, n m apart) = A^H for a strided batch of m x n
+// matrices; dtype as svdb_dtype_t.
+hipError_t launch_conj_transpose(int dtype, int batch, int m, int n, const void *A, int lda,
+                                 long long sA, void *At, hipStream_t stream);
 
 }  // namespace svdb

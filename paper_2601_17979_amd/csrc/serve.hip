@@ -97,6 +97,7 @@ struct Request {
     int dtype = 1, m = 0, n = 0, lda = 1, ldu = 1, ldv = 1;
     int group = 1;   // kernel group (dtype of the working copies)
     int pc = 0;      // QR-preconditioned: FP64 Jacobi on R^T, U = Q J
+    int trans = 0;   // wide request run as A^H: m, n, U, V here are those of A^H
     const void *A = nullptr;
     void *S = nullptr, *U = nullptr, *V = nullptr;
     int *info = nullptr, *sweeps = nullptr;
@@ -288,6 +289,7 @@ void describe(svdb_server *s, Group &G, int b)
         G.h_jobs[b] = J;
     } else {
         D.A = r.A;
+        D.trans = r.trans;
         D.S = r.S;
         D.U = r.U;
         D.V = r.V;
@@ -633,29 +635,37 @@ long long svdb_server_submit(svdb_server_t *s, svdb_dtype_t dtype, int m, int n,
     if (!s) return -1;
     if ((int)dtype < SVDB_R32 || (int)dtype > SVDB_C128) return -2;
     if (m < 0) return -3;
-    if (n < 0 || n > m) return -4;
-    if (n > s->max_n) return SVDB_ERR_UNSUPPORTED;
-    if (!A && n > 0) return -5;
+    if (n < 0) return -4;
+    const int k = m < n ? m : n;
+    if (k > s->max_n) return SVDB_ERR_UNSUPPORTED;
+    if (!A && k > 0) return -5;
     if (lda < (m > 1 ? m : 1)) return -6;
-    if (!S && n > 0) return -7;
+    if (!S && k > 0) return -7;
     if (U && ldu < (m > 1 ? m : 1)) return -9;
     if (V && ldv < (n > 1 ? n : 1)) return -11;
     if (!info) return -13;
     Request r;
     r.dtype = (int)dtype;
-    r.m = m;
-    r.n = n;
     r.A = A;
     r.lda = lda;
     r.S = S;
-    r.U = U;
-    r.ldu = U ? ldu : 1;
-    r.V = V;
-    r.ldv = V ? ldv : 1;
     r.info = info;
     r.sweeps = sweeps;
+    // a wide request runs as A^H = V S U^H: read transposed, U and V exchanged
+    r.trans = n > m;
+    r.m = r.trans ? n : m;
+    r.n = k;
+    void *u = U, *v = V;
+    const int lu = U ? ldu : 1, lv = V ? ldv : 1;
+    r.U = r.trans ? v : u;
+    r.ldu = r.trans ? lv : lu;
+    r.V = r.trans ? u : v;
+    r.ldv = r.trans ? lu : lv;
+    m = r.m;
+    n = r.n;
     const int np = n > 0 ? svdb::blocked_np(n, svdb::vb_nb()) : 0;
-    r.pc = s->precondition && (dtype == SVDB_R32 || dtype == SVDB_R64) && n > 0 && m <= 1024;
+    r.pc = s->precondition && !r.trans && (dtype == SVDB_R32 || dtype == SVDB_R64) && n > 0 &&
+           m <= 1024;
     r.group = r.pc ? SVDB_R64 : r.dtype;
     r.bytes = r.pc ? pc_layout(m, n, np, dtype == SVDB_R32).bytes
                    : al256(((size_t)m * np + (size_t)np * np) * (size_t)elt_of(r.dtype));

@@ -149,7 +149,9 @@ def svd(A: torch.Tensor, tol: float = 0.0, max_sweeps: int = 100, path="auto", n
         compute_u: bool = True, compute_v: bool = True, masking: bool = True,
         precision: int = 0, want_sweeps: bool = True, stream=None, out=None, waves: int = 0,
         precondition: int = -1):
-    """Batched reduced SVD of a (batch, m, n) column-major GPU tensor (m >= n).
+    """Batched reduced SVD of a (batch, m, n) column-major GPU tensor:
+    A = U diag(S) V^H with k = min(m, n) singular values, U (m x k), V (n x k)
+    (a wide matrix, m < n, is solved through its conjugate transpose).
 
     Returns (S, U, V, info, sweeps); U/V are None when not requested, sweeps
     is None unless want_sweeps.  Enqueued on `stream` (default: torch's
@@ -157,14 +159,15 @@ def svd(A: torch.Tensor, tol: float = 0.0, max_sweeps: int = 100, path="auto", n
     """
     _check_cm(A, "A")
     b, m, n = A.shape
+    k = min(m, n)
     dev = A.device
     code = dtype_code(A.dtype)
     if out is not None:
         S, U, V, info, sweeps = out
     else:
-        S = torch.empty((b, n), dtype=_REAL[A.dtype], device=dev)
-        U = empty_col_major(b, m, n, A.dtype, dev) if compute_u else None
-        V = empty_col_major(b, n, n, A.dtype, dev) if compute_v else None
+        S = torch.empty((b, k), dtype=_REAL[A.dtype], device=dev)
+        U = empty_col_major(b, m, k, A.dtype, dev) if compute_u else None
+        V = empty_col_major(b, n, k, A.dtype, dev) if compute_v else None
         info = torch.empty(b, dtype=torch.int32, device=dev)
         sweeps = torch.empty(b, dtype=torch.int32, device=dev) if want_sweeps else None
     o = make_opts(max_sweeps, path, nb, masking, precision, sweeps, waves, precondition)
@@ -174,8 +177,8 @@ def svd(A: torch.Tensor, tol: float = 0.0, max_sweeps: int = 100, path="auto", n
     ws = torch.empty(max(ws_bytes, 1), dtype=torch.uint8, device=dev) if ws_bytes else None
     st = (stream or torch.cuda.current_stream(dev)).cuda_stream
     lda = max(A.stride(2), 1) if n > 1 else max(m, 1)
-    ldu = (U.stride(2) if n > 1 else max(m, 1)) if U is not None else 1
-    ldv = (V.stride(2) if n > 1 else max(n, 1)) if V is not None else 1
+    ldu = (U.stride(2) if k > 1 else max(m, 1)) if U is not None else 1
+    ldv = (V.stride(2) if k > 1 else max(n, 1)) if V is not None else 1
     rc = lib().svdb_svd_strided_batched(
         code, b, m, n, A.data_ptr(), lda, A.stride(0), S.data_ptr(), S.stride(0),
         U.data_ptr() if U is not None else None, ldu, U.stride(0) if U is not None else 0,
@@ -191,7 +194,8 @@ class BatchedCall:
     """A prepared svdb_svd_batched call: outputs, pointer arrays and the
     workspace are built once; calling the object enqueues the SVD of every
     matrix of `mats` (a list of column-major (m_b, n_b) GPU tensors of one
-    dtype) and returns (S, U, V, info, sweeps) (lists for S, U, V)."""
+    dtype, any shapes) and returns (S, U, V, info, sweeps) (lists for S, U,
+    V, with k_b = min(m_b, n_b) columns)."""
 
     def __init__(self, mats, tol: float = 0.0, max_sweeps: int = 100, compute_u: bool = True,
                  compute_v: bool = True, masking: bool = True, precision: int = 0):
@@ -205,11 +209,12 @@ class BatchedCall:
                 raise ValueError("every matrix must be a 2-D column-major tensor of one dtype")
         self.ms = (C.c_int * bsz)(*[int(x.shape[0]) for x in mats])
         self.ns = (C.c_int * bsz)(*[int(x.shape[1]) for x in mats])
-        self.S = [torch.empty(int(x.shape[1]), dtype=_REAL[dt], device=dev) for x in mats]
-        self.U = [torch.empty((int(x.shape[1]), int(x.shape[0])), dtype=dt, device=dev).t()
-                  for x in mats] if compute_u else None
-        self.V = [torch.empty((int(x.shape[1]), int(x.shape[1])), dtype=dt, device=dev).t()
-                  for x in mats] if compute_v else None
+        ks = [min(int(x.shape[0]), int(x.shape[1])) for x in mats]
+        self.S = [torch.empty(k, dtype=_REAL[dt], device=dev) for k in ks]
+        self.U = [torch.empty((k, int(x.shape[0])), dtype=dt, device=dev).t()
+                  for x, k in zip(mats, ks)] if compute_u else None
+        self.V = [torch.empty((k, int(x.shape[1])), dtype=dt, device=dev).t()
+                  for x, k in zip(mats, ks)] if compute_v else None
         self.info = torch.empty(bsz, dtype=torch.int32, device=dev)
         self.sweeps = torch.empty(bsz, dtype=torch.int32, device=dev)
         P = C.c_void_p * bsz
@@ -283,17 +288,18 @@ class Server:
         if A.dim() != 2 or (A.shape[0] > 1 and A.stride(0) != 1):
             raise ValueError("A must be a 2-D column-major tensor")
         m, n = int(A.shape[0]), int(A.shape[1])
+        k = min(m, n)
         dt = A.dtype
-        S = torch.empty(n, dtype=_REAL[dt], device=A.device)
-        U = torch.empty((n, m), dtype=dt, device=A.device).t() if compute_u else None
-        V = torch.empty((n, n), dtype=dt, device=A.device).t() if compute_v else None
+        S = torch.empty(k, dtype=_REAL[dt], device=A.device)
+        U = torch.empty((k, m), dtype=dt, device=A.device).t() if compute_u else None
+        V = torch.empty((k, n), dtype=dt, device=A.device).t() if compute_v else None
         info = torch.empty(1, dtype=torch.int32, device=A.device)
         sweeps = torch.empty(1, dtype=torch.int32, device=A.device)
         lda = max(A.stride(1), m, 1) if n > 1 else max(m, 1)
         rid = lib().svdb_server_submit(
-            self._h, dtype_code(dt), m, n, A.data_ptr() if n else None, lda,
-            S.data_ptr() if n else None, U.data_ptr() if U is not None and n else None,
-            max(m, 1), V.data_ptr() if V is not None and n else None, max(n, 1), 0.0,
+            self._h, dtype_code(dt), m, n, A.data_ptr() if k else None, lda,
+            S.data_ptr() if k else None, U.data_ptr() if U is not None and k else None,
+            max(m, 1), V.data_ptr() if V is not None and k else None, max(n, 1), 0.0,
             info.data_ptr(), sweeps.data_ptr())
         if rid < 0:
             raise SvdbError(int(rid), self.error() or "svdb_server_submit failed")

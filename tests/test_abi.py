@@ -54,7 +54,14 @@ def _call(**kw):
     (dict(dtype=9), -1),
     (dict(batch=-1), -2),
     (dict(m=-1), -3),
-    (dict(m=3, n=4, lda=4), -4),          # wide matrices are rejected
+    (dict(n=-1), -4),
+    # wide (m < n): k = min(m, n) = 4 columns of U (4 x 4) and V (8 x 4)
+    (dict(m=4, n=8, lda=3, sA=32, sS=4, ldu=4, sU=16, ldv=8, sV=32), -6),
+    (dict(m=4, n=8, lda=4, sA=32, sS=3, ldu=4, sU=16, ldv=8, sV=32), -9),
+    (dict(m=4, n=8, lda=4, sA=32, sS=4, ldu=4, sU=15, ldv=8, sV=32), -12),
+    (dict(m=4, n=8, lda=4, sA=32, sS=4, ldu=4, sU=16, ldv=7, sV=32), -14),
+    (dict(m=4, n=8, lda=4, sA=32, sS=4, ldu=4, sU=16, ldv=8, sV=31), -15),
+    (dict(m=4, n=8, lda=4, sA=32, sS=4, ldu=4, sU=16, ldv=8, sV=32), -19),   # A^H copy
     (dict(A=None), -5),
     (dict(lda=7), -6),
     (dict(sA=31), -7),
@@ -81,9 +88,16 @@ def test_empty_batch_is_a_noop():
 def test_plan_and_workspace():
     p, nb, th = svdb.plan(svdb.torch.float64, 16, 16)
     assert p in (svdb.PATH_PLAIN, svdb.PATH_RESIDENT, svdb.PATH_BLOCKED)
-    assert svdb.lib().svdb_workspace_size(svdb.R64, 10, 4, 8, None) == C.c_size_t(-1).value
-    with pytest.raises(svdb.SvdbError):
-        svdb.plan(svdb.torch.float64, 4, 8)
+    L = svdb.lib()
+    assert L.svdb_workspace_size(svdb.R64, 10, -1, 8, None) == C.c_size_t(-1).value
+    # a wide matrix runs the plan of A^H, with the A^H copy added to the workspace
+    for dt, code, es in ((svdb.torch.float64, svdb.R64, 8), (svdb.torch.complex64, svdb.C64, 8),
+                         (svdb.torch.float32, svdb.R32, 4)):
+        for m, n in ((4, 8), (24, 100), (40, 64)):
+            assert svdb.plan(dt, m, n) == svdb.plan(dt, n, m)
+            tall = L.svdb_workspace_size(code, 10, n, m, None)
+            wide = L.svdb_workspace_size(code, 10, m, n, None)
+            assert wide == tall + (10 * m * n * es + 255) // 256 * 256
 
 
 def test_batched_argument_errors():
@@ -96,6 +110,14 @@ def test_batched_argument_errors():
     lda = I(8, 4)
     S = P(0x3000, 0x4000)
     info = 0x5000
+    rc = L.svdb_svd_batched(svdb.R64, 2, m, n, A, lda, S, None, None, None, None, 0.0, info,
+                            None, 0, None, None)
+    assert rc == -14                       # wide matrices are accepted; no workspace given
+    # the workspace of a wide matrix is that of its (tall) conjugate transpose
+    wide = L.svdb_batched_workspace_size(svdb.R64, 2, m, n, None)
+    mt, nt = (C.c_int * 2)(8, 6), (C.c_int * 2)(4, 4)
+    assert wide == L.svdb_batched_workspace_size(svdb.R64, 2, mt, nt, None)
+    n[1] = -1
     rc = L.svdb_svd_batched(svdb.R64, 2, m, n, A, lda, S, None, None, None, None, 0.0, info,
                             None, 0, None, None)
     assert rc == -4

@@ -148,3 +148,31 @@ def test_server_precondition_modes(precondition):
         k = ids[rid]
         assert out[0].dtype == (torch.float64 if reqs[k].dtype == np.float64 else torch.float32)
         _check(reqs[k], out, f"precondition={precondition} #{k} {reqs[k].shape}")
+
+
+def test_server_wide_requests():
+    """Wide requests (m < n) run as A^H, read transposed, with U and V
+    exchanged; each is checked as the SVD of the tall matrix A^H."""
+    import torch
+    from paper_2601_17979_amd import svdb
+    shapes = [(16, 40), (40, 16), (30, 64), (64, 30), (1, 9), (100, 200)]
+    reqs = []
+    for k, (m, n) in enumerate(shapes):
+        dt = np.float64 if k % 2 == 0 else np.float32
+        reqs.append(_mat(9700, k, n, m, dt).T.copy() if m < n else _mat(9700, k, m, n, dt))
+    dev = [_to_dev(A) for A in reqs]
+    torch.cuda.synchronize()
+    srv = svdb.Server(budget_bytes=64 << 20, max_requests=16)
+    ids = {srv.submit(x): k for k, x in enumerate(dev)}
+    got = _drain(srv, len(reqs))
+    srv.close()
+    for rid, (ts, td, out) in got.items():
+        k = ids[rid]
+        A = reqs[k]
+        m, n = A.shape
+        S, U, V = out[0], out[1], out[2]
+        assert S.shape == (min(m, n),) and U.shape == (m, min(m, n)) and V.shape == (n, min(m, n))
+        if m >= n:
+            _check(A, out, f"serve tall {A.shape}")
+        else:   # A^H = V S U^H
+            _check(A.T.copy(), (out[0], out[2], out[1], out[3], out[4]), f"serve wide {A.shape}")
