@@ -93,10 +93,18 @@ typedef struct {
                          SVDB_ERR_UNSUPPORTED where it does not apply).  The
                          sweeps count is that of the iteration on the
                          triangular factor.                                  */
+    int inner_sweeps; /* block method: sweeps of Alg. 1 per block-pair
+                         solve ("Inexact Hermitian Eigendecomposition").  0
+                         (default, tuned): one (Design 2) when the matrix
+                         has more than two block columns; with two (l = 2)
+                         two, or for m >= 8 np the converged solve (FP64)
+                         or three (FP32); k > 0: at most k, stopping at a
+                         sweep that rotates nothing; < 0: to convergence (at
+                         most 100).                                          */
 } svdb_opts_t;
 
 /* Fills *o with the defaults (AUTO path, 100 sweeps, masking on,
- * precondition -1). */
+ * precondition -1, inner_sweeps 0). */
 void svdb_opts_default(svdb_opts_t *o);
 
 /*

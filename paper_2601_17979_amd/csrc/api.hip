@@ -65,6 +65,7 @@ svdb_opts_t resolve_opts(const svdb_opts_t *o)
         if (r.max_sweeps <= 0) r.max_sweeps = 100;
         if (r.masking < 0) r.masking = 1;
         if (r.waves < 0) r.waves = 0;
+        if (r.inner_sweeps < -1) r.inner_sweeps = -1;
     }
     return r;
 }
@@ -164,6 +165,7 @@ void svdb_opts_default(svdb_opts_t *o)
     o->sweeps = nullptr;
     o->waves = 0;
     o->precondition = -1;
+    o->inner_sweeps = 0;
 }
 
 const char *svdb_last_error(void) { return g_err.c_str(); }
@@ -230,26 +232,28 @@ hipError_t run_tall(svdb_dtype_t dtype, const Plan &p, const svdb_opts_t &o, int
     } else if (p.path == SVDB_PATH_BLOCKED && dtype == SVDB_R32) {
         e = svdb::launch_blocked_s(batch, m, n, p.nb, (const float *)A, lda, strideA, (float *)S,
                                    strideS, (float *)U, ldu, strideU, (float *)V, ldv, strideV,
-                                   tol, o.max_sweeps, o.masking, info, o.sweeps, workspace, s);
+                                   tol, o.max_sweeps, o.masking, info, o.sweeps, workspace, s,
+                                   o.inner_sweeps);
     } else if (p.path == SVDB_PATH_BLOCKED && dtype == SVDB_C128) {
         e = svdb::launch_blocked_z(batch, m, n, p.nb, A, lda, strideA, (double *)S, strideS, U,
                                    ldu, strideU, V, ldv, strideV, tol, o.max_sweeps, o.masking,
-                                   info, o.sweeps, workspace, s);
+                                   info, o.sweeps, workspace, s, o.inner_sweeps);
     } else if (p.path == SVDB_PATH_BLOCKED && dtype == SVDB_C64) {
         e = svdb::launch_blocked_c(batch, m, n, p.nb, A, lda, strideA, (float *)S, strideS, U,
                                    ldu, strideU, V, ldv, strideV, tol, o.max_sweeps, o.masking,
-                                   info, o.sweeps, workspace, s);
+                                   info, o.sweeps, workspace, s, o.inner_sweeps);
     } else if (p.path == SVDB_PATH_BLOCKED && o.precision == 1) {
         const double tol32 = fmax(tol, default_tol(SVDB_R32));
         e = svdb::launch_blocked_mixed_d(batch, m, n, p.nb, (const double *)A, lda, strideA,
                                          (double *)S, strideS, (double *)U, ldu, strideU,
                                          (double *)V, ldv, strideV, tol, tol32, o.max_sweeps,
-                                         o.masking, info, o.sweeps, workspace, s);
+                                         o.masking, info, o.sweeps, workspace, s,
+                                         o.inner_sweeps);
     } else if (p.path == SVDB_PATH_BLOCKED) {
         e = svdb::launch_blocked_d(batch, m, n, p.nb, (const double *)A, lda, strideA,
                                    (double *)S, strideS, (double *)U, ldu, strideU, (double *)V,
                                    ldv, strideV, tol, o.max_sweeps, o.masking, info, o.sweeps,
-                                   workspace, s);
+                                   workspace, s, o.inner_sweeps);
     } else if (p.path == SVDB_PATH_PLAIN) {
         e = svdb::launch_plain_d(batch, m, n, (const double *)A, lda, strideA, (double *)S,
                                  strideS, (double *)U, ldu, strideU, (double *)V, ldv, strideV,
@@ -389,7 +393,7 @@ int svdb_svd_batched(svdb_dtype_t dtype, int batch, const int *m, const int *n,
     hipError_t e = svdb::launch_vbatched((int)dtype, batch, mt.data(), nt.data(), A, lda, S,
                                          Ut.data(), ldut.data(), Vt.data(), ldvt.data(), tol,
                                          o.max_sweeps, o.masking, info, o.sweeps, workspace,
-                                         (hipStream_t)stream, tr.data());
+                                         (hipStream_t)stream, tr.data(), o.inner_sweeps);
     if (e != hipSuccess) return hip_fail(e, "launch");
     return 0;
 }

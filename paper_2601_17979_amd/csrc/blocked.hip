@@ -216,6 +216,23 @@ __global__ __launch_bounds__(kBT) void blk_init(int m, int n, int np, const EA *
 // real columns of the streamed chunk.  The chunk and the real Gram matrix
 // share storage (never live together); a complex G has its own arrays.
 // ---------------------------------------------------------------------------
+// Inner sweeps of one block pair's solve: inner > 0 caps them at inner, < 0
+// runs the solve to convergence (at most kInnerCap sweeps).  0 (auto), from
+// measurements on MI355X: one sweep (Design 2) when the matrix has more than
+// two block columns, where more inner sweeps barely lower the outer count;
+// with two (l = 2: one pair, the whole matrix, per sweep) two sweeps, and
+// for tall matrices (m >= 8 np), whose Gram and update passes dominate, the
+// converged solve in FP64 and three sweeps in FP32.
+constexpr int kInnerCap = 100;
+__host__ __device__ inline int inner_sweeps_of(int inner, int l, int m, int np, bool fp32)
+{
+    if (inner > 0) return inner;
+    if (inner < 0) return kInnerCap;
+    if (l > 2) return 1;
+    if (m >= 8 * np) return fp32 ? 3 : kInnerCap;
+    return 2;
+}
+
 template <class T, bool CX, int NB>
 struct IterShared {
     static constexpr int N2 = 2 * NB, NR = (CX ? 2 : 1) * N2;
@@ -555,7 +572,7 @@ template <class T, bool CX, int NB>
 __device__ __forceinline__ void iter_body(IterShared<T, CX, NB> &s, int m, int np, int l, int it,
                                           int pair, typename Elem<T, CX>::type *W,
                                           typename Elem<T, CX>::type *Vw, BlkState *stb,
-                                          double tol)
+                                          double tol, int inner)
 {
     using E = typename Elem<T, CX>::type;
     using Sh = IterShared<T, CX, NB>;
@@ -618,12 +635,28 @@ __device__ __forceinline__ void iter_body(IterShared<T, CX, NB> &s, int m, int n
     if (tid == 0) s.rot = 0;
     __syncthreads();
 
-    // ---- 2. one inner sweep of Alg. 1 on G (FP64), round robin -------------
-    double mc;
-    if constexpr (CX)
-        mc = inner_sweep_cx<T, NB>(s, tol);
-    else
-        mc = inner_sweep_real<T, NB>(s, tol);
+    // ---- 2. inner sweeps of Alg. 1 on G (FP64), round robin -------------
+    // Design 2 ("Inexact Hermitian Eigendecomposition") runs one; more, up
+    // to the solve's convergence, are the variants of the same section.  A
+    // sweep that rotates nothing ends the solve, so "no rotation in the whole
+    // outer sweep" still means that every first inner sweep rotated nothing.
+    const int nsw = inner_sweeps_of(inner, l, m, np, sizeof(T) == 4);
+    bool any = false;
+    double mc = 0.0;
+    for (int k = 0; k < nsw; k++) {
+        double mck;
+        if constexpr (CX)
+            mck = inner_sweep_cx<T, NB>(s, tol);
+        else
+            mck = inner_sweep_real<T, NB>(s, tol);
+        if (k == 0) mc = mck;   // the switch test of the mixed mode uses the first
+        const bool r = s.rot != 0;   // the sweep ended with a barrier
+        __syncthreads();             // every thread has read the flag
+        if (!r) break;
+        any = true;
+        if (tid == 0) s.rot = 0;
+        __syncthreads();
+    }
     if (wave == 0) {
         mc = wave_max(mc);
         if (lane == 0 && mc > 0.0)
@@ -631,7 +664,7 @@ __device__ __forceinline__ void iter_body(IterShared<T, CX, NB> &s, int m, int n
     }
 
     // ---- 3. fused update of the block columns of W and V --------------------
-    if (s.rot != 0) {
+    if (any) {
         update_block_columns<T, CX, NB, E>(s, W, m, p, q);
         update_block_columns<T, CX, NB, E>(s, Vw, np, p, q);
         if (tid == 0) atomicOr(&stb->rotated, 1);
@@ -642,13 +675,13 @@ template <class T, bool CX, int NB>
 __global__ __launch_bounds__(kBT) void blk_iter(int m, int np, int l, int it,
                                                 typename Elem<T, CX>::type *W,
                                                 typename Elem<T, CX>::type *Vw, BlkState *st,
-                                                double tol)
+                                                double tol, int inner)
 {
     __shared__ IterShared<T, CX, NB> s;
     const int b = blockIdx.x / (l / 2), pair = blockIdx.x % (l / 2);
     if (!st[b].active) return;
     iter_body<T, CX, NB>(s, m, np, l, it, pair, W + (size_t)b * m * np, Vw + (size_t)b * np * np,
-                         st + b, tol);
+                         st + b, tol, inner);
 }
 
 // End of a sweep: a matrix with no rotation is converged (done); with
@@ -960,19 +993,19 @@ hipError_t pinned_counter(int **out)
 template <class T, bool CX>
 void launch_iter(int nb, unsigned grid, hipStream_t stream, int m, int np, int l, int it,
                  typename Elem<T, CX>::type *W, typename Elem<T, CX>::type *Vw, BlkState *st,
-                 double tol)
+                 double tol, int inner)
 {
     if constexpr (CX) {
         hipLaunchKernelGGL((blk_iter<T, true, 16>), dim3(grid), dim3(kBT), 0, stream, m, np, l,
-                           it, W, Vw, st, tol);
+                           it, W, Vw, st, tol, inner);
         (void)nb;
     } else {
         if (nb == 16)
             hipLaunchKernelGGL((blk_iter<T, false, 16>), dim3(grid), dim3(kBT), 0, stream, m, np,
-                               l, it, W, Vw, st, tol);
+                               l, it, W, Vw, st, tol, inner);
         else
             hipLaunchKernelGGL((blk_iter<T, false, 32>), dim3(grid), dim3(kBT), 0, stream, m, np,
-                               l, it, W, Vw, st, tol);
+                               l, it, W, Vw, st, tol, inner);
     }
 }
 
@@ -980,7 +1013,7 @@ void launch_iter(int nb, unsigned grid, hipStream_t stream, int m, int np, int l
 template <class T, bool CX>
 hipError_t run_sweeps(int batch, int m, int np, int nb, typename Elem<T, CX>::type *W,
                       typename Elem<T, CX>::type *Vw, BlkState *st, int *pending, double tol,
-                      int max_sweeps, int masking, int phase32, hipStream_t stream)
+                      int max_sweeps, int masking, int phase32, int inner, hipStream_t stream)
 {
     const int l = np / nb;
     int *host_count;
@@ -989,7 +1022,7 @@ hipError_t run_sweeps(int batch, int m, int np, int nb, typename Elem<T, CX>::ty
     const unsigned grid = (unsigned)batch * (unsigned)(l / 2);
     for (int sw = 0; sw < max_sweeps; sw++) {
         for (int it = 0; it < l - 1; it++)
-            launch_iter<T, CX>(nb, grid, stream, m, np, l, it, W, Vw, st, tol);
+            launch_iter<T, CX>(nb, grid, stream, m, np, l, it, W, Vw, st, tol, inner);
         e = hipMemsetAsync(pending, 0, sizeof(int), stream);
         if (e != hipSuccess) return e;
         hipLaunchKernelGGL(blk_sweep_end, dim3((batch + 255) / 256), dim3(256), 0, stream, batch,
@@ -1049,7 +1082,7 @@ hipError_t launch_blocked(int batch, int m, int n, int nb, const typename Elem<T
                           typename Elem<T, CX>::type *U, int ldu, long long sU,
                           typename Elem<T, CX>::type *V, int ldv, long long sV, double tol,
                           int max_sweeps, int masking, int *info, int *sweeps, void *ws,
-                          hipStream_t stream)
+                          hipStream_t stream, int inner)
 {
     using E = typename Elem<T, CX>::type;
     const int np = blocked_np(n, nb);
@@ -1060,7 +1093,7 @@ hipError_t launch_blocked(int batch, int m, int n, int nb, const typename Elem<T
     hipError_t e = hipGetLastError();
     if (e != hipSuccess) return e;
     e = run_sweeps<T, CX>(batch, m, np, nb, W, Vw, L.st, L.pending, tol, max_sweeps, masking, 0,
-                          stream);
+                          inner, stream);
     if (e != hipSuccess) return e;
     const size_t lds = (size_t)n * (sizeof(double) + sizeof(int));
     hipLaunchKernelGGL((blk_finalize<E, E>), dim3(batch), dim3(kBT), lds, stream, m, n, np,
@@ -1092,7 +1125,7 @@ __global__ __launch_bounds__(kBT) void vb_init(const VbDesc *d, const int *idx, 
 
 template <class T, bool CX>
 __global__ __launch_bounds__(kBT) void vb_iter(const VbDesc *d, const int2 *work, int itg,
-                                               void *base, BlkState *st, double tol)
+                                               void *base, BlkState *st, double tol, int inner)
 {
     using E = typename Elem<T, CX>::type;
     __shared__ IterShared<T, CX, kVbNb> s;
@@ -1102,7 +1135,7 @@ __global__ __launch_bounds__(kBT) void vb_iter(const VbDesc *d, const int2 *work
     const int m = D.m, np = D.np, l = D.l;
     E *Wb = (E *)base;
     iter_body<T, CX, kVbNb>(s, m, np, l, (itg - D.it0) % (l - 1), w.y, Wb + D.woff, Wb + D.voff,
-                            st + w.x, tol);
+                            st + w.x, tol, inner);
 }
 
 // Closes the sweeps of the matrices whose sweep ends at launch itg; a matrix
@@ -1219,10 +1252,10 @@ hipError_t vb_staging(size_t bytes, char **out)
 
 template <class T, bool CX>
 void vb_launch_iter_t(const VbDesc *d, const int2 *work, int nwork, int itg, void *base,
-                      BlkState *st, double tol, hipStream_t stream)
+                      BlkState *st, double tol, int inner, hipStream_t stream)
 {
     hipLaunchKernelGGL((vb_iter<T, CX>), dim3((unsigned)nwork), dim3(kBT), 0, stream, d, work, itg,
-                       base, st, tol);
+                       base, st, tol, inner);
 }
 
 template <class E>
@@ -1258,14 +1291,14 @@ void vb_launch_init(int dtype, const VbDesc *d, const int *idx, int count, void 
 }
 
 void vb_launch_iter(int dtype, const VbDesc *d, const int2 *work, int nwork, int itg, void *base,
-                    void *st, double tol, hipStream_t stream)
+                    void *st, double tol, hipStream_t stream, int inner)
 {
     BlkState *S = (BlkState *)st;
     switch (dtype) {
-    case 0: vb_launch_iter_t<float, false>(d, work, nwork, itg, base, S, tol, stream); break;
-    case 1: vb_launch_iter_t<double, false>(d, work, nwork, itg, base, S, tol, stream); break;
-    case 2: vb_launch_iter_t<float, true>(d, work, nwork, itg, base, S, tol, stream); break;
-    default: vb_launch_iter_t<double, true>(d, work, nwork, itg, base, S, tol, stream); break;
+    case 0: vb_launch_iter_t<float, false>(d, work, nwork, itg, base, S, tol, inner, stream); break;
+    case 1: vb_launch_iter_t<double, false>(d, work, nwork, itg, base, S, tol, inner, stream); break;
+    case 2: vb_launch_iter_t<float, true>(d, work, nwork, itg, base, S, tol, inner, stream); break;
+    default: vb_launch_iter_t<double, true>(d, work, nwork, itg, base, S, tol, inner, stream); break;
     }
 }
 
@@ -1310,7 +1343,7 @@ hipError_t launch_vb(int dtype, size_t elt, int batch, const int *m, const int *
                      const void *const *A, const int *lda, void *const *S, void *const *U,
                      const int *ldu, void *const *V, const int *ldv, double tol, int max_sweeps,
                      int masking, int *info, int *sweeps, void *ws, hipStream_t stream,
-                     const int *trans)
+                     const int *trans, int inner)
 {
     VbLayout L = vb_layout(ws, batch, m, n, elt);
     // descriptors, then the work table with the largest matrices first
@@ -1374,7 +1407,8 @@ hipError_t launch_vb(int dtype, size_t elt, int batch, const int *m, const int *
         if (e != hipSuccess) return e;
         for (int k = 0; k < lmax - 1; k++, itg++) {
             if (nwork)
-                vb_launch_iter(dtype, L.desc, L.work, (int)nwork, itg, L.base, L.st, tol, stream);
+                vb_launch_iter(dtype, L.desc, L.work, (int)nwork, itg, L.base, L.st, tol, stream,
+                               inner);
             vb_launch_sweep_end(batch, L.desc, itg, L.st, max_sweeps, masking,
                                 k == lmax - 2 ? L.pending : (int *)nullptr, stream);
         }
@@ -1423,39 +1457,40 @@ size_t blocked_workspace_bytes(int batch, int m, int n, int nb, int elt, bool mi
 hipError_t launch_blocked_d(int batch, int m, int n, int nb, const double *A, int lda, long long sA,
                             double *S, long long sS, double *U, int ldu, long long sU, double *V,
                             int ldv, long long sV, double tol, int max_sweeps, int masking,
-                            int *info, int *sweeps, void *ws, hipStream_t stream)
+                            int *info, int *sweeps, void *ws, hipStream_t stream, int inner)
 {
     return launch_blocked<double, false>(batch, m, n, nb, A, lda, sA, S, sS, U, ldu, sU, V, ldv,
-                                         sV, tol, max_sweeps, masking, info, sweeps, ws, stream);
+                                         sV, tol, max_sweeps, masking, info, sweeps, ws, stream,
+                                         inner);
 }
 
 hipError_t launch_blocked_s(int batch, int m, int n, int nb, const float *A, int lda, long long sA,
                             float *S, long long sS, float *U, int ldu, long long sU, float *V,
                             int ldv, long long sV, double tol, int max_sweeps, int masking,
-                            int *info, int *sweeps, void *ws, hipStream_t stream)
+                            int *info, int *sweeps, void *ws, hipStream_t stream, int inner)
 {
     return launch_blocked<float, false>(batch, m, n, nb, A, lda, sA, S, sS, U, ldu, sU, V, ldv, sV,
-                                        tol, max_sweeps, masking, info, sweeps, ws, stream);
+                                        tol, max_sweeps, masking, info, sweeps, ws, stream, inner);
 }
 
 hipError_t launch_blocked_z(int batch, int m, int n, int nb, const void *A, int lda, long long sA,
                             double *S, long long sS, void *U, int ldu, long long sU, void *V,
                             int ldv, long long sV, double tol, int max_sweeps, int masking,
-                            int *info, int *sweeps, void *ws, hipStream_t stream)
+                            int *info, int *sweeps, void *ws, hipStream_t stream, int inner)
 {
     return launch_blocked<double, true>(batch, m, n, nb, (const double2 *)A, lda, sA, S, sS,
                                         (double2 *)U, ldu, sU, (double2 *)V, ldv, sV, tol,
-                                        max_sweeps, masking, info, sweeps, ws, stream);
+                                        max_sweeps, masking, info, sweeps, ws, stream, inner);
 }
 
 hipError_t launch_blocked_c(int batch, int m, int n, int nb, const void *A, int lda, long long sA,
                             float *S, long long sS, void *U, int ldu, long long sU, void *V,
                             int ldv, long long sV, double tol, int max_sweeps, int masking,
-                            int *info, int *sweeps, void *ws, hipStream_t stream)
+                            int *info, int *sweeps, void *ws, hipStream_t stream, int inner)
 {
     return launch_blocked<float, true>(batch, m, n, nb, (const float2 *)A, lda, sA, S, sS,
                                        (float2 *)U, ldu, sU, (float2 *)V, ldv, sV, tol, max_sweeps,
-                                       masking, info, sweeps, ws, stream);
+                                       masking, info, sweeps, ws, stream, inner);
 }
 
 // Mixed mode: FP32 sweeps (FP32 matrix cores, FP64 inner solves) with
@@ -1467,7 +1502,7 @@ hipError_t launch_blocked_mixed_d(int batch, int m, int n, int nb, const double 
                                   long long sA, double *S, long long sS, double *U, int ldu,
                                   long long sU, double *V, int ldv, long long sV, double tol,
                                   double tol32, int max_sweeps, int masking, int *info,
-                                  int *sweeps, void *ws, hipStream_t stream)
+                                  int *sweeps, void *ws, hipStream_t stream, int inner)
 {
     const int np = blocked_np(n, nb);
     WsLayout L = carve(ws, batch, m, n, np, sizeof(double), true);
@@ -1478,7 +1513,7 @@ hipError_t launch_blocked_mixed_d(int batch, int m, int n, int nb, const double 
     hipError_t e = hipGetLastError();
     if (e != hipSuccess) return e;
     e = run_sweeps<float, false>(batch, m, np, nb, W32, V32, L.st, L.pending, tol32, max_sweeps,
-                                 1, 1, stream);
+                                 1, 1, inner, stream);
     if (e != hipSuccess) return e;
 
     // Newton-Schulz on Q; Q1 lives in the (not yet used) FP64 V area, ld n
@@ -1512,7 +1547,7 @@ hipError_t launch_blocked_mixed_d(int batch, int m, int n, int nb, const double 
     e = hipGetLastError();
     if (e != hipSuccess) return e;
     e = run_sweeps<double, false>(batch, m, np, nb, W, Vw, L.st, L.pending, tol, max_sweeps,
-                                  masking, 0, stream);
+                                  masking, 0, inner, stream);
     if (e != hipSuccess) return e;
     const size_t lds = (size_t)n * (sizeof(double) + sizeof(int));
     hipLaunchKernelGGL((blk_finalize<double, double>), dim3(batch), dim3(kBT), lds, stream, m, n,
@@ -1534,11 +1569,11 @@ hipError_t launch_vbatched(int dtype, int batch, const int *m, const int *n, con
                            const int *lda, void *const *S, void *const *U, const int *ldu,
                            void *const *V, const int *ldv, double tol, int max_sweeps,
                            int masking, int *info, int *sweeps, void *ws, hipStream_t stream,
-                           const int *trans)
+                           const int *trans, int inner)
 {
     const size_t elt = dtype == 0 ? 4 : dtype == 3 ? 16 : 8;
     return launch_vb(dtype, elt, batch, m, n, A, lda, S, U, ldu, V, ldv, tol, max_sweeps, masking,
-                     info, sweeps, ws, stream, trans);
+                     info, sweeps, ws, stream, trans, inner);
 }
 
 }  // namespace svdb

@@ -58,30 +58,37 @@ hipError_t launch_precond_big_d(int batch, int m, int n, int nb, const double *A
 // blocked.hip: block one-sided Jacobi with MFMA Gram/updates (real and
 // complex, FP64 and FP32, and FP32 sweeps followed by an FP64 refinement).
 // blocked_nb returns the block width for a request (0: not supported).
+// `inner` (all block launchers): inner sweeps per block-pair solve; 0 = one,
+// or the converged solve for two block columns; k > 0 = at most k; < 0 = to
+// convergence.
 int blocked_nb(int m, int n, int nb, bool complex_);
 int blocked_np(int n, int nb);
 size_t blocked_workspace_bytes(int batch, int m, int n, int nb, int elt, bool mixed);
 hipError_t launch_blocked_d(int batch, int m, int n, int nb, const double *A, int lda, long long sA,
                             double *S, long long sS, double *U, int ldu, long long sU, double *V,
                             int ldv, long long sV, double tol, int max_sweeps, int masking,
-                            int *info, int *sweeps, void *ws, hipStream_t stream);
+                            int *info, int *sweeps, void *ws, hipStream_t stream,
+                            int inner = 0);
 hipError_t launch_blocked_s(int batch, int m, int n, int nb, const float *A, int lda, long long sA,
                             float *S, long long sS, float *U, int ldu, long long sU, float *V,
                             int ldv, long long sV, double tol, int max_sweeps, int masking,
-                            int *info, int *sweeps, void *ws, hipStream_t stream);
+                            int *info, int *sweeps, void *ws, hipStream_t stream,
+                            int inner = 0);
 hipError_t launch_blocked_z(int batch, int m, int n, int nb, const void *A, int lda, long long sA,
                             double *S, long long sS, void *U, int ldu, long long sU, void *V,
                             int ldv, long long sV, double tol, int max_sweeps, int masking,
-                            int *info, int *sweeps, void *ws, hipStream_t stream);
+                            int *info, int *sweeps, void *ws, hipStream_t stream,
+                            int inner = 0);
 hipError_t launch_blocked_c(int batch, int m, int n, int nb, const void *A, int lda, long long sA,
                             float *S, long long sS, void *U, int ldu, long long sU, void *V,
                             int ldv, long long sV, double tol, int max_sweeps, int masking,
-                            int *info, int *sweeps, void *ws, hipStream_t stream);
+                            int *info, int *sweeps, void *ws, hipStream_t stream,
+                            int inner = 0);
 hipError_t launch_blocked_mixed_d(int batch, int m, int n, int nb, const double *A, int lda,
                                   long long sA, double *S, long long sS, double *U, int ldu,
                                   long long sU, double *V, int ldv, long long sV, double tol,
                                   double tol32, int max_sweeps, int masking, int *info,
-                                  int *sweeps, void *ws, hipStream_t stream);
+                                  int *sweeps, void *ws, hipStream_t stream, int inner = 0);
 
 // Per-matrix descriptor of the uneven-batch kernels (device memory).
 struct VbDesc {
@@ -99,7 +106,7 @@ struct VbDesc {
 void vb_launch_init(int dtype, const VbDesc *d, const int *idx, int count, void *base, void *st,
                     hipStream_t stream);
 void vb_launch_iter(int dtype, const VbDesc *d, const int2 *work, int nwork, int itg, void *base,
-                    void *st, double tol, hipStream_t stream);
+                    void *st, double tol, hipStream_t stream, int inner = 0);
 void vb_launch_sweep_end(int count, const VbDesc *d, int itg, void *st, int max_sweeps,
                          int masking, int *pending, hipStream_t stream);
 void vb_launch_collect(int count, const void *st, int *flags, hipStream_t stream);
@@ -117,7 +124,7 @@ hipError_t launch_vbatched(int dtype, int batch, const int *m, const int *n, con
                            const int *lda, void *const *S, void *const *U, const int *ldu,
                            void *const *V, const int *ldv, double tol, int max_sweeps,
                            int masking, int *info, int *sweeps, void *ws, hipStream_t stream,
-                           const int *trans = nullptr);
+                           const int *trans = nullptr, int inner = 0);
 
 // layout.hip: At (n x m, ld n, n m apart) = A^H for a strided batch of m x n
 // matrices; dtype as svdb_dtype_t.

@@ -192,6 +192,7 @@ struct svdb_server {
     int max_sweeps = 100;
     int max_n = 512;
     int precondition = 1;
+    int inner = 0;   // inner sweeps per block-pair solve (svdb_opts_t.inner_sweeps)
     std::mutex mu;
     std::condition_variable cv_work, cv_done;
     std::deque<Request> queue;
@@ -446,7 +447,7 @@ void worker_main(svdb_server *s)
                 if (!G.nused) continue;
                 if (G.nwork)
                     svdb::vb_launch_iter(G.dtype, G.d_desc, G.d_work, G.nwork, s->itg, s->arena,
-                                         G.d_st, G.tol, s->stream);
+                                         G.d_st, G.tol, s->stream, s->inner);
                 svdb::vb_launch_sweep_end(G.cap, G.d_desc, s->itg, G.d_st, s->max_sweeps, 1,
                                           nullptr, s->stream);
             }
@@ -583,6 +584,7 @@ int svdb_server_create(svdb_server_t **out, size_t budget_bytes, int max_request
     s->budget = al256(budget_bytes);
     s->max_sweeps = o.max_sweeps > 0 ? o.max_sweeps : 100;
     s->precondition = o.precondition == 1;
+    s->inner = o.inner_sweeps < -1 ? -1 : o.inner_sweeps;
     hipError_t e = hipStreamCreateWithFlags(&s->stream, hipStreamNonBlocking);
     for (hipStream_t &a : s->aux)
         if (e == hipSuccess) e = hipStreamCreateWithFlags(&a, hipStreamNonBlocking);

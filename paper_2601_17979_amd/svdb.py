@@ -29,7 +29,7 @@ _PATHS = {"auto": PATH_AUTO, "plain": PATH_PLAIN, "resident": PATH_RESIDENT,
 class Opts(C.Structure):
     _fields_ = [("max_sweeps", C.c_int), ("path", C.c_int), ("nb", C.c_int),
                 ("masking", C.c_int), ("precision", C.c_int), ("sweeps", C.c_void_p),
-                ("waves", C.c_int), ("precondition", C.c_int)]
+                ("waves", C.c_int), ("precondition", C.c_int), ("inner_sweeps", C.c_int)]
 
 
 class SvdbError(RuntimeError):
@@ -95,7 +95,7 @@ def version() -> str:
 
 
 def make_opts(max_sweeps=100, path="auto", nb=0, masking=True, precision=0, sweeps=None,
-              waves=0, precondition=-1):
+              waves=0, precondition=-1, inner_sweeps=0):
     o = Opts()
     lib().svdb_opts_default(C.byref(o))
     o.max_sweeps = int(max_sweeps)
@@ -106,6 +106,7 @@ def make_opts(max_sweeps=100, path="auto", nb=0, masking=True, precision=0, swee
     o.sweeps = sweeps.data_ptr() if sweeps is not None else None
     o.waves = int(waves)
     o.precondition = int(precondition)
+    o.inner_sweeps = int(inner_sweeps)
     return o
 
 
@@ -148,7 +149,7 @@ def _check_cm(x: torch.Tensor, name: str):
 def svd(A: torch.Tensor, tol: float = 0.0, max_sweeps: int = 100, path="auto", nb: int = 0,
         compute_u: bool = True, compute_v: bool = True, masking: bool = True,
         precision: int = 0, want_sweeps: bool = True, stream=None, out=None, waves: int = 0,
-        precondition: int = -1):
+        precondition: int = -1, inner_sweeps: int = 0):
     """Batched reduced SVD of a (batch, m, n) column-major GPU tensor:
     A = U diag(S) V^H with k = min(m, n) singular values, U (m x k), V (n x k)
     (a wide matrix, m < n, is solved through its conjugate transpose).
@@ -170,7 +171,8 @@ def svd(A: torch.Tensor, tol: float = 0.0, max_sweeps: int = 100, path="auto", n
         V = empty_col_major(b, n, k, A.dtype, dev) if compute_v else None
         info = torch.empty(b, dtype=torch.int32, device=dev)
         sweeps = torch.empty(b, dtype=torch.int32, device=dev) if want_sweeps else None
-    o = make_opts(max_sweeps, path, nb, masking, precision, sweeps, waves, precondition)
+    o = make_opts(max_sweeps, path, nb, masking, precision, sweeps, waves, precondition,
+                  inner_sweeps)
     ws_bytes = lib().svdb_workspace_size(code, b, m, n, C.byref(o))
     if ws_bytes == C.c_size_t(-1).value:
         raise SvdbError(-1, last_error() or "invalid arguments")
@@ -198,7 +200,8 @@ class BatchedCall:
     V, with k_b = min(m_b, n_b) columns)."""
 
     def __init__(self, mats, tol: float = 0.0, max_sweeps: int = 100, compute_u: bool = True,
-                 compute_v: bool = True, masking: bool = True, precision: int = 0):
+                 compute_v: bool = True, masking: bool = True, precision: int = 0,
+                 inner_sweeps: int = 0):
         dt = mats[0].dtype
         dev = mats[0].device
         self.code = dtype_code(dt)
@@ -230,7 +233,8 @@ class BatchedCall:
         self.ldu = I(*[ld(u, u.shape[0]) for u in self.U]) if self.U is not None else None
         self.Vp = P(*[v.data_ptr() for v in self.V]) if self.V is not None else None
         self.ldv = I(*[ld(v, v.shape[0]) for v in self.V]) if self.V is not None else None
-        self.opts = make_opts(max_sweeps, "auto", 0, masking, precision, self.sweeps)
+        self.opts = make_opts(max_sweeps, "auto", 0, masking, precision, self.sweeps,
+                              inner_sweeps=inner_sweeps)
         self.tol = float(tol)
         self.ws_bytes = lib().svdb_batched_workspace_size(self.code, bsz, self.ms, self.ns,
                                                           C.byref(self.opts))
@@ -251,14 +255,15 @@ class BatchedCall:
 
 def svd_batched(mats, tol: float = 0.0, max_sweeps: int = 100, path="auto", nb: int = 0,
                 compute_u: bool = True, compute_v: bool = True, masking: bool = True,
-                precision: int = 0, stream=None):
+                precision: int = 0, stream=None, inner_sweeps: int = 0):
     """Mixed-shape batch: `mats` is a list of (m_b, n_b) column-major GPU
     tensors of one dtype.  Returns lists (S, U, V) and tensors (info, sweeps).
     (path and nb are accepted for symmetry with svd(); uneven batches always
     run the block method with nb = 16.)"""
     if not mats:
         return [], [], [], None, None
-    call = BatchedCall(mats, tol, max_sweeps, compute_u, compute_v, masking, precision)
+    call = BatchedCall(mats, tol, max_sweeps, compute_u, compute_v, masking, precision,
+                       inner_sweeps)
     return call(stream)
 
 

@@ -65,7 +65,8 @@ def test_complex_one_sweep_elementwise():
     import torch
     for m, n in [(24, 16), (40, 32)]:
         A = _cbatch((m, n), 6, seed=7900 + n, kinds=("gauss",))
-        S, U, V, info, sw = run_gpu(A, dtype=torch.complex128, path="blocked", max_sweeps=1)
+        S, U, V, info, sw = run_gpu(A, dtype=torch.complex128, path="blocked", max_sweeps=1,
+                                    inner_sweeps=1)
         ref = [oracle.block_gesvj(A[k], 16, max_sweeps=1) for k in range(6)]
         r = np.random.default_rng(3)
         for k in range(6):

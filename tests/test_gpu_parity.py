@@ -113,7 +113,7 @@ def test_one_sweep_elementwise(path):
     whichever is larger."""
     for m, n in [(24, 16), (40, 32), (64, 64)]:
         A = _batch([(m, n)] * 8, seed=400 + n)
-        S, U, V, info, sw = run_gpu(A, path=path, max_sweeps=1)
+        S, U, V, info, sw = run_gpu(A, path=path, max_sweeps=1, inner_sweeps=1)
         Sr, Ur, Vr, swr, infor = _one_sweep_oracle(A, path)
         dw, dv, ds = _one_sweep_sensitivity(A, path)
         tol_w, tol_v, tol_s = max(1e-13, 10 * dw), max(1e-12, 10 * dv), max(1e-13, 10 * ds)
@@ -134,7 +134,7 @@ def test_sweep_counts_match_round_robin_oracle(path):
     """Same ordering, same threshold: the sweep counts agree (within one
     sweep, since rounding can move the last decision)."""
     A = _batch([(32, 32)] * 16, seed=500, kind="geo", kappa=1e6)
-    S, U, V, info, sw = run_gpu(A, path=path)
+    S, U, V, info, sw = run_gpu(A, path=path, inner_sweeps=1)
     if path == "blocked":
         Sr, Ur, Vr, swr, infor = _block_oracle(A, 16)
     else:
