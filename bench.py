@@ -276,6 +276,46 @@ def uneven_main(args, dev):
     print(json.dumps(line), flush=True)
 
 
+def tallskinny_main(args, dev):
+    """The paper's tall-skinny experiment (section "Performance on
+    Tall-Skinny Matrices"): batches of 1000 FP64 matrices with 16 columns and
+    100 to 2000 rows, uniform [0, 1] entries, with and without the QR
+    pre-processing.  The headline value is the m = 1000 point (AUTO)."""
+    import torch
+    from paper_2601_17979_amd import svdb
+    from workloads import gen
+    batch = args.batch if args.batch != 10000 else 1000
+    points = {}
+    for m in (100, 200, 500, 1000, 1500, 2000):
+        A = np.stack([gen.uniform01(gen.rng_for(gen.BASE_SEED + 5000 + m, k), m, 16)
+                      for k in range(batch)])
+        Ag = svdb.col_major(torch.from_numpy(A).to(dev))
+        row = {}
+        for name, pc in (("auto", -1), ("qr", 1), ("no_qr", 0)):
+            try:
+                p = svdb.plan(torch.float64, m, 16, precondition=pc)
+            except svdb.SvdbError:
+                continue
+            wall, ms, out = timed_calls(lambda: svdb.svd(Ag, precondition=pc), args.steps,
+                                        args.warmup)
+            info, sw = out[3].cpu().numpy(), out[4].cpu().numpy()
+            row[name] = {"svds_per_s": batch / wall, "ms": wall * 1e3,
+                         "sweeps_mean": float(np.mean(sw)), "not_converged": int(np.sum(info != 0)),
+                         "path": ["auto", "plain", "resident", "blocked"][p[0]]}
+        points[m] = row
+    head = points[1000]["auto"]
+    line = {
+        "metric": "SVDs/sec, 1000 FP64 tall-skinny 1000x16 (uniform [0,1]); rows 100..2000 in config",
+        "value": head["svds_per_s"], "unit": "SVDs/s", "n_gpus": 1, "steps": args.steps,
+        "warmup": args.warmup, "ms_per_step": head["ms"], "higher_is_better": True,
+        "scaling": "weak", "vs_baseline": None, "dtype": "f64", "data": "synthetic",
+        "config": {"workload": f"{batch} FP64 m x 16, m in 100..2000, uniform [0,1] entries",
+                   "points": {str(k): v for k, v in points.items()}},
+        "roofline": None, "cpu_baseline": None,
+    }
+    print(json.dumps(line), flush=True)
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -294,7 +334,7 @@ def main():
                     help="1: QR-precondition the real requests of the serving leg")
     ap.add_argument("--serve-load", type=float, default=0.5,
                     help="offered load as a fraction of the measured saturation rate")
-    ap.add_argument("--workload", default="mixed", choices=["mixed", "square256", "uneven"],
+    ap.add_argument("--workload", default="mixed", choices=["mixed", "square256", "uneven", "tallskinny"],
                     help="mixed: the headline workload (default); square256: 4000 FP64 "
                          "256 x 256, all-FP64 and mixed precision; uneven: 20000 complex128 "
                          "of random shapes in one svdb_svd_batched call")
@@ -321,6 +361,8 @@ def main():
         return
     if args.workload == "square256":
         return square256_main(args, dev)
+    if args.workload == "tallskinny":
+        return tallskinny_main(args, dev)
     if args.workload == "uneven":
         return uneven_main(args, dev)
     groups = gen.mixed_64_128x32(batch=args.batch)

@@ -84,10 +84,12 @@ typedef struct {
     int waves;        /* SVDB_PATH_RESIDENT: wavefronts per matrix (1, 2, 4);
                          0 -> tuned                                           */
     int precondition; /* QR pre-processing of real FP64 matrices.  n <= 64
-                         (m n <= 8192): A P = Q1 R1 with column pivoting,
-                         R1^T = Q2 R2, the resident kernel on R2^T, U = Q1
-                         U_x, V = P Q2 J.  n > 64 (m <= 1024): A = Q R, the
-                         block method on R^T, U = Q J.  -1 (default): on
+                         and m <= 256 (m n <= 8192): A P = Q1 R1 with column
+                         pivoting, R1^T = Q2 R2, the resident kernel on
+                         R2^T, U = Q1 U_x, V = P Q2 J.  n <= 64 and larger
+                         m (AUTO: m <= 1024; 1: m <= 4096): A = Q R, the
+                         resident kernel on R^T, U = Q J.  n > 64 (m <=
+                         1024): A = Q R, the block method on R^T, U = Q J.  -1 (default): on
                          for the AUTO path where it applies; 0: off; 1: on
                          (AUTO, RESIDENT or BLOCKED path;
                          SVDB_ERR_UNSUPPORTED where it does not apply).  The

@@ -54,6 +54,7 @@ struct Plan {
     int threads = 0;
     bool precond = false;   // QR pre-processing, resident Jacobi on R^T
     bool precond_big = false;   // QR pre-processing, block Jacobi on R^T
+    bool precond_tall = false;  // QR in global memory, resident Jacobi on R^T
 };
 
 svdb_opts_t resolve_opts(const svdb_opts_t *o)
@@ -95,6 +96,19 @@ int make_plan(svdb_dtype_t dt, int m, int n, const svdb_opts_t &o, Plan *p)
         p->nb = 0;
         p->threads = 64 * rW;
         p->precond = true;
+        return 0;
+    }
+    // tall matrices with few columns beyond the register QR (m <= 4096): QR
+    // in global memory, the resident Jacobi on R^T (AUTO, or RESIDENT with 1)
+    const bool pct_ok = dt == SVDB_R64 && o.precision == 0 && !pc_ok &&
+                        (o.precondition == 1 ? svdb::precond_tall_supported(m, n)
+                                             : svdb::precond_tall_auto(m, n));
+    if (pc_req && pct_ok) {
+        svdb::resident_config(n, n, 0, &rN, &rR, &rW);
+        p->path = SVDB_PATH_RESIDENT;
+        p->nb = 0;
+        p->threads = 64 * rW;
+        p->precond_tall = true;
         return 0;
     }
     // wide matrices: the block Jacobi on R^T (AUTO, or BLOCKED with 1)
@@ -200,6 +214,7 @@ size_t svdb_workspace_size(svdb_dtype_t dtype, int batch, int m, int n, const sv
     if (make_plan(dtype, m, n, o, &p)) return (size_t)-1;
     if (p.precond) return svdb::precond_workspace_bytes(batch, m, n);
     if (p.precond_big) return svdb::precond_big_workspace_bytes(batch, m, n, p.nb);
+    if (p.precond_tall) return svdb::precond_tall_workspace_bytes(batch, m, n);
     if (p.path == SVDB_PATH_BLOCKED)
         return svdb::blocked_workspace_bytes(batch, m, n, p.nb, elt_bytes(dtype),
                                              o.precision == 1);
@@ -215,7 +230,11 @@ hipError_t run_tall(svdb_dtype_t dtype, const Plan &p, const svdb_opts_t &o, int
                     double tol, int *info, void *workspace, hipStream_t s)
 {
     hipError_t e = hipSuccess;
-    if (p.precond_big) {
+    if (p.precond_tall) {
+        e = svdb::launch_precond_tall_d(batch, m, n, (const double *)A, lda, strideA, (double *)S,
+                                        strideS, (double *)U, ldu, strideU, (double *)V, ldv,
+                                        strideV, tol, o.max_sweeps, info, o.sweeps, workspace, s);
+    } else if (p.precond_big) {
         e = svdb::launch_precond_big_d(batch, m, n, p.nb, (const double *)A, lda, strideA,
                                        (double *)S, strideS, (double *)U, ldu, strideU,
                                        (double *)V, ldv, strideV, tol, o.max_sweeps, o.masking,

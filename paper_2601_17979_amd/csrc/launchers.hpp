@@ -29,6 +29,13 @@ hipError_t launch_precond_d(int batch, int m, int n, int ns, const double *A, in
                             long long sA, double *S, long long sS, double *U, int ldu,
                             long long sU, double *V, int ldv, long long sV, double tol,
                             int max_sweeps, int *info, int *sweeps, void *ws, hipStream_t stream);
+bool precond_tall_supported(int m, int n);
+bool precond_tall_auto(int m, int n);   // where AUTO takes it (m <= 1024)
+size_t precond_tall_workspace_bytes(int batch, int m, int n);
+hipError_t launch_precond_tall_d(int batch, int m, int n, const double *A, int lda, long long sA,
+                                 double *S, long long sS, double *U, int ldu, long long sU,
+                                 double *V, int ldv, long long sV, double tol, int max_sweeps,
+                                 int *info, int *sweeps, void *ws, hipStream_t stream);
 bool precond_big_supported(int m, int n);
 
 // QR preconditioning of single requests (serving runtime): one QrJob per

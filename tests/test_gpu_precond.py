@@ -171,3 +171,64 @@ def test_precond_wide_edge_cases():
     Sr, _, _, _, infor = oracle_batch(A[keep])
     compare_with_oracle(A[keep], S[keep], U[keep], V[keep], info[keep], Sr, infor,
                         label="precond wide edge")
+
+
+@pytest.mark.parametrize("m,n,count", [(257, 16, 4), (512, 16, 4), (1000, 16, 3), (2000, 16, 2),
+                                       (4096, 16, 2), (1000, 40, 2), (300, 64, 3), (4000, 7, 2),
+                                       (600, 1, 2)])
+def test_precond_tall_vs_oracle(m, n, count):
+    """Tall matrices with few columns beyond the register QR (the paper's
+    tall-skinny experiment, n = 16 and m up to 2000): QR in global memory,
+    the resident Jacobi on R^T, U = Q J by one wave per column."""
+    import torch
+    from paper_2601_17979_amd import svdb
+    # AUTO takes the tall path up to m = 1024; precondition = 1 up to 4096
+    assert (svdb.plan(torch.float64, m, n)[0] == svdb.PATH_RESIDENT) == (m <= 1024)
+    assert svdb.plan(torch.float64, m, n, precondition=1)[0] == svdb.PATH_RESIDENT
+    A = _batch((m, n), count, seed=8700 + m + n, kinds=("geo", "gauss", "random"), kappa=1e8)
+    say(f"[precond tall {m}x{n}]")
+    S, U, V, info, sw = run_gpu(A, precondition=1)
+    Sr, Ur, Vr, swr, infor = oracle_batch(A)
+    compare_with_oracle(A, S, U, V, info, Sr, infor, label=f"precond tall {m}x{n}")
+    say(f"  sweeps on R^T {sw.tolist()} oracle on A {swr.tolist()}")
+
+
+def test_precond_tall_edge_cases_and_outputs():
+    """Zero and rank-deficient tall matrices, non-finite input (info 2,
+    outputs untouched), and each optional output."""
+    import torch
+    from paper_2601_17979_amd import svdb
+    m, n = 700, 12
+    A = _batch((m, n), 5, seed=8800)
+    A[0] = 0.0
+    A[1][:, 3] = 0.0
+    A[1][:, 7] = A[1][:, 5]
+    A[2][4, 4] = np.nan
+    A[3] *= 2.0 ** 400
+    Ag = svdb.col_major(torch.from_numpy(A).cuda())
+    out = (torch.full((5, n), 7.0, dtype=torch.float64, device="cuda"),
+           svdb.empty_col_major(5, m, n, torch.float64, "cuda").fill_(7.0),
+           svdb.empty_col_major(5, n, n, torch.float64, "cuda").fill_(7.0),
+           torch.empty(5, dtype=torch.int32, device="cuda"),
+           torch.empty(5, dtype=torch.int32, device="cuda"))
+    svdb.svd(Ag, out=out)
+    torch.cuda.synchronize()
+    S, U, V, info, sw = (x.cpu().numpy() for x in out)
+    assert info[2] == 2 and np.all(U[2] == 7.0) and np.all(V[2] == 7.0)
+    keep = [0, 1, 3, 4]
+    scales = np.array([1.0, 1.0, 2.0 ** 400, 1.0])
+    A0 = A[keep] / scales[:, None, None]
+    Sr, _, _, _, infor = oracle_batch(A0)
+    compare_with_oracle(A0, S[keep] / scales[:, None], U[keep], V[keep], info[keep], Sr, infor,
+                        label="precond tall edge")
+    assert np.all(S[0] == 0.0)
+    B = A[[0, 1, 4]]
+    Sr = oracle_batch(B)[0]
+    for cu, cv in ((True, False), (False, True)):
+        S, U, V, info, sw = run_gpu(B, compute_u=cu, compute_v=cv)
+        assert np.all(info == 0)
+        assert np.abs(S - Sr).max() <= 1e-12 * max(Sr.max(), 1.0)
+        if U is not None:
+            assert max(np.linalg.norm(U[k].T @ U[k] - np.eye(n)) for k in (1, 2)) <= 1e-13 * n
+        if V is not None:
+            assert max(np.linalg.norm(V[k].T @ V[k] - np.eye(n)) for k in range(3)) <= 1e-13 * n
