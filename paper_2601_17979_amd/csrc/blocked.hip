@@ -869,7 +869,9 @@ __global__ __launch_bounds__(kBT) void blk_finalize(int m, int n, int np, const 
 //   C = alpha_b op(A) B + beta D,  op(A) = A (M x K) or A^T (A is K x M),
 // alpha_b = alpha * st[b].scale when st is given.  One 64 x 64 tile of C per
 // workgroup (each wave four 16 x 16 tiles), K staged through LDS 16 at a
-// time; workgroup x = b * tiles + tile.  C must not alias A, B or D.
+// time; workgroup x = b * tiles + tile.  C must not overlap A or B; it may
+// be D itself (each element of D is read by the lane that then writes the
+// same element of C).
 // ---------------------------------------------------------------------------
 template <bool TRANS_A>
 __global__ __launch_bounds__(kBT) void gemm_f64(int M, int N, int K, double alpha,
@@ -1574,6 +1576,24 @@ hipError_t launch_vbatched(int dtype, int batch, const int *m, const int *n, con
     const size_t elt = dtype == 0 ? 4 : dtype == 3 ? 16 : 8;
     return launch_vb(dtype, elt, batch, m, n, A, lda, S, U, ldu, V, ldv, tol, max_sweeps, masking,
                      info, sweeps, ws, stream, trans, inner);
+}
+
+hipError_t launch_gemm_f64(bool trans_a, int batch, int M, int N, int K, double alpha,
+                           const double *A, int lda, long long sA, const double *B, int ldb,
+                           long long sB, double beta, const double *D, int ldd, long long sD,
+                           double *C, int ldc, long long sC, hipStream_t stream)
+{
+    if (batch <= 0 || M <= 0 || N <= 0) return hipSuccess;
+    const unsigned grid = (unsigned)(batch * ((M + 63) / 64) * ((N + 63) / 64));
+    if (trans_a)
+        hipLaunchKernelGGL(gemm_f64<true>, dim3(grid), dim3(kBT), 0, stream, M, N, K, alpha,
+                           (const BlkState *)nullptr, A, lda, sA, B, ldb, sB, beta, D, ldd, sD, C,
+                           ldc, sC);
+    else
+        hipLaunchKernelGGL(gemm_f64<false>, dim3(grid), dim3(kBT), 0, stream, M, N, K, alpha,
+                           (const BlkState *)nullptr, A, lda, sA, B, ldb, sB, beta, D, ldd, sD, C,
+                           ldc, sC);
+    return hipGetLastError();
 }
 
 }  // namespace svdb

@@ -133,6 +133,14 @@ hipError_t launch_vbatched(int dtype, int batch, const int *m, const int *n, con
                            int masking, int *info, int *sweeps, void *ws, hipStream_t stream,
                            const int *trans = nullptr, int inner = 0);
 
+// blocked.hip: batched FP64 GEMM on the matrix cores, column major:
+// C = alpha op(A) B + beta D (op(A) = A^T when trans_a; D may be NULL; C may
+// equal D but must not overlap A or B).
+hipError_t launch_gemm_f64(bool trans_a, int batch, int M, int N, int K, double alpha,
+                           const double *A, int lda, long long sA, const double *B, int ldb,
+                           long long sB, double beta, const double *D, int ldd, long long sD,
+                           double *C, int ldc, long long sC, hipStream_t stream);
+
 // layout.hip: At (n x m, ld n, n m apart) = A^H for a strided batch of m x n
 // matrices; dtype as svdb_dtype_t.
 hipError_t launch_conj_transpose(int dtype, int batch, int m, int n, const void *A, int lda,

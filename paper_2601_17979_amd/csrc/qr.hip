@@ -564,6 +564,182 @@ __global__ __launch_bounds__(kQT) void apply_q_g(int m, int n, const double *__r
                               Y + (size_t)b * n * n, U + (size_t)b * sU, ldu);
 }
 
+// ---- blocked Householder QR for the wide path ------------------------------
+// A = Q R panel by panel (LAPACK's xGEQRF with xLARFT / xLARFB): a panel of
+// kPB columns is factored in registers (one workgroup per matrix), which also
+// forms the compact-WY factor T (Q_panel = I - V T V^T); the trailing columns
+// then take C <- C - V T^T (V^T C) as three batched GEMMs on the matrix
+// cores, where almost all of the QR's flops are.
+constexpr int kPB = 16;
+
+// H = s A with the power of two s that brings max |a| into [1, 2) (no
+// square overflows); bad[b] flags a non-finite entry (H = A then).
+__global__ __launch_bounds__(kQT) void qrb_init(int m, int n, const double *__restrict__ A,
+                                                int lda, long long sA, double *H, double *scale,
+                                                int *bad)
+{
+    __shared__ double s_max[kQT / 64];
+    __shared__ int s_bad[kQT / 64];
+    const int b = blockIdx.x, tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+    A += (size_t)b * sA;
+    H += (size_t)b * m * n;
+    double amax = 0.0;
+    int nf = 0;
+    for (size_t idx = tid; idx < (size_t)m * n; idx += kQT) {
+        const double a = A[(idx / m) * lda + idx % m];
+        nf |= !isfinite(a);
+        amax = fmax(amax, fabs(a));
+    }
+    amax = wave_max(amax);
+    nf = __any(nf);
+    if (lane == 0) {
+        s_max[wave] = amax;
+        s_bad[wave] = nf;
+    }
+    __syncthreads();
+    amax = fmax(fmax(s_max[0], s_max[1]), fmax(s_max[2], s_max[3]));
+    const bool finite = !(s_bad[0] | s_bad[1] | s_bad[2] | s_bad[3]);
+    const double sc = finite ? pow2_scale(amax) : 1.0;
+    for (size_t idx = tid; idx < (size_t)m * n; idx += kQT)
+        H[idx] = A[(idx / m) * lda + idx % m] * sc;
+    if (tid == 0) {
+        scale[b] = sc;
+        bad[b] = !finite;
+    }
+}
+
+// Factors the panel H[k0:m, k0:k0+pb] in place: group g owns panel column
+// k0 + g, lane x rows k0 + x, k0 + x + 16, ... (RPL of them).  At step j the
+// owner of column j forms the reflector (as in the register QR above) and
+// publishes it in LDS; the later columns of the panel apply it, and the
+// earlier ones form v_i . v_j, the entries of V^T V that T needs:
+//   T(j, j) = tau_j,  T(0:j-1, j) = -tau_j T(0:j-1, 0:j-1) (V^T v_j)(0:j-1).
+// Writes the panel back (R above, reflectors below the diagonal), tau, V
+// explicitly (rows k0 .. m-1 of Vp, unit diagonal, zero above it) and T
+// (kPB x kPB, upper triangular).
+template <int RPL>
+__global__ __launch_bounds__(kQT) void qrb_panel(int m, int n, int k0, int pb, double *H,
+                                                 double *tau_out, double *Vp, double *T)
+{
+    __shared__ double vbuf[2][16 * RPL];
+    __shared__ double s_tau[kPB];
+    __shared__ double s_z[kPB][kPB + 1];   // s_z[i][j] = v_i . v_j, i < j
+    __shared__ double s_t[kPB][kPB + 1];
+    const int b = blockIdx.x, tid = threadIdx.x, grp = tid >> 4, gl = tid & 15;
+    const bool own = grp < pb;
+    H += (size_t)b * m * n;
+    double *hc = H + (size_t)(k0 + grp) * m;
+    double h[RPL];
+#pragma unroll
+    for (int r = 0; r < RPL; r++) {
+        const int row = k0 + gl + 16 * r;
+        h[r] = (own && row < m) ? hc[row] : 0.0;
+    }
+    for (int j = 0; j < pb; j++) {
+        double *vb = vbuf[j & 1];
+        if (grp == j) {
+            double s = 0.0, a = 0.0;
+#pragma unroll
+            for (int r = 0; r < RPL; r++) {
+                const int lr = gl + 16 * r;   // row k0 + lr
+                s = lr > j ? fma(h[r], h[r], s) : s;
+                a = lr == j ? h[r] : a;
+            }
+            s = row_sum16(s);
+            const double alpha = row_sum16(a);   // one nonzero term: exact
+            double beta = alpha, t = 0.0, scal = 0.0;
+            if (s > 0.0) {
+                const double nrmj = sqrt(fma(alpha, alpha, s));
+                beta = alpha >= 0.0 ? -nrmj : nrmj;
+                t = (beta - alpha) / beta;
+                scal = 1.0 / (alpha - beta);
+            }
+#pragma unroll
+            for (int r = 0; r < RPL; r++) {
+                const int lr = gl + 16 * r;
+                const double v = lr == j ? 1.0 : (lr > j ? h[r] * scal : 0.0);
+                vb[lr] = v;
+                h[r] = lr == j ? beta : (lr > j ? v : h[r]);
+            }
+            if (gl == 0) s_tau[j] = t;
+        }
+        __syncthreads();
+        if (own && grp != j) {   // uniform in the group
+            double w = 0.0;
+            if (grp > j) {       // apply H_j to a later panel column
+#pragma unroll
+                for (int r = 0; r < RPL; r++) w = fma(vb[gl + 16 * r], h[r], w);
+                w = row_sum16(w) * s_tau[j];
+#pragma unroll
+                for (int r = 0; r < RPL; r++) h[r] = fma(-w, vb[gl + 16 * r], h[r]);
+            } else {             // v_grp . v_j for T
+#pragma unroll
+                for (int r = 0; r < RPL; r++) {
+                    const int lr = gl + 16 * r;
+                    const double vi = lr == grp ? 1.0 : (lr > grp ? h[r] : 0.0);
+                    w = fma(vb[lr], vi, w);
+                }
+                w = row_sum16(w);
+                if (gl == 0) s_z[grp][j] = w;
+            }
+        }
+    }
+    __syncthreads();
+    // T row by row: row i depends only on its own earlier entries
+    if (tid < pb) {
+        const int i = tid;
+        for (int j = 0; j < pb; j++) {
+            double v = 0.0;
+            if (j == i) {
+                v = s_tau[j];
+            } else if (j > i) {
+                double acc = 0.0;
+                for (int k = i; k < j; k++) acc = fma(s_t[i][k], s_z[k][j], acc);
+                v = -s_tau[j] * acc;
+            }
+            s_t[i][j] = v;
+        }
+    }
+    __syncthreads();
+    double *Tb = T + (size_t)b * kPB * kPB;
+    for (int idx = tid; idx < kPB * kPB; idx += kQT) {
+        const int i = idx % kPB, j = idx / kPB;
+        Tb[(size_t)j * kPB + i] = (i < pb && j < pb) ? s_t[i][j] : 0.0;
+    }
+    if (tid < pb) tau_out[(size_t)b * n + k0 + tid] = s_tau[tid];
+    double *vc = Vp + (size_t)b * m * kPB + (size_t)grp * m;
+#pragma unroll
+    for (int r = 0; r < RPL; r++) {
+        const int lr = gl + 16 * r, row = k0 + lr;
+        if (!own || row >= m) continue;
+        hc[row] = h[r];
+        vc[row] = lr == grp ? 1.0 : (lr > grp ? h[r] : 0.0);
+    }
+}
+
+// X = R^T / scale (NaN for a non-finite input), then the reflectors as full
+// columns in H (ones on the diagonal, zeros above).
+__global__ __launch_bounds__(kQT) void qrb_final(int m, int n, double *H, double *X, double *tau,
+                                                 const double *scale, const int *bad)
+{
+    const int b = blockIdx.x, tid = threadIdx.x;
+    H += (size_t)b * m * n;
+    X += (size_t)b * n * n;
+    const bool nf = bad[b] != 0;
+    const double inv = 1.0 / scale[b];
+    for (size_t idx = tid; idx < (size_t)n * n; idx += kQT) {
+        const int r = (int)(idx % n), c = (int)(idx / n);   // X(r, c) = R(c, r)
+        X[idx] = nf ? __builtin_nan("") : (r >= c ? H[(size_t)r * m + c] * inv : 0.0);
+    }
+    __syncthreads();
+    for (size_t idx = tid; idx < (size_t)m * n; idx += kQT) {
+        const int row = (int)(idx % m), col = (int)(idx / m);
+        if (row <= col) H[idx] = row == col ? 1.0 : 0.0;
+    }
+    if (nf)
+        for (int j = tid; j < n; j += kQT) tau[(size_t)b * n + j] = 0.0;
+}
+
 // ---- descriptor-driven variants for the serving runtime -------------------
 __global__ __launch_bounds__(kQT) void qr_house_job(const QrJob *jobs, const int *list)
 {
@@ -752,6 +928,88 @@ void launch_apply_q_jobs(const QrJob *jobs, const int *list, int count, int max_
         hipLaunchKernelGGL(apply_q_job<64>, grid, dim3(kQT), 0, stream, jobs, list);
 }
 
+namespace {
+// scratch of the blocked QR: V of the panel (m x kPB), T, W and T^T W (kPB x
+// n), the scale and the non-finite flag of each matrix
+struct QrbWs {
+    double *Vp, *T, *W, *W2, *scale;
+    int *bad;
+};
+
+size_t qrb_carve(int batch, int m, int n, void *ws, QrbWs *w)
+{
+    const size_t vp = al256((size_t)batch * m * kPB * 8), t = al256((size_t)batch * kPB * kPB * 8);
+    const size_t wn = al256((size_t)batch * kPB * n * 8), sc = al256((size_t)batch * 8);
+    const size_t bd = al256((size_t)batch * 4);
+    if (w) {
+        char *p = (char *)ws;
+        w->Vp = (double *)p;
+        p += vp;
+        w->T = (double *)p;
+        p += t;
+        w->W = (double *)p;
+        p += wn;
+        w->W2 = (double *)p;
+        p += wn;
+        w->scale = (double *)p;
+        p += sc;
+        w->bad = (int *)p;
+    }
+    return vp + t + 2 * wn + sc + bd;
+}
+
+// A (m x n, m <= kQrMaxM) = Q R, blocked: H (m x n, ld m) gets the
+// reflectors as full columns, X = R^T (unscaled), tau.
+hipError_t launch_qr_blocked(int batch, int m, int n, const double *A, int lda, long long sA,
+                             double *H, double *X, double *tau, void *scratch, hipStream_t stream)
+{
+    QrbWs w;
+    qrb_carve(batch, m, n, scratch, &w);
+    hipLaunchKernelGGL(qrb_init, dim3(batch), dim3(kQT), 0, stream, m, n, A, lda, sA, H, w.scale,
+                       w.bad);
+    hipError_t e = hipGetLastError();
+    const long long smn = (long long)m * n, svp = (long long)m * kPB, swn = (long long)kPB * n;
+    for (int k0 = 0; k0 < n && e == hipSuccess; k0 += kPB) {
+        const int pb = n - k0 < kPB ? n - k0 : kPB, rows = m - k0;
+        const int r = (rows + 15) / 16;
+        bool launched = false;
+#define SVDB_QRB(RP)                                                                           \
+    if (!launched && r <= RP) {                                                                \
+        hipLaunchKernelGGL((qrb_panel<RP>), dim3(batch), dim3(kQT), 0, stream, m, n, k0, pb, H, \
+                           tau, w.Vp, w.T);                                                    \
+        launched = true;                                                                       \
+    }
+        SVDB_QRB(1)
+        SVDB_QRB(2)
+        SVDB_QRB(4)
+        SVDB_QRB(8)
+        SVDB_QRB(16)
+        SVDB_QRB(32)
+        SVDB_QRB(64)
+#undef SVDB_QRB
+        if (!launched) return hipErrorInvalidValue;
+        e = hipGetLastError();
+        const int nt = n - k0 - pb;
+        if (e != hipSuccess || nt <= 0) continue;
+        double *C = H + (size_t)(k0 + pb) * m + k0;
+        const double *V = w.Vp + k0;
+        // W = V^T C, W2 = T^T W, C <- C - V W2
+        e = launch_gemm_f64(true, batch, pb, nt, rows, 1.0, V, m, svp, C, m, smn, 0.0, nullptr, 0,
+                            0, w.W, kPB, swn, stream);
+        if (e == hipSuccess)
+            e = launch_gemm_f64(true, batch, pb, nt, pb, 1.0, w.T, kPB, (long long)kPB * kPB, w.W,
+                                kPB, swn, 0.0, nullptr, 0, 0, w.W2, kPB, swn, stream);
+        if (e == hipSuccess)
+            e = launch_gemm_f64(false, batch, rows, nt, pb, -1.0, V, m, svp, w.W2, kPB, swn, 1.0, C,
+                                m, smn, C, m, smn, stream);
+    }
+    if (e != hipSuccess) return e;
+    hipLaunchKernelGGL(qrb_final, dim3(batch), dim3(kQT), 0, stream, m, n, H, X, tau,
+                       (const double *)w.scale, (const int *)w.bad);
+    return hipGetLastError();
+}
+}  // namespace
+
 bool precond_big_supported(int m, int n)
 {
     return n > 64 && m >= n && m <= kQrMaxM;
@@ -759,7 +1017,8 @@ bool precond_big_supported(int m, int n)
 
 size_t precond_big_workspace_bytes(int batch, int m, int n, int nb)
 {
-    return big_head_bytes(batch, m, n) + blocked_workspace_bytes(batch, n, n, nb, 8, false);
+    return big_head_bytes(batch, m, n) + qrb_carve(batch, m, n, nullptr, nullptr) +
+           blocked_workspace_bytes(batch, n, n, nb, 8, false);
 }
 
 // Wide FP64 matrices: QR in global memory, the block Jacobi on X = R^T, and
@@ -782,10 +1041,10 @@ hipError_t launch_precond_big_d(int batch, int m, int n, int nb, const double *A
     p += al256((size_t)batch * n * n * 8);
     double *Ux = (double *)p;
     p += al256((size_t)batch * n * n * 8);
+    void *qws = p;
+    p += qrb_carve(batch, m, n, nullptr, nullptr);
     void *bws = p;
-    hipLaunchKernelGGL(qr_house_g, dim3(batch), dim3(kQT), (size_t)16 * m, stream, m, n, A, lda,
-                       sA, Vq, X, tau);
-    hipError_t e = hipGetLastError();
+    hipError_t e = launch_qr_blocked(batch, m, n, A, lda, sA, Vq, X, tau, qws, stream);
     if (e != hipSuccess) return e;
     double *vx = V ? V : Ux;
     const int ldvx = V ? ldv : n;
