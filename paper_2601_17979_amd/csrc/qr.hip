@@ -1077,12 +1077,13 @@ bool precond_tall_supported(int m, int n)
            resident_config(n, n, 0, &N, &R, &NS);
 }
 
-// AUTO takes the tall path up to m = 1024: measured on 1000 uniform-[0, 1]
-// matrices with n = 16 it beats the block method without QR from m = 300
-// (0.50 against 1.17 ms) to m = 1000 (1.43 against 1.56 ms), and loses from
-// m = 1500 on (2000: 3.14 against 2.26 ms), where the block method's
-// converged inner solves need about three sweeps and the one-workgroup QR of
-// each matrix grows with m.
+// AUTO takes the tall path up to m = 1024, where its QR is the blocked one
+// (a register panel of at most 64 rows per lane): measured on 1000 uniform
+// [0, 1] matrices with n = 16 it beats the block method without QR from
+// m = 300 (0.36 against 1.18 ms) to m = 1000 (0.67 against 1.55 ms).  Beyond
+// 1024 rows only the one-workgroup QR in global memory is left, and it loses
+// (m = 2000: 3.14 against 2.28 ms) to the block method, whose converged
+// inner solves need about three sweeps there.
 bool precond_tall_auto(int m, int n)
 {
     return precond_tall_supported(m, n) && m <= kQrMaxM;
@@ -1090,11 +1091,12 @@ bool precond_tall_auto(int m, int n)
 
 size_t precond_tall_workspace_bytes(int batch, int m, int n)
 {
-    return big_head_bytes(batch, m, n);
+    return big_head_bytes(batch, m, n) + (m <= kQrMaxM ? qrb_carve(batch, m, n, nullptr, nullptr) : 0);
 }
 
 // Tall matrices with few columns (n <= 64, m <= 4096, beyond the register
-// QR: m > 256 or m n > 8192): QR in global memory, the resident Jacobi on X = R^T (n x n), U = Q J by one wave
+// QR: m > 256 or m n > 8192): the blocked QR (m <= 1024) or the QR in global
+// memory, the resident Jacobi on X = R^T (n x n), U = Q J by one wave
 // per column.
 hipError_t launch_precond_tall_d(int batch, int m, int n, const double *A, int lda, long long sA,
                                  double *S, long long sS, double *U, int ldu, long long sU,
@@ -1112,9 +1114,17 @@ hipError_t launch_precond_tall_d(int batch, int m, int n, const double *A, int l
     double *J = (double *)p;
     p += al256((size_t)batch * n * n * 8);
     double *Ux = (double *)p;
-    hipLaunchKernelGGL(qr_house_g, dim3(batch), dim3(kQT), (size_t)16 * m, stream, m, n, A, lda,
-                       sA, Vq, X, tau);
-    hipError_t e = hipGetLastError();
+    p += al256((size_t)batch * n * n * 8);
+    // up to m = 1024 the blocked QR (a register panel, plus GEMMs for n >
+    // 16); beyond, the one-workgroup QR in global memory
+    hipError_t e;
+    if (m <= kQrMaxM) {
+        e = launch_qr_blocked(batch, m, n, A, lda, sA, Vq, X, tau, p, stream);
+    } else {
+        hipLaunchKernelGGL(qr_house_g, dim3(batch), dim3(kQT), (size_t)16 * m, stream, m, n, A,
+                           lda, sA, Vq, X, tau);
+        e = hipGetLastError();
+    }
     if (e != hipSuccess) return e;
     // the Jacobi on X = R^T: its left vectors are V, its rotations J feed U
     double *vx = V ? V : Ux;
