@@ -89,7 +89,8 @@ typedef struct {
                          R2^T, U = Q1 U_x, V = P Q2 J.  n <= 64 and larger
                          m (AUTO: m <= 1024; 1: m <= 4096): A = Q R, the
                          resident kernel on R^T, U = Q J.  n > 64 (m <=
-                         1024): A = Q R, the block method on R^T, U = Q J.  -1 (default): on
+                         1024): A = Q1 R1, R1^T = Q2 R2 (blocked QRs), the
+                         block method on R2^T, U = Q1 U_x, V = Q2 J.  -1 (default): on
                          for the AUTO path where it applies; 0: off; 1: on
                          (AUTO, RESIDENT or BLOCKED path;
                          SVDB_ERR_UNSUPPORTED where it does not apply).  The

@@ -1015,51 +1015,32 @@ bool precond_big_supported(int m, int n)
     return n > 64 && m >= n && m <= kQrMaxM;
 }
 
+// second QR of the wide path: X2 = R2^T, its reflectors (n x n) and tau
+size_t big_second_bytes(int batch, int n)
+{
+    return 2 * al256((size_t)batch * n * n * 8) + al256((size_t)batch * n * 8);
+}
+
 size_t precond_big_workspace_bytes(int batch, int m, int n, int nb)
 {
-    return big_head_bytes(batch, m, n) + qrb_carve(batch, m, n, nullptr, nullptr) +
+    return big_head_bytes(batch, m, n) + big_second_bytes(batch, n) +
+           qrb_carve(batch, m, n, nullptr, nullptr) +
            blocked_workspace_bytes(batch, n, n, nb, 8, false);
 }
 
-// Wide FP64 matrices: QR in global memory, the block Jacobi on X = R^T, and
-// U = Q J applied by column blocks.
-hipError_t launch_precond_big_d(int batch, int m, int n, int nb, const double *A, int lda,
-                                long long sA, double *S, long long sS, double *U, int ldu,
-                                long long sU, double *V, int ldv, long long sV, double tol,
-                                int max_sweeps, int masking, int *info, int *sweeps, void *ws,
-                                hipStream_t stream)
+namespace {
+// U = Q [Y; 0] on the global-memory path (m <= 1024), one block of 16
+// columns of U per workgroup
+hipError_t launch_apply_g(int batch, int m, int n, const double *Vq, const double *tau,
+                          const double *Y, double *U, int ldu, long long sU, const int *info,
+                          hipStream_t stream)
 {
-    if (!precond_big_supported(m, n)) return hipErrorInvalidValue;
-    char *p = (char *)ws;
-    double *X = (double *)p;
-    p += al256((size_t)batch * n * n * 8);
-    double *Vq = (double *)p;
-    p += al256((size_t)batch * m * n * 8);
-    double *tau = (double *)p;
-    p += al256((size_t)batch * n * 8);
-    double *J = (double *)p;
-    p += al256((size_t)batch * n * n * 8);
-    double *Ux = (double *)p;
-    p += al256((size_t)batch * n * n * 8);
-    void *qws = p;
-    p += qrb_carve(batch, m, n, nullptr, nullptr);
-    void *bws = p;
-    hipError_t e = launch_qr_blocked(batch, m, n, A, lda, sA, Vq, X, tau, qws, stream);
-    if (e != hipSuccess) return e;
-    double *vx = V ? V : Ux;
-    const int ldvx = V ? ldv : n;
-    const long long svx = V ? sV : (long long)n * n;
-    e = launch_blocked_d(batch, n, n, nb, X, n, (long long)n * n, S, sS, vx, ldvx, svx,
-                         U ? J : nullptr, n, (long long)n * n, tol, max_sweeps, masking, info,
-                         sweeps, bws, stream);
-    if (e != hipSuccess || !U) return e;
     const int rpl = (m + 15) / 16;
     const dim3 grid((unsigned)(batch * ((n + 15) / 16)));
 #define SVDB_AQG(RP)                                                                           \
     if (rpl <= RP) {                                                                           \
-        hipLaunchKernelGGL((apply_q_g<RP>), grid, dim3(kQT), 0, stream, m, n,                  \
-                           (const double *)Vq, (const double *)tau, (const double *)J, U, ldu,  \
-                           sU, (const int *)info);                                             \
+        hipLaunchKernelGGL((apply_q_g<RP>), grid, dim3(kQT), 0, stream, m, n, Vq, tau, Y, U,    \
+                           ldu, sU, info);                                                     \
         return hipGetLastError();                                                              \
     }
     SVDB_AQG(8)
@@ -1068,6 +1049,52 @@ hipError_t launch_precond_big_d(int batch, int m, int n, int nb, const double *A
     SVDB_AQG(64)
 #undef SVDB_AQG
     return hipErrorInvalidValue;
+}
+}  // namespace
+
+// Wide FP64 matrices (n > 64, m <= 1024): A = Q1 R1 and R1^T = Q2 R2 by the
+// blocked QR, the block Jacobi on X = R2^T (X J = U_x diag(S)), U = Q1 [U_x;
+// 0] and V = Q2 J by column blocks.
+hipError_t launch_precond_big_d(int batch, int m, int n, int nb, const double *A, int lda,
+                                long long sA, double *S, long long sS, double *U, int ldu,
+                                long long sU, double *V, int ldv, long long sV, double tol,
+                                int max_sweeps, int masking, int *info, int *sweeps, void *ws,
+                                hipStream_t stream)
+{
+    if (!precond_big_supported(m, n)) return hipErrorInvalidValue;
+    const long long snn = (long long)n * n;
+    char *p = (char *)ws;
+    double *X1 = (double *)p;
+    p += al256((size_t)batch * n * n * 8);
+    double *Vq1 = (double *)p;
+    p += al256((size_t)batch * m * n * 8);
+    double *tau1 = (double *)p;
+    p += al256((size_t)batch * n * 8);
+    double *J = (double *)p;
+    p += al256((size_t)batch * n * n * 8);
+    double *Ux = (double *)p;
+    p += al256((size_t)batch * n * n * 8);
+    double *X2 = (double *)p;
+    p += al256((size_t)batch * n * n * 8);
+    double *Vq2 = (double *)p;
+    p += al256((size_t)batch * n * n * 8);
+    double *tau2 = (double *)p;
+    p += al256((size_t)batch * n * 8);
+    void *qws = p;
+    p += qrb_carve(batch, m, n, nullptr, nullptr);
+    void *bws = p;
+    hipError_t e = launch_qr_blocked(batch, m, n, A, lda, sA, Vq1, X1, tau1, qws, stream);
+    if (e == hipSuccess)
+        e = launch_qr_blocked(batch, n, n, X1, n, snn, Vq2, X2, tau2, qws, stream);
+    if (e != hipSuccess) return e;
+    e = launch_blocked_d(batch, n, n, nb, X2, n, snn, S, sS, U ? Ux : nullptr, n, snn,
+                         V ? J : nullptr, n, snn, tol, max_sweeps, masking, info, sweeps, bws,
+                         stream);
+    if (e == hipSuccess && U)
+        e = launch_apply_g(batch, m, n, Vq1, tau1, Ux, U, ldu, sU, info, stream);
+    if (e == hipSuccess && V)
+        e = launch_apply_g(batch, n, n, Vq2, tau2, J, V, ldv, sV, info, stream);
+    return e;
 }
 
 bool precond_tall_supported(int m, int n)
