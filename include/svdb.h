@@ -83,7 +83,9 @@ typedef struct {
     int *sweeps;      /* optional DEVICE int[batch]: sweeps executed          */
     int waves;        /* SVDB_PATH_RESIDENT: wavefronts per matrix (1, 2, 4);
                          0 -> tuned                                           */
-    int precondition; /* QR pre-processing of real FP64 matrices.  n <= 64
+    int precondition; /* QR pre-processing of real matrices (FP32 input is
+                         widened and runs the FP64 kernels with its own
+                         threshold, then the results are narrowed).  n <= 64
                          and m <= 256 (m n <= 8192): A P = Q1 R1 with column
                          pivoting, R1^T = Q2 R2, the resident kernel on
                          R2^T, U = Q1 U_x, V = P Q2 J.  n <= 64 and larger

@@ -42,6 +42,15 @@ int elt_bytes(svdb_dtype_t dt)
     return dt == SVDB_R32 ? 4 : dt == SVDB_C128 ? 16 : 8;
 }
 
+size_t al256(size_t x) { return (x + 255) / 256 * 256; }
+
+// bytes of the FP64 copies of A (m x n), S, U (m x n) and V (n x n)
+size_t via64_bytes(int batch, int m, int n)
+{
+    const size_t mn = (size_t)batch * m * n * 8;
+    return 2 * al256(mn) + al256((size_t)batch * n * 8) + al256((size_t)batch * n * n * 8);
+}
+
 // bytes of the A^H copy of a strided batch of wide matrices
 size_t wide_copy_bytes(svdb_dtype_t dtype, int batch, int m, int n)
 {
@@ -55,6 +64,7 @@ struct Plan {
     bool precond = false;   // QR pre-processing, resident Jacobi on R^T
     bool precond_big = false;   // QR pre-processing, block Jacobi on R^T
     bool precond_tall = false;  // QR in global memory, resident Jacobi on R^T
+    bool via64 = false;         // FP32 input on an FP64 preconditioned path
 };
 
 svdb_opts_t resolve_opts(const svdb_opts_t *o)
@@ -86,8 +96,11 @@ int make_plan(svdb_dtype_t dt, int m, int n, const svdb_opts_t &o, Plan *p)
         return fail(SVDB_ERR_UNSUPPORTED, "precondition must be -1, 0 or 1");
     int path = o.path;
     int rN = 0, rR = 0, rW = 0;
-    // QR preconditioning: AUTO (precondition -1 or 1) and RESIDENT (1)
-    const bool pc_ok = dt == SVDB_R64 && o.precision == 0 && svdb::precond_supported(m, n);
+    // QR preconditioning of real matrices (FP32 input runs it in FP64): AUTO
+    // (precondition -1 or 1) and RESIDENT (1)
+    const bool real = dt == SVDB_R64 || dt == SVDB_R32;
+    p->via64 = dt == SVDB_R32;
+    const bool pc_ok = real && o.precision == 0 && svdb::precond_supported(m, n);
     const bool pc_req = (path == SVDB_PATH_AUTO && o.precondition != 0) ||
                         (path == SVDB_PATH_RESIDENT && o.precondition == 1);
     if (pc_req && pc_ok) {
@@ -100,7 +113,7 @@ int make_plan(svdb_dtype_t dt, int m, int n, const svdb_opts_t &o, Plan *p)
     }
     // tall matrices with few columns beyond the register QR (m <= 4096): QR
     // in global memory, the resident Jacobi on R^T (AUTO, or RESIDENT with 1)
-    const bool pct_ok = dt == SVDB_R64 && o.precision == 0 && !pc_ok &&
+    const bool pct_ok = real && o.precision == 0 && !pc_ok &&
                         (o.precondition == 1 ? svdb::precond_tall_supported(m, n)
                                              : svdb::precond_tall_auto(m, n));
     if (pc_req && pct_ok) {
@@ -112,7 +125,7 @@ int make_plan(svdb_dtype_t dt, int m, int n, const svdb_opts_t &o, Plan *p)
         return 0;
     }
     // wide matrices: the block Jacobi on R^T (AUTO, or BLOCKED with 1)
-    const bool pcb_ok = dt == SVDB_R64 && o.precision == 0 && !pc_ok &&
+    const bool pcb_ok = real && o.precision == 0 && !pc_ok &&
                         svdb::precond_big_supported(m, n);
     const bool pcb_req = (path == SVDB_PATH_AUTO && o.precondition != 0) ||
                          (path == SVDB_PATH_BLOCKED && o.precondition == 1);
@@ -125,6 +138,7 @@ int make_plan(svdb_dtype_t dt, int m, int n, const svdb_opts_t &o, Plan *p)
         p->precond_big = true;
         return 0;
     }
+    p->via64 = false;
     if (o.precondition == 1)
         return fail(SVDB_ERR_UNSUPPORTED, "QR preconditioning does not apply to this request");
     // the unblocked kernels are FP64 only; FP32 and the mixed mode use the block method
@@ -212,9 +226,11 @@ size_t svdb_workspace_size(svdb_dtype_t dtype, int batch, int m, int n, const sv
     svdb_opts_t o = resolve_opts(opts);
     Plan p;
     if (make_plan(dtype, m, n, o, &p)) return (size_t)-1;
-    if (p.precond) return svdb::precond_workspace_bytes(batch, m, n);
-    if (p.precond_big) return svdb::precond_big_workspace_bytes(batch, m, n, p.nb);
-    if (p.precond_tall) return svdb::precond_tall_workspace_bytes(batch, m, n);
+    // FP32 on an FP64 path: FP64 copies of A, S, U and V come first
+    const size_t w64 = p.via64 ? via64_bytes(batch, m, n) : 0;
+    if (p.precond) return w64 + svdb::precond_workspace_bytes(batch, m, n);
+    if (p.precond_big) return w64 + svdb::precond_big_workspace_bytes(batch, m, n, p.nb);
+    if (p.precond_tall) return w64 + svdb::precond_tall_workspace_bytes(batch, m, n);
     if (p.path == SVDB_PATH_BLOCKED)
         return svdb::blocked_workspace_bytes(batch, m, n, p.nb, elt_bytes(dtype),
                                              o.precision == 1);
@@ -230,6 +246,34 @@ hipError_t run_tall(svdb_dtype_t dtype, const Plan &p, const svdb_opts_t &o, int
                     double tol, int *info, void *workspace, hipStream_t s)
 {
     hipError_t e = hipSuccess;
+    if (p.via64) {
+        // FP32 input on an FP64 preconditioned path: A widened into the
+        // workspace, the FP64 results narrowed into the caller's buffers
+        // (matrices with info 2 keep their outputs untouched)
+        const long long smn = (long long)m * n, snn = (long long)n * n;
+        char *q = (char *)workspace;
+        double *A64 = (double *)q;
+        q += al256((size_t)batch * smn * 8);
+        double *U64 = (double *)q;
+        q += al256((size_t)batch * smn * 8);
+        double *S64 = (double *)q;
+        q += al256((size_t)batch * n * 8);
+        double *V64 = (double *)q;
+        q += al256((size_t)batch * snn * 8);
+        Plan p64 = p;
+        p64.via64 = false;
+        e = svdb::launch_widen_f32(batch, m, n, (const float *)A, lda, strideA, A64, m, smn, s);
+        if (e == hipSuccess)
+            e = run_tall(SVDB_R64, p64, o, batch, m, n, A64, m, smn, S64, n, U ? U64 : nullptr, m,
+                         smn, V ? V64 : nullptr, n, snn, tol, info, q, s);
+        if (e == hipSuccess)
+            e = svdb::launch_narrow_f64(batch, n, 1, S64, n, n, (float *)S, n, strideS, info, s);
+        if (e == hipSuccess && U)
+            e = svdb::launch_narrow_f64(batch, m, n, U64, m, smn, (float *)U, ldu, strideU, info, s);
+        if (e == hipSuccess && V)
+            e = svdb::launch_narrow_f64(batch, n, n, V64, n, snn, (float *)V, ldv, strideV, info, s);
+        return e;
+    }
     if (p.precond_tall) {
         e = svdb::launch_precond_tall_d(batch, m, n, (const double *)A, lda, strideA, (double *)S,
                                         strideS, (double *)U, ldu, strideU, (double *)V, ldv,

@@ -145,5 +145,12 @@ hipError_t launch_gemm_f64(bool trans_a, int batch, int M, int N, int K, double 
 // matrices; dtype as svdb_dtype_t.
 hipError_t launch_conj_transpose(int dtype, int batch, int m, int n, const void *A, int lda,
                                  long long sA, void *At, hipStream_t stream);
+// FP32 -> FP64 and FP64 -> FP32 copies of strided batches (rows x cols); the
+// narrowing skips matrices whose info is 2
+hipError_t launch_widen_f32(int batch, int rows, int cols, const float *src, int lds,
+                            long long ss, double *dst, int ldd, long long sd, hipStream_t stream);
+hipError_t launch_narrow_f64(int batch, int rows, int cols, const double *src, int lds,
+                             long long ss, float *dst, int ldd, long long sd, const int *info,
+                             hipStream_t stream);
 
 }  // namespace svdb

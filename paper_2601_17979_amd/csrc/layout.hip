@@ -1,4 +1,6 @@
-// layout.hip -- conjugate transpose of a strided batch, for wide matrices.
+// layout.hip -- layout and precision copies of strided batches: the
+// conjugate transpose for wide matrices, and FP32 <-> FP64 copies for FP32
+// input run on the FP64 preconditioned paths.
 //
 // For m < n the reduced SVD is taken from the tall matrix A^H (n x m):
 // A^H = U' diag(S) V'^H gives A = V' diag(S) U'^H, so U = V' (m x m) and
@@ -73,6 +75,55 @@ hipError_t launch_conj_transpose(int dtype, int batch, int m, int n, const void 
     case 3: return launch_t<double2>(batch, m, n, A, lda, sA, At, stream);
     default: return hipErrorInvalidValue;
     }
+}
+
+namespace {
+
+// dst (rows x cols, ld ldd, matrices sd apart) = src, element by element;
+// with info, matrices whose info is 2 (non-finite input) are skipped.
+template <class TS, class TD>
+__global__ void convert_batch(int batch, int rows, int cols, const TS *__restrict__ src, int lds,
+                              long long ss, TD *__restrict__ dst, int ldd, long long sd,
+                              const int *info)
+{
+    const size_t per = (size_t)rows * cols, total = per * batch;
+    for (size_t g = (size_t)blockIdx.x * blockDim.x + threadIdx.x; g < total;
+         g += (size_t)gridDim.x * blockDim.x) {
+        const size_t b = g / per;
+        if (info && info[b] == 2) continue;
+        const int idx = (int)(g % per), r = idx % rows, c = idx / rows;
+        dst[b * sd + (size_t)c * ldd + r] = (TD)src[b * ss + (size_t)c * lds + r];
+    }
+}
+
+template <class TS, class TD>
+hipError_t launch_convert(int batch, int rows, int cols, const TS *src, int lds, long long ss,
+                          TD *dst, int ldd, long long sd, const int *info, hipStream_t stream)
+{
+    const size_t total = (size_t)batch * rows * cols;
+    if (total == 0) return hipSuccess;
+    size_t g = (total + 255) / 256;
+    if (g > 65536) g = 65536;
+    hipLaunchKernelGGL((convert_batch<TS, TD>), dim3((unsigned)g), dim3(256), 0, stream, batch,
+                       rows, cols, src, lds, ss, dst, ldd, sd, info);
+    return hipGetLastError();
+}
+
+}  // namespace
+
+hipError_t launch_widen_f32(int batch, int rows, int cols, const float *src, int lds,
+                            long long ss, double *dst, int ldd, long long sd, hipStream_t stream)
+{
+    return launch_convert<float, double>(batch, rows, cols, src, lds, ss, dst, ldd, sd, nullptr,
+                                         stream);
+}
+
+hipError_t launch_narrow_f64(int batch, int rows, int cols, const double *src, int lds,
+                             long long ss, float *dst, int ldd, long long sd, const int *info,
+                             hipStream_t stream)
+{
+    return launch_convert<double, float>(batch, rows, cols, src, lds, ss, dst, ldd, sd, info,
+                                         stream);
 }
 
 }  // namespace svdb
