@@ -287,3 +287,23 @@ def test_precond_fp32_edge_cases():
                         V[keep].astype(np.float64), info[keep], Sr, infor, dtype=np.float32,
                         label="precond fp32 edge")
     assert np.all(S[0] == 0.0)
+
+
+@pytest.mark.parametrize("m,n", [(1024, 1024), (1024, 520)])
+def test_precond_wide_at_the_maximum_size(m, n):
+    """The largest wide preconditioned shapes (m = 1024): the oracle would
+    take minutes here, so the result is judged by properties that hold at
+    any size (reconstruction, orthogonality, ordering) and by LAPACK's
+    singular values (numpy.linalg.svd) at the FP64 tolerances."""
+    from metrics import orth_err, recon_err, tolerances
+    A = _batch((m, n), 1, seed=9000 + n, kinds=("geo",), kappa=1e6)
+    say(f"[precond wide max {m}x{n}]")
+    S, U, V, info, sw = run_gpu(A)
+    ref = np.linalg.svd(A[0], compute_uv=False)
+    tol_s, tol_r, tol_o = tolerances(np.float64, n)
+    assert info[0] == 0
+    assert np.abs(S[0] - ref).max() / ref[0] <= tol_s
+    assert recon_err(A[0], S[0], U[0], V[0]) <= tol_r
+    assert orth_err(U[0]) <= tol_o and orth_err(V[0]) <= tol_o
+    assert np.all(np.diff(S[0]) <= 0)
+    say(f"  sweeps {sw.tolist()}")
