@@ -133,6 +133,26 @@ def serve_leg(args, dev):
             "qr_preconditioning": bool(args.serve_precondition)}
 
 
+def host_cpu():
+    """The host's CPU model and the cores this process may run on."""
+    model = None
+    try:
+        with open("/proc/cpuinfo") as f:
+            for line in f:
+                if line.startswith("model name"):
+                    model = line.split(":", 1)[1].strip()
+                    break
+    except OSError:
+        pass
+    return {"cpu_model": model, "nproc": len(os.sched_getaffinity(0))}
+
+
+def sweep_histogram(sw):
+    """Number of matrices per executed sweep count."""
+    vals, counts = np.unique(np.asarray(sw), return_counts=True)
+    return {str(int(v)): int(c) for v, c in zip(vals, counts)}
+
+
 def flops_blocked(m, n, nb, sweeps, cf=1):
     """Block method work per executed sweep: cf P nb^2 (14 m + 8 n + 72 nb)
     with P = l (l - 1) / 2 block pairs (Gram 6 nb^2 m, update 8 nb^2 (m + n),
@@ -203,7 +223,7 @@ def square256_main(args, dev):
         cpu = {"value": len(pick) / t_cpu, "unit": "SVDs/s", "cores": oracle.num_threads(),
                "kind": "oracle", "sample": f"{len(pick)} matrices (half per kappa), FP64 "
                                            f"row-cyclic one-sided Jacobi, OpenMP over the batch",
-               "seconds": t_cpu}
+               "seconds": t_cpu, **host_cpu()}
         sig_err = {p: float(np.max(np.abs(res[p][2][pick] - Sr) / Sr[:, :1])) for p in res}
     line = {
         "metric": "SVDs/sec, 256 x 256 FP64: all-FP64, FP32 sweeps + FP64 refinement, QR + "
@@ -214,14 +234,11 @@ def square256_main(args, dev):
         "config": {"workload": f"{batch} FP64 256x256, geometric spectrum, half kappa 1e2 "
                                f"half 1e8 (Haar factors); block method nb 16",
                    "best_mode": {0: "fp64", 1: "fp32+fp64", 2: "qr+fp64"}[best],
-                   "fp64": {"svds_per_s": batch / res[0][0], "sweeps_mean": float(np.mean(res[0][4])),
-                            "not_converged": int(np.sum(res[0][3] != 0))},
-                   "fp32+fp64": {"svds_per_s": batch / res[1][0],
-                                 "sweeps_mean": float(np.mean(res[1][4])),
-                                 "not_converged": int(np.sum(res[1][3] != 0))},
-                   "qr+fp64": {"svds_per_s": batch / res[2][0],
-                               "sweeps_mean": float(np.mean(res[2][4])),
-                               "not_converged": int(np.sum(res[2][3] != 0))},
+                   **{name: {"svds_per_s": batch / res[k][0],
+                             "sweeps_mean": float(np.mean(res[k][4])),
+                             "sweeps_hist": sweep_histogram(res[k][4]),
+                             "not_converged": int(np.sum(res[k][3] != 0))}
+                      for k, name in enumerate(("fp64", "fp32+fp64", "qr+fp64"))},
                    "sigma_rel_err_vs_oracle_sample": sig_err},
         "roofline": {"bound": "mfma", "achieved": achieved / 1e12, "peak": 78.6, "unit": "TFLOP/s",
                      "frac": achieved / 78.6e12, "traffic": None,
@@ -258,7 +275,8 @@ def uneven_main(args, dev):
             oracle.gesvj(As[k])
         t_cpu = time.perf_counter() - t0
         cpu = {"value": len(pick) / t_cpu, "unit": "SVDs/s", "cores": 1, "kind": "oracle",
-               "sample": f"{len(pick)} evenly spaced matrices, one at a time", "seconds": t_cpu}
+               "sample": f"{len(pick)} evenly spaced matrices, one at a time", "seconds": t_cpu,
+               **host_cpu()}
     line = {
         "metric": "SVDs/sec, uneven complex128 batch in one call",
         "value": len(flat) / wall, "unit": "SVDs/s", "n_gpus": 1, "steps": args.steps,
@@ -267,7 +285,7 @@ def uneven_main(args, dev):
         "config": {"workload": f"{len(flat)} complex128, n ~ U{{8..256}}, m ~ U{{n..2n}}, "
                                f"complex Gaussian entries; {len(groups)} distinct shapes",
                    "not_converged": int(np.sum(info != 0)),
-                   "sweeps_mean": float(np.mean(sw))},
+                   "sweeps_mean": float(np.mean(sw)), "sweeps_hist": sweep_histogram(sw)},
         "roofline": {"bound": "mfma", "achieved": achieved / 1e12, "peak": 78.6, "unit": "TFLOP/s",
                      "frac": achieved / 78.6e12, "traffic": None,
                      "kernel": "vb_iter (whole call)", "kernel_ms": ms, "flops_per_call": fl},
@@ -481,7 +499,7 @@ def main():
                "sample": f"{n_cpu} matrices ({args.cpu_sample} evenly spaced per shape, both "
                          f"spectrum families), FP64 row-cyclic one-sided Jacobi, OpenMP over "
                          f"the batch", "seconds": t_cpu,
-               "oracle_sweeps_per_gpu_sweep": sw_ratio}
+               "oracle_sweeps_per_gpu_sweep": sw_ratio, **host_cpu()}
         sig_err = max(errs)
 
     serve = serve_leg(args, dev) if args.serve_seconds > 0 else None
@@ -493,6 +511,7 @@ def main():
         "config": {"workload": WORKLOAD, "path": args.path, "batch": total,
                    "sigma_rel_err_vs_oracle_sample": sig_err, "not_converged": bad,
                    "sweeps_mean": {f"{r[0].m}x{r[0].n}": float(np.mean(r[5])) for r in results},
+                   "sweeps_hist": {f"{r[0].m}x{r[0].n}": sweep_histogram(r[5]) for r in results},
                    "kernel_ms": {f"{r[0].m}x{r[0].n}": float(k) for r, k in
                                  zip(results, per_kernel)}},
         "plain_gpu_jacobi": plain,

@@ -4,7 +4,10 @@
 // Layout.  The matrix is held as the stacked matrix [W; V] (W starts as A, V
 // as I; a rotation acts on whole stacked columns) in registers: lane L holds
 // row 64 t + L of W in slot t < RW and row L of V in slot RW.  N is n rounded
-// up to 16, 32 or 64 (extra columns are zero and never rotate).
+// up to 16, 32 or 64 (extra columns are zero and never rotate).  For m <= 32
+// and N <= 32 the packed layout (RW = 0) keeps both in one slot: row L of W
+// in lane L < 32 and row L of V in lane 32 + L, so no lane holds only
+// padding.
 //
 // Ordering.  The round-robin ordering (Fig. "rr"; "Parallel Ordering") is a
 // tournament table
@@ -95,7 +98,10 @@ struct OpMax {
 // wave.  On return lane L = 16 rho + x holds the reduction of value
 // (x mod KG/4) + (KG/4) rho, with identical bits in every lane that holds the
 // same value.  buf: 64 * KG/4 doubles of LDS private to the calling wave.
-template <int KG, class Op>
+//
+// HALF: only lanes 0..31 carry terms (the W rows of the packed layout); the
+// values of lanes 32..63 are ignored.
+template <int KG, class Op, bool HALF = false>
 __device__ __forceinline__ double reduce_pairs(double (&g)[KG], double *buf)
 {
     constexpr int H = KG / 2, Q = KG / 4;
@@ -105,7 +111,7 @@ __device__ __forceinline__ double reduce_pairs(double (&g)[KG], double *buf)
     for (int v = 0; v < H; v++) {
         double a = g[v], b = g[v + H];
         swap32(a, b);
-        h[v] = Op::apply(a, b);
+        h[v] = HALF ? a : Op::apply(a, b);
     }
     double f[Q];
 #pragma unroll
@@ -188,7 +194,7 @@ struct Shared {
 };
 
 // Waves per SIMD the register allocation is asked to allow, from the stored
-// doubles per lane d = (RW + 1) N / NS: 3 up to d = 32 (168 VGPRs), 2 up to
+// doubles per lane d = (RW + 1) N / NS (packed: N / NS): 3 up to d = 32 (168 VGPRs), 2 up to
 // d = 64 (256), else 1.  With these bounds the iteration loop stays free of
 // spills; what does not fit goes to scratch in the per-sweep fold and the
 // finalisation, which run once per sweep, while a second or third resident
@@ -199,14 +205,21 @@ constexpr int res_waves_per_eu(int N, int RW, int NS)
 }
 
 // W rows live in slots 0..RW-1 (row 64 t + lane), V rows in slot RW (row =
-// lane); padding rows are zero, so Gram entries need no masks.
+// lane); padding rows are zero, so Gram entries need no masks.  RW = 0 is
+// the packed layout: W row L in lane L of slot 0, V row L in lane 32 + L,
+// and the reductions over W rows read lanes 0..31 only.
 template <int N, int RW, int NS>
 __global__ __launch_bounds__(64 * NS, res_waves_per_eu(N, RW, NS)) void resident_jacobi_d(
     int m, int n, const double *__restrict__ A, int lda, long long sA, double *S, long long sS,
     double *U, int ldu, long long sU, double *V, int ldv, long long sV, double tol,
     int max_sweeps, int *info, int *sweeps_out)
 {
-    constexpr int R = RW + 1;
+    constexpr bool PK = RW == 0;
+    constexpr int R = PK ? 1 : RW + 1;   // register slots per column
+    constexpr int WS = PK ? 1 : RW;      // slots holding W rows
+    constexpr int VS = PK ? 0 : RW;      // slot holding V rows
+    constexpr int VL = PK ? 32 : 0;      // lane of V row 0
+    static_assert(!PK || N <= 32, "packed layout: n <= 32");
     using SH = Shared<N, R, NS>;
     constexpr int K = SH::K, KG = SH::KG, Q = SH::Q;
     static_assert(KG >= 4 && (KG & (KG - 1)) == 0, "4 <= pairs per wave, power of two");
@@ -231,8 +244,8 @@ __global__ __launch_bounds__(64 * NS, res_waves_per_eu(N, RW, NS)) void resident
     for (int q = 0; q < KG; q++) {
         const int ct = 2 * (q0 + q), cb = ct + 1;
 #pragma unroll
-        for (int t = 0; t < RW; t++) {
-            const int s = 64 * t + lane;
+        for (int t = 0; t < WS; t++) {
+            const int s = 64 * t + lane;   // packed: m <= 32, lanes >= 32 read nothing
             double xt = 0.0, xb = 0.0;
             if (s < m) {
                 if (ct < n) xt = A[(size_t)ct * lda + s];
@@ -243,8 +256,8 @@ __global__ __launch_bounds__(64 * NS, res_waves_per_eu(N, RW, NS)) void resident
             T[q][t] = xt;
             B[q][t] = xb;
         }
-        T[q][RW] = (lane == ct) ? 1.0 : 0.0;
-        B[q][RW] = (lane == cb) ? 1.0 : 0.0;
+        T[q][VS] = (lane == VL + ct) ? 1.0 : (PK ? T[q][VS] : 0.0);
+        B[q][VS] = (lane == VL + cb) ? 1.0 : (PK ? B[q][VS] : 0.0);
     }
     bad = __any(bad);
     amax = wave_max(amax);
@@ -268,12 +281,13 @@ __global__ __launch_bounds__(64 * NS, res_waves_per_eu(N, RW, NS)) void resident
     }
     const double scale = pow2_scale(amax);
     if (scale != 1.0) {
+        const double sc = (PK && lane >= 32) ? 1.0 : scale;   // not the V rows
 #pragma unroll
         for (int q = 0; q < KG; q++)
 #pragma unroll
-            for (int t = 0; t < RW; t++) {
-                T[q][t] *= scale;
-                B[q][t] *= scale;
+            for (int t = 0; t < WS; t++) {
+                T[q][t] *= sc;
+                B[q][t] *= sc;
             }
     }
     const double tol2 = tol * tol;
@@ -302,10 +316,10 @@ __global__ __launch_bounds__(64 * NS, res_waves_per_eu(N, RW, NS)) void resident
 #pragma unroll
                         for (int t = 0; t < R; t++) X[t] *= dq;
 #pragma unroll
-                        for (int t = 0; t < RW; t++) p[k] = fma(X[t], X[t], p[k]);
+                        for (int t = 0; t < WS; t++) p[k] = fma(X[t], X[t], p[k]);
                     }
                     // lane (rho, x) holds pair h0 + (x mod QC) + QC rho
-                    const double nv = reduce_pairs<KC, OpSum>(p, buf);
+                    const double nv = reduce_pairs<KC, OpSum, PK>(p, buf);
                     // a column whose squared norm is below kNegligible (a
                     // norm below 2^-480 of the pre-scaled matrix, whose
                     // largest entry is about 1) is set to zero in W: rotating
@@ -321,13 +335,14 @@ __global__ __launch_bounds__(64 * NS, res_waves_per_eu(N, RW, NS)) void resident
                 }
             if (__any(dead)) {
                 wave_sync_lds();
+                const bool wl = !PK || lane < 32;   // lanes of W rows
 #pragma unroll
                 for (int q = 0; q < KG; q++) {
                     const double2 nn = *reinterpret_cast<const double2 *>(&sh.nrm[2 * (q0 + q)]);
 #pragma unroll
-                    for (int t = 0; t < RW; t++) {
-                        T[q][t] = nn.x == 0.0 ? 0.0 : T[q][t];
-                        B[q][t] = nn.y == 0.0 ? 0.0 : B[q][t];
+                    for (int t = 0; t < WS; t++) {
+                        T[q][t] = (wl && nn.x == 0.0) ? 0.0 : T[q][t];
+                        B[q][t] = (wl && nn.y == 0.0) ? 0.0 : B[q][t];
                     }
                 }
             }
@@ -343,9 +358,9 @@ __global__ __launch_bounds__(64 * NS, res_waves_per_eu(N, RW, NS)) void resident
             for (int q = 0; q < KG; q++) {
                 g[q] = 0.0;
 #pragma unroll
-                for (int t = 0; t < RW; t++) g[q] = fma(T[q][t], B[q][t], g[q]);
+                for (int t = 0; t < WS; t++) g[q] = fma(T[q][t], B[q][t], g[q]);
             }
-            const double gs = reduce_pairs<KG, OpSum>(g, buf);
+            const double gs = reduce_pairs<KG, OpSum, PK>(g, buf);
             // ---- rotate-or-skip and the rotation, one pair per lane group ---
             int ct, cb;
             rr_seats(N, it, q0 + qloc, ct, cb);
@@ -494,13 +509,13 @@ __global__ __launch_bounds__(64 * NS, res_waves_per_eu(N, RW, NS)) void resident
                     B[q][t] *= fb;
                 }
 #pragma unroll
-                for (int t = 0; t < RW; t++) {
+                for (int t = 0; t < WS; t++) {
                     pt[q] = fma(T[q][t], T[q][t], pt[q]);
                     pb[q] = fma(B[q][t], B[q][t], pb[q]);
                 }
             }
-            const double nt = reduce_pairs<KG, OpSum>(pt, buf);
-            const double nb = reduce_pairs<KG, OpSum>(pb, buf);
+            const double nt = reduce_pairs<KG, OpSum, PK>(pt, buf);
+            const double nb = reduce_pairs<KG, OpSum, PK>(pb, buf);
             if (x < Q) {
                 sh.nrm[c] = nt;
                 sh.nrm[c + 1] = nb;
@@ -539,12 +554,14 @@ __global__ __launch_bounds__(64 * NS, res_waves_per_eu(N, RW, NS)) void resident
             const double inv = nc > 0.0 ? rsq_nr(nc) : 0.0;   // 1 / ||stored column||
             const double dv = sh.d[c];
 #pragma unroll
-            for (int t = 0; t < RW; t++) {
+            for (int t = 0; t < WS; t++) {
                 const double val = h ? B[q][t] : T[q][t];
                 const int s = 64 * t + lane;
                 if (U && s < m) U[(size_t)rk * ldu + s] = val * inv;
             }
-            if (V && lane < n) V[(size_t)rk * ldv + lane] = (h ? B[q][RW] : T[q][RW]) * dv;
+            const int vr = lane - VL;
+            if (V && vr >= 0 && vr < n)
+                V[(size_t)rk * ldv + vr] = (h ? B[q][VS] : T[q][VS]) * dv;
         }
     }
     bool any_zero = false;
@@ -607,7 +624,8 @@ hipError_t launch_one(int batch, int m, int n, const double *A, int lda, long lo
 }  // namespace
 
 // Shape classes: N = n rounded up to 16/32/64; RW = ceil(m/64) slots of W
-// rows per lane (m <= 256) plus one slot of V rows; NS = waves (seat groups)
+// rows per lane (m <= 256) plus one slot of V rows, or RW = 0 (the packed
+// layout, W and V in one slot) for m <= 32 and N <= 32; NS = waves (seat groups)
 // per matrix, with at most 96 stored doubles per lane.  `ns` = 0 picks the
 // tuned default.  Returns false when no instance covers (m, n, ns).
 bool resident_config(int m, int n, int ns, int *N, int *R, int *NS)
@@ -615,7 +633,7 @@ bool resident_config(int m, int n, int ns, int *N, int *R, int *NS)
     if (n < 1 || m < n) return false;
     const int nn = n <= 16 ? 16 : (n <= 32 ? 32 : (n <= 64 ? 64 : 0));
     if (!nn) return false;
-    const int rw = (m + 63) / 64;
+    const int rw = (m <= 32 && nn <= 32) ? 0 : (m + 63) / 64;
     if (rw > 4) return false;
     if (ns == 0) ns = ((rw + 1) * nn > 96) ? 2 : 1;
     if (ns != 1 && ns != 2 && ns != 4) return false;
@@ -638,6 +656,11 @@ hipError_t launch_resident_d(int batch, int m, int n, int ns, const double *A, i
     if (N == NN && RW == RR && NS == WW)                                                       \
         return launch_one<NN, RR, WW>(batch, m, n, A, lda, sA, S, sS, U, ldu, sU, V, ldv, sV,  \
                                       tol, max_sweeps, info, sweeps, stream);
+    SVDB_RES(16, 0, 1)
+    SVDB_RES(16, 0, 2)
+    SVDB_RES(32, 0, 1)
+    SVDB_RES(32, 0, 2)
+    SVDB_RES(32, 0, 4)
     SVDB_RES(16, 1, 1)
     SVDB_RES(16, 2, 1)
     SVDB_RES(16, 3, 1)
