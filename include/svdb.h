@@ -93,7 +93,9 @@ typedef struct {
                          resident kernel on R^T, U = Q J.  n > 64 (m <=
                          1024): A = Q1 R1, R1^T = Q2 R2 (blocked QRs), the
                          block method on R2^T, U = Q1 U_x, V = Q2 J.  -1 (default): on
-                         for the AUTO path where it applies; 0: off; 1: on
+                         for the AUTO path where it applies, except FP64
+                         with n <= 16 and m < 8 n (there the QRs cost more
+                         than the sweeps they save); 0: off; 1: on
                          (AUTO, RESIDENT or BLOCKED path;
                          SVDB_ERR_UNSUPPORTED where it does not apply).  The
                          sweeps count is that of the iteration on the

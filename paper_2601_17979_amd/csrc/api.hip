@@ -103,7 +103,12 @@ int make_plan(svdb_dtype_t dt, int m, int n, const svdb_opts_t &o, Plan *p)
     const bool pc_ok = real && o.precision == 0 && svdb::precond_supported(m, n);
     const bool pc_req = (path == SVDB_PATH_AUTO && o.precondition != 0) ||
                         (path == SVDB_PATH_RESIDENT && o.precondition == 1);
-    if (pc_req && pc_ok) {
+    // FP64 with n <= 16 and m < 8 n: the two QRs and the two applications of
+    // Q cost more than the sweeps they save (measured on batches of Gaussian,
+    // geometric-spectrum and uniform [0, 1] matrices), so AUTO without an
+    // explicit request runs the resident kernel on A itself
+    const bool pc_pays = !(dt == SVDB_R64 && n <= 16 && m < 8 * n);
+    if (pc_req && pc_ok && (pc_pays || o.precondition == 1)) {
         svdb::resident_config(n, n, o.waves, &rN, &rR, &rW);
         p->path = SVDB_PATH_RESIDENT;
         p->nb = 0;

@@ -307,3 +307,19 @@ def test_precond_wide_at_the_maximum_size(m, n):
     assert orth_err(U[0]) <= tol_o and orth_err(V[0]) <= tol_o
     assert np.all(np.diff(S[0]) <= 0)
     say(f"  sweeps {sw.tolist()}")
+
+
+@pytest.mark.parametrize("m,n,qr", [(16, 16, False), (100, 16, False), (127, 16, False),
+                                    (128, 16, True), (63, 8, False), (64, 8, True),
+                                    (17, 17, True), (40, 24, True)])
+def test_auto_skips_qr_for_few_columns(m, n, qr):
+    """AUTO leaves out the QR pre-processing for FP64 with n <= 16 and
+    m < 8 n (where it costs more than the sweeps it saves): its result is
+    bit for bit that of precondition 0 there, and of precondition 1 elsewhere."""
+    A = _batch((m, n), 6, seed=9800 + m + n, kinds=("gauss", "geo", "random"))
+    auto = run_gpu(A)
+    ref = run_gpu(A, precondition=1 if qr else 0)
+    for x, y in zip(auto, ref):
+        assert np.array_equal(x, y)
+    Sr, _, _, _, infor = oracle_batch(A)
+    compare_with_oracle(A, auto[0], auto[1], auto[2], auto[3], Sr, infor, label=f"auto {m}x{n}")
