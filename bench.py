@@ -72,7 +72,7 @@ def serve_leg(args, dev):
     torch.cuda.synchronize()
     budget = 8 << 30
     srv = svdb.Server(budget_bytes=budget, max_requests=2048,
-                      precondition=1 if args.serve_precondition else 0)
+                      precondition=args.serve_precondition)
 
     def drain(n, t_limit):
         lat, t0 = [], time.time()
@@ -130,7 +130,7 @@ def serve_leg(args, dev):
             "p50_ms": float(np.percentile(lat, 50) * 1e3) if lat.size else None,
             "p99_ms": float(np.percentile(lat, 99) * 1e3) if lat.size else None,
             "per_class": per_class, "budget_bytes": budget,
-            "qr_preconditioning": bool(args.serve_precondition)}
+            "qr_preconditioning": args.serve_precondition != 0}
 
 
 def host_cpu():
@@ -348,8 +348,9 @@ def main():
                     help="skip the plain GPU Jacobi comparator run")
     ap.add_argument("--serve-seconds", type=float, default=8.0,
                     help="length of the Poisson serving run (0 = skip the serving leg)")
-    ap.add_argument("--serve-precondition", type=int, default=0,
-                    help="1: QR-precondition the real requests of the serving leg")
+    ap.add_argument("--serve-precondition", type=int, default=-1,
+                    help="QR preconditioning of the serving leg's real requests: -1 (the "
+                         "server default) or 1 on, 0 off")
     ap.add_argument("--serve-load", type=float, default=0.5,
                     help="offered load as a fraction of the measured saturation rate")
     ap.add_argument("--workload", default="mixed", choices=["mixed", "square256", "uneven", "tallskinny"],
@@ -479,6 +480,10 @@ def main():
                  "ms_per_step": wall_p / max(1, args.steps // 2) * 1e3,
                  "kernel_ms": [float(x) for x in per_p]}
 
+    # the serving leg runs before the oracle, whose OpenMP worker threads may
+    # keep host cores busy after it returns
+    serve = serve_leg(args, dev) if args.serve_seconds > 0 else None
+
     # accuracy vs the FP64 oracle and the CPU baseline on a bounded sample
     cpu = None
     sig_err = None
@@ -502,7 +507,6 @@ def main():
                "oracle_sweeps_per_gpu_sweep": sw_ratio, **host_cpu()}
         sig_err = max(errs)
 
-    serve = serve_leg(args, dev) if args.serve_seconds > 0 else None
 
     line = {
         "metric": METRIC, "value": value, "unit": "SVDs/s", "n_gpus": 1, "steps": args.steps,

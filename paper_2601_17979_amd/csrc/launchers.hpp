@@ -53,6 +53,13 @@ struct QrJob {
     const int *info;          // the request's status
 };
 void launch_qr_jobs(const QrJob *jobs, const int *list, int count, hipStream_t stream);
+// the blocked QR of a strided batch (m <= 1024, n <= 512): reflectors as
+// full columns into H (m n apart), X = R^T, tau; A may equal H.  scratch
+// holds qr_blocked_scratch_bytes of any larger or equal batch and shape
+size_t qr_blocked_scratch_bytes(int batch, int m, int n);
+hipError_t launch_qr_blocked_batch(int batch, int m, int n, const double *A, int lda,
+                                   long long sA, double *H, double *X, double *tau,
+                                   void *scratch, hipStream_t stream);
 void launch_apply_q_jobs(const QrJob *jobs, const int *list, int count, int max_m,
                          hipStream_t stream);
 size_t precond_big_workspace_bytes(int batch, int m, int n, int nb);

@@ -1010,6 +1010,25 @@ hipError_t launch_qr_blocked(int batch, int m, int n, const double *A, int lda, 
 }
 }  // namespace
 
+// The blocked Householder QR of a strided batch, for the serving runtime's
+// requests with more than 64 columns (one workgroup per matrix would run the
+// whole factorisation serially): H (m x n per matrix, ld m, m n apart) gets
+// the reflectors as full columns, X = R^T (n x n apart), tau (n apart).  A
+// may equal H (lda = m, sA = m n).
+size_t qr_blocked_scratch_bytes(int batch, int m, int n)
+{
+    return qrb_carve(batch, m, n, nullptr, nullptr);
+}
+
+hipError_t launch_qr_blocked_batch(int batch, int m, int n, const double *A, int lda,
+                                   long long sA, double *H, double *X, double *tau,
+                                   void *scratch, hipStream_t stream)
+{
+    if (batch < 1 || m < n || n < 1 || m > kQrMaxM || n > kQrMaxN || lda < m)
+        return hipErrorInvalidValue;
+    return launch_qr_blocked(batch, m, n, A, lda, sA, H, X, tau, scratch, stream);
+}
+
 bool precond_big_supported(int m, int n)
 {
     return n > 64 && m >= n && m <= kQrMaxM;

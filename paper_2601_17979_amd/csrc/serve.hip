@@ -113,6 +113,8 @@ struct Completion {
 
 int elt_of(int dtype) { return dtype == 0 ? 4 : dtype == 3 ? 16 : 8; }
 
+constexpr int kWideChunk = 8;   // requests per blocked-QR launch of the wide QR lane
+
 // Arena layout of a QR-preconditioned request (FP64, byte offsets from its
 // range): the Jacobi's W (n x np) and V (np x np), X = R^T, the reflectors
 // (m x n), tau, J, and for FP32 requests the FP64 staging of S and V.
@@ -186,6 +188,10 @@ struct svdb_server {
     hipStream_t aux[3] = {};       // the lanes of preconditioned requests
     hipEvent_t ev_fin = nullptr;   // end of the finalisations of a round
     void *arena = nullptr;
+    // the wide QR lane: up to kWideChunk same-shape requests are gathered
+    // into H, factored by one blocked-QR launch, and scattered back
+    double *qrb_h = nullptr, *qrb_x = nullptr, *qrb_tau = nullptr;
+    void *qrb_ws = nullptr;
     size_t budget = 0;
     Arena alloc;
     Group g[4];
@@ -343,6 +349,55 @@ hipError_t lane_done(Group::Lane &L, bool *done)
     return hipSuccess;
 }
 
+// QR of the wide lane's requests: same-shape requests, kWideChunk at a time,
+// are gathered (FP32 widened) into the staging H, factored by one launch of
+// the blocked QR, and their reflectors, X = R^T and tau copied to the
+// request's arena range, where the Jacobi and the application of Q expect
+// them.
+hipError_t wide_qr(svdb_server *s, Group &G, const std::vector<int> &cur, hipStream_t st)
+{
+    std::vector<int> todo(cur);
+    while (!todo.empty()) {
+        const svdb::QrJob &J0 = G.h_jobs[todo[0]];
+        const int m = J0.m, n = J0.n;
+        std::vector<int> chunk, rest;
+        for (int b : todo) {
+            const svdb::QrJob &J = G.h_jobs[b];
+            if (J.m == m && J.n == n && (int)chunk.size() < kWideChunk)
+                chunk.push_back(b);
+            else
+                rest.push_back(b);
+        }
+        const size_t mn = (size_t)m * n, nn = (size_t)n * n;
+        hipError_t e = hipSuccess;
+        for (size_t k = 0; k < chunk.size() && e == hipSuccess; k++) {
+            const svdb::QrJob &J = G.h_jobs[chunk[k]];
+            double *h = s->qrb_h + k * mn;
+            if (J.f32)
+                e = svdb::launch_widen_f32(1, m, n, (const float *)J.A, J.lda, 0, h, m, 0, st);
+            else
+                e = hipMemcpy2DAsync(h, (size_t)m * 8, J.A, (size_t)J.lda * 8, (size_t)m * 8, n,
+                                     hipMemcpyDeviceToDevice, st);
+        }
+        if (e == hipSuccess)
+            e = svdb::launch_qr_blocked_batch((int)chunk.size(), m, n, s->qrb_h, m,
+                                              (long long)mn, s->qrb_h, s->qrb_x, s->qrb_tau,
+                                              s->qrb_ws, st);
+        for (size_t k = 0; k < chunk.size() && e == hipSuccess; k++) {
+            const svdb::QrJob &J = G.h_jobs[chunk[k]];
+            e = hipMemcpyAsync(J.Vq, s->qrb_h + k * mn, mn * 8, hipMemcpyDeviceToDevice, st);
+            if (e == hipSuccess)
+                e = hipMemcpyAsync(J.X, s->qrb_x + k * nn, nn * 8, hipMemcpyDeviceToDevice, st);
+            if (e == hipSuccess)
+                e = hipMemcpyAsync(J.tau, s->qrb_tau + k * n, (size_t)n * 8,
+                                   hipMemcpyDeviceToDevice, st);
+        }
+        if (e != hipSuccess) return e;
+        todo.swap(rest);
+    }
+    return hipSuccess;
+}
+
 void worker_main(svdb_server *s)
 {
     std::vector<int> init;   // slots to initialise this round
@@ -405,8 +460,13 @@ void worker_main(svdb_server *s)
                     }
                 if (!L.busy && !L.wait.empty()) {
                     SRV_CHECK(lane_stage(G, L, s->aux[q]));
-                    svdb::launch_qr_jobs(G.d_jobs, G.d_ring + L.pos, (int)L.cur.size(), s->aux[q]);
-                    SRV_CHECK(hipGetLastError());
+                    if (q == 0) {   // n <= 64: one workgroup per request
+                        svdb::launch_qr_jobs(G.d_jobs, G.d_ring + L.pos, (int)L.cur.size(),
+                                             s->aux[q]);
+                        SRV_CHECK(hipGetLastError());
+                    } else {        // wider: the blocked QR, same shapes batched
+                        SRV_CHECK(wide_qr(s, G, L.cur, s->aux[q]));
+                    }
                     SRV_CHECK(hipEventRecord(L.ev, s->aux[q]));
                     L.busy = true;
                 }
@@ -557,6 +617,8 @@ void destroy_resources(svdb_server *s)
         if (G.h_ring) (void)hipHostFree(G.h_ring);
     }
     if (s->arena) (void)hipFree(s->arena);
+    for (void *p : {(void *)s->qrb_h, (void *)s->qrb_x, (void *)s->qrb_tau, s->qrb_ws})
+        if (p) (void)hipFree(p);
     if (s->ev_fin) (void)hipEventDestroy(s->ev_fin);
     for (hipStream_t a : s->aux)
         if (a) (void)hipStreamDestroy(a);
@@ -583,13 +645,23 @@ int svdb_server_create(svdb_server_t **out, size_t budget_bytes, int max_request
     svdb_server *s = new svdb_server();
     s->budget = al256(budget_bytes);
     s->max_sweeps = o.max_sweeps > 0 ? o.max_sweeps : 100;
-    s->precondition = o.precondition == 1;
+    s->precondition = o.precondition != 0;   // -1 (default) and 1: on
     s->inner = o.inner_sweeps < -1 ? -1 : o.inner_sweeps;
     hipError_t e = hipStreamCreateWithFlags(&s->stream, hipStreamNonBlocking);
     for (hipStream_t &a : s->aux)
         if (e == hipSuccess) e = hipStreamCreateWithFlags(&a, hipStreamNonBlocking);
     if (e == hipSuccess) e = hipEventCreateWithFlags(&s->ev_fin, hipEventDisableTiming);
     if (e == hipSuccess) e = hipMalloc(&s->arena, s->budget);
+    if (s->precondition) {
+        const size_t mn = (size_t)kWideChunk * 1024 * s->max_n,
+                     nn = (size_t)kWideChunk * s->max_n * s->max_n;
+        if (e == hipSuccess) e = hipMalloc((void **)&s->qrb_h, mn * sizeof(double));
+        if (e == hipSuccess) e = hipMalloc((void **)&s->qrb_x, nn * sizeof(double));
+        if (e == hipSuccess)
+            e = hipMalloc((void **)&s->qrb_tau, (size_t)kWideChunk * s->max_n * sizeof(double));
+        if (e == hipSuccess)
+            e = hipMalloc(&s->qrb_ws, svdb::qr_blocked_scratch_bytes(kWideChunk, 1024, s->max_n));
+    }
     const int pairs = s->max_n / svdb::vb_nb() / 2;   // block pairs of the widest request
     for (int gi = 0; gi < 4 && e == hipSuccess; gi++) {
         Group &G = s->g[gi];

@@ -69,8 +69,11 @@ def test_server_mixed_requests_vs_oracle():
         _check(reqs[k], out, f"serve #{k} {reqs[k].shape} {reqs[k].dtype}")
 
 
-def test_server_alone_equals_in_mix():
-    """A request's outputs do not depend on what else is being served."""
+@pytest.mark.parametrize("precondition", [-1, 0])
+def test_server_alone_equals_in_mix(precondition):
+    """A request's outputs do not depend on what else is being served (with
+    the default QR preconditioning, whose wide QRs are batched by shape, and
+    without)."""
     import torch
     from paper_2601_17979_amd import svdb
     probe = _mat(9600, 0, 96, 80, np.float64)
@@ -80,7 +83,7 @@ def test_server_alone_equals_in_mix():
     def run(mats):
         dev = [_to_dev(A) for A in mats]
         torch.cuda.synchronize()
-        srv = svdb.Server(budget_bytes=128 << 20, max_requests=16)
+        srv = svdb.Server(budget_bytes=128 << 20, max_requests=16, precondition=precondition)
         ids = [srv.submit(x) for x in dev]
         got = _drain(srv, len(mats))
         srv.close()
@@ -88,8 +91,10 @@ def test_server_alone_equals_in_mix():
 
     alone = run([probe])[0]
     mixed = run(others[:4] + [probe] + others[4:])[4]
-    for a, b in zip(alone, mixed):
-        assert np.array_equal(a, b)
+    # the same shape as the probe in the mix: one blocked-QR launch for both
+    twin = run([_mat(9600, 9, 96, 80, np.float64), probe])[1]
+    for a, b, c in zip(alone, mixed, twin):
+        assert np.array_equal(a, b) and np.array_equal(a, c)
 
 
 def test_server_budget_admission():
@@ -176,3 +181,25 @@ def test_server_wide_requests():
             _check(A, out, f"serve tall {A.shape}")
         else:   # A^H = V S U^H
             _check(A.T.copy(), (out[0], out[2], out[1], out[3], out[4]), f"serve wide {A.shape}")
+
+
+def test_server_precondition_wide_qr():
+    """Preconditioned requests with more than 64 columns take the blocked QR
+    (request by request on the wide QR lane), up to m = 1024; FP32 requests
+    are widened into the reflector buffer first."""
+    import torch
+    from paper_2601_17979_amd import svdb
+    shapes = [(700, 300, np.float64), (700, 300, np.float32), (1024, 128, np.float64),
+              (256, 256, np.float32), (90, 65, np.float64)]
+    reqs = [_mat(9900, k, m, n, dt, kappa=1e8) for k, (m, n, dt) in enumerate(shapes)]
+    dev = [_to_dev(A) for A in reqs]
+    torch.cuda.synchronize()
+    srv = svdb.Server(budget_bytes=1 << 30, max_requests=8, precondition=1)
+    ids = {srv.submit(x): k for k, x in enumerate(dev)}
+    got = _drain(srv, len(reqs))
+    srv.close()
+    for rid, (ts, td, out) in got.items():
+        k = ids[rid]
+        say(f"  wide QR {reqs[k].shape} {reqs[k].dtype}: sweeps {int(out[4].item())}, "
+            f"{(td - ts) * 1e3:.1f} ms")
+        _check(reqs[k], out, f"precond wide #{k} {reqs[k].shape}")
