@@ -211,7 +211,8 @@ int svdb_plan(svdb_dtype_t dtype, int m, int n, const svdb_opts_t *opts,
  *     with QR preconditioning: A = Q R, the FP64 Jacobi on R^T, U = Q J
  *     (FP32 requests are solved in FP64 and returned in FP32; requests with
  *     more than 64 columns take the blocked QR, up to eight of one shape
- *     per launch); 0: off.
+ *     per launch, through about 50 MB of staging memory that the server
+ *     allocates beside its arena); 0: off.
  *     Returns 0, -k for invalid argument k, SVDB_ERR_HIP.
  *  svdb_server_submit: device pointers as svdb_svd_batched; A must hold its
  *     values when the call is made (the server reads it on its own stream)
