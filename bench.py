@@ -341,6 +341,11 @@ def main():
     ap.add_argument("--warmup", type=int, default=2)
     ap.add_argument("--path", default="auto")
     ap.add_argument("--batch", type=int, default=10000)
+    ap.add_argument("--streams", type=int, default=1,
+                    help="HIP streams the headline's two shape groups are issued on (they are "
+                         "independent): 1 = one after the other (default; the roofline is "
+                         "then that of the dominant call); 2 = one each, overlapped (the "
+                         "roofline is then that of the whole step)")
     ap.add_argument("--cpu-sample", type=int, default=5000,
                     help="matrices per shape for the CPU oracle baseline (default: the whole "
                          "workload, about 20 core-seconds; 0 = skip)")
@@ -401,13 +406,28 @@ def main():
             work.append((g, Ag, out))
         return work
 
+    # the shape groups are independent: with --streams 2 the first group's
+    # call runs on the current stream and every other group's on a side
+    # stream of its own, joined back before the step ends
+    sides = [torch.cuda.Stream(dev) for _ in groups[1:]] if args.streams > 1 else []
+
+    def issue(calls, events=None):
+        for s_ in sides:
+            s_.wait_stream(stream)
+        for k, call in enumerate(calls):
+            st = sides[k - 1] if (k > 0 and sides) else stream
+            with torch.cuda.stream(st):
+                if events is not None:
+                    events[k][0].record(st)
+                call()
+                if events is not None:
+                    events[k][1].record(st)
+        for s_ in sides:
+            stream.wait_stream(s_)
+
     def run(work, path, events=None):
-        for k, (g, Ag, out) in enumerate(work):
-            if events is not None:
-                events[k][0].record(stream)
-            svdb.svd(Ag, path=path, out=out)
-            if events is not None:
-                events[k][1].record(stream)
+        issue([lambda Ag=Ag, out=out: svdb.svd(Ag, path=path, out=out)
+               for g, Ag, out in work], events)
 
     def timed(path, steps, warmup):
         work = prepare(path)
@@ -416,16 +436,21 @@ def main():
         torch.cuda.synchronize()
         ev = [[(torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True))
                for _ in work] for _ in range(steps)]
+        sev = [(torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True))
+               for _ in range(steps)]
         t0 = time.perf_counter()
         for s in range(steps):
+            sev[s][0].record(stream)
             run(work, path, ev[s])
+            sev[s][1].record(stream)   # after the side streams have joined
         torch.cuda.synchronize()
         wall = time.perf_counter() - t0
         per_kernel = [np.mean([ev[s][k][0].elapsed_time(ev[s][k][1]) for s in range(steps)])
                       for k in range(len(work))]
-        return work, wall, per_kernel
+        step_ms = float(np.mean([a.elapsed_time(b) for a, b in sev]))
+        return work, wall, per_kernel, step_ms
 
-    work, wall, per_kernel = timed(args.path, args.steps, args.warmup)
+    work, wall, per_kernel, step_ms = timed(args.path, args.steps, args.warmup)
     ms_per_step = wall / args.steps * 1e3
     value = total * args.steps / wall
 
@@ -435,47 +460,63 @@ def main():
         results.append((g, S, U, V, info, sw))
     bad = int(sum(int(np.sum(r[4] != 0)) for r in results))
 
-    # dominant call: the launch sequence with the longest average duration.
-    # With QR preconditioning (the AUTO default for these shapes) one call is
-    # the pivoted QR of A (2n^2(m - n/3)), the QR of R1^T (4n^3/3), the
-    # Jacobi on R2^T (n x n), U = Q1 [U_x; 0] (2n^2(2m - n)) and V = P Q2 J
-    # (2n^3); its work is counted as all five.
-    kdom = int(np.argmax(per_kernel))
-    gd, Sd, Ud, Vd, infod, swd = results[kdom]
-    try:   # AUTO preconditions exactly where precondition = 1 is accepted
-        svdb.plan(torch.float64, gd.m, gd.n, path="auto", precondition=1)
-        precond = args.path == "auto"
-    except svdb.SvdbError:
-        precond = False
-    if precond:
-        m_, n_ = gd.m, gd.n
-        fl = flops_unblocked(n_, n_, swd) + len(swd) * (
+    # Work of one call.  With QR preconditioning (the AUTO default for these
+    # shapes) a call is the pivoted QR of A (2n^2(m - n/3)), the QR of R1^T
+    # (4n^3/3), the Jacobi on R2^T (n x n), U = Q1 [U_x; 0] (2n^2(2m - n))
+    # and V = P Q2 J (2n^3); its work is counted as all five.
+    def call_flops(g, sw):
+        # AUTO preconditions where precondition = 1 is accepted, except FP64
+        # with n <= 16 and m < 8 n
+        try:
+            svdb.plan(torch.float64, g.m, g.n, path="auto", precondition=1)
+            pc = args.path == "auto" and not (g.n <= 16 and g.m < 8 * g.n)
+        except svdb.SvdbError:
+            pc = False
+        if not pc:
+            return flops_unblocked(g.m, g.n, sw), False
+        m_, n_ = g.m, g.n
+        return flops_unblocked(n_, n_, sw) + len(sw) * (
             2.0 * n_ * n_ * (m_ - n_ / 3.0) + 4.0 * n_ ** 3 / 3.0 +
-            2.0 * n_ * n_ * (2 * m_ - n_) + 2.0 * n_ ** 3)
+            2.0 * n_ * n_ * (2 * m_ - n_) + 2.0 * n_ ** 3), True
+
+    flc = [call_flops(r[0], r[5]) for r in results]
+    label = " (pivoted QR, QR of R1^T, Jacobi on R2^T, Q1 and Q2 applied)"
+    if sides:
+        # the calls overlap on two streams: the unit is one whole step, timed
+        # from before the first launch to after the side streams joined
+        fl = sum(f for f, _ in flc)
+        traffic = [measured_traffic(f"{r[0].m}x{r[0].n}") if pc else None
+                   for r, (_, pc) in zip(results, flc)]
+        kname = ("one step: " + " and ".join(f"{r[0].m}x{r[0].n}" for r in results) +
+                 " calls on two streams" + (label if all(pc for _, pc in flc) else ""))
+        kms = step_ms
+        tr = sum(traffic) if all(t is not None for t in traffic) else None
     else:
-        fl = flops_unblocked(gd.m, gd.n, swd)
-    achieved = fl / (per_kernel[kdom] * 1e-3)
+        # the dominant call: the launch sequence with the longest duration
+        kdom = int(np.argmax(per_kernel))
+        gd = results[kdom][0]
+        fl, pc = flc[kdom]
+        kname = f"{gd.m}x{gd.n} call" + (label if pc else " (resident Jacobi)")
+        kms = per_kernel[kdom]
+        tr = measured_traffic(f"{gd.m}x{gd.n}") if pc else None
+    achieved = fl / (kms * 1e-3)
     roofline = {"bound": "alu", "achieved": achieved / 1e12, "peak": FP64_VALU_PEAK / 1e12,
-                "unit": "TFLOP/s", "frac": achieved / FP64_VALU_PEAK,
-                "traffic": measured_traffic(f"{gd.m}x{gd.n}") if precond else None,
-                "kernel": f"{gd.m}x{gd.n} call" + (" (pivoted QR, QR of R1^T, Jacobi on R2^T, "
-                                                   "Q1 and Q2 applied)"
-                                                   if precond else " (resident Jacobi)"),
-                "kernel_ms": per_kernel[kdom], "flops_per_launch": fl}
+                "unit": "TFLOP/s", "frac": achieved / FP64_VALU_PEAK, "traffic": tr,
+                "kernel": kname, "kernel_ms": kms, "flops_per_launch": fl}
 
     # the same kernels without QR preconditioning (the iteration on A itself)
     noqr = None
     if args.path == "auto" and not args.no_plain:
         def run_noqr():
-            for g, Ag, out in work:
-                svdb.svd(Ag, path="auto", precondition=0, out=out)
+            issue([lambda Ag=Ag, out=out: svdb.svd(Ag, path="auto", precondition=0, out=out)
+                   for g, Ag, out in work])
         wall_n, ms_n, _ = timed_calls(run_noqr, max(1, args.steps // 2), 1)
         noqr = {"value": total / wall_n, "unit": "SVDs/s", "ms_per_step": wall_n * 1e3}
 
     # the plain GPU Jacobi on the same workload (the comparator of the metric)
     plain = None
     if args.path != "plain" and not args.no_plain:
-        _, wall_p, per_p = timed("plain", max(1, args.steps // 2), 1)
+        _, wall_p, per_p, _ = timed("plain", max(1, args.steps // 2), 1)
         plain = {"value": total * max(1, args.steps // 2) / wall_p, "unit": "SVDs/s",
                  "ms_per_step": wall_p / max(1, args.steps // 2) * 1e3,
                  "kernel_ms": [float(x) for x in per_p]}
@@ -513,6 +554,7 @@ def main():
         "warmup": args.warmup, "ms_per_step": ms_per_step, "higher_is_better": True,
         "scaling": "weak", "vs_baseline": None, "dtype": "f64", "data": "synthetic",
         "config": {"workload": WORKLOAD, "path": args.path, "batch": total,
+                   "streams": 2 if sides else 1,
                    "sigma_rel_err_vs_oracle_sample": sig_err, "not_converged": bad,
                    "sweeps_mean": {f"{r[0].m}x{r[0].n}": float(np.mean(r[5])) for r in results},
                    "sweeps_hist": {f"{r[0].m}x{r[0].n}": sweep_histogram(r[5]) for r in results},
