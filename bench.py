@@ -56,12 +56,10 @@ def flops_unblocked(m, n, sweeps):
     return float(np.sum(pairs * (6 * m * s + 6 * (m + n) * np.maximum(s - 1, 0))))
 
 
-def serve_leg(args, dev):
-    """Serving workload: requests from 12 shape classes (n in {16..512} x
-    {square, m = 2n}), FP64/FP32 alternating, kappa log-uniform in [1, 1e8].
-    Saturation = a closed batch of requests submitted at once; then Poisson
-    arrivals at `serve_load` x saturation for `serve_seconds`; latency =
-    completion - arrival (server clock)."""
+def serve_setup(args, dev):
+    """The serving pool on the device and a server over it; saturation =
+    a closed batch of 8 x the pool submitted at once (after one warm-up
+    pass), in requests per second."""
     import torch
     from paper_2601_17979_amd import svdb
     from workloads import gen
@@ -69,19 +67,18 @@ def serve_leg(args, dev):
     tdt = {"f64": torch.float64, "f32": torch.float32}
     dev_pool = [svdb.col_major(torch.from_numpy(A)[None].to(tdt[d]).to(dev))[0]
                 for A, d in pool]
+    names = [f"{A.shape[0]}x{A.shape[1]}" for A, d in pool]
     torch.cuda.synchronize()
     budget = 8 << 30
     srv = svdb.Server(budget_bytes=budget, max_requests=2048,
                       precondition=args.serve_precondition)
 
     def drain(n, t_limit):
-        lat, t0 = [], time.time()
-        while len(lat) < n and time.time() - t0 < t_limit:
-            for rid, ts, td, out in srv.poll(timeout_ms=100):
-                lat.append(td - ts)
-        return lat
+        got, t0 = 0, time.time()
+        while got < n and time.time() - t0 < t_limit:
+            got += len(srv.poll(timeout_ms=100))
+        return got
 
-    # warm-up and saturation: closed batches of the whole pool
     for x in dev_pool:
         srv.submit(x)
     drain(len(dev_pool), 120)
@@ -92,11 +89,15 @@ def serve_leg(args, dev):
             srv.submit(x)
     drain(reps * len(dev_pool), 300)
     sat = reps * len(dev_pool) / (svdb.Server.clock() - t0)
-    # open loop: Poisson arrivals
-    rate = args.serve_load * sat
-    rng = np.random.default_rng(17979 + 4000)
-    lat, n_sub, cls = [], 0, {}
-    by_class = {}
+    return srv, dev_pool, names, sat, budget
+
+
+def poisson_run(srv, dev_pool, names, rate, seconds, max_requests, seed):
+    """Poisson arrivals at `rate` for `seconds` or until max_requests were
+    submitted; latency = completion - submission on the server's clock."""
+    from paper_2601_17979_amd import svdb
+    rng = np.random.default_rng(seed)
+    lat, n_sub, cls, by_class = [], 0, {}, {}
 
     def collect(items):
         for rid, ts, td, out in items:
@@ -104,7 +105,7 @@ def serve_leg(args, dev):
             by_class.setdefault(cls.pop(rid), []).append(td - ts)
     t_start = svdb.Server.clock()
     t_next = t_start
-    while t_next - t_start < args.serve_seconds:
+    while t_next - t_start < seconds and n_sub < max_requests:
         now = svdb.Server.clock()
         if now < t_next:
             collect(srv.poll(timeout_ms=0))
@@ -112,25 +113,69 @@ def serve_leg(args, dev):
             continue
         k = int(rng.integers(len(dev_pool)))
         rid = srv.submit(dev_pool[k])
-        cls[rid] = f"{pool[k][0].shape[0]}x{pool[k][0].shape[1]}"
+        cls[rid] = names[k]
         n_sub += 1
         t_next += rng.exponential(1.0 / rate)
+    t_sub_end = svdb.Server.clock()
     t0 = time.time()
     while len(lat) < n_sub and time.time() - t0 < 120:
         collect(srv.poll(timeout_ms=100))
-    srv.close()
+    t_end = svdb.Server.clock()
     lat = np.sort(np.asarray(lat))
     per_class = {c: {"count": len(v), "p50_ms": float(np.percentile(v, 50) * 1e3),
                      "p99_ms": float(np.percentile(v, 99) * 1e3)}
                  for c, v in sorted(by_class.items(), key=lambda kv: int(kv[0].split("x")[1]))}
-    return {"workload": "12 shape classes n in {16,...,512} x {square, 2n x n}, FP64/FP32 "
-                        "alternating, geometric spectrum kappa log-uniform [1, 1e8]",
-            "saturation_svds_per_s": sat, "offered_load": args.serve_load,
-            "offered_rate_per_s": rate, "requests": int(n_sub), "completed": int(lat.size),
+    return {"offered_rate_per_s": rate, "requests": int(n_sub), "completed": int(lat.size),
+            "submit_seconds": t_sub_end - t_start,
+            "completed_per_s": lat.size / max(t_end - t_start, 1e-9),
             "p50_ms": float(np.percentile(lat, 50) * 1e3) if lat.size else None,
             "p99_ms": float(np.percentile(lat, 99) * 1e3) if lat.size else None,
-            "per_class": per_class, "budget_bytes": budget,
+            "per_class": per_class}
+
+
+SERVE_WORKLOAD = ("12 shape classes n in {16,...,512} x {square, 2n x n}, FP64/FP32 "
+                  "alternating, geometric spectrum kappa log-uniform [1, 1e8]")
+
+
+def serve_leg(args, dev):
+    """Serving workload: requests from 12 shape classes (n in {16..512} x
+    {square, m = 2n}), FP64/FP32 alternating, kappa log-uniform in [1, 1e8].
+    Saturation = a closed batch of requests submitted at once; then Poisson
+    arrivals at `serve_load` x saturation for `serve_seconds`."""
+    srv, dev_pool, names, sat, budget = serve_setup(args, dev)
+    r = poisson_run(srv, dev_pool, names, args.serve_load * sat, args.serve_seconds, 10 ** 9,
+                    17979 + 4000)
+    srv.close()
+    return {"workload": SERVE_WORKLOAD, "saturation_svds_per_s": sat,
+            "offered_load": args.serve_load, **r, "budget_bytes": budget,
             "qr_preconditioning": args.serve_precondition != 0}
+
+
+def serve_main(args, dev):
+    """The serving rate sweep: Poisson arrivals at 0.25, 0.5, 0.75, 0.9, 1.0
+    and 1.2 x the measured saturation, each for 20000 requests or 60 s
+    (whichever comes first), p50 / p99 latency per rate."""
+    srv, dev_pool, names, sat, budget = serve_setup(args, dev)
+    rates = {}
+    for i, load in enumerate((0.25, 0.5, 0.75, 0.9, 1.0, 1.2)):
+        r = poisson_run(srv, dev_pool, names, load * sat, 60.0, 20000, 17979 + 4100 + i)
+        rates[str(load)] = r
+        print(json.dumps({"load": load, "rate": r["offered_rate_per_s"],
+                          "requests": r["requests"], "p50_ms": r["p50_ms"],
+                          "p99_ms": r["p99_ms"]}), file=sys.stderr, flush=True)
+    srv.close()
+    head = rates["0.5"]
+    line = {
+        "metric": "serve p50/p99 latency (ms) vs offered load", "value": head["p99_ms"],
+        "unit": "ms (p99 at 0.5 x saturation)", "n_gpus": 1, "steps": len(rates), "warmup": 1,
+        "ms_per_step": None, "higher_is_better": False, "scaling": "weak",
+        "vs_baseline": None, "dtype": "f64/f32", "data": "synthetic",
+        "config": {"workload": SERVE_WORKLOAD, "saturation_svds_per_s": sat,
+                   "budget_bytes": budget, "qr_preconditioning": args.serve_precondition != 0,
+                   "rates": rates},
+        "roofline": None, "cpu_baseline": None,
+    }
+    print(json.dumps(line), flush=True)
 
 
 def host_cpu():
@@ -184,112 +229,151 @@ def timed_calls(fn, steps, warmup):
     return wall, float(np.mean([a.elapsed_time(b) for a, b in ev])), out
 
 
-def square256_main(args, dev):
-    """4000 FP64 256 x 256 (geometric spectra, kappa 1e2 / 1e8), block
-    method, all-FP64 and FP32 sweeps + FP64 refinement."""
+def oracle_each(mats, threads=16):
+    """The oracle on a list of matrices of any shapes, one matrix per host
+    thread (each a single-threaded row-cyclic Jacobi).  Returns (S list,
+    sweeps list, seconds, threads)."""
+    import oracle
+    from concurrent.futures import ThreadPoolExecutor
+    t0 = time.perf_counter()
+    with ThreadPoolExecutor(max_workers=threads) as ex:
+        res = list(ex.map(lambda A: oracle.gesvj(A, want_u=False, want_v=False), mats))
+    return [r[0] for r in res], [r[3] for r in res], time.perf_counter() - t0, threads
+
+
+def square256_leg(dev, grp, steps=2, warmup=1, cpu_sample=40):
+    """configs: 4000 FP64 256 x 256, geometric spectra, half kappa 1e2, half
+    1e8.  Three modes of the same call: all-FP64 block sweeps on A, FP32 MFMA
+    sweeps + FP64 refinement, and the default (QR preconditioning, block
+    sweeps on R2^T).  Each with its sigma error against the oracle on a
+    sample."""
     import torch
     from paper_2601_17979_amd import svdb
-    from workloads import gen
-    batch = args.batch if args.batch != 10000 else 4000
+    batch = grp.A.shape[0]
     half = batch // 2
-    idx = list(range(half)) + list(range(2000, 2000 + batch - half))
-    grp = gen.square256(batch=4000, indices=idx)[0]
     Ag = svdb.col_major(torch.from_numpy(grp.A).to(dev))
+    modes = {"fp64": dict(path="blocked", nb=16, precision=0, precondition=0),
+             "fp32+fp64": dict(path="blocked", nb=16, precision=1, precondition=0),
+             "qr+fp64": dict()}
+    k = max(2, cpu_sample)
+    pick = np.r_[0:k // 2, half:half + k - k // 2]
+    Sr, swr, t_cpu, thr = oracle_each([grp.A[i] for i in pick])
+    Sr = np.stack(Sr)
     res = {}
-    modes = {0: dict(precision=0, precondition=0), 1: dict(precision=1, precondition=0),
-             2: dict(precision=0, precondition=1)}
-    for mode, kw in modes.items():
-        wall, ms, out = timed_calls(lambda: svdb.svd(Ag, path="blocked", nb=16, **kw),
-                                    args.steps, args.warmup)
-        S, U, V, info, sw = (x.cpu().numpy() for x in out)
-        res[mode] = (wall, ms, S, info, sw)
-    best = min(res, key=lambda k: res[k][0])
-    wall, ms, S, info, sw = res[best]
-    # the block Jacobi's work (on A, or on R^T after QR) plus, after QR, the
-    # QR and the application of Q
+    for name, kw in modes.items():
+        wall, ms, out = timed_calls(lambda: svdb.svd(Ag, **kw), steps, warmup)
+        S, info, sw = out[0].cpu().numpy(), out[3].cpu().numpy(), out[4].cpu().numpy()
+        res[name] = {"svds_per_s": batch / wall, "ms": wall * 1e3, "event_ms": ms,
+                     "sweeps_mean": float(np.mean(sw)), "sweeps_hist": sweep_histogram(sw),
+                     "not_converged": int(np.sum(info != 0)),
+                     "sigma_rel_err_vs_oracle_sample":
+                         float(np.max(np.abs(S[pick] - Sr) / Sr[:, :1])),
+                     "_sw": sw}
+    best = max(res, key=lambda n_: res[n_]["svds_per_s"])
+    # block-method work on the iteration's own matrix (A or R2^T) over the
+    # sweeps executed, plus the two QRs and the two applications of Q
+    sw = res[best].pop("_sw")
     fl = flops_blocked(256, 256, 16, sw)
-    if best == 2:
-        fl += len(sw) * (2.0 * 256 ** 2 * (256 - 256 / 3.0) + 2.0 * 256 ** 2 * 256)
-    achieved = fl / (ms * 1e-3)
-    cpu = None
-    sig_err = None
-    if args.cpu_sample > 0:
-        import oracle
-        k = max(2, min(args.cpu_sample // 50, 40))
-        pick = np.r_[0:k // 2, half:half + k - k // 2]
-        t0 = time.perf_counter()
-        Sr, _, _, swr, infor = oracle.gesvj_batch(grp.A[pick])
-        t_cpu = time.perf_counter() - t0
-        cpu = {"value": len(pick) / t_cpu, "unit": "SVDs/s", "cores": oracle.num_threads(),
-               "kind": "oracle", "sample": f"{len(pick)} matrices (half per kappa), FP64 "
-                                           f"row-cyclic one-sided Jacobi, OpenMP over the batch",
-               "seconds": t_cpu, **host_cpu()}
-        sig_err = {p: float(np.max(np.abs(res[p][2][pick] - Sr) / Sr[:, :1])) for p in res}
+    if best == "qr+fp64":
+        fl += len(sw) * (2 * (4.0 * 256 ** 3 / 3.0) + 2.0 * 256 ** 3 + 2.0 * 256 ** 3)
+    for r in res.values():
+        r.pop("_sw", None)
+    achieved = fl / (res[best]["event_ms"] * 1e-3)
+    return {
+        "workload": f"{batch} FP64 256x256, geometric spectrum, half kappa 1e2, half 1e8 "
+                    f"(Haar factors)",
+        "value": res[best]["svds_per_s"], "unit": "SVDs/s", "best_mode": best, "modes": res,
+        "mixed_vs_fp64": res["fp32+fp64"]["svds_per_s"] / res["fp64"]["svds_per_s"],
+        "roofline": {"bound": "mfma", "achieved": achieved / 1e12, "peak": 78.6,
+                     "unit": "TFLOP/s", "frac": achieved / 78.6e12, "traffic": None,
+                     "kernel": f"{best} call (block method dominant)",
+                     "kernel_ms": res[best]["event_ms"], "flops_per_call": fl},
+        "cpu_baseline": {"value": len(pick) / t_cpu, "unit": "SVDs/s", "cores": thr,
+                         "kind": "oracle",
+                         "sample": f"{len(pick)} matrices (half per kappa), FP64 row-cyclic "
+                                   f"one-sided Jacobi, one matrix per host thread",
+                         "seconds": t_cpu, "oracle_sweeps_mean": float(np.mean(swr)),
+                         **host_cpu()},
+    }
+
+
+def square256_main(args, dev):
+    from workloads import gen
+    grp = gen.square256(batch=4000, workers=min(16, os.cpu_count() or 1))[0]
+    leg = square256_leg(dev, grp, args.steps, args.warmup, max(2, args.cpu_sample // 125))
     line = {
         "metric": "SVDs/sec, 256 x 256 FP64: all-FP64, FP32 sweeps + FP64 refinement, QR + "
                   "Jacobi on R^T",
-        "value": batch / res[best][0], "unit": "SVDs/s", "n_gpus": 1, "steps": args.steps,
-        "warmup": args.warmup, "ms_per_step": res[best][0] * 1e3, "higher_is_better": True,
-        "scaling": "weak", "vs_baseline": None, "dtype": "f64", "data": "synthetic",
-        "config": {"workload": f"{batch} FP64 256x256, geometric spectrum, half kappa 1e2 "
-                               f"half 1e8 (Haar factors); block method nb 16",
-                   "best_mode": {0: "fp64", 1: "fp32+fp64", 2: "qr+fp64"}[best],
-                   **{name: {"svds_per_s": batch / res[k][0],
-                             "sweeps_mean": float(np.mean(res[k][4])),
-                             "sweeps_hist": sweep_histogram(res[k][4]),
-                             "not_converged": int(np.sum(res[k][3] != 0))}
-                      for k, name in enumerate(("fp64", "fp32+fp64", "qr+fp64"))},
-                   "sigma_rel_err_vs_oracle_sample": sig_err},
-        "roofline": {"bound": "mfma", "achieved": achieved / 1e12, "peak": 78.6, "unit": "TFLOP/s",
-                     "frac": achieved / 78.6e12, "traffic": None,
-                     "kernel": "best mode's whole call (blk_iter dominant)", "kernel_ms": ms,
-                     "flops_per_call": fl},
-        "cpu_baseline": cpu,
+        "value": leg["value"], "unit": "SVDs/s", "n_gpus": 1, "steps": args.steps,
+        "warmup": args.warmup, "ms_per_step": leg["modes"][leg["best_mode"]]["ms"],
+        "higher_is_better": True, "scaling": "weak", "vs_baseline": None, "dtype": "f64",
+        "data": "synthetic",
+        "config": {k: v for k, v in leg.items() if k not in ("roofline", "cpu_baseline")},
+        "roofline": leg["roofline"], "cpu_baseline": leg["cpu_baseline"],
     }
     print(json.dumps(line), flush=True)
 
 
-def uneven_main(args, dev):
-    """20000 complex128 matrices, n ~ U{8..256}, m ~ U{n..2n}, complex
-    Gaussian entries, in one svdb_svd_batched call."""
+def flops_unblocked_cx(m, n, sweeps, cf):
+    """Alg. 2 work (as flops_unblocked) times the flop factor cf (4 for
+    complex data)."""
+    return cf * flops_unblocked(m, n, sweeps)
+
+
+def uneven_leg(dev, groups, steps=2, warmup=1, cpu_sample=16):
+    """configs: 20000 complex128 matrices, n ~ U{8..256}, m ~ U{n..2n},
+    complex Gaussian entries, in one svdb_svd_batched call (one persistent
+    launch over every shape)."""
     import torch
     from paper_2601_17979_amd import svdb
-    from workloads import gen
-    batch = args.batch if args.batch != 10000 else 20000
-    groups = gen.uneven_complex(batch=batch)
     mats = [svdb.col_major(torch.from_numpy(g.A).to(dev)) for g in groups]
     flat = [x[k] for x in mats for k in range(x.shape[0])]
-    call = svdb.BatchedCall(flat)
-    wall, ms, out = timed_calls(call, args.steps, args.warmup)
-    info, sw = out[3].cpu().numpy(), out[4].cpu().numpy()
     shapes = [(g.m, g.n) for g in groups for _ in range(g.A.shape[0])]
-    fl = sum(flops_blocked(m, n, 16, [s], cf=4) for (m, n), s in zip(shapes, sw))
+    host = [g.A[k] for g in groups for k in range(g.A.shape[0])]
+    call = svdb.BatchedCall(flat)
+    wall, ms, out = timed_calls(call, steps, warmup)
+    info, sw = out[3].cpu().numpy(), out[4].cpu().numpy()
+    pick = np.linspace(0, len(flat) - 1, cpu_sample).astype(int)
+    Sr, swr, t_cpu, thr = oracle_each([host[i] for i in pick])
+    err = max(float(np.max(np.abs(out[0][i].cpu().numpy() - s) / s[0])) for i, s in zip(pick, Sr))
+    # work as in the roofline rule: Alg. 2 on the real shape (complex flops),
+    # over the oracle's sweeps; the oracle ran on a sample, so the GPU's
+    # sweep counts are scaled by the sample's oracle / GPU sweep ratio
+    ratio = float(np.sum(swr) / max(np.sum(sw[pick]), 1))
+    fl = sum(flops_unblocked_cx(m, n, [s * ratio], 4) for (m, n), s in zip(shapes, sw))
     achieved = fl / (ms * 1e-3)
-    cpu = None
-    if args.cpu_sample > 0:
-        import oracle
-        pick = list(range(0, len(flat), max(1, len(flat) // 12)))[:12]
-        As = [groups_A for groups_A in (g.A[k] for g in groups for k in range(g.A.shape[0]))]
-        t0 = time.perf_counter()
-        for k in pick:
-            oracle.gesvj(As[k])
-        t_cpu = time.perf_counter() - t0
-        cpu = {"value": len(pick) / t_cpu, "unit": "SVDs/s", "cores": 1, "kind": "oracle",
-               "sample": f"{len(pick)} evenly spaced matrices, one at a time", "seconds": t_cpu,
-               **host_cpu()}
+    return {
+        "workload": f"{len(flat)} complex128, n ~ U{{8..256}}, m ~ U{{n..2n}}, complex Gaussian "
+                    f"entries; {len(groups)} distinct shapes, one svdb_svd_batched call",
+        "value": len(flat) / wall, "unit": "SVDs/s", "ms": wall * 1e3, "event_ms": ms,
+        "not_converged": int(np.sum(info != 0)), "sweeps_mean": float(np.mean(sw)),
+        "sweeps_hist": sweep_histogram(sw),
+        "sigma_rel_err_vs_oracle_sample": err,
+        "roofline": {"bound": "alu", "achieved": achieved / 1e12, "peak": FP64_VALU_PEAK / 1e12,
+                     "unit": "TFLOP/s", "frac": achieved / FP64_VALU_PEAK, "traffic": None,
+                     "kernel": "whole call (vb_persist dominant); work = Alg. 2 on the real "
+                               "shapes over the oracle's sweeps",
+                     "kernel_ms": ms, "flops_per_call": fl,
+                     "oracle_sweeps_per_gpu_sweep": ratio},
+        "cpu_baseline": {"value": len(pick) / t_cpu, "unit": "SVDs/s", "cores": thr,
+                         "kind": "oracle",
+                         "sample": f"{len(pick)} evenly spaced matrices, complex128 row-cyclic "
+                                   f"one-sided Jacobi, one matrix per host thread",
+                         "seconds": t_cpu, **host_cpu()},
+    }
+
+
+def uneven_main(args, dev):
+    from workloads import gen
+    groups = gen.uneven_complex(batch=20000, workers=min(16, os.cpu_count() or 1))
+    leg = uneven_leg(dev, groups, args.steps, args.warmup)
     line = {
         "metric": "SVDs/sec, uneven complex128 batch in one call",
-        "value": len(flat) / wall, "unit": "SVDs/s", "n_gpus": 1, "steps": args.steps,
-        "warmup": args.warmup, "ms_per_step": wall * 1e3, "higher_is_better": True,
+        "value": leg["value"], "unit": "SVDs/s", "n_gpus": 1, "steps": args.steps,
+        "warmup": args.warmup, "ms_per_step": leg["ms"], "higher_is_better": True,
         "scaling": "weak", "vs_baseline": None, "dtype": "c128", "data": "synthetic",
-        "config": {"workload": f"{len(flat)} complex128, n ~ U{{8..256}}, m ~ U{{n..2n}}, "
-                               f"complex Gaussian entries; {len(groups)} distinct shapes",
-                   "not_converged": int(np.sum(info != 0)),
-                   "sweeps_mean": float(np.mean(sw)), "sweeps_hist": sweep_histogram(sw)},
-        "roofline": {"bound": "mfma", "achieved": achieved / 1e12, "peak": 78.6, "unit": "TFLOP/s",
-                     "frac": achieved / 78.6e12, "traffic": None,
-                     "kernel": "vb_iter (whole call)", "kernel_ms": ms, "flops_per_call": fl},
-        "cpu_baseline": cpu,
+        "config": {k: v for k, v in leg.items() if k not in ("roofline", "cpu_baseline")},
+        "roofline": leg["roofline"], "cpu_baseline": leg["cpu_baseline"],
     }
     print(json.dumps(line), flush=True)
 
@@ -358,21 +442,38 @@ def main():
                          "server default) or 1 on, 0 off")
     ap.add_argument("--serve-load", type=float, default=0.5,
                     help="offered load as a fraction of the measured saturation rate")
-    ap.add_argument("--workload", default="mixed", choices=["mixed", "square256", "uneven", "tallskinny"],
+    ap.add_argument("--workload", default="mixed",
+                    choices=["mixed", "square256", "uneven", "tallskinny", "serve"],
                     help="mixed: the headline workload (default); square256: 4000 FP64 "
                          "256 x 256, all-FP64 and mixed precision; uneven: 20000 complex128 "
-                         "of random shapes in one svdb_svd_batched call")
+                         "of random shapes in one svdb_svd_batched call; serve: the "
+                         "serving rate sweep (0.25 ... 1.2 x saturation)")
     ap.add_argument("--copy-bytes", type=int, default=0,
                     help="only run one device-to-device copy of this many bytes (used to "
                          "calibrate the FETCH_SIZE / WRITE_SIZE counters) and exit")
+    ap.add_argument("--no-extras", action="store_true",
+                    help="skip the extra keys of the default line: the 256 x 256 precision "
+                         "workload and the uneven complex128 workload (each timed with one "
+                         "warm-up and two timed calls), and the blocked nb = 8 / 16 runs of "
+                         "the headline workload")
+    ap.add_argument("--serve-after-oracle", action="store_true",
+                    help="run the serving leg after the CPU oracle instead of before it")
     args = ap.parse_args()
     if args.gpus != 1:
         print(json.dumps({"error": "this build runs on one GPU; --gpus must be 1"}))
         sys.exit(2)
 
+    from workloads import gen
+    # inputs of the default line's extra keys, drawn in worker processes
+    # before this process touches the GPU
+    workers = min(16, os.cpu_count() or 1)
+    extras = None
+    if args.workload == "mixed" and not args.no_extras and not args.copy_bytes:
+        extras = (gen.square256(batch=4000, workers=workers)[0],
+                  gen.uneven_complex(batch=20000, workers=workers))
+
     import torch
     from paper_2601_17979_amd import svdb
-    from workloads import gen
 
     dev = torch.device("cuda:0")
     if args.copy_bytes:
@@ -389,6 +490,8 @@ def main():
         return tallskinny_main(args, dev)
     if args.workload == "uneven":
         return uneven_main(args, dev)
+    if args.workload == "serve":
+        return serve_main(args, dev)
     groups = gen.mixed_64_128x32(batch=args.batch)
     total = sum(g.A.shape[0] for g in groups)
     stream = torch.cuda.current_stream(dev)
@@ -515,15 +618,34 @@ def main():
 
     # the plain GPU Jacobi on the same workload (the comparator of the metric)
     plain = None
+    plain_S = None
     if args.path != "plain" and not args.no_plain:
-        _, wall_p, per_p, _ = timed("plain", max(1, args.steps // 2), 1)
+        work_p, wall_p, per_p, _ = timed("plain", max(1, args.steps // 2), 1)
         plain = {"value": total * max(1, args.steps // 2) / wall_p, "unit": "SVDs/s",
                  "ms_per_step": wall_p / max(1, args.steps // 2) * 1e3,
                  "kernel_ms": [float(x) for x in per_p]}
+        plain_S = [out[0].cpu().numpy() for g, Ag, out in work_p]
 
-    # the serving leg runs before the oracle, whose OpenMP worker threads may
-    # keep host cores busy after it returns
-    serve = serve_leg(args, dev) if args.serve_seconds > 0 else None
+    # the block method on the same workload with nb = 8 and nb = 16 (no QR)
+    blocked = {}
+    blocked_S = {}
+    if extras is not None:
+        for nb_ in (8, 16):
+            def run_nb(nb_=nb_):
+                return [svdb.svd(Ag, path="blocked", nb=nb_, precondition=0, out=out)
+                        for g, Ag, out in work]
+            wall_b, ms_b, outs = timed_calls(run_nb, 2, 1)
+            blocked[f"nb{nb_}"] = {"value": total / wall_b, "unit": "SVDs/s",
+                                   "ms_per_step": wall_b * 1e3,
+                                   "not_converged": int(sum(int((o[3] != 0).sum()) for o in outs)),
+                                   "sweeps_mean": {f"{g.m}x{g.n}": float(o[4].double().mean())
+                                                   for (g, _, _), o in zip(work, outs)}}
+            blocked_S[f"nb{nb_}"] = [o[0].cpu().numpy() for o in outs]
+
+    def serve_now():
+        return serve_leg(args, dev) if args.serve_seconds > 0 else None
+    # by default the serving leg runs before the CPU oracle
+    serve = None if args.serve_after_oracle else serve_now()
 
     # accuracy vs the FP64 oracle and the CPU baseline on a bounded sample
     cpu = None
@@ -531,7 +653,9 @@ def main():
     if args.cpu_sample > 0:
         import oracle
         t_cpu, n_cpu, errs, sw_ratio = 0.0, 0, [], []
-        for g, S, U, V, info, sw in results:
+        perr = []
+        berr = {k: [] for k in blocked_S}
+        for gi, (g, S, U, V, info, sw) in enumerate(results):
             b = g.A.shape[0]
             idx = np.linspace(0, b - 1, min(args.cpu_sample, b)).astype(int)
             t0 = time.perf_counter()
@@ -539,7 +663,15 @@ def main():
             t_cpu += time.perf_counter() - t0
             n_cpu += len(idx)
             errs.append(float(np.max(np.abs(S[idx] - Sr) / Sr[:, :1])))
+            if plain_S is not None:
+                perr.append(float(np.max(np.abs(plain_S[gi][idx] - Sr) / Sr[:, :1])))
+            for k in blocked_S:
+                berr[k].append(float(np.max(np.abs(blocked_S[k][gi][idx] - Sr) / Sr[:, :1])))
             sw_ratio.append(float(np.sum(swr) / max(np.sum(sw[idx]), 1)))
+        if plain is not None and perr:
+            plain["sigma_rel_err_vs_oracle_sample"] = max(perr)
+        for k in blocked:
+            blocked[k]["sigma_rel_err_vs_oracle_sample"] = max(berr[k])
         cpu = {"value": n_cpu / t_cpu, "unit": "SVDs/s", "cores": oracle.num_threads(),
                "kind": "oracle",
                "sample": f"{n_cpu} matrices ({args.cpu_sample} evenly spaced per shape, both "
@@ -547,7 +679,13 @@ def main():
                          f"the batch", "seconds": t_cpu,
                "oracle_sweeps_per_gpu_sweep": sw_ratio, **host_cpu()}
         sig_err = max(errs)
+    if serve is None:
+        serve = serve_now()
 
+    square = uneven = None
+    if extras is not None:
+        square = square256_leg(dev, extras[0])
+        uneven = uneven_leg(dev, extras[1])
 
     line = {
         "metric": METRIC, "value": value, "unit": "SVDs/s", "n_gpus": 1, "steps": args.steps,
@@ -562,10 +700,13 @@ def main():
                                  zip(results, per_kernel)}},
         "plain_gpu_jacobi": plain,
         "resident_without_qr": noqr,
+        "blocked_without_qr": blocked or None,
         "speedup_vs_plain": (value / plain["value"]) if plain else 1.0,
         "roofline": roofline,
         "cpu_baseline": cpu,
         "serve": serve,
+        "square256": square,
+        "uneven_complex128": uneven,
     }
     print(json.dumps(line), flush=True)
 

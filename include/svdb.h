@@ -31,7 +31,10 @@
  *    failure of the calling thread.
  *  - Per-matrix status info[b]: 0 converged; 1 not converged within
  *    max_sweeps (outputs hold the last iterate, finalised); 2 non-finite
- *    entry in A (outputs untouched).
+ *    entry in A (outputs untouched); 3 the persistent launch of the block
+ *    method was stopped by its device-side watchdog (a grid barrier that
+ *    waited more than 20 s; outputs as for 1; not expected to occur, and
+ *    reported instead of hanging the device).
  *  - `tol` is the rotation threshold k*u of Alg. 2: the pair (i, j) is
  *    rotated iff g_ij != 0 and |g_ij| >= tol * sqrt(g_ii) * sqrt(g_jj).
  *    tol <= 0 selects 30 u of the working precision (the paper's k = 30,
@@ -73,7 +76,8 @@ typedef enum {
 typedef struct {
     int max_sweeps;   /* cap on sweeps (Alg. 2 max_nsweeps); <= 0 -> 100       */
     int path;         /* svdb_path_t                                          */
-    int nb;           /* block width for SVDB_PATH_BLOCKED; 0 -> tuned         */
+    int nb;           /* block width for SVDB_PATH_BLOCKED: 8, 16 or 32 (real), 16
+                         (complex); 0 -> tuned                                */
     int masking;      /* blocked path: skip converged matrices ("Masked
                          Batch Operations");
                          < 0 -> default (on)                                   */
@@ -108,10 +112,30 @@ typedef struct {
                          or three (FP32); k > 0: at most k, stopping at a
                          sweep that rotates nothing; < 0: to convergence (at
                          most 100).                                          */
+    int persistent;   /* block method (BLOCKED path, uneven batches, the wide
+                         preconditioned path): 1 (default) runs every sweep
+                         of the batch in one cooperative launch, a grid
+                         barrier between round-robin iterations and the
+                         convergence test on the device, so the call never
+                         waits on the host; 0 launches one kernel per
+                         round-robin iteration and waits on the host for
+                         the count of unconverged matrices after every
+                         sweep (synchronous; the results are the same bit
+                         for bit).                                           */
+    double inner_tol_start; /* block method, persistent launches: the dynamic
+                         tolerance of the inner eigensolver ("Inexact
+                         Hermitian Eigendecomposition", subsection
+                         "Motivation", first way).  > tol: outer sweep s
+                         (from 0) solves the Gram matrices with threshold
+                         max(tol, inner_tol_start * inner_tol_rate^s), and a
+                         matrix converges only in a sweep run at tol itself;
+                         <= 0 (default): tol in every sweep.               */
+    double inner_tol_rate;  /* the shrink factor per outer sweep, in (0, 1)  */
 } svdb_opts_t;
 
 /* Fills *o with the defaults (AUTO path, 100 sweeps, masking on,
- * precondition -1, inner_sweeps 0). */
+ * precondition -1, inner_sweeps 0, persistent 1, no dynamic inner
+ * tolerance). */
 void svdb_opts_default(svdb_opts_t *o);
 
 /*

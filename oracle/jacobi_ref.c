@@ -560,6 +560,57 @@ int oracle_block_gesvj_z(int m, int n, int nb, const zc *A, int lda, double tol,
     return converged ? 0 : 1;
 }
 
+/*
+ * The block solver with the dynamic tolerance of the inner eigensolver
+ * ("Inexact Hermitian Eigendecomposition", subsection "Motivation", first
+ * way): outer sweep s (counted from 0) solves every Gram matrix with the
+ * threshold t_s = max(tol, tol_start * tol_rate^s), starting large and
+ * shrinking at a constant rate until it reaches tol.  A sweep without
+ * rotation at a threshold above tol does not mean convergence; the solver
+ * has converged when a sweep at t_s = tol applies no rotation.  With
+ * tol_start <= tol this is oracle_block_gesvj_z.  Outputs as that.
+ */
+int oracle_block_gesvj_dyn_z(int m, int n, int nb, const zc *A, int lda, double tol,
+                             int max_sweeps, int inner_sweeps, double tol_start,
+                             double tol_rate, double *S, zc *U, int ldu, zc *V, int ldv,
+                             int *sweeps_out)
+{
+    if (sweeps_out) *sweeps_out = 0;
+    if (nb < 1 || 2 * nb > 256) return -1;
+    if (!(tol_rate > 0.0 && tol_rate < 1.0) && tol_start > tol) return -1;
+    for (int j = 0; j < n; j++)
+        for (int k = 0; k < m; k++) {
+            zc a = A[(size_t)j * lda + k];
+            if (!isfinite(creal(a)) || !isfinite(cimag(a))) return 2;
+        }
+    int l = (n + nb - 1) / nb;
+    if (l & 1) l++;
+    if (l < 2) l = 2;
+    int np = l * nb;
+    zc *W = calloc((size_t)m * np + 1, sizeof(zc));
+    zc *Vw = calloc((size_t)np * np + 1, sizeof(zc));
+    for (int j = 0; j < n; j++)
+        for (int k = 0; k < m; k++) W[(size_t)j * m + k] = A[(size_t)j * lda + k];
+    for (int j = 0; j < np; j++) Vw[(size_t)j * np + j] = 1.0;
+    int converged = 0, sweeps = 0;
+    double ts = tol_start > tol ? tol_start : tol;
+    while (!converged && sweeps < max_sweeps) {
+        sweeps++;
+        long nrot = 0;
+        for (int it = 0; it < l - 1; it++)
+            nrot += oracle_block_iter_z(m, np, l, nb, W, Vw, it, ts, inner_sweeps);
+        converged = (nrot == 0 && ts <= tol);
+        ts = ts * tol_rate > tol ? ts * tol_rate : tol;
+    }
+    zc *Vn = malloc(sizeof(zc) * (size_t)n * n + 1);
+    for (int j = 0; j < n; j++)
+        for (int k = 0; k < n; k++) Vn[(size_t)j * n + k] = Vw[(size_t)j * np + k];
+    finalize_z(m, n, W, Vn, S, U, ldu, V, ldv);
+    if (sweeps_out) *sweeps_out = sweeps;
+    free(W); free(Vw); free(Vn);
+    return converged ? 0 : 1;
+}
+
 /* ------------------------------------------------------------------ */
 /* Batch drivers: OpenMP parallel for over the batch (the paper's CPU    */
 /* baseline pattern, "Comparison with Existing Batch SVD Solvers"), one matrix per thread at a time.        */

@@ -39,7 +39,12 @@ def build(force: bool = False) -> str:
 
 
 def load(path: str):
-    """Open a compiled oracle library and declare its signatures."""
+    """Open a compiled oracle library and declare its signatures.
+
+    Its OpenMP threads wait passively between parallel regions (unless the
+    caller chose otherwise): the oracle shares the host with the GPU
+    library's threads, which must not compete with spinning idle workers."""
+    os.environ.setdefault("OMP_WAIT_POLICY", "passive")
     L = C.CDLL(path)
     P, I, D, L_ = C.c_void_p, C.c_int, C.c_double, C.c_long
     L.oracle_round_robin.argtypes = [I, P]
@@ -55,6 +60,8 @@ def load(path: str):
     L.oracle_block_iter_z.restype = L_
     L.oracle_block_gesvj_z.argtypes = [I, I, I, P, I, D, I, I, P, P, I, P, I, P]
     L.oracle_block_gesvj_z.restype = I
+    L.oracle_block_gesvj_dyn_z.argtypes = [I, I, I, P, I, D, I, I, D, D, P, P, I, P, I, P]
+    L.oracle_block_gesvj_dyn_z.restype = I
     L.oracle_num_threads.restype = I
     L.oracle_set_num_threads.argtypes = [I]
     L.oracle_gesvj_strided_d.argtypes = [I, I, I, P, I, L_, D, I, I, P, L_, P, I, L_,
@@ -225,10 +232,12 @@ def block_iter(W, V, l, nb, it, tol=None, inner_sweeps=1):
                                          float(tol), int(inner_sweeps)))
 
 
-def block_gesvj(A, nb, tol=None, max_sweeps=100, inner_sweeps=1):
+def block_gesvj(A, nb, tol=None, max_sweeps=100, inner_sweeps=1, tol_start=0.0,
+                tol_rate=0.0):
     """Blocked one-sided Jacobi ("Algorithmic Background" to "Inexact Hermitian
     Eigendecomposition").  Returns (S, U, V, sweeps, info);
-    U and V are real when A is real."""
+    U and V are real when A is real.  tol_start > tol selects the dynamic
+    inner tolerance: outer sweep s uses max(tol, tol_start * tol_rate^s)."""
     A = np.asarray(A)
     m, n = A.shape
     cplx = _is_complex(A)
@@ -239,9 +248,15 @@ def block_gesvj(A, nb, tol=None, max_sweeps=100, inner_sweeps=1):
     U = np.zeros((m, n), dtype=np.complex128, order="F")
     V = np.zeros((n, n), dtype=np.complex128, order="F")
     sw = C.c_int(0)
-    info = lib().oracle_block_gesvj_z(m, n, nb, _p(Af), max(m, 1), float(tol), int(max_sweeps),
-                                      int(inner_sweeps), _p(S), _p(U), max(m, 1), _p(V),
-                                      max(n, 1), C.byref(sw))
+    if tol_start > tol:
+        info = lib().oracle_block_gesvj_dyn_z(m, n, nb, _p(Af), max(m, 1), float(tol),
+                                              int(max_sweeps), int(inner_sweeps),
+                                              float(tol_start), float(tol_rate), _p(S), _p(U),
+                                              max(m, 1), _p(V), max(n, 1), C.byref(sw))
+    else:
+        info = lib().oracle_block_gesvj_z(m, n, nb, _p(Af), max(m, 1), float(tol),
+                                          int(max_sweeps), int(inner_sweeps), _p(S), _p(U),
+                                          max(m, 1), _p(V), max(n, 1), C.byref(sw))
     if not cplx:
         U, V = U.real.copy(), V.real.copy()
     return S, U, V, sw.value, info

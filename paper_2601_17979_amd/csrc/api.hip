@@ -61,6 +61,9 @@ struct Plan {
     int path = SVDB_PATH_AUTO;
     int nb = 0;
     int threads = 0;
+    int inner = 0;              // block method: inner sweeps (0: the built-in rule)
+    double tol_start = 0.0;     // block method: dynamic inner tolerance
+    double tol_rate = 0.0;
     bool precond = false;   // QR pre-processing, resident Jacobi on R^T
     bool precond_big = false;   // QR pre-processing, block Jacobi on R^T
     bool precond_tall = false;  // QR in global memory, resident Jacobi on R^T
@@ -77,8 +80,36 @@ svdb_opts_t resolve_opts(const svdb_opts_t *o)
         if (r.masking < 0) r.masking = 1;
         if (r.waves < 0) r.waves = 0;
         if (r.inner_sweeps < -1) r.inner_sweeps = -1;
+        r.persistent = r.persistent != 0;
     }
     return r;
+}
+
+// Block width and inner solve of the block method for an m x n request of
+// this dtype: the caller's choices where given, else the measured table,
+// else the built-in rules.  Returns 0 when the width is not supported.
+int block_choice(svdb_dtype_t dt, int m, int n, const svdb_opts_t &o, Plan *p)
+{
+    const bool cx = dt == SVDB_C64 || dt == SVDB_C128;
+    svdb::BlockChoice t;
+    const bool have = svdb::tuned_block((int)dt, m, n, &t);
+    int nb = o.nb;
+    if (nb == 0 && have && svdb::blocked_nb(m, n, t.nb, cx) == t.nb) nb = t.nb;
+    nb = svdb::blocked_nb(m, n, nb, cx);
+    if (!nb) return 0;
+    p->nb = nb;
+    p->inner = o.inner_sweeps;
+    p->tol_start = o.inner_tol_start;
+    p->tol_rate = o.inner_tol_rate;
+    // the table's inner solve was measured with its own width
+    if (o.inner_sweeps == 0 && have && nb == t.nb) {
+        p->inner = t.inner;
+        if (o.inner_tol_start <= 0.0 && o.persistent && t.tol_start > 0.0) {
+            p->tol_start = t.tol_start;
+            p->tol_rate = t.tol_rate;
+        }
+    }
+    return nb;
 }
 
 bool plain_fits(int m, int n)
@@ -94,6 +125,13 @@ int make_plan(svdb_dtype_t dt, int m, int n, const svdb_opts_t &o, Plan *p)
         return fail(SVDB_ERR_UNSUPPORTED, "precision mode 1 needs SVDB_R64 input");
     if (o.precondition < -1 || o.precondition > 1)
         return fail(SVDB_ERR_UNSUPPORTED, "precondition must be -1, 0 or 1");
+    if (o.inner_tol_start > 0.0) {
+        if (!(o.inner_tol_rate > 0.0 && o.inner_tol_rate < 1.0) || !isfinite(o.inner_tol_start))
+            return fail(SVDB_ERR_UNSUPPORTED, "dynamic inner tolerance: rate must be in (0, 1)");
+        if (!o.persistent)
+            return fail(SVDB_ERR_UNSUPPORTED,
+                        "the dynamic inner tolerance runs in the persistent launches only");
+    }
     int path = o.path;
     int rN = 0, rR = 0, rW = 0;
     // QR preconditioning of real matrices (FP32 input runs it in FP64): AUTO
@@ -135,8 +173,9 @@ int make_plan(svdb_dtype_t dt, int m, int n, const svdb_opts_t &o, Plan *p)
     const bool pcb_req = (path == SVDB_PATH_AUTO && o.precondition != 0) ||
                          (path == SVDB_PATH_BLOCKED && o.precondition == 1);
     if (pcb_req && pcb_ok) {
-        const int nb = svdb::blocked_nb(n, n, o.nb, false);
-        if (!nb) return fail(SVDB_ERR_UNSUPPORTED, "blocked path: nb must be 16 or 32");
+        // the block method runs on the n x n FP64 factor R2^T
+        const int nb = block_choice(SVDB_R64, n, n, o, p);
+        if (!nb) return fail(SVDB_ERR_UNSUPPORTED, "blocked path: nb must be 8, 16 or 32");
         p->path = SVDB_PATH_BLOCKED;
         p->nb = nb;
         p->threads = 256;
@@ -152,10 +191,11 @@ int make_plan(svdb_dtype_t dt, int m, int n, const svdb_opts_t &o, Plan *p)
     if (path == SVDB_PATH_AUTO) path = res_ok ? SVDB_PATH_RESIDENT : SVDB_PATH_BLOCKED;
     if (path == SVDB_PATH_BLOCKED) {
         const bool cx = dt == SVDB_C64 || dt == SVDB_C128;
-        const int nb = svdb::blocked_nb(m, n, o.nb, cx);
+        // the mixed mode takes the choices measured for FP64 input
+        const int nb = block_choice(o.precision == 1 ? SVDB_R64 : dt, m, n, o, p);
         if (!nb)
             return fail(SVDB_ERR_UNSUPPORTED, cx ? "blocked path: complex needs nb = 16"
-                                                 : "blocked path: nb must be 16 or 32");
+                                                 : "blocked path: nb must be 8, 16 or 32");
         if (n < 1) return fail(SVDB_ERR_UNSUPPORTED, "blocked path: n must be >= 1");
         p->path = SVDB_PATH_BLOCKED;
         p->nb = nb;
@@ -199,6 +239,9 @@ void svdb_opts_default(svdb_opts_t *o)
     o->waves = 0;
     o->precondition = -1;
     o->inner_sweeps = 0;
+    o->persistent = 1;
+    o->inner_tol_start = 0.0;
+    o->inner_tol_rate = 0.0;
 }
 
 const char *svdb_last_error(void) { return g_err.c_str(); }
@@ -223,6 +266,7 @@ int svdb_plan(svdb_dtype_t dtype, int m, int n, const svdb_opts_t *opts, int *pa
 size_t svdb_workspace_size(svdb_dtype_t dtype, int batch, int m, int n, const svdb_opts_t *opts)
 {
     if (batch < 0 || m < 0 || n < 0) return (size_t)-1;
+    if (m == 0 || n == 0) return 0;   // nothing to factor
     if (n > m) {   // A^H (n x m) in the workspace, then the tall call's own
         const size_t tall = svdb_workspace_size(dtype, batch, n, m, opts);
         if (tall == (size_t)-1) return tall;
@@ -287,7 +331,8 @@ hipError_t run_tall(svdb_dtype_t dtype, const Plan &p, const svdb_opts_t &o, int
         e = svdb::launch_precond_big_d(batch, m, n, p.nb, (const double *)A, lda, strideA,
                                        (double *)S, strideS, (double *)U, ldu, strideU,
                                        (double *)V, ldv, strideV, tol, o.max_sweeps, o.masking,
-                                       info, o.sweeps, workspace, s);
+                                       info, o.sweeps, workspace, s, p.inner, o.persistent,
+                                       p.tol_start, p.tol_rate);
     } else if (p.precond) {
         e = svdb::launch_precond_d(batch, m, n, o.waves, (const double *)A, lda, strideA,
                                    (double *)S, strideS, (double *)U, ldu, strideU, (double *)V,
@@ -301,27 +346,32 @@ hipError_t run_tall(svdb_dtype_t dtype, const Plan &p, const svdb_opts_t &o, int
         e = svdb::launch_blocked_s(batch, m, n, p.nb, (const float *)A, lda, strideA, (float *)S,
                                    strideS, (float *)U, ldu, strideU, (float *)V, ldv, strideV,
                                    tol, o.max_sweeps, o.masking, info, o.sweeps, workspace, s,
-                                   o.inner_sweeps);
+                                   p.inner, o.persistent,
+                                   p.tol_start, p.tol_rate);
     } else if (p.path == SVDB_PATH_BLOCKED && dtype == SVDB_C128) {
         e = svdb::launch_blocked_z(batch, m, n, p.nb, A, lda, strideA, (double *)S, strideS, U,
                                    ldu, strideU, V, ldv, strideV, tol, o.max_sweeps, o.masking,
-                                   info, o.sweeps, workspace, s, o.inner_sweeps);
+                                   info, o.sweeps, workspace, s, p.inner, o.persistent,
+                                   p.tol_start, p.tol_rate);
     } else if (p.path == SVDB_PATH_BLOCKED && dtype == SVDB_C64) {
         e = svdb::launch_blocked_c(batch, m, n, p.nb, A, lda, strideA, (float *)S, strideS, U,
                                    ldu, strideU, V, ldv, strideV, tol, o.max_sweeps, o.masking,
-                                   info, o.sweeps, workspace, s, o.inner_sweeps);
+                                   info, o.sweeps, workspace, s, p.inner, o.persistent,
+                                   p.tol_start, p.tol_rate);
     } else if (p.path == SVDB_PATH_BLOCKED && o.precision == 1) {
         const double tol32 = fmax(tol, default_tol(SVDB_R32));
         e = svdb::launch_blocked_mixed_d(batch, m, n, p.nb, (const double *)A, lda, strideA,
                                          (double *)S, strideS, (double *)U, ldu, strideU,
                                          (double *)V, ldv, strideV, tol, tol32, o.max_sweeps,
                                          o.masking, info, o.sweeps, workspace, s,
-                                         o.inner_sweeps);
+                                         p.inner, o.persistent,
+                                   p.tol_start, p.tol_rate);
     } else if (p.path == SVDB_PATH_BLOCKED) {
         e = svdb::launch_blocked_d(batch, m, n, p.nb, (const double *)A, lda, strideA,
                                    (double *)S, strideS, (double *)U, ldu, strideU, (double *)V,
                                    ldv, strideV, tol, o.max_sweeps, o.masking, info, o.sweeps,
-                                   workspace, s, o.inner_sweeps);
+                                   workspace, s, p.inner, o.persistent,
+                                   p.tol_start, p.tol_rate);
     } else if (p.path == SVDB_PATH_PLAIN) {
         e = svdb::launch_plain_d(batch, m, n, (const double *)A, lda, strideA, (double *)S,
                                  strideS, (double *)U, ldu, strideU, (double *)V, ldv, strideV,
@@ -347,20 +397,27 @@ int svdb_svd_strided_batched(svdb_dtype_t dtype, int batch, int m, int n, const 
     const bool empty = (batch == 0 || k == 0);
     if (!A && !empty) return fail(-5, "A is NULL");
     if (lda < (m > 1 ? m : 1)) return fail(-6, "lda < max(1, m)");
-    if (batch > 1 && strideA < (long long)lda * n) return fail(-7, "strideA < lda * n");
+    if (batch > 1 && !empty && strideA < (long long)lda * n) return fail(-7, "strideA < lda * n");
     if (!S && !empty) return fail(-8, "S is NULL");
-    if (batch > 1 && strideS < k) return fail(-9, "strideS < min(m, n)");
+    if (batch > 1 && !empty && strideS < k) return fail(-9, "strideS < min(m, n)");
     if (U) {
         if (ldu < (m > 1 ? m : 1)) return fail(-11, "ldu < max(1, m)");
-        if (batch > 1 && strideU < (long long)ldu * k) return fail(-12, "strideU < ldu * min(m, n)");
+        if (batch > 1 && !empty && strideU < (long long)ldu * k) return fail(-12, "strideU < ldu * min(m, n)");
     }
     if (V) {
         if (ldv < (n > 1 ? n : 1)) return fail(-14, "ldv < max(1, n)");
-        if (batch > 1 && strideV < (long long)ldv * k) return fail(-15, "strideV < ldv * min(m, n)");
+        if (batch > 1 && !empty && strideV < (long long)ldv * k) return fail(-15, "strideV < ldv * min(m, n)");
     }
     if (!isfinite(tol)) return fail(-16, "tol is not finite");
     if (!info && batch > 0) return fail(-17, "info is NULL");
     svdb_opts_t o = resolve_opts(opts);
+    if (empty) {
+        // no singular values: every matrix is trivially converged
+        if (batch == 0) return 0;
+        hipError_t e = svdb::launch_fill_int(info, batch, 0, (hipStream_t)stream);
+        if (e == hipSuccess) e = svdb::launch_fill_int(o.sweeps, batch, 0, (hipStream_t)stream);
+        return e == hipSuccess ? 0 : hip_fail(e, "launch");
+    }
     const bool wide = n > m;
     Plan p;
     int rc = wide ? make_plan(dtype, n, m, o, &p) : make_plan(dtype, m, n, o, &p);
@@ -438,6 +495,10 @@ int svdb_svd_batched(svdb_dtype_t dtype, int batch, const int *m, const int *n,
     svdb_opts_t o = resolve_opts(opts);
     if (o.precision != 0)
         return fail(SVDB_ERR_UNSUPPORTED, "uneven batches run in the working precision only");
+    if (o.inner_tol_start > 0.0 &&
+        (!(o.inner_tol_rate > 0.0 && o.inner_tol_rate < 1.0) || !o.persistent))
+        return fail(SVDB_ERR_UNSUPPORTED,
+                    "dynamic inner tolerance: rate in (0, 1) and persistent launches");
     const size_t need = svdb_batched_workspace_size(dtype, batch, m, n, &o);
     if (!workspace || ws_bytes < need)
         return fail(-14, "workspace too small: need %zu bytes", need);
@@ -461,7 +522,8 @@ int svdb_svd_batched(svdb_dtype_t dtype, int batch, const int *m, const int *n,
     hipError_t e = svdb::launch_vbatched((int)dtype, batch, mt.data(), nt.data(), A, lda, S,
                                          Ut.data(), ldut.data(), Vt.data(), ldvt.data(), tol,
                                          o.max_sweeps, o.masking, info, o.sweeps, workspace,
-                                         (hipStream_t)stream, tr.data(), o.inner_sweeps);
+                                         (hipStream_t)stream, tr.data(), o.inner_sweeps,
+                                         o.persistent, o.inner_tol_start, o.inner_tol_rate);
     if (e != hipSuccess) return hip_fail(e, "launch");
     return 0;
 }

@@ -29,7 +29,10 @@
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
+#include <map>
+#include <mutex>
 #include <type_traits>
+#include <utility>
 #include <vector>
 
 #include "device_common.hpp"
@@ -719,6 +722,186 @@ __global__ void blk_rearm(int batch, BlkState *st, int *sweeps32)
     state_reset(st[b], st[b].bad);
 }
 
+// ---------------------------------------------------------------------------
+// Sweep control on the device.  One cooperative launch (every workgroup
+// resident) runs all the sweeps of a batch: a phase is one round-robin
+// iteration, whose (matrix, block pair) items the workgroups claim from a
+// counter, largest matrices first; a grid barrier ends the phase, the
+// matrices whose sweep ends there are closed (converged, capped or still
+// sweeping), another barrier publishes that, and the launch ends once no
+// matrix is still sweeping.  The host never waits, so the whole call stays
+// asynchronous on its stream.  The barrier waits are bounded by a watchdog
+// on the device's wall clock: if it ever fires, every workgroup leaves and
+// the unfinished matrices report info 3.
+// ---------------------------------------------------------------------------
+struct PersistCtl {
+    unsigned bar;     // grid-barrier arrivals (monotonic within a launch)
+    int remaining;    // matrices still sweeping
+    int next[2];      // item counters of even and odd phases
+    int abort;        // the watchdog fired (kept across the launches of a call)
+    int pad[3];
+};
+constexpr int kCtlInts = (int)(sizeof(PersistCtl) / sizeof(int));
+constexpr int kCtlLaunchInts = 4;   // the fields a launch starts from zero
+
+// Grid barrier over the workgroups of a cooperative launch; `target` is the
+// arrival count that completes it.  Returns false if the watchdog fired.
+__device__ bool grid_sync(PersistCtl *ctl, unsigned target, long long limit)
+{
+    __shared__ int s_ok;
+    __threadfence();   // release: this workgroup's writes, at device scope
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        __hip_atomic_fetch_add(&ctl->bar, 1u, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_AGENT);
+        const long long t0 = wall_clock64();
+        int ok = 1;
+        while (__hip_atomic_load(&ctl->bar, __ATOMIC_ACQUIRE, __HIP_MEMORY_SCOPE_AGENT) < target) {
+            if (__hip_atomic_load(&ctl->abort, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT)) {
+                ok = 0;
+                break;
+            }
+            if (wall_clock64() - t0 > limit) {
+                __hip_atomic_store(&ctl->abort, 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+                ok = 0;
+                break;
+            }
+            __builtin_amdgcn_s_sleep(2);
+        }
+        s_ok = ok;
+    }
+    __syncthreads();
+    __threadfence();   // acquire: the other workgroups' writes
+    return s_ok != 0;
+}
+
+// Threshold of the inner eigensolver in outer sweep s (counted from 0) with
+// the dynamic tolerance of "Inexact Hermitian Eigendecomposition"
+// (subsection "Motivation", first way): tol_start shrinks by tol_rate per
+// sweep until it reaches tol; tol_start <= tol keeps tol throughout.  The
+// products are formed one sweep at a time, as the sequence is defined.
+__device__ __forceinline__ double inner_tol(double tol, double t0, double rate, int s)
+{
+    if (!(t0 > tol)) return tol;
+    double ts = t0;
+    for (int k = 0; k < s; k++) ts = ts * rate > tol ? ts * rate : tol;
+    return ts;
+}
+
+// End of a sweep of one matrix: a sweep without rotation converges it
+// (`phase32`, the FP32 phase of the mixed mode: so does a largest pair
+// cosine of at most kSwitchCos); one that reaches max_sweeps stops
+// unconverged.  With masking a converged matrix is retired; without, it
+// keeps being swept until the whole batch has stopped.  Returns true when
+// the matrix stopped sweeping at this sweep end.
+// With the dynamic inner tolerance (t0 > tol) a sweep converges a matrix
+// only if it ran at the final threshold tol.
+__device__ __forceinline__ bool close_sweep(BlkState &s, int max_sweeps, int masking, int phase32,
+                                            double tol = 0.0, double t0 = 0.0, double rate = 0.0)
+{
+    if (!s.active) return false;
+    bool stopped = false;
+    if (!s.done) {
+        const bool at_tol = inner_tol(tol, t0, rate, s.sweeps) <= tol;
+        s.sweeps += 1;
+        const double mc = __longlong_as_double((long long)s.maxcos);
+        bool fin = !s.rotated && at_tol;
+        if (phase32 && mc <= kSwitchCos) fin = true;
+        s.prevcos = mc;
+        if (fin) {
+            s.done = 1;
+            stopped = true;
+        } else if (s.sweeps >= max_sweeps) {
+            s.active = 0;
+            stopped = true;
+        }
+    }
+    s.rotated = 0;
+    s.maxcos = 0ull;
+    if (masking && s.done) s.active = 0;
+    return stopped;
+}
+
+// The phase loop of a persistent launch.  item(w, itg) runs work item w of
+// phase itg (every thread of the workgroup calls it with the same w);
+// ends(itg) says whether any sweep can end at phase itg (uniform over the
+// grid); end_of(b, itg) closes matrix b's sweep if it ends there.
+template <class ItemFn, class EndsFn, class EndFn>
+__device__ void persist_loop(PersistCtl *ctl, int nitems, int count, int max_phases,
+                             long long limit, ItemFn item, EndsFn ends, EndFn end_of)
+{
+    __shared__ int s_w;
+    const unsigned G = gridDim.x;
+    unsigned nbar = 0;
+    for (int itg = 0; itg < max_phases; itg++) {
+        // the other counter was last claimed from in the previous phase,
+        // which every workgroup has left; it serves the next phase
+        if (blockIdx.x == 0 && threadIdx.x == 0)
+            __hip_atomic_store(&ctl->next[(itg + 1) & 1], 0, __ATOMIC_RELAXED,
+                               __HIP_MEMORY_SCOPE_AGENT);
+        for (;;) {
+            if (threadIdx.x == 0) s_w = atomicAdd(&ctl->next[itg & 1], 1);
+            __syncthreads();
+            const int w = s_w;
+            __syncthreads();
+            if (w >= nitems) break;
+            item(w, itg);
+        }
+        if (!grid_sync(ctl, ++nbar * G, limit)) return;
+        if (!ends(itg)) continue;
+        for (int b = blockIdx.x * blockDim.x + threadIdx.x; b < count; b += G * blockDim.x)
+            if (end_of(b, itg)) atomicSub(&ctl->remaining, 1);
+        if (!grid_sync(ctl, ++nbar * G, limit)) return;
+        if (__hip_atomic_load(&ctl->remaining, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) <= 0)
+            return;
+    }
+}
+
+// Uniform batch: matrix b's W at W + b m np, V at Vw + b np np, l block
+// columns; one item per (matrix, block pair).
+template <class T, bool CX, int NB>
+__global__ __launch_bounds__(kBT) void blk_persist(int batch, int m, int np, int l,
+                                                   typename Elem<T, CX>::type *W,
+                                                   typename Elem<T, CX>::type *Vw,
+                                                   BlkState *st, double tol, int inner,
+                                                   double t0, double rate, int max_sweeps,
+                                                   int masking, int phase32, PersistCtl *ctl,
+                                                   long long limit)
+{
+    __shared__ IterShared<T, CX, NB> s;
+    const int pairs = l / 2;
+    persist_loop(
+        ctl, batch * pairs, batch, max_sweeps * (l - 1), limit,
+        [&](int w, int itg) {
+            const int b = w / pairs, pair = w % pairs;
+            if (!st[b].active) return;
+            iter_body<T, CX, NB>(s, m, np, l, itg % (l - 1), pair, W + (size_t)b * m * np,
+                                 Vw + (size_t)b * np * np, st + b,
+                                 inner_tol(tol, t0, rate, st[b].sweeps), inner);
+        },
+        [&](int itg) { return (itg + 1) % (l - 1) == 0; },
+        [&](int b, int) {
+            return close_sweep(st[b], max_sweeps, masking, phase32, tol, t0, rate);
+        });
+}
+
+// Counts the matrices that are sweeping (at the start of a persistent launch).
+__global__ void count_active(int count, const BlkState *st, PersistCtl *ctl)
+{
+    const int b = blockIdx.x * blockDim.x + threadIdx.x;
+    if (b < count && st[b].active) atomicAdd(&ctl->remaining, 1);
+}
+
+// Unfinished matrices of a launch whose watchdog fired report info 3 (after
+// the finalisation, which wrote 0 or 1).  info: uniform batch, or NULL with
+// the descriptors' info pointers.
+__global__ void mark_aborted(int count, const BlkState *st, const PersistCtl *ctl, int *info,
+                             const VbDesc *d)
+{
+    const int b = blockIdx.x * blockDim.x + threadIdx.x;
+    if (b >= count || !ctl->abort) return;
+    if (!st[b].done && !st[b].bad) *(info ? info + b : d[b].info) = 3;
+}
+
 // sigma_c = ||w_c|| (FP64 sums, power-of-two scaling), stable descending
 // rank, U = W diag(sigma)^-1 (sigma = 0: Gram-Schmidt completion), outputs
 // permuted.  EW: working element type, EO: output element type.
@@ -992,6 +1175,45 @@ hipError_t pinned_counter(int **out)
     return hipSuccess;
 }
 
+// Resident workgroups of a kernel on the current device (its occupancy times
+// the compute units), and the watchdog limit of the persistent launches in
+// wall-clock ticks (20 s, far beyond any phase), cached per device.
+struct DeviceLimits {
+    int cus = 0;
+    long long watchdog = 0;
+};
+
+hipError_t device_limits(const void *fn, int *resident, long long *watchdog)
+{
+    static std::mutex mu;
+    static std::map<int, DeviceLimits> dev_cache;
+    static std::map<std::pair<const void *, int>, int> occ_cache;
+    int dev = 0;
+    hipError_t e = hipGetDevice(&dev);
+    if (e != hipSuccess) return e;
+    std::lock_guard<std::mutex> lk(mu);
+    auto it = dev_cache.find(dev);
+    if (it == dev_cache.end()) {
+        DeviceLimits L;
+        int khz = 0;
+        e = hipDeviceGetAttribute(&L.cus, hipDeviceAttributeMultiprocessorCount, dev);
+        if (e == hipSuccess) e = hipDeviceGetAttribute(&khz, hipDeviceAttributeWallClockRate, dev);
+        if (e != hipSuccess) return e;
+        L.watchdog = (long long)(khz > 0 ? khz : 100000) * 1000LL * 20;
+        it = dev_cache.emplace(dev, L).first;
+    }
+    auto oc = occ_cache.find({fn, dev});
+    if (oc == occ_cache.end()) {
+        int occ = 0;
+        e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&occ, fn, kBT, 0);
+        if (e != hipSuccess) return e;
+        oc = occ_cache.emplace(std::make_pair(fn, dev), occ).first;
+    }
+    *resident = oc->second * it->second.cus;
+    *watchdog = it->second.watchdog;
+    return *resident > 0 ? hipSuccess : hipErrorInvalidConfiguration;
+}
+
 template <class T, bool CX>
 void launch_iter(int nb, unsigned grid, hipStream_t stream, int m, int np, int l, int it,
                  typename Elem<T, CX>::type *W, typename Elem<T, CX>::type *Vw, BlkState *st,
@@ -1002,7 +1224,10 @@ void launch_iter(int nb, unsigned grid, hipStream_t stream, int m, int np, int l
                            it, W, Vw, st, tol, inner);
         (void)nb;
     } else {
-        if (nb == 16)
+        if (nb == 8)
+            hipLaunchKernelGGL((blk_iter<T, false, 8>), dim3(grid), dim3(kBT), 0, stream, m, np,
+                               l, it, W, Vw, st, tol, inner);
+        else if (nb == 16)
             hipLaunchKernelGGL((blk_iter<T, false, 16>), dim3(grid), dim3(kBT), 0, stream, m, np,
                                l, it, W, Vw, st, tol, inner);
         else
@@ -1011,11 +1236,15 @@ void launch_iter(int nb, unsigned grid, hipStream_t stream, int m, int np, int l
     }
 }
 
-// Sweeps until no matrix is pending or max_sweeps.
+// Sweeps with a host-side loop: one launch per round-robin iteration, and a
+// host wait for the count of pending matrices after every sweep.  Kept as
+// the per-iteration form of the block method (svdb_opts_t.persistent = 0);
+// it is synchronous.
 template <class T, bool CX>
-hipError_t run_sweeps(int batch, int m, int np, int nb, typename Elem<T, CX>::type *W,
-                      typename Elem<T, CX>::type *Vw, BlkState *st, int *pending, double tol,
-                      int max_sweeps, int masking, int phase32, int inner, hipStream_t stream)
+hipError_t run_sweeps_host(int batch, int m, int np, int nb, typename Elem<T, CX>::type *W,
+                           typename Elem<T, CX>::type *Vw, BlkState *st, int *pending,
+                           double tol, int max_sweeps, int masking, int phase32, int inner,
+                           hipStream_t stream)
 {
     const int l = np / nb;
     int *host_count;
@@ -1038,12 +1267,63 @@ hipError_t run_sweeps(int batch, int m, int np, int nb, typename Elem<T, CX>::ty
     return hipGetLastError();
 }
 
+template <class T, bool CX>
+using PersistFn = void (*)(int, int, int, int, typename Elem<T, CX>::type *,
+                           typename Elem<T, CX>::type *, BlkState *, double, int, double, double,
+                           int, int, int, PersistCtl *, long long);
+
+template <class T, bool CX>
+PersistFn<T, CX> persist_kernel(int nb)
+{
+    if constexpr (CX) {
+        (void)nb;
+        return blk_persist<T, true, 16>;
+    } else {
+        if (nb == 8) return blk_persist<T, false, 8>;
+        if (nb == 32) return blk_persist<T, false, 32>;
+        return blk_persist<T, false, 16>;
+    }
+}
+
+// All sweeps of a uniform batch in one persistent launch (nothing waits on
+// the host).  ctl: the control block in the workspace; its launch fields are
+// cleared here (by a kernel, so that the call can be captured in a graph).
+template <class T, bool CX>
+hipError_t run_sweeps(int batch, int m, int np, int nb, typename Elem<T, CX>::type *W,
+                      typename Elem<T, CX>::type *Vw, BlkState *st, PersistCtl *ctl, double tol,
+                      int max_sweeps, int masking, int phase32, int inner, int persistent,
+                      hipStream_t stream, double t0 = 0.0, double rate = 0.0)
+{
+    if (!persistent)
+        return run_sweeps_host<T, CX>(batch, m, np, nb, W, Vw, st, (int *)ctl, tol, max_sweeps,
+                                      masking, phase32, inner, stream);
+    int l = np / nb;
+    hipError_t e = launch_fill_int((int *)ctl, kCtlLaunchInts, 0, stream);
+    if (e != hipSuccess) return e;
+    hipLaunchKernelGGL(count_active, dim3((batch + 255) / 256), dim3(256), 0, stream, batch,
+                       (const BlkState *)st, ctl);
+    e = hipGetLastError();
+    if (e != hipSuccess) return e;
+    PersistFn<T, CX> fn = persist_kernel<T, CX>(nb);
+    int resident = 0;
+    long long limit = 0;
+    e = device_limits((const void *)fn, &resident, &limit);
+    if (e != hipSuccess) return e;
+    const int items = batch * (l / 2);
+    const int grid = items < resident ? items : resident;
+    void *args[] = {&batch, &m, &np, &l, &W, &Vw, &st, &tol, &inner, &t0, &rate, &max_sweeps,
+                    &masking, &phase32, &ctl, &limit};
+    return hipLaunchCooperativeKernel((const void *)fn, dim3((unsigned)(grid > 0 ? grid : 1)),
+                                      dim3(kBT), args, 0, stream);
+}
+
 // Workspace carving; the same order as blocked_workspace_bytes.
 struct WsLayout {
     void *W, *Vw, *W32, *V32;
     double *Q, *X;
     BlkState *st;
-    int *sw32, *pending;
+    int *sw32;
+    PersistCtl *ctl;   // sweep control (the host loop's pending count shares it)
 };
 
 WsLayout carve(void *ws, int batch, int m, int n, int np, size_t elt, bool mixed)
@@ -1068,7 +1348,7 @@ WsLayout carve(void *ws, int batch, int m, int n, int np, size_t elt, bool mixed
     p += align256((size_t)batch * sizeof(BlkState));
     L.sw32 = (int *)p;
     p += align256((size_t)batch * sizeof(int));
-    L.pending = (int *)p;
+    L.ctl = (PersistCtl *)p;
     return L;
 }
 
@@ -1084,23 +1364,29 @@ hipError_t launch_blocked(int batch, int m, int n, int nb, const typename Elem<T
                           typename Elem<T, CX>::type *U, int ldu, long long sU,
                           typename Elem<T, CX>::type *V, int ldv, long long sV, double tol,
                           int max_sweeps, int masking, int *info, int *sweeps, void *ws,
-                          hipStream_t stream, int inner)
+                          hipStream_t stream, int inner, int persistent, double t0, double rate)
 {
     using E = typename Elem<T, CX>::type;
     const int np = blocked_np(n, nb);
     WsLayout L = carve(ws, batch, m, n, np, sizeof(E), false);
     E *W = (E *)L.W, *Vw = (E *)L.Vw;
+    hipError_t e = persistent ? launch_fill_int((int *)L.ctl, kCtlInts, 0, stream) : hipSuccess;
+    if (e != hipSuccess) return e;
     hipLaunchKernelGGL((blk_init<E, E>), dim3(batch), dim3(kBT), 0, stream, m, n, np, A, lda, sA,
                        W, Vw, L.st);
-    hipError_t e = hipGetLastError();
+    e = hipGetLastError();
     if (e != hipSuccess) return e;
-    e = run_sweeps<T, CX>(batch, m, np, nb, W, Vw, L.st, L.pending, tol, max_sweeps, masking, 0,
-                          inner, stream);
+    e = run_sweeps<T, CX>(batch, m, np, nb, W, Vw, L.st, L.ctl, tol, max_sweeps, masking, 0,
+                          inner, persistent, stream, t0, rate);
     if (e != hipSuccess) return e;
     const size_t lds = (size_t)n * (sizeof(double) + sizeof(int));
     hipLaunchKernelGGL((blk_finalize<E, E>), dim3(batch), dim3(kBT), lds, stream, m, n, np,
                        (const E *)W, (const E *)Vw, (const BlkState *)L.st, (const int *)nullptr,
                        S, sS, U, ldu, sU, V, ldv, sV, info, sweeps);
+    if (persistent)
+        hipLaunchKernelGGL(mark_aborted, dim3((batch + 255) / 256), dim3(256), 0, stream, batch,
+                           (const BlkState *)L.st, (const PersistCtl *)L.ctl, info,
+                           (const VbDesc *)nullptr);
     return hipGetLastError();
 }
 
@@ -1137,7 +1423,7 @@ __global__ __launch_bounds__(kBT) void vb_iter(const VbDesc *d, const int2 *work
     const int m = D.m, np = D.np, l = D.l;
     E *Wb = (E *)base;
     iter_body<T, CX, kVbNb>(s, m, np, l, (itg - D.it0) % (l - 1), w.y, Wb + D.woff, Wb + D.voff,
-                            st + w.x, tol, inner);
+                            st + w.x, tol, inner != 0 ? inner : D.inner);
 }
 
 // Closes the sweeps of the matrices whose sweep ends at launch itg; a matrix
@@ -1192,6 +1478,41 @@ __global__ __launch_bounds__(kBT) void vb_finalize(const VbDesc *d, const int *i
                         (E *)D.U, D.ldu, (E *)D.V, D.ldv, D.info, D.sweeps);
 }
 
+// Uneven batch, all sweeps in one cooperative launch: the work table lists
+// (matrix, block pair) largest matrices first; matrix b runs iteration
+// (itg - it0_b) mod (l_b - 1) at phase itg and closes a sweep at its own
+// boundary, so a small matrix completes several sweeps while a large one
+// completes one.
+template <class T, bool CX>
+__global__ __launch_bounds__(kBT) void vb_persist(const VbDesc *d, const int2 *work, int nwork,
+                                                  int count, int lmax, void *base, BlkState *st,
+                                                  double tol, int inner, double t0, double rate,
+                                                  int max_sweeps, int masking, PersistCtl *ctl,
+                                                  long long limit)
+{
+    using E = typename Elem<T, CX>::type;
+    __shared__ IterShared<T, CX, kVbNb> s;
+    E *Wb = (E *)base;
+    persist_loop(
+        ctl, nwork, count, max_sweeps * (lmax - 1), limit,
+        [&](int w, int itg) {
+            const int2 wk = work[w];
+            if (!st[wk.x].active) return;
+            const VbDesc &D = d[wk.x];
+            iter_body<T, CX, kVbNb>(s, D.m, D.np, D.l, (itg - D.it0) % (D.l - 1), wk.y,
+                                    Wb + D.woff, Wb + D.voff, st + wk.x,
+                                    inner_tol(tol, t0, rate, st[wk.x].sweeps),
+                                    inner != 0 ? inner : D.inner);
+        },
+        [&](int) { return true; },
+        [&](int b, int itg) {
+            if (!st[b].active) return false;
+            const VbDesc &D = d[b];
+            if ((itg - D.it0 + 1) % (D.l - 1) != 0) return false;
+            return close_sweep(st[b], max_sweeps, masking, 0, tol, t0, rate);
+        });
+}
+
 struct VbLayout {
     VbDesc *desc;
     int2 *work;
@@ -1234,22 +1555,58 @@ VbLayout vb_layout(void *ws, int batch, const int *m, const int *n, size_t elt)
     return L;
 }
 
-// host staging for descriptors and the work table; one per process and host
-// thread, reused once the previous call has synchronised
-hipError_t vb_staging(size_t bytes, char **out)
+// Host staging of the descriptors and the work table: pinned buffers, each
+// reused only once the copy that last read it has executed (an event is
+// recorded after the copy), so an asynchronous call never overwrites data
+// that a previous call's copy has yet to read.
+struct Staging {
+    char *buf = nullptr;
+    size_t cap = 0;
+    hipEvent_t ev = nullptr;
+    bool taken = false;
+};
+
+hipError_t vb_staging(size_t bytes, Staging **out)
 {
-    static thread_local char *buf = nullptr;
-    static thread_local size_t cap = 0;
-    if (bytes > cap) {
-        if (buf) (void)hipHostFree(buf);
-        buf = nullptr;
-        cap = 0;
-        hipError_t e = hipHostMalloc((void **)&buf, bytes, hipHostMallocDefault);
-        if (e != hipSuccess) return e;
-        cap = bytes;
+    static std::mutex mu;
+    static std::map<int, std::vector<Staging *>> pools;   // per device (its events)
+    int dev = 0;
+    hipError_t e = hipGetDevice(&dev);
+    if (e != hipSuccess) return e;
+    std::lock_guard<std::mutex> lk(mu);
+    std::vector<Staging *> &pool = pools[dev];
+    for (Staging *st : pool) {
+        if (st->taken || st->cap < bytes) continue;
+        const hipError_t q = hipEventQuery(st->ev);
+        if (q == hipErrorNotReady) continue;
+        if (q != hipSuccess) return q;
+        st->taken = true;
+        *out = st;
+        return hipSuccess;
     }
-    *out = buf;
+    Staging *st = new Staging();
+    size_t cap = 4096;
+    while (cap < bytes) cap *= 2;
+    e = hipHostMalloc((void **)&st->buf, cap, hipHostMallocDefault);
+    if (e == hipSuccess) e = hipEventCreateWithFlags(&st->ev, hipEventDisableTiming);
+    if (e != hipSuccess) {
+        if (st->buf) (void)hipHostFree(st->buf);
+        delete st;
+        return e;
+    }
+    st->cap = cap;
+    st->taken = true;
+    pool.push_back(st);
+    *out = st;
     return hipSuccess;
+}
+
+// Marks a staging buffer as read by the copies enqueued so far on `stream`.
+hipError_t vb_staging_release(Staging *st, hipStream_t stream)
+{
+    const hipError_t e = hipEventRecord(st->ev, stream);
+    st->taken = false;   // the event now guards the buffer
+    return e;
 }
 
 template <class T, bool CX>
@@ -1345,7 +1702,7 @@ hipError_t launch_vb(int dtype, size_t elt, int batch, const int *m, const int *
                      const void *const *A, const int *lda, void *const *S, void *const *U,
                      const int *ldu, void *const *V, const int *ldv, double tol, int max_sweeps,
                      int masking, int *info, int *sweeps, void *ws, hipStream_t stream,
-                     const int *trans, int inner)
+                     const int *trans, int inner, int persistent, double t0, double rate)
 {
     VbLayout L = vb_layout(ws, batch, m, n, elt);
     // descriptors, then the work table with the largest matrices first
@@ -1356,9 +1713,10 @@ hipError_t launch_vb(int dtype, size_t elt, int batch, const int *m, const int *
     size_t nwork = 0;
     for (int b = 0; b < batch; b++)
         if (n[b] > 0) nwork += blocked_np(n[b], kVbNb) / kVbNb / 2;
-    char *host;
-    hipError_t e = vb_staging(dbytes + nwork * sizeof(int2) + 16, &host);
+    Staging *stg;
+    hipError_t e = vb_staging(dbytes + nwork * sizeof(int2) + 16, &stg);
     if (e != hipSuccess) return e;
+    char *host = stg->buf;
     VbDesc *hd = (VbDesc *)host;
     int2 *hw = (int2 *)(host + dbytes);
     long long off = 0;   // elements
@@ -1380,6 +1738,8 @@ hipError_t launch_vb(int dtype, size_t elt, int batch, const int *m, const int *
         D.l = n[b] > 0 ? D.np / kVbNb : 2;
         D.it0 = 0;
         D.trans = trans ? trans[b] : 0;
+        BlockChoice ch;
+        D.inner = (inner == 0 && n[b] > 0 && tuned_block(dtype, m[b], n[b], &ch)) ? ch.inner : 0;
         D.woff = off;
         off += (long long)D.m * D.np;
         D.voff = off;
@@ -1392,14 +1752,56 @@ hipError_t launch_vb(int dtype, size_t elt, int batch, const int *m, const int *
     for (int b : order)
         for (int q = 0; n[b] > 0 && q < hd[b].l / 2; q++) hw[w++] = make_int2(b, q);
     e = hipMemcpyAsync(L.desc, hd, dbytes, hipMemcpyHostToDevice, stream);
-    if (e != hipSuccess) return e;
-    if (nwork) {
+    if (e == hipSuccess && nwork)
         e = hipMemcpyAsync(L.work, hw, nwork * sizeof(int2), hipMemcpyHostToDevice, stream);
+    const hipError_t er = vb_staging_release(stg, stream);
+    if (e != hipSuccess) return e;
+    if (er != hipSuccess) return er;
+    PersistCtl *ctl = (PersistCtl *)L.pending;
+    if (persistent) {
+        e = launch_fill_int((int *)ctl, kCtlInts, 0, stream);
         if (e != hipSuccess) return e;
     }
     vb_launch_init(dtype, L.desc, nullptr, batch, L.base, L.st, stream);
     e = hipGetLastError();
     if (e != hipSuccess) return e;
+    if (persistent) {
+        hipLaunchKernelGGL(count_active, dim3((batch + 255) / 256), dim3(256), 0, stream, batch,
+                           (const BlkState *)L.st, ctl);
+        e = hipGetLastError();
+        if (e == hipSuccess && nwork) {
+            using VbFn = void (*)(const VbDesc *, const int2 *, int, int, int, void *, BlkState *,
+                                  double, int, double, double, int, int, PersistCtl *, long long);
+            VbFn fn = dtype == 0   ? vb_persist<float, false>
+                      : dtype == 1 ? vb_persist<double, false>
+                      : dtype == 2 ? vb_persist<float, true>
+                                   : vb_persist<double, true>;
+            int resident = 0;
+            long long limit = 0;
+            e = device_limits((const void *)fn, &resident, &limit);
+            int nw = (int)nwork;
+            const int grid = nw < resident ? nw : resident;
+            const VbDesc *dd = L.desc;
+            const int2 *ww = L.work;
+            void *base = L.base;
+            BlkState *stp = L.st;
+            void *args[] = {&dd, &ww, &nw, &batch, &lmax, &base, &stp, &tol, &inner, &t0, &rate,
+                            &max_sweeps, &masking, &ctl, &limit};
+            if (e == hipSuccess)
+                e = hipLaunchCooperativeKernel((const void *)fn, dim3((unsigned)grid), dim3(kBT),
+                                               args, 0, stream);
+        } else if (e == hipSuccess) {
+            // no block pairs (every n is 0): close the single sweep of each
+            vb_launch_sweep_end(batch, L.desc, 0, L.st, max_sweeps, masking, nullptr, stream);
+            e = hipGetLastError();
+        }
+        if (e != hipSuccess) return e;
+        vb_launch_finalize(dtype, L.desc, nullptr, batch, maxn, L.base, L.st, stream);
+        hipLaunchKernelGGL(mark_aborted, dim3((batch + 255) / 256), dim3(256), 0, stream, batch,
+                           (const BlkState *)L.st, (const PersistCtl *)ctl, (int *)nullptr,
+                           (const VbDesc *)L.desc);
+        return hipGetLastError();
+    }
     int *host_count;
     e = pinned_counter(&host_count);
     if (e != hipSuccess) return e;
@@ -1430,7 +1832,7 @@ int blocked_nb(int m, int n, int nb, bool complex_)
 {
     (void)m;
     if (complex_) return (nb == 0 || nb == 16) ? 16 : 0;
-    if (nb == 16 || nb == 32) return nb;
+    if (nb == 8 || nb == 16 || nb == 32) return nb;
     if (nb != 0) return 0;
     return 16;   // nb = 32 has half the pairs but a 4x longer inner sweep
                  // and lower occupancy: slower at every measured size
@@ -1459,40 +1861,44 @@ size_t blocked_workspace_bytes(int batch, int m, int n, int nb, int elt, bool mi
 hipError_t launch_blocked_d(int batch, int m, int n, int nb, const double *A, int lda, long long sA,
                             double *S, long long sS, double *U, int ldu, long long sU, double *V,
                             int ldv, long long sV, double tol, int max_sweeps, int masking,
-                            int *info, int *sweeps, void *ws, hipStream_t stream, int inner)
+                            int *info, int *sweeps, void *ws, hipStream_t stream, int inner,
+                            int persistent, double t0, double rate)
 {
     return launch_blocked<double, false>(batch, m, n, nb, A, lda, sA, S, sS, U, ldu, sU, V, ldv,
                                          sV, tol, max_sweeps, masking, info, sweeps, ws, stream,
-                                         inner);
+                                         inner, persistent, t0, rate);
 }
 
 hipError_t launch_blocked_s(int batch, int m, int n, int nb, const float *A, int lda, long long sA,
                             float *S, long long sS, float *U, int ldu, long long sU, float *V,
                             int ldv, long long sV, double tol, int max_sweeps, int masking,
-                            int *info, int *sweeps, void *ws, hipStream_t stream, int inner)
+                            int *info, int *sweeps, void *ws, hipStream_t stream, int inner,
+                            int persistent, double t0, double rate)
 {
     return launch_blocked<float, false>(batch, m, n, nb, A, lda, sA, S, sS, U, ldu, sU, V, ldv, sV,
-                                        tol, max_sweeps, masking, info, sweeps, ws, stream, inner);
+                                        tol, max_sweeps, masking, info, sweeps, ws, stream, inner, persistent, t0, rate);
 }
 
 hipError_t launch_blocked_z(int batch, int m, int n, int nb, const void *A, int lda, long long sA,
                             double *S, long long sS, void *U, int ldu, long long sU, void *V,
                             int ldv, long long sV, double tol, int max_sweeps, int masking,
-                            int *info, int *sweeps, void *ws, hipStream_t stream, int inner)
+                            int *info, int *sweeps, void *ws, hipStream_t stream, int inner,
+                            int persistent, double t0, double rate)
 {
     return launch_blocked<double, true>(batch, m, n, nb, (const double2 *)A, lda, sA, S, sS,
                                         (double2 *)U, ldu, sU, (double2 *)V, ldv, sV, tol,
-                                        max_sweeps, masking, info, sweeps, ws, stream, inner);
+                                        max_sweeps, masking, info, sweeps, ws, stream, inner, persistent, t0, rate);
 }
 
 hipError_t launch_blocked_c(int batch, int m, int n, int nb, const void *A, int lda, long long sA,
                             float *S, long long sS, void *U, int ldu, long long sU, void *V,
                             int ldv, long long sV, double tol, int max_sweeps, int masking,
-                            int *info, int *sweeps, void *ws, hipStream_t stream, int inner)
+                            int *info, int *sweeps, void *ws, hipStream_t stream, int inner,
+                            int persistent, double t0, double rate)
 {
     return launch_blocked<float, true>(batch, m, n, nb, (const float2 *)A, lda, sA, S, sS,
                                        (float2 *)U, ldu, sU, (float2 *)V, ldv, sV, tol, max_sweeps,
-                                       masking, info, sweeps, ws, stream, inner);
+                                       masking, info, sweeps, ws, stream, inner, persistent, t0, rate);
 }
 
 // Mixed mode: FP32 sweeps (FP32 matrix cores, FP64 inner solves) with
@@ -1504,18 +1910,21 @@ hipError_t launch_blocked_mixed_d(int batch, int m, int n, int nb, const double 
                                   long long sA, double *S, long long sS, double *U, int ldu,
                                   long long sU, double *V, int ldv, long long sV, double tol,
                                   double tol32, int max_sweeps, int masking, int *info,
-                                  int *sweeps, void *ws, hipStream_t stream, int inner)
+                                  int *sweeps, void *ws, hipStream_t stream, int inner,
+                                  int persistent, double t0, double rate)
 {
     const int np = blocked_np(n, nb);
     WsLayout L = carve(ws, batch, m, n, np, sizeof(double), true);
     double *W = (double *)L.W, *Vw = (double *)L.Vw;
     float *W32 = (float *)L.W32, *V32 = (float *)L.V32;
+    hipError_t e = persistent ? launch_fill_int((int *)L.ctl, kCtlInts, 0, stream) : hipSuccess;
+    if (e != hipSuccess) return e;
     hipLaunchKernelGGL((blk_init<double, float>), dim3(batch), dim3(kBT), 0, stream, m, n, np, A,
                        lda, sA, W32, V32, L.st);
-    hipError_t e = hipGetLastError();
+    e = hipGetLastError();
     if (e != hipSuccess) return e;
-    e = run_sweeps<float, false>(batch, m, np, nb, W32, V32, L.st, L.pending, tol32, max_sweeps,
-                                 1, 1, inner, stream);
+    e = run_sweeps<float, false>(batch, m, np, nb, W32, V32, L.st, L.ctl, tol32, max_sweeps,
+                                 1, 1, inner, persistent, stream, t0, rate);
     if (e != hipSuccess) return e;
 
     // Newton-Schulz on Q; Q1 lives in the (not yet used) FP64 V area, ld n
@@ -1548,13 +1957,17 @@ hipError_t launch_blocked_mixed_d(int batch, int m, int n, int nb, const double 
                        L.sw32);
     e = hipGetLastError();
     if (e != hipSuccess) return e;
-    e = run_sweeps<double, false>(batch, m, np, nb, W, Vw, L.st, L.pending, tol, max_sweeps,
-                                  masking, 0, inner, stream);
+    e = run_sweeps<double, false>(batch, m, np, nb, W, Vw, L.st, L.ctl, tol, max_sweeps,
+                                  masking, 0, inner, persistent, stream, t0, rate);
     if (e != hipSuccess) return e;
     const size_t lds = (size_t)n * (sizeof(double) + sizeof(int));
     hipLaunchKernelGGL((blk_finalize<double, double>), dim3(batch), dim3(kBT), lds, stream, m, n,
                        np, (const double *)W, (const double *)Vw, (const BlkState *)L.st,
                        (const int *)L.sw32, S, sS, U, ldu, sU, V, ldv, sV, info, sweeps);
+    if (persistent)
+        hipLaunchKernelGGL(mark_aborted, dim3((batch + 255) / 256), dim3(256), 0, stream, batch,
+                           (const BlkState *)L.st, (const PersistCtl *)L.ctl, info,
+                           (const VbDesc *)nullptr);
     return hipGetLastError();
 }
 
@@ -1571,11 +1984,11 @@ hipError_t launch_vbatched(int dtype, int batch, const int *m, const int *n, con
                            const int *lda, void *const *S, void *const *U, const int *ldu,
                            void *const *V, const int *ldv, double tol, int max_sweeps,
                            int masking, int *info, int *sweeps, void *ws, hipStream_t stream,
-                           const int *trans, int inner)
+                           const int *trans, int inner, int persistent, double t0, double rate)
 {
     const size_t elt = dtype == 0 ? 4 : dtype == 3 ? 16 : 8;
     return launch_vb(dtype, elt, batch, m, n, A, lda, S, U, ldu, V, ldv, tol, max_sweeps, masking,
-                     info, sweeps, ws, stream, trans, inner);
+                     info, sweeps, ws, stream, trans, inner, persistent, t0, rate);
 }
 
 hipError_t launch_gemm_f64(bool trans_a, int batch, int M, int N, int K, double alpha,

@@ -67,14 +67,19 @@ hipError_t launch_precond_big_d(int batch, int m, int n, int nb, const double *A
                                 long long sA, double *S, long long sS, double *U, int ldu,
                                 long long sU, double *V, int ldv, long long sV, double tol,
                                 int max_sweeps, int masking, int *info, int *sweeps, void *ws,
-                                hipStream_t stream);
+                                hipStream_t stream, int inner = 0, int persistent = 1,
+                                double tol_start = 0.0, double tol_rate = 0.0);
 
 // blocked.hip: block one-sided Jacobi with MFMA Gram/updates (real and
 // complex, FP64 and FP32, and FP32 sweeps followed by an FP64 refinement).
 // blocked_nb returns the block width for a request (0: not supported).
 // `inner` (all block launchers): inner sweeps per block-pair solve; 0 = one,
 // or the converged solve for two block columns; k > 0 = at most k; < 0 = to
-// convergence.
+// convergence.  `persistent`: 1 = all sweeps in one cooperative launch
+// (asynchronous); 0 = one launch per round-robin iteration with a host-side
+// loop that waits for the pending count after every sweep.  tol_start >
+// tol (persistent launches only): the dynamic inner tolerance, outer sweep s
+// solving with max(tol, tol_start tol_rate^s).
 int blocked_nb(int m, int n, int nb, bool complex_);
 int blocked_np(int n, int nb);
 size_t blocked_workspace_bytes(int batch, int m, int n, int nb, int elt, bool mixed);
@@ -82,27 +87,44 @@ hipError_t launch_blocked_d(int batch, int m, int n, int nb, const double *A, in
                             double *S, long long sS, double *U, int ldu, long long sU, double *V,
                             int ldv, long long sV, double tol, int max_sweeps, int masking,
                             int *info, int *sweeps, void *ws, hipStream_t stream,
-                            int inner = 0);
+                            int inner = 0, int persistent = 1, double tol_start = 0.0,
+                            double tol_rate = 0.0);
 hipError_t launch_blocked_s(int batch, int m, int n, int nb, const float *A, int lda, long long sA,
                             float *S, long long sS, float *U, int ldu, long long sU, float *V,
                             int ldv, long long sV, double tol, int max_sweeps, int masking,
                             int *info, int *sweeps, void *ws, hipStream_t stream,
-                            int inner = 0);
+                            int inner = 0, int persistent = 1, double tol_start = 0.0,
+                            double tol_rate = 0.0);
 hipError_t launch_blocked_z(int batch, int m, int n, int nb, const void *A, int lda, long long sA,
                             double *S, long long sS, void *U, int ldu, long long sU, void *V,
                             int ldv, long long sV, double tol, int max_sweeps, int masking,
                             int *info, int *sweeps, void *ws, hipStream_t stream,
-                            int inner = 0);
+                            int inner = 0, int persistent = 1, double tol_start = 0.0,
+                            double tol_rate = 0.0);
 hipError_t launch_blocked_c(int batch, int m, int n, int nb, const void *A, int lda, long long sA,
                             float *S, long long sS, void *U, int ldu, long long sU, void *V,
                             int ldv, long long sV, double tol, int max_sweeps, int masking,
                             int *info, int *sweeps, void *ws, hipStream_t stream,
-                            int inner = 0);
+                            int inner = 0, int persistent = 1, double tol_start = 0.0,
+                            double tol_rate = 0.0);
 hipError_t launch_blocked_mixed_d(int batch, int m, int n, int nb, const double *A, int lda,
                                   long long sA, double *S, long long sS, double *U, int ldu,
                                   long long sU, double *V, int ldv, long long sV, double tol,
                                   double tol32, int max_sweeps, int masking, int *info,
-                                  int *sweeps, void *ws, hipStream_t stream, int inner = 0);
+                                  int *sweeps, void *ws, hipStream_t stream, int inner = 0,
+                                  int persistent = 1, double tol_start = 0.0,
+                                  double tol_rate = 0.0);
+
+// tuning.hip: the measured launch table.  tuned_block fills the block
+// method's choices for a request of this dtype and shape (false: no row,
+// the built-in rules apply); tuned_resident_waves gives the wavefronts per
+// matrix of the resident kernel for (N, rows per lane), 0 if none.
+struct BlockChoice {
+    int nb = 0, inner = 0;
+    double tol_start = 0.0, tol_rate = 0.0;
+};
+bool tuned_block(int dtype, int m, int n, BlockChoice *c);
+int tuned_resident_waves(int N, int rw);
 
 // Per-matrix descriptor of the uneven-batch kernels (device memory).
 struct VbDesc {
@@ -112,6 +134,8 @@ struct VbDesc {
     long long woff, voff;   // element offsets of W (m x np) and V (np x np) from the base
     int m, n, np, l, lda, ldu, ldv, it0;   // it0: launch index of its first iteration
     int trans;   // 1: A holds the n x m matrix whose conjugate transpose is this m x n one
+    int inner;   // inner sweeps of its block-pair solves when the call leaves them
+                 // open (0: the built-in rule)
 };
 
 // Launchers of the uneven-batch kernels; dtype as svdb_dtype_t, st points to
@@ -138,7 +162,8 @@ hipError_t launch_vbatched(int dtype, int batch, const int *m, const int *n, con
                            const int *lda, void *const *S, void *const *U, const int *ldu,
                            void *const *V, const int *ldv, double tol, int max_sweeps,
                            int masking, int *info, int *sweeps, void *ws, hipStream_t stream,
-                           const int *trans = nullptr, int inner = 0);
+                           const int *trans = nullptr, int inner = 0, int persistent = 1,
+                           double tol_start = 0.0, double tol_rate = 0.0);
 
 // blocked.hip: batched FP64 GEMM on the matrix cores, column major:
 // C = alpha op(A) B + beta D (op(A) = A^T when trans_a; D may be NULL; C may
@@ -159,5 +184,9 @@ hipError_t launch_widen_f32(int batch, int rows, int cols, const float *src, int
 hipError_t launch_narrow_f64(int batch, int rows, int cols, const double *src, int lds,
                              long long ss, float *dst, int ldd, long long sd, const int *info,
                              hipStream_t stream);
+
+// p[0 .. count) = value, by a small kernel (no hipMemsetAsync, so that a
+// caller may capture the call in a HIP graph)
+hipError_t launch_fill_int(int *p, int count, int value, hipStream_t stream);
 
 }  // namespace svdb

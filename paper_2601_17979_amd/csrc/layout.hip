@@ -126,4 +126,22 @@ hipError_t launch_narrow_f64(int batch, int rows, int cols, const double *src, i
                                          stream);
 }
 
+namespace {
+
+__global__ void fill_int(int *__restrict__ p, int count, int value)
+{
+    for (int i = blockIdx.x * blockDim.x + threadIdx.x; i < count; i += gridDim.x * blockDim.x)
+        p[i] = value;
+}
+
+}  // namespace
+
+hipError_t launch_fill_int(int *p, int count, int value, hipStream_t stream)
+{
+    if (!p || count <= 0) return hipSuccess;
+    const int g = (count + 255) / 256 < 1024 ? (count + 255) / 256 : 1024;
+    hipLaunchKernelGGL(fill_int, dim3((unsigned)g), dim3(256), 0, stream, p, count, value);
+    return hipGetLastError();
+}
+
 }  // namespace svdb

@@ -1078,7 +1078,8 @@ hipError_t launch_precond_big_d(int batch, int m, int n, int nb, const double *A
                                 long long sA, double *S, long long sS, double *U, int ldu,
                                 long long sU, double *V, int ldv, long long sV, double tol,
                                 int max_sweeps, int masking, int *info, int *sweeps, void *ws,
-                                hipStream_t stream)
+                                hipStream_t stream, int inner, int persistent, double tol_start,
+                                double tol_rate)
 {
     if (!precond_big_supported(m, n)) return hipErrorInvalidValue;
     const long long snn = (long long)n * n;
@@ -1108,7 +1109,7 @@ hipError_t launch_precond_big_d(int batch, int m, int n, int nb, const double *A
     if (e != hipSuccess) return e;
     e = launch_blocked_d(batch, n, n, nb, X2, n, snn, S, sS, U ? Ux : nullptr, n, snn,
                          V ? J : nullptr, n, snn, tol, max_sweeps, masking, info, sweeps, bws,
-                         stream);
+                         stream, inner, persistent, tol_start, tol_rate);
     if (e == hipSuccess && U)
         e = launch_apply_g(batch, m, n, Vq1, tau1, Ux, U, ldu, sU, info, stream);
     if (e == hipSuccess && V)

@@ -635,7 +635,12 @@ bool resident_config(int m, int n, int ns, int *N, int *R, int *NS)
     if (!nn) return false;
     const int rw = (m <= 32 && nn <= 32) ? 0 : (m + 63) / 64;
     if (rw > 4) return false;
-    if (ns == 0) ns = ((rw + 1) * nn > 96) ? 2 : 1;
+    if (ns == 0) {
+        // the measured choice for this class if it fits, else the rule
+        const int t = tuned_resident_waves(nn, rw);
+        ns = ((rw + 1) * nn > 96) ? 2 : 1;
+        if ((t == 1 || t == 2 || t == 4) && (nn / 2) / t >= 4 && (rw + 1) * nn / t <= 96) ns = t;
+    }
     if (ns != 1 && ns != 2 && ns != 4) return false;
     if ((nn / 2) / ns < 4) return false;
     if ((rw + 1) * nn / ns > 96) return false;

@@ -154,7 +154,10 @@ struct Group {
     void *d_st = nullptr;
     int *d_flags = nullptr, *h_flags = nullptr;
     int2 *d_work = nullptr, *h_work = nullptr;
-    int *d_idx = nullptr, *h_idx = nullptr;
+    // slot lists of the init and the finalize launches: two host buffers, so
+    // that a round's init list is never written while the previous round's
+    // finalize list may still be in flight to the device
+    int *d_idx = nullptr, *h_idx = nullptr, *h_fin = nullptr;
     svdb::QrJob *d_jobs = nullptr, *h_jobs = nullptr;   // QR preconditioning (FP64 group)
     std::vector<Request> slot;
     std::vector<char> used;
@@ -187,6 +190,9 @@ struct svdb_server {
     hipStream_t stream = nullptr;
     hipStream_t aux[3] = {};       // the lanes of preconditioned requests
     hipEvent_t ev_fin = nullptr;   // end of the finalisations of a round
+    // the worker's waits for its own stream: a blocking-sync event, so that
+    // the worker sleeps in the driver instead of spinning on a host core
+    hipEvent_t ev_wait = nullptr;
     void *arena = nullptr;
     // the wide QR lane: up to kWideChunk same-shape requests are gathered
     // into H, factored by one blocked-QR launch, and scattered back
@@ -398,6 +404,13 @@ hipError_t wide_qr(svdb_server *s, Group &G, const std::vector<int> &cur, hipStr
     return hipSuccess;
 }
 
+// Waits until the worker's stream has finished the work enqueued so far.
+hipError_t wait_stream(svdb_server *s)
+{
+    const hipError_t e = hipEventRecord(s->ev_wait, s->stream);
+    return e == hipSuccess ? hipEventSynchronize(s->ev_wait) : e;
+}
+
 void worker_main(svdb_server *s)
 {
     std::vector<int> init;   // slots to initialise this round
@@ -519,7 +532,7 @@ void worker_main(svdb_server *s)
             SRV_CHECK(hipMemcpyAsync(G.h_flags, G.d_flags, (size_t)G.cap * sizeof(int),
                                      hipMemcpyDeviceToHost, s->stream));
         }
-        SRV_CHECK(hipStreamSynchronize(s->stream));
+        SRV_CHECK(wait_stream(s));
         std::vector<std::pair<int, int>> retired;   // (group, slot) complete now
         bool any_pc = false;
         for (int gi = 0; gi < 4; gi++) {
@@ -528,7 +541,7 @@ void worker_main(svdb_server *s)
             int cnt = 0, maxn = 0;
             for (int b = 0; b < G.cap; b++)
                 if (G.used[b] && G.stage[b] == 0 && G.h_flags[b]) {
-                    G.h_idx[cnt++] = b;
+                    G.h_fin[cnt++] = b;
                     maxn = G.slot[b].n > maxn ? G.slot[b].n : maxn;
                     if (G.slot[b].pc)
                         any_pc = true;
@@ -536,7 +549,7 @@ void worker_main(svdb_server *s)
                         retired.push_back({gi, b});
                 }
             if (!cnt) continue;
-            SRV_CHECK(hipMemcpyAsync(G.d_idx, G.h_idx, (size_t)cnt * sizeof(int),
+            SRV_CHECK(hipMemcpyAsync(G.d_idx, G.h_fin, (size_t)cnt * sizeof(int),
                                      hipMemcpyHostToDevice, s->stream));
             svdb::vb_launch_finalize(G.dtype, G.d_desc, G.d_idx, cnt, maxn, s->arena, G.d_st,
                                      s->stream);
@@ -575,7 +588,7 @@ void worker_main(svdb_server *s)
             L.busy = true;
         }
         if (!retired.empty()) {
-            SRV_CHECK(hipStreamSynchronize(s->stream));
+            SRV_CHECK(wait_stream(s));
             const double t = now_seconds();
             {
                 std::lock_guard<std::mutex> lk(s->mu);
@@ -593,7 +606,13 @@ void worker_main(svdb_server *s)
             }
             s->cv_done.notify_all();
         }
-        if (K == 0 && retired.empty()) std::this_thread::sleep_for(std::chrono::microseconds(20));
+        if (K == 0 && retired.empty()) {
+            // every admitted request is in a QR lane: wait briefly, or less
+            // when a new request arrives
+            std::unique_lock<std::mutex> lk(s->mu);
+            s->cv_work.wait_for(lk, std::chrono::microseconds(200),
+                                [&] { return s->stop || !s->queue.empty(); });
+        }
     }
 }
 
@@ -609,6 +628,7 @@ void destroy_resources(svdb_server *s)
         if (G.h_flags) (void)hipHostFree(G.h_flags);
         if (G.h_work) (void)hipHostFree(G.h_work);
         if (G.h_idx) (void)hipHostFree(G.h_idx);
+        if (G.h_fin) (void)hipHostFree(G.h_fin);
         if (G.d_jobs) (void)hipFree(G.d_jobs);
         if (G.h_jobs) (void)hipHostFree(G.h_jobs);
         for (auto &L : G.lane)
@@ -620,6 +640,7 @@ void destroy_resources(svdb_server *s)
     for (void *p : {(void *)s->qrb_h, (void *)s->qrb_x, (void *)s->qrb_tau, s->qrb_ws})
         if (p) (void)hipFree(p);
     if (s->ev_fin) (void)hipEventDestroy(s->ev_fin);
+    if (s->ev_wait) (void)hipEventDestroy(s->ev_wait);
     for (hipStream_t a : s->aux)
         if (a) (void)hipStreamDestroy(a);
     if (s->stream) (void)hipStreamDestroy(s->stream);
@@ -651,6 +672,8 @@ int svdb_server_create(svdb_server_t **out, size_t budget_bytes, int max_request
     for (hipStream_t &a : s->aux)
         if (e == hipSuccess) e = hipStreamCreateWithFlags(&a, hipStreamNonBlocking);
     if (e == hipSuccess) e = hipEventCreateWithFlags(&s->ev_fin, hipEventDisableTiming);
+    if (e == hipSuccess)
+        e = hipEventCreateWithFlags(&s->ev_wait, hipEventDisableTiming | hipEventBlockingSync);
     if (e == hipSuccess) e = hipMalloc(&s->arena, s->budget);
     if (s->precondition) {
         const size_t mn = (size_t)kWideChunk * 1024 * s->max_n,
@@ -686,6 +709,7 @@ int svdb_server_create(svdb_server_t **out, size_t budget_bytes, int max_request
         if (e == hipSuccess) e = hipHostMalloc((void **)&G.h_flags, nc * sizeof(int), 0);
         if (e == hipSuccess) e = hipHostMalloc((void **)&G.h_work, nc * pairs * sizeof(int2), 0);
         if (e == hipSuccess) e = hipHostMalloc((void **)&G.h_idx, nc * sizeof(int), 0);
+        if (e == hipSuccess) e = hipHostMalloc((void **)&G.h_fin, nc * sizeof(int), 0);
         if (e == hipSuccess) e = hipMalloc((void **)&G.d_jobs, nc * sizeof(svdb::QrJob));
         if (e == hipSuccess) e = hipHostMalloc((void **)&G.h_jobs, nc * sizeof(svdb::QrJob), 0);
         if (e == hipSuccess) svdb::vb_launch_mark_empty(G.cap, G.d_st, s->stream);

@@ -29,7 +29,9 @@ _PATHS = {"auto": PATH_AUTO, "plain": PATH_PLAIN, "resident": PATH_RESIDENT,
 class Opts(C.Structure):
     _fields_ = [("max_sweeps", C.c_int), ("path", C.c_int), ("nb", C.c_int),
                 ("masking", C.c_int), ("precision", C.c_int), ("sweeps", C.c_void_p),
-                ("waves", C.c_int), ("precondition", C.c_int), ("inner_sweeps", C.c_int)]
+                ("waves", C.c_int), ("precondition", C.c_int), ("inner_sweeps", C.c_int),
+                ("persistent", C.c_int), ("inner_tol_start", C.c_double),
+                ("inner_tol_rate", C.c_double)]
 
 
 class SvdbError(RuntimeError):
@@ -95,7 +97,7 @@ def version() -> str:
 
 
 def make_opts(max_sweeps=100, path="auto", nb=0, masking=True, precision=0, sweeps=None,
-              waves=0, precondition=-1, inner_sweeps=0):
+              waves=0, precondition=-1, inner_sweeps=0, persistent=True, inner_tol=None):
     o = Opts()
     lib().svdb_opts_default(C.byref(o))
     o.max_sweeps = int(max_sweeps)
@@ -107,6 +109,9 @@ def make_opts(max_sweeps=100, path="auto", nb=0, masking=True, precision=0, swee
     o.waves = int(waves)
     o.precondition = int(precondition)
     o.inner_sweeps = int(inner_sweeps)
+    o.persistent = 1 if persistent else 0
+    if inner_tol is not None:   # (start, rate) of the dynamic inner tolerance
+        o.inner_tol_start, o.inner_tol_rate = float(inner_tol[0]), float(inner_tol[1])
     return o
 
 
@@ -149,7 +154,8 @@ def _check_cm(x: torch.Tensor, name: str):
 def svd(A: torch.Tensor, tol: float = 0.0, max_sweeps: int = 100, path="auto", nb: int = 0,
         compute_u: bool = True, compute_v: bool = True, masking: bool = True,
         precision: int = 0, want_sweeps: bool = True, stream=None, out=None, waves: int = 0,
-        precondition: int = -1, inner_sweeps: int = 0):
+        precondition: int = -1, inner_sweeps: int = 0, persistent: bool = True,
+        inner_tol=None):
     """Batched reduced SVD of a (batch, m, n) column-major GPU tensor:
     A = U diag(S) V^H with k = min(m, n) singular values, U (m x k), V (n x k)
     (a wide matrix, m < n, is solved through its conjugate transpose).
@@ -159,6 +165,14 @@ def svd(A: torch.Tensor, tol: float = 0.0, max_sweeps: int = 100, path="auto", n
     current stream); synchronise before reading results on the host.
     """
     _check_cm(A, "A")
+    if stream is not None:
+        # outputs and workspace belong to the stream the kernels run on, so
+        # that torch's caching allocator does not hand their memory to another
+        # stream while the kernels still use it
+        with torch.cuda.stream(stream):
+            return svd(A, tol, max_sweeps, path, nb, compute_u, compute_v, masking, precision,
+                       want_sweeps, None, out, waves, precondition, inner_sweeps, persistent,
+                       inner_tol)
     b, m, n = A.shape
     k = min(m, n)
     dev = A.device
@@ -172,15 +186,15 @@ def svd(A: torch.Tensor, tol: float = 0.0, max_sweeps: int = 100, path="auto", n
         info = torch.empty(b, dtype=torch.int32, device=dev)
         sweeps = torch.empty(b, dtype=torch.int32, device=dev) if want_sweeps else None
     o = make_opts(max_sweeps, path, nb, masking, precision, sweeps, waves, precondition,
-                  inner_sweeps)
-    ws_bytes = lib().svdb_workspace_size(code, b, m, n, C.byref(o))
-    if ws_bytes == C.c_size_t(-1).value:
-        raise SvdbError(-1, last_error() or "invalid arguments")
-    ws = torch.empty(max(ws_bytes, 1), dtype=torch.uint8, device=dev) if ws_bytes else None
+                  inner_sweeps, persistent, inner_tol)
     st = (stream or torch.cuda.current_stream(dev)).cuda_stream
     lda = max(A.stride(2), 1) if n > 1 else max(m, 1)
     ldu = (U.stride(2) if k > 1 else max(m, 1)) if U is not None else 1
     ldv = (V.stride(2) if k > 1 else max(n, 1)) if V is not None else 1
+    ws_bytes = lib().svdb_workspace_size(code, b, m, n, C.byref(o))
+    if ws_bytes == C.c_size_t(-1).value:
+        raise SvdbError(-1, last_error() or "invalid arguments")
+    ws = torch.empty(max(ws_bytes, 1), dtype=torch.uint8, device=dev) if ws_bytes else None
     rc = lib().svdb_svd_strided_batched(
         code, b, m, n, A.data_ptr(), lda, A.stride(0), S.data_ptr(), S.stride(0),
         U.data_ptr() if U is not None else None, ldu, U.stride(0) if U is not None else 0,
@@ -201,7 +215,7 @@ class BatchedCall:
 
     def __init__(self, mats, tol: float = 0.0, max_sweeps: int = 100, compute_u: bool = True,
                  compute_v: bool = True, masking: bool = True, precision: int = 0,
-                 inner_sweeps: int = 0):
+                 inner_sweeps: int = 0, persistent: bool = True, inner_tol=None):
         dt = mats[0].dtype
         dev = mats[0].device
         self.code = dtype_code(dt)
@@ -234,7 +248,8 @@ class BatchedCall:
         self.Vp = P(*[v.data_ptr() for v in self.V]) if self.V is not None else None
         self.ldv = I(*[ld(v, v.shape[0]) for v in self.V]) if self.V is not None else None
         self.opts = make_opts(max_sweeps, "auto", 0, masking, precision, self.sweeps,
-                              inner_sweeps=inner_sweeps)
+                              inner_sweeps=inner_sweeps, persistent=persistent,
+                              inner_tol=inner_tol)
         self.tol = float(tol)
         self.ws_bytes = lib().svdb_batched_workspace_size(self.code, bsz, self.ms, self.ns,
                                                           C.byref(self.opts))
@@ -243,6 +258,12 @@ class BatchedCall:
         self.ws = torch.empty(max(self.ws_bytes, 1), dtype=torch.uint8, device=dev)
 
     def __call__(self, stream=None):
+        if stream is not None:
+            # the workspace and outputs are in use on `stream` until its work
+            # has finished
+            for t in [self.ws, self.info, self.sweeps, *self.S, *(self.U or []),
+                      *(self.V or [])]:
+                t.record_stream(stream)
         st = (stream or torch.cuda.current_stream(self.info.device)).cuda_stream
         rc = lib().svdb_svd_batched(self.code, self.bsz, self.ms, self.ns, self.Ap, self.lda,
                                     self.Sp, self.Up, self.ldu, self.Vp, self.ldv, self.tol,
@@ -255,7 +276,8 @@ class BatchedCall:
 
 def svd_batched(mats, tol: float = 0.0, max_sweeps: int = 100, path="auto", nb: int = 0,
                 compute_u: bool = True, compute_v: bool = True, masking: bool = True,
-                precision: int = 0, stream=None, inner_sweeps: int = 0):
+                precision: int = 0, stream=None, inner_sweeps: int = 0,
+                persistent: bool = True, inner_tol=None):
     """Mixed-shape batch: `mats` is a list of (m_b, n_b) column-major GPU
     tensors of one dtype.  Returns lists (S, U, V) and tensors (info, sweeps).
     (path and nb are accepted for symmetry with svd(); uneven batches always
@@ -263,7 +285,7 @@ def svd_batched(mats, tol: float = 0.0, max_sweeps: int = 100, path="auto", nb: 
     if not mats:
         return [], [], [], None, None
     call = BatchedCall(mats, tol, max_sweeps, compute_u, compute_v, masking, precision,
-                       inner_sweeps)
+                       inner_sweeps, persistent, inner_tol)
     return call(stream)
 
 

@@ -85,6 +85,19 @@ def test_empty_batch_is_a_noop():
     assert _call(batch=0, A=None, S=None, info=None) == 0
 
 
+@pytest.mark.parametrize("m,n", [(3, 0), (0, 0), (0, 3)])
+def test_no_singular_values_is_accepted(m, n):
+    """min(m, n) = 0: no workspace, NULL A and S accepted, and the call only
+    sets info (a small kernel, so without a GPU it can fail only in the HIP
+    runtime, never as an unsupported shape)."""
+    L = svdb.lib()
+    for code in (svdb.R32, svdb.R64, svdb.C64, svdb.C128):
+        assert L.svdb_workspace_size(code, 5, m, n, None) == 0
+        rc = _call(dtype=code, batch=5, m=m, n=n, A=None, lda=max(m, 1), sA=0, S=None, sS=0,
+                   U=None, ldu=max(m, 1), sU=0, V=None, ldv=max(n, 1), sV=0)
+        assert rc in (0, svdb.ERR_HIP), (code, rc, svdb.last_error())
+
+
 def test_plan_and_workspace():
     p, nb, th = svdb.plan(svdb.torch.float64, 16, 16)
     assert p in (svdb.PATH_PLAIN, svdb.PATH_RESIDENT, svdb.PATH_BLOCKED)
@@ -162,3 +175,4 @@ def test_precondition_option_in_plan():
     ws_no = svdb.lib().svdb_workspace_size(svdb.R64, 10, 64, 64,
                                            C.byref(svdb.make_opts(precondition=0)))
     assert ws_pc > 0 and ws_no == 0
+

@@ -123,3 +123,47 @@ def test_uneven_complex_workload_sample():
         Sr, _, _, _, infor = oracle_batch(A)
         compare_with_oracle(A, S, U, V, info, Sr, infor, dtype=np.complex128,
                             label=f"uneven {g.m}x{g.n}")
+
+
+@pytest.mark.parametrize("m,n", [(256, 256), (512, 256), (480, 240), (300, 250)])
+def test_complex128_upper_range(m, n):
+    """The top of the uneven complex128 range (n up to 256, m up to 2n),
+    through the uniform-shape call and through the mixed-shape call; the two
+    run the same block method (nb = 16) on the same schedule, so they agree
+    bit for bit."""
+    import torch
+    from paper_2601_17979_amd import svdb
+    A = _cbatch((m, n), 2, seed=7600 + m + n, kinds=("gauss", "geo"))
+    say(f"[c128 upper {m}x{n}]")
+    S, U, V, info, sw = run_gpu(A, dtype=torch.complex128)
+    Sr, _, _, swr, infor = oracle_batch(A)
+    compare_with_oracle(A, S, U, V, info, Sr, infor, dtype=np.complex128,
+                        label=f"c128 {m}x{n} strided")
+    gm = [svdb.col_major(torch.from_numpy(A[k])[None].cuda())[0] for k in range(2)]
+    Sb, Ub, Vb, infob, swb = svdb.svd_batched(gm)
+    torch.cuda.synchronize()
+    for k in range(2):
+        assert int(infob[k]) == int(info[k])
+        assert np.array_equal(Sb[k].cpu().numpy(), S[k])
+        assert np.array_equal(Ub[k].cpu().numpy(), U[k])
+        assert np.array_equal(Vb[k].cpu().numpy(), V[k])
+    say(f"  sweeps gpu {sw.tolist()} oracle {swr.tolist()}")
+
+
+def test_complex128_upper_range_mixed_batch():
+    """One mixed-shape call over shapes from the whole uneven range, largest
+    ones included (n = 256, m = 512), against the oracle."""
+    import torch
+    from paper_2601_17979_amd import svdb
+    shapes = [(512, 256), (256, 256), (300, 241), (17, 9), (64, 33), (130, 128), (8, 8)]
+    mats = [gen.family(gen.rng_for(7700, k), "gauss", m, n, 1.0, complex_=True)
+            for k, (m, n) in enumerate(shapes)]
+    gm = [svdb.col_major(torch.from_numpy(a)[None].cuda())[0] for a in mats]
+    S, U, V, info, sw = svdb.svd_batched(gm)
+    torch.cuda.synchronize()
+    import oracle
+    for k, A in enumerate(mats):
+        Sk, _, _, _, ik = oracle.gesvj(A)
+        compare_with_oracle(A[None], S[k].cpu().numpy()[None], U[k].cpu().numpy()[None],
+                            V[k].cpu().numpy()[None], info[k:k + 1].cpu().numpy(), Sk[None],
+                            np.array([ik]), dtype=np.complex128, label=f"mixed #{k} {A.shape}")

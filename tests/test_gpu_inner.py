@@ -119,3 +119,58 @@ def test_fp32_inner_modes():
                             V.astype(np.float64), info, Sr, infor, dtype=np.float32,
                             label=f"fp32 inner {inner}")
         say(f"  fp32 inner {inner}: sweeps {sw.tolist()}")
+
+
+DYN = (1e-1, 1e-2)   # (start, rate) of the dynamic inner tolerance
+
+
+@pytest.mark.parametrize("cx", [False, True])
+def test_dynamic_tolerance_first_sweep_elementwise(cx):
+    """The dynamic inner tolerance ("Inexact Hermitian Eigendecomposition",
+    first way): the first outer sweep solves every Gram matrix at the start
+    threshold; the iterate matches the oracle's dynamic-tolerance driver
+    element by element (same bound as above)."""
+    import torch
+    dt = torch.complex128 if cx else torch.float64
+    for m, n in [(40, 32), (64, 48)]:
+        A = _batch(m, n, 4, seed=9700 + n + 7 * int(cx), complex_=cx, kinds=("gauss",))
+        S, U, V, info, sw = run_gpu(A, dtype=dt, path="blocked", max_sweeps=1, inner_sweeps=-1,
+                                    inner_tol=DYN)
+        r = np.random.default_rng(12)
+        for k in range(A.shape[0]):
+            Sr, Ur, Vr, swr, ir = oracle.block_gesvj(A[k], 16, max_sweeps=1, inner_sweeps=0,
+                                                     tol_start=DYN[0], tol_rate=DYN[1])
+            noise = r.standard_normal(A[k].shape) + (1j * r.standard_normal(A[k].shape) if cx
+                                                     else 0.0)
+            Sp, Up, Vp, _, _ = oracle.block_gesvj(A[k] * (1 + 2.0 ** -52 * noise), 16,
+                                                  max_sweeps=1, inner_sweeps=0,
+                                                  tol_start=DYN[0], tol_rate=DYN[1])
+            amax = np.abs(A[k]).max()
+            bound = max(1e-13, 10 * np.abs(Up * Sp - Ur * Sr).max() / amax)
+            ew = np.abs(U[k] * S[k] - Ur * Sr).max() / amax
+            say(f"  dyn {m}x{n} cx={cx}: W diff {ew:.2e} (bound {bound:.2e})")
+            assert info[k] == 1 and ir == 1
+            assert ew <= bound, (m, n, k, ew, bound)
+
+
+@pytest.mark.parametrize("cx", [False, True])
+def test_dynamic_tolerance_to_convergence(cx):
+    """To convergence the dynamic tolerance meets the FP64 tolerances, the
+    sweep counts agree with the oracle's dynamic driver within one, and no
+    matrix stops before the threshold has shrunk to tol."""
+    import torch
+    dt = torch.complex128 if cx else torch.float64
+    tol = oracle.default_tol(np.float64)
+    need = int(np.ceil(np.log(tol / DYN[0]) / np.log(DYN[1]))) + 1
+    for m, n in [(64, 64), (130, 96), (40, 24)]:
+        A = _batch(m, n, 4, seed=9750 + m + n + int(cx), complex_=cx)
+        S, U, V, info, sw = run_gpu(A, dtype=dt, path="blocked", inner_sweeps=-1,
+                                    inner_tol=DYN)
+        out = [oracle.block_gesvj(A[k], 16, inner_sweeps=0, tol_start=DYN[0],
+                                  tol_rate=DYN[1]) for k in range(A.shape[0])]
+        Sr = np.stack([o[0] for o in out])
+        swr = np.array([o[3] for o in out])
+        infor = np.array([o[4] for o in out])
+        compare_with_oracle(A, S, U, V, info, Sr, infor, label=f"dyn {m}x{n} cx={cx}")
+        say(f"  dyn {m}x{n}: sweeps gpu {sw.tolist()} oracle {swr.tolist()} (>= {need})")
+        assert np.all(sw >= need) and np.all(np.abs(sw - swr) <= 1)

@@ -227,3 +227,17 @@ def test_blocked_larger_shapes(nb, m, n):
     Sr, Ur, Vr, swr, infor = oracle_batch(A)
     compare_with_oracle(A, S, U, V, info, Sr, infor, label=f"blocked {m}x{n} nb{nb}")
     say(f"  sweeps gpu {list(sw)} oracle {list(swr)}")
+
+
+@pytest.mark.parametrize("m,n", [(3, 0), (0, 0), (0, 3)])
+def test_no_singular_values(m, n):
+    """min(m, n) = 0 in every dtype: nothing to factor, info 0 and sweeps 0
+    for every matrix of the batch."""
+    import torch
+    from paper_2601_17979_amd import svdb
+    for dt in (torch.float32, torch.float64, torch.complex64, torch.complex128):
+        A = torch.zeros((4, m, n), dtype=dt, device="cuda")
+        S, U, V, info, sw = svdb.svd(A)
+        torch.cuda.synchronize()
+        assert S.shape == (4, 0) and U.shape == (4, m, 0) and V.shape == (4, n, 0)
+        assert info.cpu().tolist() == [0] * 4 and sw.cpu().tolist() == [0] * 4

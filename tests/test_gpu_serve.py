@@ -203,3 +203,46 @@ def test_server_precondition_wide_qr():
         say(f"  wide QR {reqs[k].shape} {reqs[k].dtype}: sweeps {int(out[4].item())}, "
             f"{(td - ts) * 1e3:.1f} ms")
         _check(reqs[k], out, f"precond wide #{k} {reqs[k].shape}")
+
+
+@pytest.mark.parametrize("precondition", [-1, 0])
+def test_server_late_admission_bitwise(precondition):
+    """A request submitted while others are already on the GPU (admitted and
+    sweeping, none finished) joins the running launches with its own
+    schedule; its outputs equal those of the same request served alone, bit
+    for bit, and match the oracle.  With QR preconditioning the probe also
+    has to wait for, and pass through, the QR lanes while the others'
+    applications of Q are queued."""
+    import torch
+    from paper_2601_17979_amd import svdb
+    probe = _mat(9650, 0, 96, 80, np.float64, kappa=1e6)
+    big = [_mat(9650, k, 1024, 512, np.float64, kappa=1e8) for k in range(1, 5)]
+    dev_probe = _to_dev(probe)
+    dev_big = [_to_dev(A) for A in big]
+    torch.cuda.synchronize()
+
+    srv = svdb.Server(budget_bytes=512 << 20, max_requests=16, precondition=precondition)
+    pid = srv.submit(dev_probe)
+    alone = _drain(srv, 1)[pid][2]
+    alone = tuple(t.cpu().numpy() for t in alone[:3])
+    srv.close()
+
+    srv = svdb.Server(budget_bytes=512 << 20, max_requests=16, precondition=precondition)
+    ids = [srv.submit(x) for x in dev_big]
+    t0 = time.time()
+    while srv.stats()["active"] < len(big):
+        assert time.time() - t0 < 30
+        time.sleep(0.0005)
+    time.sleep(0.01)   # let the admitted requests run a few launches
+    st = srv.stats()
+    pid = srv.submit(dev_probe)
+    say(f"[late admission pc={precondition}] probe submitted with {st['active']} active, "
+        f"{st['completed']} completed")
+    assert st["completed"] == 0 and st["active"] == len(big)
+    got = _drain(srv, len(big) + 1)
+    srv.close()
+    mixed = tuple(t.cpu().numpy() for t in got[pid][2][:3])
+    for a, b in zip(alone, mixed):
+        assert np.array_equal(a, b)
+    _check(probe, got[pid][2], f"late probe pc={precondition}")
+    assert got[pid][1] < max(got[i][1] for i in ids), "the probe should finish first"

@@ -340,6 +340,37 @@ def pin_block_matches_definition():
                 assert orth_err(U) <= 1e-13 * n and orth_err(V) <= 1e-13 * n
 
 
+def pin_block_dynamic_tolerance():
+    """The dynamic inner tolerance ("Inexact Hermitian Eigendecomposition",
+    first way): with a start at or below tol it is the fixed-threshold block
+    solver bit for bit; from a large start it reaches the same SVD, and it
+    cannot stop before the threshold has shrunk to tol (a matrix with
+    orthogonal columns converges in exactly that sweep)."""
+    tol = oracle.default_tol(np.float64)
+    t0, rate = 1e-1, 1e-2
+    # sweeps until max(tol, t0 rate^s) = tol, plus the sweep at tol
+    need = int(np.ceil(np.log(tol / t0) / np.log(rate))) + 1
+    for complex_ in (False, True):
+        rng = gen.rng_for(23, int(complex_))
+        for m, n, nb in [(20, 11, 3), (16, 16, 4), (30, 13, 8), (24, 24, 2)]:
+            A = gen.from_spectrum(rng, m, n, gen.spectrum("geo", n, 1e6), complex_)
+            fixed = oracle.block_gesvj(A, nb, inner_sweeps=0)
+            same = oracle.block_gesvj(A, nb, inner_sweeps=0, tol_start=tol, tol_rate=rate)
+            for x, y in zip(fixed[:3], same[:3]):
+                assert np.array_equal(x, y)
+            S, U, V, sw, info = oracle.block_gesvj(A, nb, inner_sweeps=0, tol_start=t0,
+                                                   tol_rate=rate)
+            ref = np.linalg.svd(A, compute_uv=False)
+            assert info == 0 and sw >= need, (m, n, nb, sw, need)
+            assert sigma_err(S, ref) <= 1e-14, (m, n, nb)
+            assert recon_err(A, S, U, V) <= 1e-13 * n
+            assert orth_err(U) <= 1e-13 * n and orth_err(V) <= 1e-13 * n
+        D = np.diag(np.arange(1.0, 9.0))[:, ::-1] * (1 + 1j if complex_ else 1)
+        S, U, V, sw, info = oracle.block_gesvj(D, 2, inner_sweeps=0, tol_start=t0,
+                                               tol_rate=rate)
+        assert info == 0 and sw == need and np.allclose(S, np.abs(np.diag(D[:, ::-1]))[::-1])
+
+
 def pin_rank_deficient():
     """sigma = 0: U is completed to orthonormal columns; zero matrices and
     exact rank-1 matrices."""
@@ -434,6 +465,7 @@ PINS = {
     "worked_example": pin_worked_example,
     "heevj": pin_heevj,
     "block_matches_definition": pin_block_matches_definition,
+    "block_dynamic_tolerance": pin_block_dynamic_tolerance,
     "rank_deficient": pin_rank_deficient,
     "info_codes": pin_info_codes,
     "batch_driver": pin_batch_driver,
@@ -478,6 +510,10 @@ MUTATIONS = [
     ("block update uses J^T", "acc += X[(size_t)col[a] * rows + k] * J[(size_t)b * n2 + a];",
      "acc += X[(size_t)col[a] * rows + k] * J[(size_t)a * n2 + b];"),
     ("sign(0) = -1", "double sg = (tau >= 0.0) ? 1.0 : -1.0;", "double sg = (tau > 0.0) ? 1.0 : -1.0;"),
+    ("dynamic tolerance stops above tol", "converged = (nrot == 0 && ts <= tol);",
+     "converged = (nrot == 0);"),
+    ("dynamic tolerance never shrinks", "ts = ts * tol_rate > tol ? ts * tol_rate : tol;",
+     "ts = ts > tol ? ts : tol;"),
 ]
 
 

@@ -139,24 +139,56 @@ def mixed_64_128x32(batch: int = 10000, seed: int = BASE_SEED + 1000) -> list:
     return groups
 
 
-def square256(batch: int = 4000, seed: int = BASE_SEED + 2000, indices=None) -> list:
+def _pool_map(fn, chunks, workers):
+    """fn over chunks, in worker processes when workers > 1 (forked: call this
+    before the process uses a GPU).  Every matrix has its own seeded stream,
+    so the result does not depend on the split."""
+    if not workers or workers <= 1 or len(chunks) <= 1:
+        return [fn(c) for c in chunks]
+    import multiprocessing as mp
+    from concurrent.futures import ProcessPoolExecutor
+    with ProcessPoolExecutor(max_workers=workers, mp_context=mp.get_context("fork")) as ex:
+        return list(ex.map(fn, chunks))
+
+
+def _split(ks, workers):
+    step = max(1, -(-len(ks) // max(4 * (workers or 1), 1)))
+    return [ks[i:i + step] for i in range(0, len(ks), step)]
+
+
+def _one_thread():
+    """Single-threaded BLAS inside a worker process (the pool supplies the
+    parallelism)."""
+    from threadpoolctl import threadpool_limits
+    return threadpool_limits(1)
+
+
+def _square256_part(arg):
+    seed, half, ks = arg
+    with _one_thread():
+        return np.stack([from_spectrum(rng_for(seed, k), 256, 256,
+                                       spectrum("geo", 256, 1e2 if k < half else 1e8))
+                         for k in ks])
+
+
+def square256(batch: int = 4000, seed: int = BASE_SEED + 2000, indices=None,
+              workers: int = 0) -> list:
     """batch x (256 x 256) FP64 geometric spectra, half kappa = 1e2, half 1e8.
     `indices` selects a subset of the batch (the same matrices as in the
-    full batch)."""
+    full batch); `workers` > 1 draws them in that many processes."""
     half = batch // 2
     ks = list(range(batch)) if indices is None else [int(k) for k in indices]
-
-    def make(r, k):
-        return from_spectrum(r, 256, 256, spectrum("geo", 256, 1e2 if k < half else 1e8))
-    A = np.stack([make(rng_for(seed, k), k) for k in ks])
+    parts = _pool_map(_square256_part, [(seed, half, c) for c in _split(ks, workers)], workers)
+    A = np.concatenate(parts) if parts else np.zeros((0, 256, 256))
     kinds = ["geo1e2" if k < half else "geo1e8" for k in ks]
     return [Group(256, 256, A, kinds, (seed, ks[0] if ks else 0))]
 
 
 def uneven_complex(batch: int = 20000, seed: int = BASE_SEED + 3000, nmin: int = 8,
-                   nmax: int = 256) -> list:
+                   nmax: int = 256, workers: int = 0) -> list:
     """complex128 matrices with n ~ U{nmin..nmax}, m ~ U{n..2n}, i.i.d.
-    complex Gaussian entries; returned as one group per shape."""
+    complex Gaussian entries; returned as one group per shape, in order of
+    shape.  `workers` > 1 draws them in that many processes."""
     shapes = []
     for k in range(batch):
         r = rng_for(seed, k)
@@ -166,11 +198,47 @@ def uneven_complex(batch: int = 20000, seed: int = BASE_SEED + 3000, nmin: int =
     by = {}
     for m, n, k in shapes:
         by.setdefault((m, n), []).append(k)
-    groups = []
-    for (m, n), ks in sorted(by.items()):
-        A = np.stack([gaussian(rng_for(seed + 1, k), m, n, True) for k in ks])
-        groups.append(Group(m, n, A, ["cgauss"] * len(ks), (seed, ks[0])))
-    return groups
+    keys = sorted(by.items())
+    offs, total = [], 0
+    for (m, n), ks in keys:
+        offs.append(total)
+        total += m * n * len(ks)
+    global _SHARED
+    if workers and workers > 1:
+        # workers fill one anonymous shared mapping, created before they fork
+        import mmap
+        _SHARED = mmap.mmap(-1, max(total, 1) * 16)
+        tasks = [(seed, [(kk, offs[i]) for i, kk in enumerate(keys)][a:b])
+                 for a, b in _ranges(len(keys), 4 * workers)]
+        _pool_map(_uneven_fill, tasks, workers)
+        flat = np.frombuffer(_SHARED, dtype=np.complex128, count=total).copy()
+        _SHARED.close()
+        _SHARED = None
+    else:
+        flat = np.empty(total, np.complex128)
+        for ((m, n), ks), o in zip(keys, offs):
+            flat[o:o + m * n * len(ks)] = np.stack(
+                [gaussian(rng_for(seed + 1, k), m, n, True) for k in ks]).ravel()
+    return [Group(m, n, flat[o:o + m * n * len(ks)].reshape(len(ks), m, n), ["cgauss"] * len(ks),
+                  (seed, ks[0])) for ((m, n), ks), o in zip(keys, offs)]
+
+
+_SHARED = None
+
+
+def _ranges(count, parts):
+    step = max(1, -(-count // max(parts, 1)))
+    return [(a, min(a + step, count)) for a in range(0, count, step)]
+
+
+def _uneven_fill(arg):
+    seed, items = arg
+    buf = np.frombuffer(_SHARED, dtype=np.complex128)
+    with _one_thread():
+        for ((m, n), ks), o in items:
+            buf[o:o + m * n * len(ks)] = np.stack(
+                [gaussian(rng_for(seed + 1, k), m, n, True) for k in ks]).ravel()
+    return len(items)
 
 
 SERVE_CLASSES = [(n * r, n) for n in (16, 32, 64, 128, 256, 512) for r in (1, 2)]
