@@ -20,9 +20,15 @@
  *    pointers owned by the caller; the library allocates no device memory in
  *    these calls.  Host-side arrays (m[], n[], lda[], and the pointer arrays
  *    of svdb_svd_batched) are read during the call only.
- *  - Work is enqueued on `stream` (a hipStream_t; NULL = the null stream) and
- *    is asynchronous: outputs and info[] are valid after the stream is
- *    synchronised.
+ *  - Work is enqueued on `stream` (a hipStream_t; NULL = the null stream);
+ *    outputs and info[] are valid after the stream is synchronised.  The
+ *    resident and QR-preconditioned resident paths are fully asynchronous.
+ *    The block method (BLOCKED path, the mixed-precision mode, the wide and
+ *    tall preconditioned paths that end in it, and svdb_svd_batched) runs
+ *    one launch per round-robin iteration and waits on the host for the
+ *    count of unconverged matrices after every sweep: those calls return
+ *    only when their sweeps are done (the finalisation is still
+ *    asynchronous), and cannot be captured into a HIP graph.
  *  - Return value: 0 on success; -k when argument k (1-based) is invalid,
  *    detected on the host before anything is launched; SVDB_ERR_UNSUPPORTED
  *    when a valid request is outside what this build implements;
@@ -31,10 +37,7 @@
  *    failure of the calling thread.
  *  - Per-matrix status info[b]: 0 converged; 1 not converged within
  *    max_sweeps (outputs hold the last iterate, finalised); 2 non-finite
- *    entry in A (outputs untouched); 3 the persistent launch of the block
- *    method was stopped by its device-side watchdog (a grid barrier that
- *    waited more than 20 s; outputs as for 1; not expected to occur, and
- *    reported instead of hanging the device).
+ *    entry in A (outputs untouched).
  *  - `tol` is the rotation threshold k*u of Alg. 2: the pair (i, j) is
  *    rotated iff g_ij != 0 and |g_ij| >= tol * sqrt(g_ii) * sqrt(g_jj).
  *    tol <= 0 selects 30 u of the working precision (the paper's k = 30,
@@ -112,17 +115,13 @@ typedef struct {
                          or three (FP32); k > 0: at most k, stopping at a
                          sweep that rotates nothing; < 0: to convergence (at
                          most 100).                                          */
-    int persistent;   /* block method (BLOCKED path, uneven batches, the wide
-                         preconditioned path): 1 (default) runs every sweep
-                         of the batch in one cooperative launch, a grid
-                         barrier between round-robin iterations and the
-                         convergence test on the device, so the call never
-                         waits on the host; 0 launches one kernel per
-                         round-robin iteration and waits on the host for
-                         the count of unconverged matrices after every
-                         sweep (synchronous; the results are the same bit
-                         for bit).                                           */
-    double inner_tol_start; /* block method, persistent launches: the dynamic
+    int persistent;   /* block method: must be 0 (default): one launch per
+                         round-robin iteration, the host waiting for the
+                         count of unconverged matrices after every sweep.
+                         1 (every sweep in one cooperative launch with grid
+                         barriers) is disabled in this version and returns
+                         SVDB_ERR_UNSUPPORTED.                               */
+    double inner_tol_start; /* block method: the dynamic
                          tolerance of the inner eigensolver ("Inexact
                          Hermitian Eigendecomposition", subsection
                          "Motivation", first way).  > tol: outer sweep s
@@ -134,7 +133,7 @@ typedef struct {
 } svdb_opts_t;
 
 /* Fills *o with the defaults (AUTO path, 100 sweeps, masking on,
- * precondition -1, inner_sweeps 0, persistent 1, no dynamic inner
+ * precondition -1, inner_sweeps 0, persistent 0, no dynamic inner
  * tolerance). */
 void svdb_opts_default(svdb_opts_t *o);
 

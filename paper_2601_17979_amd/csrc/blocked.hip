@@ -687,21 +687,38 @@ __global__ __launch_bounds__(kBT) void blk_iter(int m, int np, int l, int it,
                          st + b, tol, inner);
 }
 
+// Threshold of the inner eigensolver in outer sweep s (counted from 0) with
+// the dynamic tolerance of "Inexact Hermitian Eigendecomposition"
+// (subsection "Motivation", first way): tol_start shrinks by tol_rate per
+// sweep until it reaches tol; tol_start <= tol keeps tol throughout.  The
+// products are formed one sweep at a time, as the sequence is defined, so
+// host and device obtain the same doubles.
+__host__ __device__ __forceinline__ double inner_tol(double tol, double t0, double rate, int s)
+{
+    if (!(t0 > tol)) return tol;
+    double ts = t0;
+    for (int k = 0; k < s; k++) ts = ts * rate > tol ? ts * rate : tol;
+    return ts;
+}
+
 // End of a sweep: a matrix with no rotation is converged (done); with
 // `phase32` (FP32 phase of the mixed mode) one whose largest cosine is at
-// most kSwitchCos is done too.  With masking a done matrix is retired;
-// without, every matrix stays active until the whole batch is done.
-// *pending counts the matrices not done.
-__global__ void blk_sweep_end(int batch, BlkState *st, int *pending, int masking, int phase32)
+// most kSwitchCos is done too.  With the dynamic inner tolerance (t0 > tol)
+// only a sweep run at the final threshold tol can converge a matrix.  With
+// masking a done matrix is retired; without, every matrix stays active
+// until the whole batch is done.  *pending counts the matrices not done.
+__global__ void blk_sweep_end(int batch, BlkState *st, int *pending, int masking, int phase32,
+                              double tol, double t0, double rate)
 {
     const int b = blockIdx.x * blockDim.x + threadIdx.x;
     if (b >= batch) return;
     BlkState &s = st[b];
     if (!s.active) return;
     if (!s.done) {
+        const bool at_tol = inner_tol(tol, t0, rate, s.sweeps) <= tol;
         s.sweeps += 1;
         const double mc = __longlong_as_double((long long)s.maxcos);
-        bool fin = !s.rotated;
+        bool fin = !s.rotated && at_tol;
         if (phase32 && mc <= kSwitchCos) fin = true;
         s.prevcos = mc;
         if (fin) s.done = 1;
@@ -772,19 +789,6 @@ __device__ bool grid_sync(PersistCtl *ctl, unsigned target, long long limit)
     __syncthreads();
     __threadfence();   // acquire: the other workgroups' writes
     return s_ok != 0;
-}
-
-// Threshold of the inner eigensolver in outer sweep s (counted from 0) with
-// the dynamic tolerance of "Inexact Hermitian Eigendecomposition"
-// (subsection "Motivation", first way): tol_start shrinks by tol_rate per
-// sweep until it reaches tol; tol_start <= tol keeps tol throughout.  The
-// products are formed one sweep at a time, as the sequence is defined.
-__device__ __forceinline__ double inner_tol(double tol, double t0, double rate, int s)
-{
-    if (!(t0 > tol)) return tol;
-    double ts = t0;
-    for (int k = 0; k < s; k++) ts = ts * rate > tol ? ts * rate : tol;
-    return ts;
 }
 
 // End of a sweep of one matrix: a sweep without rotation converges it
@@ -1244,7 +1248,7 @@ template <class T, bool CX>
 hipError_t run_sweeps_host(int batch, int m, int np, int nb, typename Elem<T, CX>::type *W,
                            typename Elem<T, CX>::type *Vw, BlkState *st, int *pending,
                            double tol, int max_sweeps, int masking, int phase32, int inner,
-                           hipStream_t stream)
+                           hipStream_t stream, double t0, double rate)
 {
     const int l = np / nb;
     int *host_count;
@@ -1252,12 +1256,14 @@ hipError_t run_sweeps_host(int batch, int m, int np, int nb, typename Elem<T, CX
     if (e != hipSuccess) return e;
     const unsigned grid = (unsigned)batch * (unsigned)(l / 2);
     for (int sw = 0; sw < max_sweeps; sw++) {
+        // every matrix still sweeping is in its sweep sw
+        const double ts = inner_tol(tol, t0, rate, sw);
         for (int it = 0; it < l - 1; it++)
-            launch_iter<T, CX>(nb, grid, stream, m, np, l, it, W, Vw, st, tol, inner);
+            launch_iter<T, CX>(nb, grid, stream, m, np, l, it, W, Vw, st, ts, inner);
         e = hipMemsetAsync(pending, 0, sizeof(int), stream);
         if (e != hipSuccess) return e;
         hipLaunchKernelGGL(blk_sweep_end, dim3((batch + 255) / 256), dim3(256), 0, stream, batch,
-                           st, pending, masking, phase32);
+                           st, pending, masking, phase32, tol, t0, rate);
         e = hipMemcpyAsync(host_count, pending, sizeof(int), hipMemcpyDeviceToHost, stream);
         if (e != hipSuccess) return e;
         e = hipStreamSynchronize(stream);
@@ -1296,7 +1302,7 @@ hipError_t run_sweeps(int batch, int m, int np, int nb, typename Elem<T, CX>::ty
 {
     if (!persistent)
         return run_sweeps_host<T, CX>(batch, m, np, nb, W, Vw, st, (int *)ctl, tol, max_sweeps,
-                                      masking, phase32, inner, stream);
+                                      masking, phase32, inner, stream, t0, rate);
     int l = np / nb;
     hipError_t e = launch_fill_int((int *)ctl, kCtlLaunchInts, 0, stream);
     if (e != hipSuccess) return e;
@@ -1413,7 +1419,8 @@ __global__ __launch_bounds__(kBT) void vb_init(const VbDesc *d, const int *idx, 
 
 template <class T, bool CX>
 __global__ __launch_bounds__(kBT) void vb_iter(const VbDesc *d, const int2 *work, int itg,
-                                               void *base, BlkState *st, double tol, int inner)
+                                               void *base, BlkState *st, double tol, int inner,
+                                               double t0, double rate)
 {
     using E = typename Elem<T, CX>::type;
     __shared__ IterShared<T, CX, kVbNb> s;
@@ -1423,22 +1430,24 @@ __global__ __launch_bounds__(kBT) void vb_iter(const VbDesc *d, const int2 *work
     const int m = D.m, np = D.np, l = D.l;
     E *Wb = (E *)base;
     iter_body<T, CX, kVbNb>(s, m, np, l, (itg - D.it0) % (l - 1), w.y, Wb + D.woff, Wb + D.voff,
-                            st + w.x, tol, inner != 0 ? inner : D.inner);
+                            st + w.x, inner_tol(tol, t0, rate, st[w.x].sweeps),
+                            inner != 0 ? inner : D.inner);
 }
 
 // Closes the sweeps of the matrices whose sweep ends at launch itg; a matrix
 // that reaches max_sweeps unconverged stops (info 1).  With `pending`, counts
 // the matrices still sweeping.
 __global__ void vb_sweep_end(int count, const VbDesc *d, int itg, BlkState *st, int max_sweeps,
-                             int masking, int *pending)
+                             int masking, int *pending, double tol, double t0, double rate)
 {
     const int b = blockIdx.x * blockDim.x + threadIdx.x;
     if (b >= count) return;
     BlkState &s = st[b];
     if (s.active && (itg - d[b].it0 + 1) % (d[b].l - 1) == 0) {
         if (!s.done) {
+            const bool at_tol = inner_tol(tol, t0, rate, s.sweeps) <= tol;
             s.sweeps += 1;
-            if (!s.rotated)
+            if (!s.rotated && at_tol)
                 s.done = 1;
             else if (s.sweeps >= max_sweeps)
                 s.active = 0;
@@ -1611,10 +1620,11 @@ hipError_t vb_staging_release(Staging *st, hipStream_t stream)
 
 template <class T, bool CX>
 void vb_launch_iter_t(const VbDesc *d, const int2 *work, int nwork, int itg, void *base,
-                      BlkState *st, double tol, int inner, hipStream_t stream)
+                      BlkState *st, double tol, int inner, double t0, double rate,
+                      hipStream_t stream)
 {
     hipLaunchKernelGGL((vb_iter<T, CX>), dim3((unsigned)nwork), dim3(kBT), 0, stream, d, work, itg,
-                       base, st, tol, inner);
+                       base, st, tol, inner, t0, rate);
 }
 
 template <class E>
@@ -1650,22 +1660,31 @@ void vb_launch_init(int dtype, const VbDesc *d, const int *idx, int count, void 
 }
 
 void vb_launch_iter(int dtype, const VbDesc *d, const int2 *work, int nwork, int itg, void *base,
-                    void *st, double tol, hipStream_t stream, int inner)
+                    void *st, double tol, hipStream_t stream, int inner, double t0, double rate)
 {
     BlkState *S = (BlkState *)st;
     switch (dtype) {
-    case 0: vb_launch_iter_t<float, false>(d, work, nwork, itg, base, S, tol, inner, stream); break;
-    case 1: vb_launch_iter_t<double, false>(d, work, nwork, itg, base, S, tol, inner, stream); break;
-    case 2: vb_launch_iter_t<float, true>(d, work, nwork, itg, base, S, tol, inner, stream); break;
-    default: vb_launch_iter_t<double, true>(d, work, nwork, itg, base, S, tol, inner, stream); break;
+    case 0:
+        vb_launch_iter_t<float, false>(d, work, nwork, itg, base, S, tol, inner, t0, rate, stream);
+        break;
+    case 1:
+        vb_launch_iter_t<double, false>(d, work, nwork, itg, base, S, tol, inner, t0, rate, stream);
+        break;
+    case 2:
+        vb_launch_iter_t<float, true>(d, work, nwork, itg, base, S, tol, inner, t0, rate, stream);
+        break;
+    default:
+        vb_launch_iter_t<double, true>(d, work, nwork, itg, base, S, tol, inner, t0, rate, stream);
+        break;
     }
 }
 
 void vb_launch_sweep_end(int count, const VbDesc *d, int itg, void *st, int max_sweeps,
-                         int masking, int *pending, hipStream_t stream)
+                         int masking, int *pending, hipStream_t stream, double tol, double t0,
+                         double rate)
 {
     hipLaunchKernelGGL(vb_sweep_end, dim3((unsigned)((count + 255) / 256)), dim3(256), 0, stream,
-                       count, d, itg, (BlkState *)st, max_sweeps, masking, pending);
+                       count, d, itg, (BlkState *)st, max_sweeps, masking, pending, tol, t0, rate);
 }
 
 void vb_launch_collect(int count, const void *st, int *flags, hipStream_t stream)
@@ -1812,9 +1831,10 @@ hipError_t launch_vb(int dtype, size_t elt, int batch, const int *m, const int *
         for (int k = 0; k < lmax - 1; k++, itg++) {
             if (nwork)
                 vb_launch_iter(dtype, L.desc, L.work, (int)nwork, itg, L.base, L.st, tol, stream,
-                               inner);
+                               inner, t0, rate);
             vb_launch_sweep_end(batch, L.desc, itg, L.st, max_sweeps, masking,
-                                k == lmax - 2 ? L.pending : (int *)nullptr, stream);
+                                k == lmax - 2 ? L.pending : (int *)nullptr, stream, tol, t0,
+                                rate);
         }
         e = hipMemcpyAsync(host_count, L.pending, sizeof(int), hipMemcpyDeviceToHost, stream);
         if (e != hipSuccess) return e;

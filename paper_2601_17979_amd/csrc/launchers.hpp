@@ -29,6 +29,16 @@ hipError_t launch_precond_d(int batch, int m, int n, int ns, const double *A, in
                             long long sA, double *S, long long sS, double *U, int ldu,
                             long long sU, double *V, int ldv, long long sV, double tol,
                             int max_sweeps, int *info, int *sweeps, void *ws, hipStream_t stream);
+// qr_lane.hip: one-wave QR (optionally pivoted) and application of Q for
+// small matrices (n <= 64, m n <= 4096 with m rounded as qr_lane_shape).
+bool qr_lane_shape(int m, int n, int *rpl, int *lpc);
+bool qr_lane_available(bool piv, int m, int n);
+hipError_t launch_qr_lane_d(bool piv, int batch, int m, int n, const double *A, int lda,
+                            long long sA, double *X, double *Vq, double *tau, int *perm,
+                            hipStream_t stream);
+hipError_t launch_apply_q_lane_d(int batch, int m, int n, const double *Vq, const double *tau,
+                                 const double *Y, double *U, int ldu, long long sU,
+                                 const int *info, const int *perm, hipStream_t stream);
 bool precond_tall_supported(int m, int n);
 bool precond_tall_auto(int m, int n);   // where AUTO takes it (m <= 1024)
 size_t precond_tall_workspace_bytes(int batch, int m, int n);
@@ -67,7 +77,7 @@ hipError_t launch_precond_big_d(int batch, int m, int n, int nb, const double *A
                                 long long sA, double *S, long long sS, double *U, int ldu,
                                 long long sU, double *V, int ldv, long long sV, double tol,
                                 int max_sweeps, int masking, int *info, int *sweeps, void *ws,
-                                hipStream_t stream, int inner = 0, int persistent = 1,
+                                hipStream_t stream, int inner = 0, int persistent = 0,
                                 double tol_start = 0.0, double tol_rate = 0.0);
 
 // blocked.hip: block one-sided Jacobi with MFMA Gram/updates (real and
@@ -76,10 +86,10 @@ hipError_t launch_precond_big_d(int batch, int m, int n, int nb, const double *A
 // `inner` (all block launchers): inner sweeps per block-pair solve; 0 = one,
 // or the converged solve for two block columns; k > 0 = at most k; < 0 = to
 // convergence.  `persistent`: 1 = all sweeps in one cooperative launch
-// (asynchronous); 0 = one launch per round-robin iteration with a host-side
-// loop that waits for the pending count after every sweep.  tol_start >
-// tol (persistent launches only): the dynamic inner tolerance, outer sweep s
-// solving with max(tol, tol_start tol_rate^s).
+// (disabled at the public interface: it stalled on the GPU); 0 = one launch
+// per round-robin iteration with a host-side loop that waits for the
+// pending count after every sweep.  tol_start > tol: the dynamic inner
+// tolerance, outer sweep s solving with max(tol, tol_start tol_rate^s).
 int blocked_nb(int m, int n, int nb, bool complex_);
 int blocked_np(int n, int nb);
 size_t blocked_workspace_bytes(int batch, int m, int n, int nb, int elt, bool mixed);
@@ -87,32 +97,32 @@ hipError_t launch_blocked_d(int batch, int m, int n, int nb, const double *A, in
                             double *S, long long sS, double *U, int ldu, long long sU, double *V,
                             int ldv, long long sV, double tol, int max_sweeps, int masking,
                             int *info, int *sweeps, void *ws, hipStream_t stream,
-                            int inner = 0, int persistent = 1, double tol_start = 0.0,
+                            int inner = 0, int persistent = 0, double tol_start = 0.0,
                             double tol_rate = 0.0);
 hipError_t launch_blocked_s(int batch, int m, int n, int nb, const float *A, int lda, long long sA,
                             float *S, long long sS, float *U, int ldu, long long sU, float *V,
                             int ldv, long long sV, double tol, int max_sweeps, int masking,
                             int *info, int *sweeps, void *ws, hipStream_t stream,
-                            int inner = 0, int persistent = 1, double tol_start = 0.0,
+                            int inner = 0, int persistent = 0, double tol_start = 0.0,
                             double tol_rate = 0.0);
 hipError_t launch_blocked_z(int batch, int m, int n, int nb, const void *A, int lda, long long sA,
                             double *S, long long sS, void *U, int ldu, long long sU, void *V,
                             int ldv, long long sV, double tol, int max_sweeps, int masking,
                             int *info, int *sweeps, void *ws, hipStream_t stream,
-                            int inner = 0, int persistent = 1, double tol_start = 0.0,
+                            int inner = 0, int persistent = 0, double tol_start = 0.0,
                             double tol_rate = 0.0);
 hipError_t launch_blocked_c(int batch, int m, int n, int nb, const void *A, int lda, long long sA,
                             float *S, long long sS, void *U, int ldu, long long sU, void *V,
                             int ldv, long long sV, double tol, int max_sweeps, int masking,
                             int *info, int *sweeps, void *ws, hipStream_t stream,
-                            int inner = 0, int persistent = 1, double tol_start = 0.0,
+                            int inner = 0, int persistent = 0, double tol_start = 0.0,
                             double tol_rate = 0.0);
 hipError_t launch_blocked_mixed_d(int batch, int m, int n, int nb, const double *A, int lda,
                                   long long sA, double *S, long long sS, double *U, int ldu,
                                   long long sU, double *V, int ldv, long long sV, double tol,
                                   double tol32, int max_sweeps, int masking, int *info,
                                   int *sweeps, void *ws, hipStream_t stream, int inner = 0,
-                                  int persistent = 1, double tol_start = 0.0,
+                                  int persistent = 0, double tol_start = 0.0,
                                   double tol_rate = 0.0);
 
 // tuning.hip: the measured launch table.  tuned_block fills the block
@@ -143,10 +153,13 @@ struct VbDesc {
 // NULL = 0 .. count-1.
 void vb_launch_init(int dtype, const VbDesc *d, const int *idx, int count, void *base, void *st,
                     hipStream_t stream);
+// t0, rate: the dynamic inner tolerance (t0 <= tol: tol in every sweep).
 void vb_launch_iter(int dtype, const VbDesc *d, const int2 *work, int nwork, int itg, void *base,
-                    void *st, double tol, hipStream_t stream, int inner = 0);
+                    void *st, double tol, hipStream_t stream, int inner = 0, double t0 = 0.0,
+                    double rate = 0.0);
 void vb_launch_sweep_end(int count, const VbDesc *d, int itg, void *st, int max_sweeps,
-                         int masking, int *pending, hipStream_t stream);
+                         int masking, int *pending, hipStream_t stream, double tol = 0.0,
+                         double t0 = 0.0, double rate = 0.0);
 void vb_launch_collect(int count, const void *st, int *flags, hipStream_t stream);
 void vb_launch_mark_empty(int count, void *st, hipStream_t stream);
 void vb_launch_finalize(int dtype, const VbDesc *d, const int *idx, int count, int maxn,
@@ -162,7 +175,7 @@ hipError_t launch_vbatched(int dtype, int batch, const int *m, const int *n, con
                            const int *lda, void *const *S, void *const *U, const int *ldu,
                            void *const *V, const int *ldv, double tol, int max_sweeps,
                            int masking, int *info, int *sweeps, void *ws, hipStream_t stream,
-                           const int *trans = nullptr, int inner = 0, int persistent = 1,
+                           const int *trans = nullptr, int inner = 0, int persistent = 0,
                            double tol_start = 0.0, double tol_rate = 0.0);
 
 // blocked.hip: batched FP64 GEMM on the matrix cores, column major:

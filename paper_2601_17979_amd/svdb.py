@@ -97,7 +97,7 @@ def version() -> str:
 
 
 def make_opts(max_sweeps=100, path="auto", nb=0, masking=True, precision=0, sweeps=None,
-              waves=0, precondition=-1, inner_sweeps=0, persistent=True, inner_tol=None):
+              waves=0, precondition=-1, inner_sweeps=0, persistent=False, inner_tol=None):
     o = Opts()
     lib().svdb_opts_default(C.byref(o))
     o.max_sweeps = int(max_sweeps)
@@ -154,7 +154,7 @@ def _check_cm(x: torch.Tensor, name: str):
 def svd(A: torch.Tensor, tol: float = 0.0, max_sweeps: int = 100, path="auto", nb: int = 0,
         compute_u: bool = True, compute_v: bool = True, masking: bool = True,
         precision: int = 0, want_sweeps: bool = True, stream=None, out=None, waves: int = 0,
-        precondition: int = -1, inner_sweeps: int = 0, persistent: bool = True,
+        precondition: int = -1, inner_sweeps: int = 0, persistent: bool = False,
         inner_tol=None):
     """Batched reduced SVD of a (batch, m, n) column-major GPU tensor:
     A = U diag(S) V^H with k = min(m, n) singular values, U (m x k), V (n x k)
@@ -215,7 +215,7 @@ class BatchedCall:
 
     def __init__(self, mats, tol: float = 0.0, max_sweeps: int = 100, compute_u: bool = True,
                  compute_v: bool = True, masking: bool = True, precision: int = 0,
-                 inner_sweeps: int = 0, persistent: bool = True, inner_tol=None):
+                 inner_sweeps: int = 0, persistent: bool = False, inner_tol=None):
         dt = mats[0].dtype
         dev = mats[0].device
         self.code = dtype_code(dt)
@@ -277,7 +277,7 @@ class BatchedCall:
 def svd_batched(mats, tol: float = 0.0, max_sweeps: int = 100, path="auto", nb: int = 0,
                 compute_u: bool = True, compute_v: bool = True, masking: bool = True,
                 precision: int = 0, stream=None, inner_sweeps: int = 0,
-                persistent: bool = True, inner_tol=None):
+                persistent: bool = False, inner_tol=None):
     """Mixed-shape batch: `mats` is a list of (m_b, n_b) column-major GPU
     tensors of one dtype.  Returns lists (S, U, V) and tensors (info, sweeps).
     (path and nb are accepted for symmetry with svd(); uneven batches always

@@ -176,3 +176,16 @@ def test_precondition_option_in_plan():
                                            C.byref(svdb.make_opts(precondition=0)))
     assert ws_pc > 0 and ws_no == 0
 
+
+
+def test_persistent_launch_is_refused():
+    """The single cooperative launch of the block method is switched off:
+    asking for it is an unsupported request (refused on the host, before
+    anything is launched), and the default is the per-iteration form."""
+    o = svdb.Opts()
+    svdb.lib().svdb_opts_default(C.byref(o))
+    assert o.persistent == 0
+    assert svdb.plan(torch.float64, 256, 256)[0] == svdb.PATH_BLOCKED
+    with pytest.raises(svdb.SvdbError) as e:
+        svdb.plan(torch.float64, 256, 256, persistent=True)
+    assert e.value.code == svdb.ERR_UNSUPPORTED and "disabled" in str(e.value)

@@ -18,6 +18,12 @@ from gpu_util import compare_with_oracle, run_gpu, say
 
 pytestmark = pytest.mark.gpu
 
+# The cooperative single-launch form stalled on the GPU (the complex128 9 x 9
+# case of test_gpu_complex.py did not finish within 150 s) and its cause is
+# not established, so the library refuses persistent = 1; these tests stay
+# in the tree, skipped, until it is.
+OFF = pytest.mark.skip(reason="persistent launch disabled: it stalled on the GPU, cause unknown")
+
 
 def _batch(m, n, count, seed, cx=False, kinds=("gauss", "geo", "random")):
     return np.stack([gen.family(gen.rng_for(seed, k), kinds[k % len(kinds)], m, n, 1e6,
@@ -39,6 +45,7 @@ CASES = [
 ]
 
 
+@OFF
 @pytest.mark.parametrize("label,npdt,tdt,shape,nb,kw", CASES, ids=[c[0] for c in CASES])
 def test_persistent_equals_per_iteration_launches(label, npdt, tdt, shape, nb, kw):
     import torch
@@ -63,6 +70,7 @@ def test_persistent_equals_per_iteration_launches(label, npdt, tdt, shape, nb, k
                         P[3], Sr, infor, dtype=npdt, label=label)
 
 
+@OFF
 @pytest.mark.parametrize("dt", ["f64", "c128", "f32"])
 def test_uneven_persistent_equals_per_iteration_launches(dt):
     import torch
@@ -104,6 +112,7 @@ def test_uneven_persistent_equals_per_iteration_launches(dt):
                             label=f"uneven {dt} #{k} {A.shape}")
 
 
+@OFF
 def test_calls_return_before_the_work_is_done():
     """The strided and the mixed-shape calls only enqueue work: each returns
     long before its stream has finished (the per-iteration form waits on the
@@ -128,6 +137,7 @@ def test_calls_return_before_the_work_is_done():
         assert t_all > 0.02 and t_host < 0.25 * t_all, (label, t_host, t_all)
 
 
+@OFF
 def test_strided_call_replays_from_a_graph():
     """The whole strided call (workspace clears by kernels, init, the
     persistent sweeps, finalisation) captured in a HIP graph: every replay,
