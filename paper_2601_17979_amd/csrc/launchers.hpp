@@ -29,16 +29,6 @@ hipError_t launch_precond_d(int batch, int m, int n, int ns, const double *A, in
                             long long sA, double *S, long long sS, double *U, int ldu,
                             long long sU, double *V, int ldv, long long sV, double tol,
                             int max_sweeps, int *info, int *sweeps, void *ws, hipStream_t stream);
-// qr_lane.hip: one-wave QR (optionally pivoted) and application of Q for
-// small matrices (n <= 64, m n <= 4096 with m rounded as qr_lane_shape).
-bool qr_lane_shape(int m, int n, int *rpl, int *lpc);
-bool qr_lane_available(bool piv, int m, int n);
-hipError_t launch_qr_lane_d(bool piv, int batch, int m, int n, const double *A, int lda,
-                            long long sA, double *X, double *Vq, double *tau, int *perm,
-                            hipStream_t stream);
-hipError_t launch_apply_q_lane_d(int batch, int m, int n, const double *Vq, const double *tau,
-                                 const double *Y, double *U, int ldu, long long sU,
-                                 const int *info, const int *perm, hipStream_t stream);
 bool precond_tall_supported(int m, int n);
 bool precond_tall_auto(int m, int n);   // where AUTO takes it (m <= 1024)
 size_t precond_tall_workspace_bytes(int batch, int m, int n);
