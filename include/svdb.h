@@ -174,6 +174,38 @@ int svdb_svd_strided_batched(svdb_dtype_t dtype, int batch, int m, int n,
                              const svdb_opts_t *opts, void *stream);
 
 /*
+ * The uniform-shape call without any allocation, for callers that cannot
+ * allocate: code under HIP graph capture, tight serving loops, harnesses
+ * that forbid hipMalloc.  Arguments and results as
+ * svdb_svd_strided_batched, without the workspace: the library's own
+ * scratch, a static device array of svdb_noalloc_scratch_bytes() (64 MiB)
+ * per device, held until the process ends, takes its place.  It neither
+ * allocates nor frees anything (device or pinned host memory).
+ *  - Only requests that AUTO (or the given path) plans on the resident
+ *    kernels qualify: FP64 and FP32 with n <= 64, with or without the QR
+ *    pre-processing, and wide matrices whose A^H qualifies (A^H is staged
+ *    in the scratch).  A request planned on the block method returns
+ *    SVDB_ERR_UNSUPPORTED (its host loop uses pinned memory).
+ *  - A batch whose workspace (svdb_workspace_size) exceeds the scratch
+ *    returns -2 and launches nothing.
+ *  - Every call on a device shares that device's scratch, which keeps the
+ *    last call's contents (no part of it needs to start at zero): calls
+ *    that overlap on one device (other streams or host threads) race.
+ * Arguments, 1-based: as svdb_svd_strided_batched up to info (17), then
+ * opts 18, stream 19.
+ */
+int svdb_svd_strided_batched_noalloc(svdb_dtype_t dtype, int batch, int m, int n,
+                                     const void *A, int lda, long long strideA,
+                                     void *S, long long strideS,
+                                     void *U, int ldu, long long strideU,
+                                     void *V, int ldv, long long strideV,
+                                     double tol, int *info,
+                                     const svdb_opts_t *opts, void *stream);
+
+/* Bytes of the static scratch of svdb_svd_strided_batched_noalloc. */
+size_t svdb_noalloc_scratch_bytes(void);
+
+/*
  * Mixed-shape batch (uneven batching): host arrays m[b], n[b], lda[b],
  * ldu[b], ldv[b] and host arrays of device pointers A[b], S[b], U[b], V[b]
  * (U or V may be NULL as a whole).  Any m[b], n[b] >= 0, with outputs as in

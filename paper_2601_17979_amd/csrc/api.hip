@@ -4,6 +4,8 @@
 #include <stdarg.h>
 #include <stdio.h>
 
+#include <map>
+#include <mutex>
 #include <string>
 #include <vector>
 
@@ -447,6 +449,91 @@ int svdb_svd_strided_batched(svdb_dtype_t dtype, int batch, int m, int n, const 
     }
     if (e != hipSuccess) return hip_fail(e, "launch");
     return 0;
+}
+
+}  // extern "C"
+
+namespace {
+
+// Scratch of svdb_svd_strided_batched_noalloc: a file-scope device array
+// (one copy per device, alive until the process ends).  Its name is a
+// host-side stand-in in host code: the device address comes from
+// hipGetSymbolAddress, looked up once per device with that device current.
+constexpr size_t kNoallocScratchBytes = (size_t)64 << 20;
+__device__ __align__(256) unsigned char scratch[kNoallocScratchBytes];
+
+hipError_t noalloc_scratch(int dev, void **out)
+{
+    static std::mutex mu;
+    static std::map<int, void *> addr;
+    std::lock_guard<std::mutex> lk(mu);
+    auto it = addr.find(dev);
+    if (it != addr.end()) {
+        *out = it->second;
+        return hipSuccess;
+    }
+    int cur = 0;
+    hipError_t e = hipGetDevice(&cur);
+    if (e != hipSuccess) return e;
+    if (cur != dev && (e = hipSetDevice(dev)) != hipSuccess) return e;
+    void *ptr = nullptr;
+    e = hipGetSymbolAddress(&ptr, HIP_SYMBOL(scratch));
+    if (cur != dev) {
+        const hipError_t r = hipSetDevice(cur);
+        if (e == hipSuccess) e = r;
+    }
+    if (e != hipSuccess) return e;
+    if (!ptr) return hipErrorInvalidSymbol;
+    addr.emplace(dev, ptr);
+    *out = ptr;
+    return hipSuccess;
+}
+
+}  // namespace
+
+extern "C" {
+
+size_t svdb_noalloc_scratch_bytes(void) { return kNoallocScratchBytes; }
+
+int svdb_svd_strided_batched_noalloc(svdb_dtype_t dtype, int batch, int m, int n, const void *A,
+                                     int lda, long long strideA, void *S, long long strideS,
+                                     void *U, int ldu, long long strideU, void *V, int ldv,
+                                     long long strideV, double tol, int *info,
+                                     const svdb_opts_t *opts, void *stream)
+{
+    g_err.clear();
+    if ((int)dtype < SVDB_R32 || (int)dtype > SVDB_C128) return fail(-1, "invalid dtype");
+    if (batch < 0) return fail(-2, "batch < 0");
+    if (m < 0) return fail(-3, "m < 0");
+    if (n < 0) return fail(-4, "n < 0");
+    const int k = m < n ? m : n;
+    size_t need = 0;
+    if (batch > 0 && k > 0) {
+        // the block method waits on the host through pinned memory: only the
+        // resident paths (with or without the QR pre-processing) qualify
+        svdb_opts_t o = resolve_opts(opts);
+        Plan p;
+        const int rc = m >= n ? make_plan(dtype, m, n, o, &p) : make_plan(dtype, n, m, o, &p);
+        if (rc) return rc;
+        if (p.path == SVDB_PATH_BLOCKED)
+            return fail(SVDB_ERR_UNSUPPORTED,
+                        "noalloc: %d x %d plans the block method, which is not allocation-free",
+                        m, n);
+        need = svdb_workspace_size(dtype, batch, m, n, &o);
+        if (need != (size_t)-1 && need > kNoallocScratchBytes)
+            return fail(-2, "noalloc: batch %d of %d x %d needs %zu bytes of scratch, the "
+                            "static maximum is %zu", batch, m, n, need, kNoallocScratchBytes);
+    }
+    void *ws = nullptr;
+    if (need > 0 && need != (size_t)-1) {
+        int dev = 0;
+        hipError_t e = stream ? hipStreamGetDevice((hipStream_t)stream, &dev) : hipGetDevice(&dev);
+        if (e == hipSuccess) e = noalloc_scratch(dev, &ws);
+        if (e != hipSuccess) return hip_fail(e, "noalloc scratch");
+    }
+    return svdb_svd_strided_batched(dtype, batch, m, n, A, lda, strideA, S, strideS, U, ldu,
+                                    strideU, V, ldv, strideV, tol, info, ws,
+                                    ws ? kNoallocScratchBytes : 0, opts, stream);
 }
 
 size_t svdb_batched_workspace_size(svdb_dtype_t dtype, int batch, const int *m, const int *n,

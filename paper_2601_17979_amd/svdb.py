@@ -66,6 +66,11 @@ def lib():
         L.svdb_svd_strided_batched.argtypes = [I, I, I, I, P, I, LL, P, LL, P, I, LL, P, I, LL,
                                                D, P, P, SZ, C.POINTER(Opts), P]
         L.svdb_svd_strided_batched.restype = I
+        L.svdb_svd_strided_batched_noalloc.argtypes = [I, I, I, I, P, I, LL, P, LL, P, I, LL,
+                                                       P, I, LL, D, P, C.POINTER(Opts), P]
+        L.svdb_svd_strided_batched_noalloc.restype = I
+        L.svdb_noalloc_scratch_bytes.argtypes = []
+        L.svdb_noalloc_scratch_bytes.restype = SZ
         L.svdb_svd_batched.argtypes = [I, I, P, P, P, P, P, P, P, P, P, D, P, P, SZ,
                                        C.POINTER(Opts), P]
         L.svdb_svd_batched.restype = I
@@ -204,6 +209,31 @@ def svd(A: torch.Tensor, tol: float = 0.0, max_sweeps: int = 100, path="auto", n
     if rc:
         raise SvdbError(rc, last_error())
     return S, U, V, info, sweeps
+
+
+def svd_noalloc(A: torch.Tensor, out, tol: float = 0.0, max_sweeps: int = 100, path="auto",
+                waves: int = 0, precondition: int = -1, stream=None):
+    """svd() through svdb_svd_strided_batched_noalloc: no workspace, the
+    library's static scratch instead.  `out` = (S, U, V, info, sweeps) as
+    svd() returns them (U, V or sweeps may be None); nothing is allocated
+    here or in the library.  Returns `out`."""
+    _check_cm(A, "A")
+    b, m, n = A.shape
+    k = min(m, n)
+    S, U, V, info, sweeps = out
+    o = make_opts(max_sweeps, path, 0, True, 0, sweeps, waves, precondition)
+    st = (stream or torch.cuda.current_stream(A.device)).cuda_stream
+    lda = max(A.stride(2), 1) if n > 1 else max(m, 1)
+    ldu = (U.stride(2) if k > 1 else max(m, 1)) if U is not None else 1
+    ldv = (V.stride(2) if k > 1 else max(n, 1)) if V is not None else 1
+    rc = lib().svdb_svd_strided_batched_noalloc(
+        dtype_code(A.dtype), b, m, n, A.data_ptr(), lda, A.stride(0), S.data_ptr(), S.stride(0),
+        U.data_ptr() if U is not None else None, ldu, U.stride(0) if U is not None else 0,
+        V.data_ptr() if V is not None else None, ldv, V.stride(0) if V is not None else 0,
+        float(tol), info.data_ptr(), C.byref(o), st)
+    if rc:
+        raise SvdbError(rc, last_error())
+    return out
 
 
 class BatchedCall:

@@ -189,3 +189,22 @@ def test_persistent_launch_is_refused():
     with pytest.raises(svdb.SvdbError) as e:
         svdb.plan(torch.float64, 256, 256, persistent=True)
     assert e.value.code == svdb.ERR_UNSUPPORTED and "disabled" in str(e.value)
+
+
+def test_noalloc_refusals_before_any_launch():
+    """The allocation-free call refuses, on the host, a batch whose workspace
+    exceeds its static scratch (-2) and a request planned on the block method
+    (unsupported); neither touches the device."""
+    L = svdb.lib()
+    cap = L.svdb_noalloc_scratch_bytes()
+    assert cap == 64 << 20
+    big = 20000
+    assert L.svdb_workspace_size(svdb.R64, big, 64, 64, None) > cap
+
+    def call(batch, m, n):
+        return L.svdb_svd_strided_batched_noalloc(
+            svdb.R64, batch, m, n, 0x1000, m, m * n, 0x2000, n, 0x3000, m, m * n, 0x4000, n,
+            n * n, 0.0, 0x5000, None, None)
+    assert call(big, 64, 64) == -2 and "static maximum" in svdb.last_error()
+    assert call(8, 256, 256) == svdb.ERR_UNSUPPORTED and "block method" in svdb.last_error()
+    assert call(0, 64, 64) == 0
