@@ -15,8 +15,7 @@ Choices and classes:
   * register-resident unblocked path (FP64, n <= 64), per (N, rows per
     lane): the wavefronts per matrix (1, 2 or 4).
 Each choice is timed on a batch of seeded matrices (half Gaussian, half with
-a geometric spectrum, kappa 1e6), through the C ABI, in the persistent
-launch; a choice whose results fail the accuracy check (every info 0, sigma
+a geometric spectrum, kappa 1e6), through the C ABI; a choice whose results fail the accuracy check (every info 0, sigma
 against LAPACK within 1e-12 normwise, 1e-5 in single precision) is never
 chosen.  The fastest admissible choice wins.
 """
