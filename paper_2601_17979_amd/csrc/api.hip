@@ -108,8 +108,13 @@ int block_choice(svdb_dtype_t dt, int m, int n, const svdb_opts_t &o, Plan *p)
     p->inner = o.inner_sweeps;
     p->tol_start = o.inner_tol_start;
     p->tol_rate = o.inner_tol_rate;
-    // the table's inner solve was measured with its own width
-    if (o.inner_sweeps == 0 && have && nb == t.nb) {
+    // the table's inner solve was measured with its own width, on m = n and
+    // m = 3 n; two block columns with m >= 8 np (much taller, where the
+    // converged solve replaces outer sweeps that each stream all m rows)
+    // keep the built-in rule
+    const int np = svdb::blocked_np(n, nb);
+    const bool very_tall = np == 2 * nb && m >= 8 * np;
+    if (o.inner_sweeps == 0 && have && nb == t.nb && !very_tall) {
         p->inner = t.inner;
         if (o.inner_tol_start <= 0.0 && t.tol_start > 0.0) {
             p->tol_start = t.tol_start;

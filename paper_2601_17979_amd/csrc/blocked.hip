@@ -249,7 +249,31 @@ struct IterShared {
     double Ji[CX ? N2 : 1][N2 + 1];
     double csc[NB];                   // c of the pairs of an inner iteration
     double cser[NB], csei[NB];        // e s (complex) or sign(g_ij) s
+    unsigned char rr[N2 - 1][NB][2];  // inner round robin: pair k of round r
     int rot;
+};
+
+// The 2x2 blocks (ka, kb), ka <= kb, of the upper triangle of the NB x NB
+// pair grid that thread tid updates in every round of an inner sweep (block
+// idx = tid + t kBT, row-major; ka = -1 past the end), decoded once.
+template <int NB>
+struct InnerBlocks {
+    static constexpr int NBLK = NB * (NB + 1) / 2, BPT = (NBLK + kBT - 1) / kBT;
+    int ka[BPT], kb[BPT];
+    __device__ __forceinline__ InnerBlocks(int tid)
+    {
+#pragma unroll
+        for (int t = 0; t < BPT; t++) {
+            const int idx = tid + t * kBT;
+            int a = 0, rem = idx;
+            while (rem >= NB - a && a < NB) {
+                rem -= NB - a;
+                a++;
+            }
+            ka[t] = idx < NBLK ? a : -1;
+            kb[t] = a + rem;
+        }
+    }
 };
 
 // Per-thread share of one chunk (kCH rows x 2nb columns) held in registers so
@@ -390,13 +414,13 @@ __device__ __forceinline__ void update_block_columns(IterShared<T, CX, NB> &s, E
 template <class T, int NB>
 __device__ __forceinline__ double inner_sweep_real(IterShared<T, false, NB> &s, double tol)
 {
-    constexpr int N2 = 2 * NB;
+    constexpr int N2 = 2 * NB, JPT = (N2 * NB + kBT - 1) / kBT;
     const int tid = threadIdx.x;
+    const InnerBlocks<NB> blk(tid);
     double mc = 0.0;
     for (int r = 0; r < N2 - 1; r++) {
         if (tid < NB) {
-            int i, j;
-            rr_pair(N2, r, tid, i, j);
+            const int i = s.rr[r][tid][0], j = s.rr[r][tid][1];
             const double gii = s.u.R[i][i], gjj = s.u.R[j][j], gij = s.u.R[i][j];
             double c = 1.0, es = 0.0;
             const double ag = fabs(gij);
@@ -417,16 +441,12 @@ __device__ __forceinline__ double inner_sweep_real(IterShared<T, false, NB> &s, 
         // ka <= kb (G stays symmetric: the block (kb, ka) is the transpose);
         // J <- J J_r.  The rotation of a pair maps column i to
         // c col_i + es col_j and column j to -es col_i + c col_j.
-        for (int idx = tid; idx < NB * (NB + 1) / 2; idx += kBT) {
-            int ka = 0, rem = idx;   // idx -> (ka, kb), ka <= kb, row-major upper triangle
-            while (rem >= NB - ka) {
-                rem -= NB - ka;
-                ka++;
-            }
-            const int kb = ka + rem;
-            int ia, ja, ib, jb;
-            rr_pair(N2, r, ka, ia, ja);
-            rr_pair(N2, r, kb, ib, jb);
+#pragma unroll
+        for (int t = 0; t < InnerBlocks<NB>::BPT; t++) {
+            const int ka = blk.ka[t], kb = blk.kb[t];
+            if (ka < 0) continue;
+            const int ia = s.rr[r][ka][0], ja = s.rr[r][ka][1];
+            const int ib = s.rr[r][kb][0], jb = s.rr[r][kb][1];
             const double ca = s.csc[ka], ea = s.cser[ka], cb = s.csc[kb], eb = s.cser[kb];
             const double g00 = s.u.R[ia][ib], g01 = s.u.R[ia][jb];
             const double g10 = s.u.R[ja][ib], g11 = s.u.R[ja][jb];
@@ -445,10 +465,12 @@ __device__ __forceinline__ double inner_sweep_real(IterShared<T, false, NB> &s, 
                 s.u.R[jb][ja] = n11;
             }
         }
-        for (int idx = tid; idx < N2 * NB; idx += kBT) {
+#pragma unroll
+        for (int t = 0; t < JPT; t++) {
+            const int idx = tid + t * kBT;
+            if (idx >= N2 * NB) break;
             const int row = idx / NB, kb = idx % NB;
-            int ib, jb;
-            rr_pair(N2, r, kb, ib, jb);
+            const int ib = s.rr[r][kb][0], jb = s.rr[r][kb][1];
             const double cb = s.csc[kb], eb = s.cser[kb];
             const double x = s.Jr[row][ib], y = s.Jr[row][jb];
             s.Jr[row][ib] = cb * x + eb * y;
@@ -479,13 +501,13 @@ __device__ __forceinline__ cd cconj(cd a) { return {a.r, -a.i}; }
 template <class T, int NB>
 __device__ __forceinline__ double inner_sweep_cx(IterShared<T, true, NB> &s, double tol)
 {
-    constexpr int N2 = 2 * NB;
+    constexpr int N2 = 2 * NB, JPT = (N2 * NB + kBT - 1) / kBT;
     const int tid = threadIdx.x;
+    const InnerBlocks<NB> blk(tid);
     double mc = 0.0;
     for (int r = 0; r < N2 - 1; r++) {
         if (tid < NB) {
-            int i, j;
-            rr_pair(N2, r, tid, i, j);
+            const int i = s.rr[r][tid][0], j = s.rr[r][tid][1];
             const double gii = s.Gr[i][i], gjj = s.Gr[j][j];
             const double gr = s.Gr[i][j], gim = s.Gi[i][j];
             double c = 1.0, er = 0.0, ei = 0.0;
@@ -507,16 +529,12 @@ __device__ __forceinline__ double inner_sweep_cx(IterShared<T, true, NB> &s, dou
         __syncthreads();
         // G <- J_r^H G J_r on the blocks with ka <= kb (the block (kb, ka)
         // is the conjugate transpose); J <- J J_r.
-        for (int idx = tid; idx < NB * (NB + 1) / 2; idx += kBT) {
-            int ka = 0, rem = idx;
-            while (rem >= NB - ka) {
-                rem -= NB - ka;
-                ka++;
-            }
-            const int kb = ka + rem;
-            int ia, ja, ib, jb;
-            rr_pair(N2, r, ka, ia, ja);
-            rr_pair(N2, r, kb, ib, jb);
+#pragma unroll
+        for (int t = 0; t < InnerBlocks<NB>::BPT; t++) {
+            const int ka = blk.ka[t], kb = blk.kb[t];
+            if (ka < 0) continue;
+            const int ia = s.rr[r][ka][0], ja = s.rr[r][ka][1];
+            const int ib = s.rr[r][kb][0], jb = s.rr[r][kb][1];
             const double ca = s.csc[ka], cb = s.csc[kb];
             const cd ea = {s.cser[ka], s.csei[ka]}, eb = {s.cser[kb], s.csei[kb]};
             const cd g00 = {s.Gr[ia][ib], s.Gi[ia][ib]}, g01 = {s.Gr[ia][jb], s.Gi[ia][jb]};
@@ -550,10 +568,12 @@ __device__ __forceinline__ double inner_sweep_cx(IterShared<T, true, NB> &s, dou
                 s.Gi[jb][ja] = -n11.i;
             }
         }
-        for (int idx = tid; idx < N2 * NB; idx += kBT) {
+#pragma unroll
+        for (int t = 0; t < JPT; t++) {
+            const int idx = tid + t * kBT;
+            if (idx >= N2 * NB) break;
             const int row = idx / NB, kb = idx % NB;
-            int ib, jb;
-            rr_pair(N2, r, kb, ib, jb);
+            const int ib = s.rr[r][kb][0], jb = s.rr[r][kb][1];
             const double cb = s.csc[kb];
             const cd eb = {s.cser[kb], s.csei[kb]};
             const cd x = {s.Jr[row][ib], s.Ji[row][ib]}, y = {s.Jr[row][jb], s.Ji[row][jb]};
@@ -635,6 +655,13 @@ __device__ __forceinline__ void iter_body(IterShared<T, CX, NB> &s, int m, int n
         }
     }
     for (int idx = tid; idx < N2 * N2; idx += kBT) s.Jr[idx / N2][idx % N2] = (idx / N2 == idx % N2);
+    // the inner solve's round-robin table (the ordering of Alg. 1's sweep)
+    for (int idx = tid; idx < (N2 - 1) * NB; idx += kBT) {
+        int i, j;
+        rr_pair(N2, idx / NB, idx % NB, i, j);
+        s.rr[idx / NB][idx % NB][0] = (unsigned char)i;
+        s.rr[idx / NB][idx % NB][1] = (unsigned char)j;
+    }
     if (tid == 0) s.rot = 0;
     __syncthreads();
 

@@ -208,3 +208,20 @@ def test_noalloc_refusals_before_any_launch():
     assert call(big, 64, 64) == -2 and "static maximum" in svdb.last_error()
     assert call(8, 256, 256) == svdb.ERR_UNSUPPORTED and "block method" in svdb.last_error()
     assert call(0, 64, 64) == 0
+
+
+def test_plan_reads_the_tuned_table():
+    """With nb left open, the block method's width is the measured table's
+    (csrc/tuned.inc) for each of its (dtype, n class, tall) rows."""
+    import re
+    txt = open(os.path.join(ROOT, "paper_2601_17979_amd", "csrc", "tuned.inc")).read()
+    blk = txt[txt.index("kTunedBlock"):txt.index("kTunedResident")]
+    rows = [tuple(int(x) for x in r.groups()) for r in
+            re.finditer(r"\{\s*(\d+),\s*(\d+),\s*(\d+),\s*(\d+),\s*(-?\d+),", blk)]
+    assert rows, "the table is empty"
+    lower = {32: 16, 64: 32, 128: 64, 256: 128, 512: 256}
+    dts = {0: torch.float32, 1: torch.float64, 2: torch.complex64, 3: torch.complex128}
+    for dt, nmax, tall, nb, _ in rows:
+        n = lower[nmax] + 5
+        m = 3 * n if tall else n
+        assert svdb.plan(dts[dt], m, n, path="blocked", precondition=0)[1] == nb, (dt, nmax, tall)

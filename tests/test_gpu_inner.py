@@ -32,9 +32,11 @@ MODES = [(2, 2), (3, 3), (-1, 0)]
 
 
 def _auto_inner(m, n, fp32=False):
-    """The oracle's inner-sweep count for the GPU's auto choice (the tuned
-    table of the library: one sweep for l > 2; for l = 2 two, or for
-    m >= 8 np the converged solve (FP64) or three (FP32))."""
+    """The oracle's inner-sweep count for the GPU's auto choice: the measured
+    table (csrc/tuned.inc) where it has a row, which for these shapes agrees
+    with the built-in rule (one sweep for l > 2; for l = 2 two, or for
+    m >= 8 np, which the table leaves to the rule, the converged solve (FP64)
+    or three (FP32))."""
     l = max(2, -(-n // 16))
     l += l & 1
     if l > 2:
@@ -164,7 +166,7 @@ def test_dynamic_tolerance_to_convergence(cx):
     need = int(np.ceil(np.log(tol / DYN[0]) / np.log(DYN[1]))) + 1
     for m, n in [(64, 64), (130, 96), (40, 24)]:
         A = _batch(m, n, 4, seed=9750 + m + n + int(cx), complex_=cx)
-        S, U, V, info, sw = run_gpu(A, dtype=dt, path="blocked", inner_sweeps=-1,
+        S, U, V, info, sw = run_gpu(A, dtype=dt, path="blocked", nb=16, inner_sweeps=-1,
                                     inner_tol=DYN)
         out = [oracle.block_gesvj(A[k], 16, inner_sweeps=0, tol_start=DYN[0],
                                   tol_rate=DYN[1]) for k in range(A.shape[0])]
