@@ -243,9 +243,10 @@ def oracle_each(mats, threads=16):
 
 def square256_leg(dev, grp, steps=2, warmup=1, cpu_sample=40):
     """configs: 4000 FP64 256 x 256, geometric spectra, half kappa 1e2, half
-    1e8.  Three modes of the same call: all-FP64 block sweeps on A, FP32 MFMA
-    sweeps + FP64 refinement, and the default (QR preconditioning, block
-    sweeps on R2^T).  Each with its sigma error against the oracle on a
+    1e8.  Four modes of the same call: all-FP64 block sweeps on A, FP32 MFMA
+    sweeps + FP64 refinement, the default (QR preconditioning, block sweeps
+    on R2^T), and the QR preconditioning with FP32 sweeps + FP64 refinement
+    on R2^T.  Each with its sigma error against the oracle on a
     sample."""
     import torch
     from paper_2601_17979_amd import svdb
@@ -254,7 +255,8 @@ def square256_leg(dev, grp, steps=2, warmup=1, cpu_sample=40):
     Ag = svdb.col_major(torch.from_numpy(grp.A).to(dev))
     modes = {"fp64": dict(path="blocked", nb=16, precision=0, precondition=0),
              "fp32+fp64": dict(path="blocked", nb=16, precision=1, precondition=0),
-             "qr+fp64": dict()}
+             "qr+fp64": dict(),
+             "qr+fp32+fp64": dict(precision=1)}
     k = max(2, cpu_sample)
     pick = np.r_[0:k // 2, half:half + k - k // 2]
     Sr, swr, t_cpu, thr = oracle_each([grp.A[i] for i in pick])
@@ -274,7 +276,7 @@ def square256_leg(dev, grp, steps=2, warmup=1, cpu_sample=40):
     # sweeps executed, plus the two QRs and the two applications of Q
     sw = res[best].pop("_sw")
     fl = flops_blocked(256, 256, 16, sw)
-    if best == "qr+fp64":
+    if best in ("qr+fp64", "qr+fp32+fp64"):
         fl += len(sw) * (2 * (4.0 * 256 ** 3 / 3.0) + 2.0 * 256 ** 3 + 2.0 * 256 ** 3)
     for r in res.values():
         r.pop("_sw", None)
@@ -284,6 +286,7 @@ def square256_leg(dev, grp, steps=2, warmup=1, cpu_sample=40):
                     f"(Haar factors)",
         "value": res[best]["svds_per_s"], "unit": "SVDs/s", "best_mode": best, "modes": res,
         "mixed_vs_fp64": res["fp32+fp64"]["svds_per_s"] / res["fp64"]["svds_per_s"],
+        "qr_mixed_vs_qr_fp64": res["qr+fp32+fp64"]["svds_per_s"] / res["qr+fp64"]["svds_per_s"],
         "roofline": {"bound": "mfma", "achieved": achieved / 1e12, "peak": 78.6,
                      "unit": "TFLOP/s", "frac": achieved / 78.6e12, "traffic": None,
                      "kernel": f"{best} call (block method dominant)",

@@ -178,7 +178,8 @@ int make_plan(svdb_dtype_t dt, int m, int n, const svdb_opts_t &o, Plan *p)
         return 0;
     }
     // wide matrices: the block Jacobi on R^T (AUTO, or BLOCKED with 1)
-    const bool pcb_ok = real && o.precision == 0 && !pc_ok &&
+    // (FP64 input may ask for the mixed mode on R2^T, precision 1)
+    const bool pcb_ok = real && (o.precision == 0 || dt == SVDB_R64) && !pc_ok &&
                         svdb::precond_big_supported(m, n);
     const bool pcb_req = (path == SVDB_PATH_AUTO && o.precondition != 0) ||
                          (path == SVDB_PATH_BLOCKED && o.precondition == 1);
@@ -288,7 +289,8 @@ size_t svdb_workspace_size(svdb_dtype_t dtype, int batch, int m, int n, const sv
     // FP32 on an FP64 path: FP64 copies of A, S, U and V come first
     const size_t w64 = p.via64 ? via64_bytes(batch, m, n) : 0;
     if (p.precond) return w64 + svdb::precond_workspace_bytes(batch, m, n);
-    if (p.precond_big) return w64 + svdb::precond_big_workspace_bytes(batch, m, n, p.nb);
+    if (p.precond_big)
+        return w64 + svdb::precond_big_workspace_bytes(batch, m, n, p.nb, o.precision == 1);
     if (p.precond_tall) return w64 + svdb::precond_tall_workspace_bytes(batch, m, n);
     if (p.path == SVDB_PATH_BLOCKED)
         return svdb::blocked_workspace_bytes(batch, m, n, p.nb, elt_bytes(dtype),
@@ -342,7 +344,8 @@ hipError_t run_tall(svdb_dtype_t dtype, const Plan &p, const svdb_opts_t &o, int
                                        (double *)S, strideS, (double *)U, ldu, strideU,
                                        (double *)V, ldv, strideV, tol, o.max_sweeps, o.masking,
                                        info, o.sweeps, workspace, s, p.inner, o.persistent,
-                                       p.tol_start, p.tol_rate);
+                                       p.tol_start, p.tol_rate,
+                                       o.precision == 1 ? fmax(tol, default_tol(SVDB_R32)) : 0.0);
     } else if (p.precond) {
         e = svdb::launch_precond_d(batch, m, n, o.waves, (const double *)A, lda, strideA,
                                    (double *)S, strideS, (double *)U, ldu, strideU, (double *)V,

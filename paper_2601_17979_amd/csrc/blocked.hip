@@ -50,10 +50,19 @@ constexpr int kCH = 64;    // rows per streamed chunk
 constexpr int kVbNb = 16;  // block width of uneven batches
 
 // The FP32 phase of the mixed mode hands over to FP64 once the largest pair
-// cosine of a sweep is at most this: FP32 sweeps cannot resolve directions
-// whose singular values are below about u32 sigma_1, so further FP32 sweeps
-// would be redone in FP64 anyway.
+// cosine of a sweep is at most kSwitchCos, or once it stalls: from sweep
+// kStallSweeps on, a sweep whose largest cosine is more than half the
+// previous one's.  FP32 sweeps cannot resolve directions whose singular
+// values are below about u32 sigma_1; on such (ill-conditioned) matrices
+// the cosine stops falling long before kSwitchCos, and the sweeps past the
+// stall would be redone in FP64 anyway.
 constexpr double kSwitchCos = 0x1p-7;
+constexpr int kStallSweeps = 4;
+
+__host__ __device__ __forceinline__ bool fp32_phase_done(double mc, double prev, int sweeps)
+{
+    return mc <= kSwitchCos || (sweeps >= kStallSweeps && mc > 0.5 * prev);
+}
 
 // A column whose squared norm is below kNegligible (a norm below 2^-480 of
 // the pre-scaled matrix, whose largest entry is about 1) is never rotated,
@@ -746,7 +755,7 @@ __global__ void blk_sweep_end(int batch, BlkState *st, int *pending, int masking
         s.sweeps += 1;
         const double mc = __longlong_as_double((long long)s.maxcos);
         bool fin = !s.rotated && at_tol;
-        if (phase32 && mc <= kSwitchCos) fin = true;
+        if (phase32 && fp32_phase_done(mc, s.prevcos, s.sweeps)) fin = true;
         s.prevcos = mc;
         if (fin) s.done = 1;
     }
@@ -836,7 +845,7 @@ __device__ __forceinline__ bool close_sweep(BlkState &s, int max_sweeps, int mas
         s.sweeps += 1;
         const double mc = __longlong_as_double((long long)s.maxcos);
         bool fin = !s.rotated && at_tol;
-        if (phase32 && mc <= kSwitchCos) fin = true;
+        if (phase32 && fp32_phase_done(mc, s.prevcos, s.sweeps)) fin = true;
         s.prevcos = mc;
         if (fin) {
             s.done = 1;

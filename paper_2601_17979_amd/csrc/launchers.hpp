@@ -62,14 +62,17 @@ hipError_t launch_qr_blocked_batch(int batch, int m, int n, const double *A, int
                                    void *scratch, hipStream_t stream);
 void launch_apply_q_jobs(const QrJob *jobs, const int *list, int count, int max_m,
                          hipStream_t stream);
-size_t precond_big_workspace_bytes(int batch, int m, int n, int nb);
+size_t precond_big_workspace_bytes(int batch, int m, int n, int nb, bool mixed = false);
 hipError_t launch_precond_big_d(int batch, int m, int n, int nb, const double *A, int lda,
                                 long long sA, double *S, long long sS, double *U, int ldu,
                                 long long sU, double *V, int ldv, long long sV, double tol,
                                 int max_sweeps, int masking, int *info, int *sweeps, void *ws,
                                 hipStream_t stream, int inner = 0, int persistent = 0,
-                                double tol_start = 0.0, double tol_rate = 0.0);
+                                double tol_start = 0.0, double tol_rate = 0.0,
+                                double tol32 = 0.0);
 
+// launch_precond_big_d: tol32 > 0 runs the block Jacobi on R2^T in the mixed
+// mode (FP32 sweeps to tol32, then FP64 refinement).
 // blocked.hip: block one-sided Jacobi with MFMA Gram/updates (real and
 // complex, FP64 and FP32, and FP32 sweeps followed by an FP64 refinement).
 // blocked_nb returns the block width for a request (0: not supported).

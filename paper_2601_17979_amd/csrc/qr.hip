@@ -1040,11 +1040,11 @@ size_t big_second_bytes(int batch, int n)
     return 2 * al256((size_t)batch * n * n * 8) + al256((size_t)batch * n * 8);
 }
 
-size_t precond_big_workspace_bytes(int batch, int m, int n, int nb)
+size_t precond_big_workspace_bytes(int batch, int m, int n, int nb, bool mixed)
 {
     return big_head_bytes(batch, m, n) + big_second_bytes(batch, n) +
            qrb_carve(batch, m, n, nullptr, nullptr) +
-           blocked_workspace_bytes(batch, n, n, nb, 8, false);
+           blocked_workspace_bytes(batch, n, n, nb, 8, mixed);
 }
 
 namespace {
@@ -1079,7 +1079,7 @@ hipError_t launch_precond_big_d(int batch, int m, int n, int nb, const double *A
                                 long long sU, double *V, int ldv, long long sV, double tol,
                                 int max_sweeps, int masking, int *info, int *sweeps, void *ws,
                                 hipStream_t stream, int inner, int persistent, double tol_start,
-                                double tol_rate)
+                                double tol_rate, double tol32)
 {
     if (!precond_big_supported(m, n)) return hipErrorInvalidValue;
     const long long snn = (long long)n * n;
@@ -1107,9 +1107,16 @@ hipError_t launch_precond_big_d(int batch, int m, int n, int nb, const double *A
     if (e == hipSuccess)
         e = launch_qr_blocked(batch, n, n, X1, n, snn, Vq2, X2, tau2, qws, stream);
     if (e != hipSuccess) return e;
-    e = launch_blocked_d(batch, n, n, nb, X2, n, snn, S, sS, U ? Ux : nullptr, n, snn,
-                         V ? J : nullptr, n, snn, tol, max_sweeps, masking, info, sweeps, bws,
-                         stream, inner, persistent, tol_start, tol_rate);
+    // the block Jacobi on X = R2^T, all-FP64 or FP32 sweeps + FP64 refinement
+    if (tol32 > 0.0)
+        e = launch_blocked_mixed_d(batch, n, n, nb, X2, n, snn, S, sS, U ? Ux : nullptr, n, snn,
+                                   V ? J : nullptr, n, snn, tol, tol32, max_sweeps, masking,
+                                   info, sweeps, bws, stream, inner, persistent, tol_start,
+                                   tol_rate);
+    else
+        e = launch_blocked_d(batch, n, n, nb, X2, n, snn, S, sS, U ? Ux : nullptr, n, snn,
+                             V ? J : nullptr, n, snn, tol, max_sweeps, masking, info, sweeps,
+                             bws, stream, inner, persistent, tol_start, tol_rate);
     if (e == hipSuccess && U)
         e = launch_apply_g(batch, m, n, Vq1, tau1, Ux, U, ldu, sU, info, stream);
     if (e == hipSuccess && V)

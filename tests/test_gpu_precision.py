@@ -103,3 +103,21 @@ def test_masking_off_gives_the_same_result():
     say(f"[masking] sweeps {s1.tolist()}")
     assert np.array_equal(i0, i1) and np.array_equal(s0, s1)
     assert np.array_equal(S0, S1) and np.array_equal(U0, U1) and np.array_equal(V0, V1)
+
+
+@pytest.mark.parametrize("m,n", [(100, 100), (130, 65), (200, 130), (256, 256)])
+def test_mixed_mode_on_the_preconditioned_path(m, n):
+    """AUTO with precision 1 on FP64 input wider than 64 columns: the QR
+    pre-processing, FP32 sweeps on R2^T, then the FP64 refinement; the FP64
+    tolerances hold, at kappa 1e8 and kappa 1e2."""
+    import torch
+    from paper_2601_17979_amd import svdb
+    assert svdb.plan(torch.float64, m, n, precision=1)[0] == svdb.PATH_BLOCKED
+    for kappa in (1e8, 1e2):
+        A = _batch((m, n), 4, seed=5600 + m + n + int(kappa > 1e3), kinds=("geo", "gauss"),
+                   kappa=kappa)
+        say(f"[qr + mixed {m}x{n} kappa {kappa:g}]")
+        S, U, V, info, sw = run_gpu(A, precision=1)
+        Sr, _, _, swr, infor = oracle_batch(A)
+        compare_with_oracle(A, S, U, V, info, Sr, infor, label=f"qr+mixed {m}x{n}")
+        say(f"  sweeps {sw.tolist()} (oracle on A: {swr.tolist()})")
