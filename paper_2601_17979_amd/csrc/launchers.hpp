@@ -17,10 +17,15 @@ hipError_t launch_plain_d(int batch, int m, int n, const double *A, int lda, lon
 
 // resident.hip: register-resident unblocked Jacobi, FP64, n <= 64.
 bool resident_config(int m, int n, int ns, int *N, int *R, int *NS);
+// nv: iterate on W alone (no V rows; V is not written), for m <= 64 and
+// 32 < n <= 64 (resident_nv_supported).  only: NULL or per-matrix flags,
+// matrices with flag 0 are skipped.
+bool resident_nv_supported(int m, int n);
 hipError_t launch_resident_d(int batch, int m, int n, int ns, const double *A, int lda,
                              long long sA, double *S, long long sS, double *U, int ldu,
                              long long sU, double *V, int ldv, long long sV, double tol,
-                             int max_sweeps, int *info, int *sweeps, hipStream_t stream);
+                             int max_sweeps, int *info, int *sweeps, hipStream_t stream,
+                             bool nv = false, const int *only = nullptr);
 
 // qr.hip: QR preconditioning (A = Q R, the resident Jacobi on R^T, U = Q J).
 bool precond_supported(int m, int n);

@@ -333,6 +333,119 @@ __global__ __launch_bounds__(kQT) void apply_q_d(int m, int n, const double *__r
     }
 }
 
+// J = X^-1 W with W = U_x diag(S): the right singular vectors of the Jacobi
+// on X = R2^T recovered from its left ones, as in the preconditioned Jacobi
+// SVD of Drmac and Veselic (the section "Algorithmic Background", paragraph
+// "Efficient implementations", cites it), so that the Jacobi need not
+// accumulate them.  X is lower triangular (n x n, ld n), U_x and J are n x n
+// (ld n), S has stride sS.  One wave per matrix, column c of J in lane c:
+// forward substitution, every lane reading the same entries of X.  The
+// product is accurate when W is the one-sided Jacobi's (column-wise
+// backward stable) iterate; it is accepted only if ||J^T J - I||_F <= thr,
+// else flag[b] = 1 asks for the V-accumulating Jacobi on this matrix.
+// Matrices with info 2 get flag 0 and are left untouched.
+template <int N>
+__global__ __launch_bounds__(64) void solve_rt_d(int n, const double *__restrict__ X,
+                                                 const double *__restrict__ Ux,
+                                                 const double *__restrict__ S, long long sS,
+                                                 double *J, int *flag,
+                                                 const int *__restrict__ info, double thr)
+{
+    static_assert(N == 64, "one column of J per lane");
+    // rows of J, each 8-column group padded by 2 doubles (conflict-free
+    // 16-byte reads of the eight groups); the same memory first holds X
+    constexpr int kRow = N + N / 4;
+    __shared__ __align__(16) double Jr[N * kRow];
+    double *Xs = Jr;   // Xs[k * N + i] = X(i - d, k - d), lower triangle
+    const int b = blockIdx.x, c = threadIdx.x;
+    if (info[b] == 2) {
+        if (c == 0) flag[b] = 0;
+        return;
+    }
+    // n < N: the system is embedded as diag(I, X), rows and columns shifted
+    // by d; every address below is clamped into the matrix so that all the
+    // loads of a lane can be in flight together
+    const int d = N - n;
+    const bool act = c < n;
+    const int cx = c >= d ? c - d : 0, cc = act ? c : n - 1;
+    X += (size_t)b * n * n;
+    Ux += (size_t)b * n * n;
+    J += (size_t)b * n * n;
+    const double sc = act ? S[(size_t)b * sS + c] : 0.0;
+    double w[N];
+    {
+        double xv[N];
+#pragma unroll
+        for (int k = 0; k < N; k++) xv[k] = X[(size_t)(k >= d ? k - d : 0) * n + cx];
+#pragma unroll
+        for (int i = 0; i < N; i++) w[i] = Ux[(size_t)cc * n + (i >= d ? i - d : 0)];
+#pragma unroll
+        for (int k = 0; k < N; k++)
+            if (c >= k) Xs[k * N + c] = k >= d ? xv[k] : (c == k ? 1.0 : 0.0);
+    }
+#pragma unroll
+    for (int i = 0; i < N; i++) w[i] = (act && i >= d) ? w[i] * sc : 0.0;
+    __syncthreads();
+    // forward substitution, all lanes reading the same entries of X
+#pragma unroll
+    for (int k = 0; k < N; k++) {
+        const double *xk = Xs + k * N;
+        w[k] = w[k] / xk[k];
+#pragma unroll
+        for (int i = (k + 1) & ~1; i < N; i += 2) {
+            const double2 x = *reinterpret_cast<const double2 *>(xk + i);
+            if (i > k) w[i] = fma(-x.x, w[k], w[i]);
+            w[i + 1] = fma(-x.y, w[k], w[i + 1]);
+        }
+    }
+    __syncthreads();
+    double *jc = J + (size_t)(act ? c : 0) * n - d;
+    const int cp = c + 2 * (c / 8);
+#pragma unroll
+    for (int i = 0; i < N; i++) {
+        if (act && i >= d) jc[i] = w[i];
+        Jr[i * kRow + cp] = act ? w[i] : 0.0;
+    }
+    __syncthreads();
+    // ||J^T J - I||_F: lane (p, q) forms the 8 x 8 block (8p.., 8q..) of
+    // J^T J as a sum of outer products of row segments
+    const int p = c / 8, q = c % 8;
+    double acc[8][8];
+#pragma unroll
+    for (int a2 = 0; a2 < 8; a2++)
+#pragma unroll
+        for (int b2 = 0; b2 < 8; b2++) acc[a2][b2] = 0.0;
+#pragma unroll 2
+    for (int r = d; r < N; r++) {
+        const double2 *rp = reinterpret_cast<const double2 *>(&Jr[r * kRow + 10 * p]);
+        const double2 *rq = reinterpret_cast<const double2 *>(&Jr[r * kRow + 10 * q]);
+        double x[8], y[8];
+#pragma unroll
+        for (int t = 0; t < 4; t++) {
+            const double2 u = rp[t], v = rq[t];
+            x[2 * t] = u.x;
+            x[2 * t + 1] = u.y;
+            y[2 * t] = v.x;
+            y[2 * t + 1] = v.y;
+        }
+#pragma unroll
+        for (int a2 = 0; a2 < 8; a2++)
+#pragma unroll
+            for (int b2 = 0; b2 < 8; b2++) acc[a2][b2] = fma(x[a2], y[b2], acc[a2][b2]);
+    }
+    double err = 0.0;
+#pragma unroll
+    for (int a2 = 0; a2 < 8; a2++)
+#pragma unroll
+        for (int b2 = 0; b2 < 8; b2++) {
+            const int i = 8 * p + a2, j = 8 * q + b2;
+            const double e = acc[a2][b2] - (i == j ? 1.0 : 0.0);
+            err = (i < n && j < n) ? fma(e, e, err) : err;
+        }
+    err = wave_sum(err);
+    if (c == 0) flag[b] = !(sqrt(err) <= thr);
+}
+
 // rows per lane (power of two) and columns per group for an m x n matrix
 bool qr_shape(int m, int n, int *rpl, int *cpg)
 {
@@ -793,7 +906,7 @@ namespace {
 // the reflectors of both QRs (m x n, n x n), tau of both, the permutation
 struct PrecondWs {
     double *X1, *X2, *J, *Ux, *Vq1, *Vq2, *tau1, *tau2;
-    int *perm;
+    int *perm, *flag;   // flag: the solve for J was rejected
 };
 
 size_t precond_carve(int batch, int m, int n, void *ws, PrecondWs *w)
@@ -816,8 +929,10 @@ size_t precond_carve(int batch, int m, int n, void *ws, PrecondWs *w)
         w->tau2 = (double *)p;
         p += tn;
         w->perm = (int *)p;
+        p += pn;
+        w->flag = (int *)p;
     }
-    return 5 * nn + mn + 2 * tn + pn;
+    return 5 * nn + mn + 2 * tn + 2 * pn;
 }
 
 // head of the wide path's workspace: X = R^T, reflectors, tau, J, U_x
@@ -894,9 +1009,26 @@ hipError_t launch_precond_d(int batch, int m, int n, int ns, const double *A, in
     e = launch_qr_d<false>(batch, n, n, w.X1, n, snn, w.X2, V ? w.Vq2 : nullptr, w.tau2, nullptr,
                            stream);
     if (e != hipSuccess) return e;
-    // Jacobi on X = R2^T: its left vectors U_x feed U, its rotations J feed V
-    e = launch_resident_d(batch, n, n, ns, w.X2, n, snn, S, sS, U ? w.Ux : nullptr, n, snn,
-                          V ? w.J : nullptr, n, snn, tol, max_sweeps, info, sweeps, stream);
+    // Jacobi on X = R2^T: its left vectors U_x feed U, its rotations J feed V.
+    // For 32 < n <= 64 it iterates on W alone and J = X^-1 U_x diag(S) comes
+    // from a triangular solve; matrices whose J fails the orthogonality check
+    // run the Jacobi again with J accumulated.
+    if (resident_nv_supported(n, n)) {
+        e = launch_resident_d(batch, n, n, ns, w.X2, n, snn, S, sS, w.Ux, n, snn, nullptr, n, snn,
+                              tol, max_sweeps, info, sweeps, stream, true, nullptr);
+        if (e == hipSuccess && V) {
+            hipLaunchKernelGGL(solve_rt_d<64>, dim3(batch), dim3(64), 0, stream, n,
+                               (const double *)w.X2, (const double *)w.Ux, (const double *)S, sS,
+                               w.J, w.flag, (const int *)info, 0x1p-46 * n);
+            e = hipGetLastError();
+            if (e == hipSuccess)
+                e = launch_resident_d(batch, n, n, ns, w.X2, n, snn, S, sS, w.Ux, n, snn, w.J, n,
+                                      snn, tol, max_sweeps, info, sweeps, stream, false, w.flag);
+        }
+    } else {
+        e = launch_resident_d(batch, n, n, ns, w.X2, n, snn, S, sS, U ? w.Ux : nullptr, n, snn,
+                              V ? w.J : nullptr, n, snn, tol, max_sweeps, info, sweeps, stream);
+    }
     if (e != hipSuccess) return e;
     if (U) {
         e = launch_apply_d(batch, m, n, w.Vq1, w.tau1, w.Ux, U, ldu, sU, info, nullptr, stream);

@@ -199,23 +199,29 @@ struct Shared {
 // spills; what does not fit goes to scratch in the per-sweep fold and the
 // finalisation, which run once per sweep, while a second or third resident
 // wave per SIMD hides the latency of the loop's reduction and rotation chain.
-constexpr int res_waves_per_eu(int N, int RW, int NS)
+constexpr int res_waves_per_eu(int N, int RW, int NS, bool NV = false)
 {
-    return (RW + 1) * N / NS <= 32 ? 3 : ((RW + 1) * N / NS <= 64 ? 2 : 1);
+    return (RW + (NV ? 0 : 1)) * N / NS <= 32 ? 3 : ((RW + (NV ? 0 : 1)) * N / NS <= 64 ? 2 : 1);
 }
 
 // W rows live in slots 0..RW-1 (row 64 t + lane), V rows in slot RW (row =
 // lane); padding rows are zero, so Gram entries need no masks.  RW = 0 is
 // the packed layout: W row L in lane L of slot 0, V row L in lane 32 + L,
 // and the reductions over W rows read lanes 0..31 only.
-template <int N, int RW, int NS>
-__global__ __launch_bounds__(64 * NS, res_waves_per_eu(N, RW, NS)) void resident_jacobi_d(
+//
+// NV: no V rows (unpacked layouts only): the kernel iterates on W alone and
+// writes S and U; the caller forms V from W (for the triangular X of the QR
+// pre-processing, J = X^-1 W).  only: NULL, or a per-matrix flag; matrices
+// whose flag is 0 are skipped (the rerun of the ones a cheaper path left).
+template <int N, int RW, int NS, bool NV = false>
+__global__ __launch_bounds__(64 * NS, res_waves_per_eu(N, RW, NS, NV)) void resident_jacobi_d(
     int m, int n, const double *__restrict__ A, int lda, long long sA, double *S, long long sS,
     double *U, int ldu, long long sU, double *V, int ldv, long long sV, double tol,
-    int max_sweeps, int *info, int *sweeps_out)
+    int max_sweeps, int *info, int *sweeps_out, const int *only)
 {
     constexpr bool PK = RW == 0;
-    constexpr int R = PK ? 1 : RW + 1;   // register slots per column
+    static_assert(!(PK && NV), "the packed layout keeps V");
+    constexpr int R = PK ? 1 : RW + (NV ? 0 : 1);   // register slots per column
     constexpr int WS = PK ? 1 : RW;      // slots holding W rows
     constexpr int VS = PK ? 0 : RW;      // slot holding V rows
     constexpr int VL = PK ? 32 : 0;      // lane of V row 0
@@ -227,6 +233,7 @@ __global__ __launch_bounds__(64 * NS, res_waves_per_eu(N, RW, NS)) void resident
     __shared__ SH sh;
 
     const int b = blockIdx.x;
+    if (only && !only[b]) return;
     const int lane = threadIdx.x & 63;
     // wave index as a scalar, so that per-wave LDS addresses stay in SGPRs
     const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
@@ -256,8 +263,10 @@ __global__ __launch_bounds__(64 * NS, res_waves_per_eu(N, RW, NS)) void resident
             T[q][t] = xt;
             B[q][t] = xb;
         }
-        T[q][VS] = (lane == VL + ct) ? 1.0 : (PK ? T[q][VS] : 0.0);
-        B[q][VS] = (lane == VL + cb) ? 1.0 : (PK ? B[q][VS] : 0.0);
+        if constexpr (!NV) {
+            T[q][VS] = (lane == VL + ct) ? 1.0 : (PK ? T[q][VS] : 0.0);
+            B[q][VS] = (lane == VL + cb) ? 1.0 : (PK ? B[q][VS] : 0.0);
+        }
     }
     bad = __any(bad);
     amax = wave_max(amax);
@@ -553,15 +562,18 @@ __global__ __launch_bounds__(64 * NS, res_waves_per_eu(N, RW, NS)) void resident
             const double nc = sh.nrm[c];
             const double inv = nc > 0.0 ? rsq_nr(nc) : 0.0;   // 1 / ||stored column||
             const double dv = sh.d[c];
+            (void)dv;
 #pragma unroll
             for (int t = 0; t < WS; t++) {
                 const double val = h ? B[q][t] : T[q][t];
                 const int s = 64 * t + lane;
                 if (U && s < m) U[(size_t)rk * ldu + s] = val * inv;
             }
-            const int vr = lane - VL;
-            if (V && vr >= 0 && vr < n)
-                V[(size_t)rk * ldv + vr] = (h ? B[q][VS] : T[q][VS]) * dv;
+            if constexpr (!NV) {
+                const int vr = lane - VL;
+                if (V && vr >= 0 && vr < n)
+                    V[(size_t)rk * ldv + vr] = (h ? B[q][VS] : T[q][VS]) * dv;
+            }
         }
     }
     bool any_zero = false;
@@ -609,15 +621,15 @@ __global__ __launch_bounds__(64 * NS, res_waves_per_eu(N, RW, NS)) void resident
     }
 }
 
-template <int N, int R, int NS>
+template <int N, int R, int NS, bool NV = false>
 hipError_t launch_one(int batch, int m, int n, const double *A, int lda, long long sA, double *S,
                       long long sS, double *U, int ldu, long long sU, double *V, int ldv,
                       long long sV, double tol, int max_sweeps, int *info, int *sweeps,
-                      hipStream_t stream)
+                      hipStream_t stream, const int *only)
 {
-    hipLaunchKernelGGL((resident_jacobi_d<N, R, NS>), dim3(batch), dim3(64 * NS), 0, stream,
+    hipLaunchKernelGGL((resident_jacobi_d<N, R, NS, NV>), dim3(batch), dim3(64 * NS), 0, stream,
                        m, n, A, lda, sA, S, sS, U, ldu, sU, V, ldv, sV, tol, max_sweeps, info,
-                       sweeps);
+                       sweeps, only);
     return hipGetLastError();
 }
 
@@ -650,17 +662,40 @@ bool resident_config(int m, int n, int ns, int *N, int *R, int *NS)
     return true;
 }
 
+bool resident_nv_supported(int m, int n)
+{
+    return n > 32 && n <= 64 && m >= n && m <= 64;
+}
+
 hipError_t launch_resident_d(int batch, int m, int n, int ns, const double *A, int lda,
                              long long sA, double *S, long long sS, double *U, int ldu,
                              long long sU, double *V, int ldv, long long sV, double tol,
-                             int max_sweeps, int *info, int *sweeps, hipStream_t stream)
+                             int max_sweeps, int *info, int *sweeps, hipStream_t stream,
+                             bool nv, const int *only)
 {
+    if (nv) {   // W alone: N = 64, one slot of W rows
+        if (!resident_nv_supported(m, n)) return hipErrorInvalidValue;
+        const int w = ns == 0 ? 2 : ns;
+        if (w == 1)
+            return launch_one<64, 1, 1, true>(batch, m, n, A, lda, sA, S, sS, U, ldu, sU, nullptr,
+                                              ldv, sV, tol, max_sweeps, info, sweeps, stream,
+                                              only);
+        if (w == 2)
+            return launch_one<64, 1, 2, true>(batch, m, n, A, lda, sA, S, sS, U, ldu, sU, nullptr,
+                                              ldv, sV, tol, max_sweeps, info, sweeps, stream,
+                                              only);
+        if (w == 4)
+            return launch_one<64, 1, 4, true>(batch, m, n, A, lda, sA, S, sS, U, ldu, sU, nullptr,
+                                              ldv, sV, tol, max_sweeps, info, sweeps, stream,
+                                              only);
+        return hipErrorInvalidValue;
+    }
     int N, RW, NS;
     if (!resident_config(m, n, ns, &N, &RW, &NS)) return hipErrorInvalidValue;
 #define SVDB_RES(NN, RR, WW)                                                                   \
     if (N == NN && RW == RR && NS == WW)                                                       \
         return launch_one<NN, RR, WW>(batch, m, n, A, lda, sA, S, sS, U, ldu, sU, V, ldv, sV,  \
-                                      tol, max_sweeps, info, sweeps, stream);
+                                      tol, max_sweeps, info, sweeps, stream, only);
     SVDB_RES(16, 0, 1)
     SVDB_RES(16, 0, 2)
     SVDB_RES(32, 0, 1)

@@ -132,6 +132,33 @@ def test_precond_sweeps_match_the_oracle_pipeline():
         assert np.all(np.abs(sw - swr) <= 1), (sw.tolist(), swr.tolist())
 
 
+@pytest.mark.parametrize("m,n", [(33, 33), (48, 40), (64, 64), (100, 64), (256, 50)])
+def test_precond_v_from_triangular_solve(m, n):
+    """For 32 < n <= 64 the Jacobi on X = R2^T accumulates no rotations:
+    J = X^-1 U_x diag(S) comes from a triangular solve, and only matrices
+    whose J fails the orthogonality check run the Jacobi again with J
+    accumulated.  The batch holds matrices that pass (well and badly
+    conditioned, graded) and ones that fail (X singular: repeated and zero
+    columns), all compared with the oracle; S and U are the same bits
+    whether V is asked for or not (the Jacobi on W does not depend on J)."""
+    A = _batch((m, n), 10, seed=8700 + m + n)
+    A[2] = _batch((m, n), 1, seed=8800 + m, kinds=("geo",), kappa=1e12)[0]
+    A[3] = _batch((m, n), 1, seed=8810 + m, kinds=("random",), kappa=1e14)[0]
+    A[4][:, 5] = A[4][:, 9]
+    A[5][:, 1] = 0.0
+    A[5][:, n - 1] = 0.0
+    A[6][:, :] = np.outer(A[6][:, 0], np.arange(1, n + 1))   # rank one
+    A[7][:, n // 2:] = A[7][:, :n - n // 2] * 3.0             # rank n - n // 2
+    say(f"[precond nv {m}x{n}]")
+    S, U, V, info, sw = run_gpu(A, precondition=1)
+    Sr, Ur, Vr, swr, infor = oracle_batch(A)
+    compare_with_oracle(A, S, U, V, info, Sr, infor, label=f"precond nv {m}x{n}")
+    S1, U1, V1, info1, sw1 = run_gpu(A, precondition=1, compute_v=False)
+    assert V1 is None
+    assert np.array_equal(S, S1) and np.array_equal(U, U1)
+    assert np.array_equal(info, info1) and np.array_equal(sw, sw1)
+
+
 @pytest.mark.parametrize("m,n,count", [(96, 65, 4), (130, 96, 4), (200, 130, 3), (256, 256, 2),
                                        (1000, 100, 2)])
 def test_precond_wide_vs_oracle(m, n, count):
