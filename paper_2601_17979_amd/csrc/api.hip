@@ -157,7 +157,9 @@ int make_plan(svdb_dtype_t dt, int m, int n, const svdb_opts_t &o, Plan *p)
     // explicit request runs the resident kernel on A itself
     const bool pc_pays = !(dt == SVDB_R64 && n <= 16 && m < 8 * n);
     if (pc_req && pc_ok && (pc_pays || o.precondition == 1)) {
-        svdb::resident_config(n, n, o.waves, &rN, &rR, &rW);
+        if (!svdb::resident_config(n, n, o.waves, &rN, &rR, &rW))
+            return fail(SVDB_ERR_UNSUPPORTED,
+                        "resident path: no kernel with this many waves per matrix for n");
         p->path = SVDB_PATH_RESIDENT;
         p->nb = 0;
         p->threads = 64 * rW;

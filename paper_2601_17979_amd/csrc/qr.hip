@@ -279,13 +279,14 @@ __global__ __launch_bounds__(kQT) void apply_q_d(int m, int n, const double *__r
                                                  const double *__restrict__ tau,
                                                  const double *__restrict__ Y, double *U, int ldu,
                                                  long long sU, const int *info,
-                                                 const int *__restrict__ perm)
+                                                 const int *__restrict__ perm,
+                                                 const int *__restrict__ only)
 {
     extern __shared__ double Vl[];   // m x n, ld m
     __shared__ double s_tau[64];
     const int b = blockIdx.x, tid = threadIdx.x;
     const int grp = tid >> 4, gl = tid & 15;
-    if (info[b] == 2) return;
+    if (info[b] == 2 || (only && !only[b])) return;
     Vq += (size_t)b * m * n;
     Y += (size_t)b * n * n;
     U += (size_t)b * sU;
@@ -333,115 +334,167 @@ __global__ __launch_bounds__(kQT) void apply_q_d(int m, int n, const double *__r
     }
 }
 
-// J = X^-1 W with W = U_x diag(S): the right singular vectors of the Jacobi
-// on X = R2^T recovered from its left ones, as in the preconditioned Jacobi
-// SVD of Drmac and Veselic (the section "Algorithmic Background", paragraph
-// "Efficient implementations", cites it), so that the Jacobi need not
-// accumulate them.  X is lower triangular (n x n, ld n), U_x and J are n x n
-// (ld n), S has stride sS.  One wave per matrix, column c of J in lane c:
-// forward substitution, every lane reading the same entries of X.  The
-// product is accurate when W is the one-sided Jacobi's (column-wise
-// backward stable) iterate; it is accepted only if ||J^T J - I||_F <= thr,
+// V from the left vectors of the Jacobi on X = R2^T, without its rotations.
+// With A P = Q1 R1 and R1^T = Q2 R2 we have X = R1 Q2, so X V_x = U_x S gives
+// V = P Q2 V_x = P R1^-1 U_x S: a back substitution with the pivoted QR's
+// triangular factor, as in the preconditioned Jacobi SVD of Drmac and
+// Veselic (the section "Algorithmic Background", paragraph "Efficient
+// implementations", cites it).  Neither the rotations of the Jacobi nor Q2
+// are applied.  The product is accurate when U_x S is the one-sided Jacobi's
+// (column-wise backward stable) iterate and R1 is well conditioned up to row
+// scaling; it is kept only if ||J^T J - I||_F <= thr for J = R1^-1 U_x S,
 // else flag[b] = 1 asks for the V-accumulating Jacobi on this matrix.
-// Matrices with info 2 get flag 0 and are left untouched.
-template <int N>
-__global__ __launch_bounds__(64) void solve_rt_d(int n, const double *__restrict__ X,
-                                                 const double *__restrict__ Ux,
-                                                 const double *__restrict__ S, long long sS,
-                                                 double *J, int *flag,
-                                                 const int *__restrict__ info, double thr)
+//
+// One wave per matrix (n <= 64), column c of J in lane c.  R1 = X1^T (X1 n x
+// n, ld n, lower triangular) is staged in LDS as a packed upper triangle,
+// column k holding rows 0..k (padded to an even length, so that pairs of
+// rows are 16-byte reads); every lane reads the same entries.  A system with
+// n < 64 is embedded as diag(R1, I).  J^T J is formed on the FP64 matrix
+// cores from rows of J passed through LDS eight at a time, ten 16 x 16
+// blocks (the upper triangle).  V(perm[k], c) = J(k, c) goes to the output
+// directly.  Matrices with info 2 get flag 0 and are left untouched.
+__host__ __device__ constexpr int rp_off(int k)
 {
-    static_assert(N == 64, "one column of J per lane");
-    // rows of J, each 8-column group padded by 2 doubles (conflict-free
-    // 16-byte reads of the eight groups); the same memory first holds X
-    constexpr int kRow = N + N / 4;
-    __shared__ __align__(16) double Jr[N * kRow];
-    double *Xs = Jr;   // Xs[k * N + i] = X(i - d, k - d), lower triangle
+    return (k & 1) ? (k + 1) * (k + 1) / 2 : k * (k + 2) / 2;
+}
+
+typedef double dbl4 __attribute__((ext_vector_type(4)));
+
+template <int N>
+__global__ __launch_bounds__(64, 2) void solve_r1_d(int n, const double *__restrict__ X1,
+                                                    const double *__restrict__ Ux,
+                                                    const double *__restrict__ S, long long sS,
+                                                    const int *__restrict__ perm, double *V,
+                                                    int ldv, long long sV, int *flag,
+                                                    const int *__restrict__ info, double thr)
+{
+    static_assert(N == 64, "one column of J per lane, four 16-column blocks");
+    constexpr int kR = rp_off(N);          // packed triangle
+    constexpr int kRow = N + 16;           // row of J in LDS (2-way bank spread)
+    constexpr int kChunk = 8;              // rows of J per pass through LDS
+    __shared__ __align__(16) double sm[kR > 2 * kChunk * kRow ? kR : 2 * kChunk * kRow];
+    __shared__ double s_inv[N], s_sink[N];
     const int b = blockIdx.x, c = threadIdx.x;
     if (info[b] == 2) {
         if (c == 0) flag[b] = 0;
         return;
     }
-    // n < N: the system is embedded as diag(I, X), rows and columns shifted
-    // by d; every address below is clamped into the matrix so that all the
-    // loads of a lane can be in flight together
-    const int d = N - n;
     const bool act = c < n;
-    const int cx = c >= d ? c - d : 0, cc = act ? c : n - 1;
-    X += (size_t)b * n * n;
+    const int cc = act ? c : n - 1;
+    X1 += (size_t)b * n * n;
     Ux += (size_t)b * n * n;
-    J += (size_t)b * n * n;
-    const double sc = act ? S[(size_t)b * sS + c] : 0.0;
-    double w[N];
+    perm += (size_t)b * n;
+    V += (size_t)b * sV;
+    // ---- R1 into LDS: lane c writes its column, rows 0..c -----------------
+    // Loads and stores are unconditional (clamped addresses; the entries
+    // below the diagonal go to a per-lane sink), so that all the loads of a
+    // lane are in flight together.
     {
-        double xv[N];
+        double *col = sm + rp_off(c);
+        double x[N];
 #pragma unroll
-        for (int k = 0; k < N; k++) xv[k] = X[(size_t)(k >= d ? k - d : 0) * n + cx];
+        for (int k = 0; k < N; k++) x[k] = X1[(size_t)(k < n ? k : n - 1) * n + cc];   // R1(k, c)
 #pragma unroll
-        for (int i = 0; i < N; i++) w[i] = Ux[(size_t)cc * n + (i >= d ? i - d : 0)];
-#pragma unroll
-        for (int k = 0; k < N; k++)
-            if (c >= k) Xs[k * N + c] = k >= d ? xv[k] : (c == k ? 1.0 : 0.0);
+        for (int k = 0; k < N; k++) {
+            double *dst = k <= c ? col + k : s_sink + c;
+            *dst = act ? x[k] : (k == c ? 1.0 : 0.0);
+        }
+        s_inv[c] = act ? 1.0 / x[c < N ? c : 0] : 1.0;
     }
+    const double sc = act ? S[(size_t)b * sS + c] : 0.0;
+    double y[N];
 #pragma unroll
-    for (int i = 0; i < N; i++) w[i] = (act && i >= d) ? w[i] * sc : 0.0;
+    for (int i = 0; i < N; i++) y[i] = Ux[(size_t)cc * n + (i < n ? i : 0)];
+#pragma unroll
+    for (int i = 0; i < N; i++) y[i] = (act && i < n) ? y[i] * sc : 0.0;
     __syncthreads();
-    // forward substitution, all lanes reading the same entries of X
+    // ---- back substitution, R1 y = U_x(:, c) s_c ---------------------------
 #pragma unroll
-    for (int k = 0; k < N; k++) {
-        const double *xk = Xs + k * N;
-        w[k] = w[k] / xk[k];
+    for (int k = N - 1; k >= 0; k--) {
+        const double *rk = sm + rp_off(k);
+        y[k] *= s_inv[k];
 #pragma unroll
-        for (int i = (k + 1) & ~1; i < N; i += 2) {
-            const double2 x = *reinterpret_cast<const double2 *>(xk + i);
-            if (i > k) w[i] = fma(-x.x, w[k], w[i]);
-            w[i + 1] = fma(-x.y, w[k], w[i + 1]);
+        for (int i = 0; i < k; i += 2) {
+            const double2 r = *reinterpret_cast<const double2 *>(rk + i);
+            y[i] = fma(-r.x, y[k], y[i]);
+            if (i + 1 < k) y[i + 1] = fma(-r.y, y[k], y[i + 1]);
         }
     }
-    __syncthreads();
-    double *jc = J + (size_t)(act ? c : 0) * n - d;
-    const int cp = c + 2 * (c / 8);
+    __syncthreads();   // the triangle is no longer read
+    // ---- V = P J, through LDS 32 columns at a time ---------------------------
+    // lane c puts J(k, c) at row perm[k] of its column (stride N + 1: the 32
+    // lanes hit distinct banks), then each column goes out as one coalesced
+    // store, lane r writing row r
+    {
+        constexpr int kLd = N + 1;
+        static_assert(32 * kLd <= kR, "32 columns of V fit in the triangle's memory");
+        const int pv = perm[cc];   // lane k holds perm[k]
 #pragma unroll
-    for (int i = 0; i < N; i++) {
-        if (act && i >= d) jc[i] = w[i];
-        Jr[i * kRow + cp] = act ? w[i] : 0.0;
-    }
-    __syncthreads();
-    // ||J^T J - I||_F: lane (p, q) forms the 8 x 8 block (8p.., 8q..) of
-    // J^T J as a sum of outer products of row segments
-    const int p = c / 8, q = c % 8;
-    double acc[8][8];
+        for (int h = 0; h < 2; h++) {
+            double *col = sm + (c & 31) * kLd;
+            const bool mine = (c >> 5) == h && act;
 #pragma unroll
-    for (int a2 = 0; a2 < 8; a2++)
-#pragma unroll
-        for (int b2 = 0; b2 < 8; b2++) acc[a2][b2] = 0.0;
-#pragma unroll 2
-    for (int r = d; r < N; r++) {
-        const double2 *rp = reinterpret_cast<const double2 *>(&Jr[r * kRow + 10 * p]);
-        const double2 *rq = reinterpret_cast<const double2 *>(&Jr[r * kRow + 10 * q]);
-        double x[8], y[8];
-#pragma unroll
-        for (int t = 0; t < 4; t++) {
-            const double2 u = rp[t], v = rq[t];
-            x[2 * t] = u.x;
-            x[2 * t + 1] = u.y;
-            y[2 * t] = v.x;
-            y[2 * t + 1] = v.y;
+            for (int k = 0; k < N; k++) {
+                const int pk = __builtin_amdgcn_readlane(pv, k);
+                if (mine && k < n) col[pk] = y[k];
+            }
+            __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+            __builtin_amdgcn_wave_barrier();
+            __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+#pragma unroll 8
+            for (int j = 0; j < 32; j++) {
+                const int cj = 32 * h + j;
+                if (cj < n && act) V[(size_t)cj * ldv + c] = sm[j * kLd + c];
+            }
+            __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+            __builtin_amdgcn_wave_barrier();
+            __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
         }
+    }
+    // ---- ||J^T J - I||_F on the matrix cores --------------------------------
+    // operand of 16-column block P at row step s: lane l supplies
+    // J(4 s + l / 16, 16 P + l % 16), as A (transposed) and as B; result
+    // register v of lane l is entry (4 v + l / 16, l % 16) of the block
+    const int l16 = c & 15, l4 = c >> 4;
+    dbl4 acc[10];
 #pragma unroll
-        for (int a2 = 0; a2 < 8; a2++)
+    for (int t = 0; t < 10; t++) acc[t] = dbl4{0.0, 0.0, 0.0, 0.0};
 #pragma unroll
-            for (int b2 = 0; b2 < 8; b2++) acc[a2][b2] = fma(x[a2], y[b2], acc[a2][b2]);
+    for (int r0 = 0; r0 < N; r0 += kChunk) {
+        double *buf = sm + ((r0 / kChunk) & 1) * kChunk * kRow;
+#pragma unroll
+        for (int r = 0; r < kChunk; r++) buf[r * kRow + c] = y[r0 + r];
+        __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+        __builtin_amdgcn_wave_barrier();
+        __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+#pragma unroll
+        for (int s4 = 0; s4 < kChunk; s4 += 4) {
+            double o[4];
+#pragma unroll
+            for (int P = 0; P < 4; P++) o[P] = buf[(s4 + l4) * kRow + 16 * P + l16];
+            int t = 0;
+#pragma unroll
+            for (int P = 0; P < 4; P++)
+#pragma unroll
+                for (int Q = P; Q < 4; Q++, t++)
+                    acc[t] = __builtin_amdgcn_mfma_f64_16x16x4f64(o[P], o[Q], acc[t], 0, 0, 0);
+        }
     }
     double err = 0.0;
+    {
+        int t = 0;
 #pragma unroll
-    for (int a2 = 0; a2 < 8; a2++)
+        for (int P = 0; P < 4; P++)
 #pragma unroll
-        for (int b2 = 0; b2 < 8; b2++) {
-            const int i = 8 * p + a2, j = 8 * q + b2;
-            const double e = acc[a2][b2] - (i == j ? 1.0 : 0.0);
-            err = (i < n && j < n) ? fma(e, e, err) : err;
-        }
+            for (int Q = P; Q < 4; Q++, t++)
+#pragma unroll
+                for (int v = 0; v < 4; v++) {
+                    const int i = 16 * P + 4 * v + l4, j = 16 * Q + l16;
+                    const double e = acc[t][v] - (i == j ? 1.0 : 0.0);
+                    const double w = P == Q ? 1.0 : 2.0;   // the lower blocks mirror these
+                    err = (i < n && j < n) ? fma(w * e, e, err) : err;
+                }
+    }
     err = wave_sum(err);
     if (c == 0) flag[b] = !(sqrt(err) <= thr);
 }
@@ -963,10 +1016,11 @@ hipError_t launch_qr_d(int batch, int m, int n, const double *A, int lda, long l
     return hipGetLastError();
 }
 
-// U = Q [Y; 0], rows permuted by perm when given (m = n)
+// U = Q [Y; 0], rows permuted by perm when given (m = n); only: NULL, or a
+// per-matrix flag, matrices whose flag is 0 are skipped
 hipError_t launch_apply_d(int batch, int m, int n, const double *Vq, const double *tau,
                           const double *Y, double *U, int ldu, long long sU, const int *info,
-                          const int *perm, hipStream_t stream)
+                          const int *perm, hipStream_t stream, const int *only = nullptr)
 {
     int rpl, cpg;
     if (!qr_shape(m, n, &rpl, &cpg)) return hipErrorInvalidValue;
@@ -974,7 +1028,7 @@ hipError_t launch_apply_d(int batch, int m, int n, const double *Vq, const doubl
 #define SVDB_AQ(RP, CP)                                                                        \
     if (rpl == RP && cpg == CP)                                                                \
         hipLaunchKernelGGL((apply_q_d<RP, CP>), dim3(batch), dim3(kQT), lds, stream, m, n, Vq, \
-                           tau, Y, U, ldu, sU, info, perm);
+                           tau, Y, U, ldu, sU, info, perm, only);
 #define SVDB_AQ_ROW(RP) SVDB_AQ(RP, 1) SVDB_AQ(RP, 2) SVDB_AQ(RP, 3) SVDB_AQ(RP, 4)
     SVDB_AQ_ROW(1)
     SVDB_AQ_ROW(2)
@@ -1010,16 +1064,19 @@ hipError_t launch_precond_d(int batch, int m, int n, int ns, const double *A, in
                            stream);
     if (e != hipSuccess) return e;
     // Jacobi on X = R2^T: its left vectors U_x feed U, its rotations J feed V.
-    // For 32 < n <= 64 it iterates on W alone and J = X^-1 U_x diag(S) comes
-    // from a triangular solve; matrices whose J fails the orthogonality check
-    // run the Jacobi again with J accumulated.
-    if (resident_nv_supported(n, n)) {
+    // For 32 < n <= 64 it iterates on W alone and V = P R1^-1 U_x diag(S)
+    // comes from a back substitution; matrices whose V fails the
+    // orthogonality check run the Jacobi again with J accumulated, and only
+    // they get V = P Q2 J.
+    const bool nv = resident_nv_supported(n, n);
+    if (nv) {
         e = launch_resident_d(batch, n, n, ns, w.X2, n, snn, S, sS, w.Ux, n, snn, nullptr, n, snn,
                               tol, max_sweeps, info, sweeps, stream, true, nullptr);
         if (e == hipSuccess && V) {
-            hipLaunchKernelGGL(solve_rt_d<64>, dim3(batch), dim3(64), 0, stream, n,
-                               (const double *)w.X2, (const double *)w.Ux, (const double *)S, sS,
-                               w.J, w.flag, (const int *)info, 0x1p-46 * n);
+            hipLaunchKernelGGL(solve_r1_d<64>, dim3(batch), dim3(64), 0, stream, n,
+                               (const double *)w.X1, (const double *)w.Ux, (const double *)S, sS,
+                               (const int *)w.perm, V, ldv, sV, w.flag, (const int *)info,
+                               0x1p-46 * n);
             e = hipGetLastError();
             if (e == hipSuccess)
                 e = launch_resident_d(batch, n, n, ns, w.X2, n, snn, S, sS, w.Ux, n, snn, w.J, n,
@@ -1034,7 +1091,9 @@ hipError_t launch_precond_d(int batch, int m, int n, int ns, const double *A, in
         e = launch_apply_d(batch, m, n, w.Vq1, w.tau1, w.Ux, U, ldu, sU, info, nullptr, stream);
         if (e != hipSuccess) return e;
     }
-    if (V) e = launch_apply_d(batch, n, n, w.Vq2, w.tau2, w.J, V, ldv, sV, info, w.perm, stream);
+    if (V)
+        e = launch_apply_d(batch, n, n, w.Vq2, w.tau2, w.J, V, ldv, sV, info, w.perm, stream,
+                           nv ? w.flag : nullptr);
     return e;
 }
 

@@ -171,6 +171,12 @@ def test_precondition_option_in_plan():
         svdb.plan(torch.complex128, 64, 64, precondition=1)
     with pytest.raises(svdb.SvdbError):
         svdb.plan(torch.float64, 2048, 100, precondition=1)
+    # waves per matrix the register layout of 64 columns cannot take are
+    # refused by the plan, before any launch
+    assert svdb.plan(torch.float64, 64, 64, waves=4)[2] == 256
+    with pytest.raises(svdb.SvdbError) as e:
+        svdb.plan(torch.float64, 64, 64, waves=1)
+    assert e.value.code == svdb.ERR_UNSUPPORTED and "waves" in str(e.value)
     ws_pc = svdb.lib().svdb_workspace_size(svdb.R64, 10, 64, 64, C.byref(svdb.make_opts()))
     ws_no = svdb.lib().svdb_workspace_size(svdb.R64, 10, 64, 64,
                                            C.byref(svdb.make_opts(precondition=0)))
