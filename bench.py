@@ -242,12 +242,12 @@ def oracle_each(mats, threads=16):
 
 
 def square256_leg(dev, grp, steps=2, warmup=1, cpu_sample=40):
-    """configs: 4000 FP64 256 x 256, geometric spectra, half kappa 1e2, half
-    1e8.  Four modes of the same call: all-FP64 block sweeps on A, FP32 MFMA
-    sweeps + FP64 refinement, the default (QR preconditioning, block sweeps
-    on R2^T), and the QR preconditioning with FP32 sweeps + FP64 refinement
-    on R2^T.  Each with its sigma error against the oracle on a
-    sample."""
+    """The 256 x 256 workload: 4000 FP64 matrices, geometric spectra, half
+    kappa 1e2, half 1e8. Four modes of the same call: all-FP64 block
+    sweeps on A, FP32 MFMA sweeps + FP64 refinement, the default (QR
+    preconditioning, block sweeps on R2^T), and the QR preconditioning
+    with FP32 sweeps + FP64 refinement on R2^T. Each with its sigma error
+    against the oracle on a sample."""
     import torch
     from paper_2601_17979_amd import svdb
     batch = grp.A.shape[0]
@@ -324,9 +324,9 @@ def flops_unblocked_cx(m, n, sweeps, cf):
 
 
 def uneven_leg(dev, groups, steps=2, warmup=1, cpu_sample=16):
-    """configs: 20000 complex128 matrices, n ~ U{8..256}, m ~ U{n..2n},
-    complex Gaussian entries, in one svdb_svd_batched call (one persistent
-    launch over every shape)."""
+    """The uneven workload: 20000 complex128 matrices, n ~ U{8..256}, m ~
+    U{n..2n}, complex Gaussian entries, in one svdb_svd_batched call (each
+    launch of one round-robin iteration covers every shape)."""
     import torch
     from paper_2601_17979_amd import svdb
     mats = [svdb.col_major(torch.from_numpy(g.A).to(dev)) for g in groups]
@@ -354,7 +354,7 @@ def uneven_leg(dev, groups, steps=2, warmup=1, cpu_sample=16):
         "sigma_rel_err_vs_oracle_sample": err,
         "roofline": {"bound": "alu", "achieved": achieved / 1e12, "peak": FP64_VALU_PEAK / 1e12,
                      "unit": "TFLOP/s", "frac": achieved / FP64_VALU_PEAK, "traffic": None,
-                     "kernel": "whole call (vb_persist dominant); work = Alg. 2 on the real "
+                     "kernel": "whole call (vb_iter dominant); work = Alg. 2 on the real "
                                "shapes over the oracle's sweeps",
                      "kernel_ms": ms, "flops_per_call": fl,
                      "oracle_sweeps_per_gpu_sweep": ratio},
@@ -569,7 +569,10 @@ def main():
     # Work of one call.  With QR preconditioning (the AUTO default for these
     # shapes) a call is the pivoted QR of A (2n^2(m - n/3)), the QR of R1^T
     # (4n^3/3), the Jacobi on R2^T (n x n), U = Q1 [U_x; 0] (2n^2(2m - n))
-    # and V = P Q2 J (2n^3); its work is counted as all five.
+    # and V = P Q2 J (2n^3); its work is counted as all five, the Jacobi with
+    # its rotations of V.  For 32 < n <= 64 the library does less than that:
+    # the Jacobi leaves V out and V = P R1^-1 U_x S comes from a back
+    # substitution (n^3) and a J^T J check (2n^3), Q2 is not applied.
     def call_flops(g, sw):
         # AUTO preconditions where precondition = 1 is accepted, except FP64
         # with n <= 16 and m < 8 n
@@ -586,7 +589,8 @@ def main():
             2.0 * n_ * n_ * (2 * m_ - n_) + 2.0 * n_ ** 3), True
 
     flc = [call_flops(r[0], r[5]) for r in results]
-    label = " (pivoted QR, QR of R1^T, Jacobi on R2^T, Q1 and Q2 applied)"
+    label = (" (pivoted QR, QR of R1^T, Jacobi on R2^T, U = Q1 U_x; work counted as"
+             " Alg. 2 with V and both applications of Q)")
     if sides:
         # the calls overlap on two streams: the unit is one whole step, timed
         # from before the first launch to after the side streams joined
