@@ -567,7 +567,7 @@ def main():
     bad = int(sum(int(np.sum(r[4] != 0)) for r in results))
 
     # Work of one call.  With QR preconditioning (the AUTO default for these
-    # shapes) a call is the pivoted QR of A (2n^2(m - n/3)), the QR of R1^T
+    # shapes) a call is the QR of A (2n^2(m - n/3)), the QR of R1^T
     # (4n^3/3), the Jacobi on R2^T (n x n), U = Q1 [U_x; 0] (2n^2(2m - n))
     # and V = P Q2 J (2n^3); its work is counted as all five, the Jacobi with
     # its rotations of V.  For 32 < n <= 64 the library does less than that:
@@ -589,7 +589,7 @@ def main():
             2.0 * n_ * n_ * (2 * m_ - n_) + 2.0 * n_ ** 3), True
 
     flc = [call_flops(r[0], r[5]) for r in results]
-    label = (" (pivoted QR, QR of R1^T, Jacobi on R2^T, U = Q1 U_x; work counted as"
+    label = (" (QR, QR of R1^T, Jacobi on R2^T, U = Q1 U_x; work counted as"
              " Alg. 2 with V and both applications of Q)")
     if sides:
         # the calls overlap on two streams: the unit is one whole step, timed

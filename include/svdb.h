@@ -90,23 +90,30 @@ typedef struct {
     int *sweeps;      /* optional DEVICE int[batch]: sweeps executed          */
     int waves;        /* SVDB_PATH_RESIDENT: wavefronts per matrix (1, 2, 4);
                          0 -> tuned                                           */
-    int precondition; /* QR pre-processing of real matrices (FP32 input is
+    int precondition; /* QR pre-processing of real matrices (section
+                         "Other Performance Considerations"; FP32 input is
                          widened and runs the FP64 kernels with its own
                          threshold, then the results are narrowed).  n <= 64
-                         and m <= 256 (m n <= 8192): A P = Q1 R1 with column
-                         pivoting, R1^T = Q2 R2, the resident kernel on
-                         R2^T, U = Q1 U_x, V = P Q2 J.  n <= 64 and larger
+                         and m <= 256 (m n <= 8192): A P = Q1 R1 (P = I
+                         unless 2), R1^T = Q2 R2, the resident kernel on
+                         R2^T, U = Q1 U_x; V = P Q2 J, or for 32 < n <= 64
+                         V = P R1^-1 U_x diag(S) by back substitution, kept
+                         where its columns are orthonormal to 2^-46 n (else
+                         the rotations are accumulated).  n <= 64 and larger
                          m (AUTO: m <= 1024; 1: m <= 4096): A = Q R, the
                          resident kernel on R^T, U = Q J.  n > 64 (m <=
                          1024): A = Q1 R1, R1^T = Q2 R2 (blocked QRs), the
-                         block method on R2^T, U = Q1 U_x, V = Q2 J.  -1 (default): on
-                         for the AUTO path where it applies, except FP64
-                         with n <= 16 and m < 8 n (there the QRs cost more
-                         than the sweeps they save); 0: off; 1: on
-                         (AUTO, RESIDENT or BLOCKED path;
-                         SVDB_ERR_UNSUPPORTED where it does not apply).  The
-                         sweeps count is that of the iteration on the
-                         triangular factor.                                  */
+                         block method on R2^T, U = Q1 U_x, V = Q2 J.
+                         -1 (default): on for the AUTO path where it
+                         applies, except FP64 with n <= 16 and m < 8 n
+                         (there the QRs cost more than the sweeps they
+                         save); 0: off; 1: on (AUTO, RESIDENT or BLOCKED
+                         path; SVDB_ERR_UNSUPPORTED where it does not
+                         apply); 2: on with column pivoting in the first QR
+                         (Businger-Golub, as LAPACK's xGEQP3; n <= 64 and
+                         m n <= 8192 only, SVDB_ERR_UNSUPPORTED elsewhere
+                         and for the server).  The sweeps count is that of
+                         the iteration on the triangular factor.          */
     int inner_sweeps; /* block method: sweeps of Alg. 1 per block-pair
                          solve ("Inexact Hermitian Eigendecomposition").  0
                          (default, tuned): one (Design 2) when the matrix
@@ -263,7 +270,8 @@ int svdb_plan(svdb_dtype_t dtype, int m, int n, const svdb_opts_t *opts,
  *
  *  svdb_server_create: opts may be NULL (defaults; precision must be 0).
  *     opts->precondition -1 (default) or 1 runs real requests (m <= 1024)
- *     with QR preconditioning: A = Q R, the FP64 Jacobi on R^T, U = Q J
+ *     with QR preconditioning (2, column pivoting, is refused with
+ *     SVDB_ERR_UNSUPPORTED): A = Q R, the FP64 Jacobi on R^T, U = Q J
  *     (FP32 requests are solved in FP64 and returned in FP32; requests with
  *     more than 64 columns take the blocked QR, up to eight of one shape
  *     per launch, through about 50 MB of staging memory that the server

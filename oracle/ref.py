@@ -169,7 +169,7 @@ def gesvj_batch(A, tol=None, max_sweeps=100, order=0, threads=None):
     return S, Ut.transpose(0, 2, 1), Vt.transpose(0, 2, 1), sweeps, info
 
 
-def precond_gesvj(A, tol=None, max_sweeps=100, order=1):
+def precond_gesvj(A, tol=None, max_sweeps=100, order=1, pivot=True):
     """Alg. 2 preconditioned after Drmac and Veselic, as the section
     "Algorithmic Background" (paragraph "Efficient implementations") cites
     them: the iteration on the transposed triangular factor of a
@@ -179,6 +179,8 @@ def precond_gesvj(A, tol=None, max_sweeps=100, order=1):
         R1^T = Q2 R2     unpivoted QR (LAPACK xGEQRF through numpy)
         X = R2^T,  X J = U_x diag(S)   Alg. 2 on X (its U is U_x, its V is J)
         A = (Q1 U_x) diag(S) (P Q2 J)^T.
+    pivot=False takes the first QR without pivoting (P = I), as the QR step
+    of the section "Other Performance Considerations" does.
     Returns (S, U, V, sweeps, info), sweeps being those of Alg. 2 on X."""
     import scipy.linalg as sl
     A = np.asarray(A, dtype=np.float64)
@@ -187,7 +189,11 @@ def precond_gesvj(A, tol=None, max_sweeps=100, order=1):
         raise ValueError("oracle requires m >= n")
     if not np.all(np.isfinite(A)):
         return np.zeros(n), None, None, 0, 2
-    Q1, R1, piv = sl.qr(A, mode="economic", pivoting=True)   # A[:, piv] = Q1 R1
+    if pivot:
+        Q1, R1, piv = sl.qr(A, mode="economic", pivoting=True)   # A[:, piv] = Q1 R1
+    else:
+        Q1, R1 = np.linalg.qr(A)
+        piv = np.arange(n)
     Q2, R2 = np.linalg.qr(R1.T)
     S, Ux, J, sw, info = gesvj(R2.T, tol, max_sweeps, order)
     U = Q1 @ Ux
@@ -196,10 +202,10 @@ def precond_gesvj(A, tol=None, max_sweeps=100, order=1):
     return S, U, V, sw, info
 
 
-def precond_gesvj_batch(A, tol=None, max_sweeps=100, order=1):
+def precond_gesvj_batch(A, tol=None, max_sweeps=100, order=1, pivot=True):
     """precond_gesvj over a batch (batch, m, n); same returns as gesvj_batch."""
     A = np.asarray(A)
-    out = [precond_gesvj(a, tol, max_sweeps, order) for a in A]
+    out = [precond_gesvj(a, tol, max_sweeps, order, pivot) for a in A]
     b, m, n = A.shape
     S = np.stack([o[0] for o in out])
     U = np.stack([o[1] if o[1] is not None else np.full((m, n), np.nan) for o in out])

@@ -67,6 +67,7 @@ struct Plan {
     double tol_start = 0.0;     // block method: dynamic inner tolerance
     double tol_rate = 0.0;
     bool precond = false;   // QR pre-processing, resident Jacobi on R^T
+    bool pivot = false;         // precond: column pivoting in the first QR
     bool precond_big = false;   // QR pre-processing, block Jacobi on R^T
     bool precond_tall = false;  // QR in global memory, resident Jacobi on R^T
     bool via64 = false;         // FP32 input on an FP64 preconditioned path
@@ -135,8 +136,8 @@ int make_plan(svdb_dtype_t dt, int m, int n, const svdb_opts_t &o, Plan *p)
         return fail(SVDB_ERR_UNSUPPORTED, "precision must be 0 or 1");
     if (o.precision == 1 && dt != SVDB_R64)
         return fail(SVDB_ERR_UNSUPPORTED, "precision mode 1 needs SVDB_R64 input");
-    if (o.precondition < -1 || o.precondition > 1)
-        return fail(SVDB_ERR_UNSUPPORTED, "precondition must be -1, 0 or 1");
+    if (o.precondition < -1 || o.precondition > 2)
+        return fail(SVDB_ERR_UNSUPPORTED, "precondition must be -1, 0, 1 or 2");
     if (o.inner_tol_start > 0.0) {
         if (!(o.inner_tol_rate > 0.0 && o.inner_tol_rate < 1.0) || !isfinite(o.inner_tol_start))
             return fail(SVDB_ERR_UNSUPPORTED, "dynamic inner tolerance: rate must be in (0, 1)");
@@ -150,13 +151,13 @@ int make_plan(svdb_dtype_t dt, int m, int n, const svdb_opts_t &o, Plan *p)
     p->via64 = dt == SVDB_R32;
     const bool pc_ok = real && o.precision == 0 && svdb::precond_supported(m, n);
     const bool pc_req = (path == SVDB_PATH_AUTO && o.precondition != 0) ||
-                        (path == SVDB_PATH_RESIDENT && o.precondition == 1);
+                        (path == SVDB_PATH_RESIDENT && o.precondition >= 1);
     // FP64 with n <= 16 and m < 8 n: the two QRs and the two applications of
     // Q cost more than the sweeps they save (measured on batches of Gaussian,
     // geometric-spectrum and uniform [0, 1] matrices), so AUTO without an
     // explicit request runs the resident kernel on A itself
     const bool pc_pays = !(dt == SVDB_R64 && n <= 16 && m < 8 * n);
-    if (pc_req && pc_ok && (pc_pays || o.precondition == 1)) {
+    if (pc_req && pc_ok && (pc_pays || o.precondition >= 1)) {
         if (!svdb::resident_config(n, n, o.waves, &rN, &rR, &rW))
             return fail(SVDB_ERR_UNSUPPORTED,
                         "resident path: no kernel with this many waves per matrix for n");
@@ -164,8 +165,12 @@ int make_plan(svdb_dtype_t dt, int m, int n, const svdb_opts_t &o, Plan *p)
         p->nb = 0;
         p->threads = 64 * rW;
         p->precond = true;
+        p->pivot = o.precondition == 2;
         return 0;
     }
+    if (o.precondition == 2)
+        return fail(SVDB_ERR_UNSUPPORTED,
+                    "column pivoting (precondition 2) applies to real n <= 64, m n <= 8192");
     // tall matrices with few columns beyond the register QR (m <= 4096): QR
     // in global memory, the resident Jacobi on R^T (AUTO, or RESIDENT with 1)
     const bool pct_ok = real && o.precision == 0 && !pc_ok &&
@@ -351,7 +356,8 @@ hipError_t run_tall(svdb_dtype_t dtype, const Plan &p, const svdb_opts_t &o, int
     } else if (p.precond) {
         e = svdb::launch_precond_d(batch, m, n, o.waves, (const double *)A, lda, strideA,
                                    (double *)S, strideS, (double *)U, ldu, strideU, (double *)V,
-                                   ldv, strideV, tol, o.max_sweeps, info, o.sweeps, workspace, s);
+                                   ldv, strideV, tol, o.max_sweeps, info, o.sweeps, workspace, s,
+                                   p.pivot);
     } else if (p.path == SVDB_PATH_RESIDENT) {
         e = svdb::launch_resident_d(batch, m, n, o.waves, (const double *)A, lda, strideA,
                                     (double *)S,

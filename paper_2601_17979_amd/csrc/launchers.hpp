@@ -27,13 +27,15 @@ hipError_t launch_resident_d(int batch, int m, int n, int ns, const double *A, i
                              int max_sweeps, int *info, int *sweeps, hipStream_t stream,
                              bool nv = false, const int *only = nullptr);
 
-// qr.hip: QR preconditioning (A = Q R, the resident Jacobi on R^T, U = Q J).
+// qr.hip: QR preconditioning (A P = Q1 R1, R1^T = Q2 R2, the resident Jacobi
+// on R2^T; P = I unless pivot).
 bool precond_supported(int m, int n);
 size_t precond_workspace_bytes(int batch, int m, int n);
 hipError_t launch_precond_d(int batch, int m, int n, int ns, const double *A, int lda,
                             long long sA, double *S, long long sS, double *U, int ldu,
                             long long sU, double *V, int ldv, long long sV, double tol,
-                            int max_sweeps, int *info, int *sweeps, void *ws, hipStream_t stream);
+                            int max_sweeps, int *info, int *sweeps, void *ws, hipStream_t stream,
+                            bool pivot = false);
 bool precond_tall_supported(int m, int n);
 bool precond_tall_auto(int m, int n);   // where AUTO takes it (m <= 1024)
 size_t precond_tall_workspace_bytes(int batch, int m, int n);

@@ -352,7 +352,8 @@ __global__ __launch_bounds__(kQT) void apply_q_d(int m, int n, const double *__r
 // n < 64 is embedded as diag(R1, I).  J^T J is formed on the FP64 matrix
 // cores from rows of J passed through LDS eight at a time, ten 16 x 16
 // blocks (the upper triangle).  V(perm[k], c) = J(k, c) goes to the output
-// directly.  Matrices with info 2 get flag 0 and are left untouched.
+// directly (perm NULL: the identity, a QR without pivoting).  Matrices with
+// info 2 get flag 0 and are left untouched.
 __host__ __device__ constexpr int rp_off(int k)
 {
     return (k & 1) ? (k + 1) * (k + 1) / 2 : k * (k + 2) / 2;
@@ -383,7 +384,6 @@ __global__ __launch_bounds__(64, 2) void solve_r1_d(int n, const double *__restr
     const int cc = act ? c : n - 1;
     X1 += (size_t)b * n * n;
     Ux += (size_t)b * n * n;
-    perm += (size_t)b * n;
     V += (size_t)b * sV;
     // ---- R1 into LDS: lane c writes its column, rows 0..c -----------------
     // Loads and stores are unconditional (clamped addresses; the entries
@@ -428,7 +428,7 @@ __global__ __launch_bounds__(64, 2) void solve_r1_d(int n, const double *__restr
     {
         constexpr int kLd = N + 1;
         static_assert(32 * kLd <= kR, "32 columns of V fit in the triangle's memory");
-        const int pv = perm[cc];   // lane k holds perm[k]
+        const int pv = perm ? perm[(size_t)b * n + cc] : cc;   // lane k holds perm[k]
 #pragma unroll
         for (int h = 0; h < 2; h++) {
             double *col = sm + (c & 31) * kLd;
@@ -1049,15 +1049,20 @@ size_t precond_workspace_bytes(int batch, int m, int n)
 hipError_t launch_precond_d(int batch, int m, int n, int ns, const double *A, int lda,
                             long long sA, double *S, long long sS, double *U, int ldu,
                             long long sU, double *V, int ldv, long long sV, double tol,
-                            int max_sweeps, int *info, int *sweeps, void *ws, hipStream_t stream)
+                            int max_sweeps, int *info, int *sweeps, void *ws, hipStream_t stream,
+                            bool pivot)
 {
     if (!precond_supported(m, n)) return hipErrorInvalidValue;
     PrecondWs w;
     precond_carve(batch, m, n, ws, &w);
     const long long snn = (long long)n * n;
-    // A P = Q1 R1 (reflectors only when U is wanted, P only when V is)
-    hipError_t e = launch_qr_d<true>(batch, m, n, A, lda, sA, w.X1, U ? w.Vq1 : nullptr, w.tau1,
-                                     V ? w.perm : nullptr, stream);
+    // A P = Q1 R1 (reflectors only when U is wanted, P only when V is and the
+    // QR pivots; P = I otherwise, as in the paper's QR step)
+    int *perm = pivot && V ? w.perm : nullptr;
+    hipError_t e = pivot ? launch_qr_d<true>(batch, m, n, A, lda, sA, w.X1, U ? w.Vq1 : nullptr,
+                                             w.tau1, perm, stream)
+                         : launch_qr_d<false>(batch, m, n, A, lda, sA, w.X1, U ? w.Vq1 : nullptr,
+                                              w.tau1, nullptr, stream);
     if (e != hipSuccess) return e;
     // R1^T = Q2 R2 (reflectors only when V is wanted)
     e = launch_qr_d<false>(batch, n, n, w.X1, n, snn, w.X2, V ? w.Vq2 : nullptr, w.tau2, nullptr,
@@ -1075,7 +1080,7 @@ hipError_t launch_precond_d(int batch, int m, int n, int ns, const double *A, in
         if (e == hipSuccess && V) {
             hipLaunchKernelGGL(solve_r1_d<64>, dim3(batch), dim3(64), 0, stream, n,
                                (const double *)w.X1, (const double *)w.Ux, (const double *)S, sS,
-                               (const int *)w.perm, V, ldv, sV, w.flag, (const int *)info,
+                               (const int *)perm, V, ldv, sV, w.flag, (const int *)info,
                                0x1p-46 * n);
             e = hipGetLastError();
             if (e == hipSuccess)
@@ -1092,7 +1097,7 @@ hipError_t launch_precond_d(int batch, int m, int n, int ns, const double *A, in
         if (e != hipSuccess) return e;
     }
     if (V)
-        e = launch_apply_d(batch, n, n, w.Vq2, w.tau2, w.J, V, ldv, sV, info, w.perm, stream,
+        e = launch_apply_d(batch, n, n, w.Vq2, w.tau2, w.J, V, ldv, sV, info, perm, stream,
                            nv ? w.flag : nullptr);
     return e;
 }

@@ -663,6 +663,7 @@ int svdb_server_create(svdb_server_t **out, size_t budget_bytes, int max_request
     svdb_opts_default(&o);
     if (opts) o = *opts;
     if (o.precision != 0) return SVDB_ERR_UNSUPPORTED;
+    if (o.precondition < -1 || o.precondition > 1) return SVDB_ERR_UNSUPPORTED;
     svdb_server *s = new svdb_server();
     s->budget = al256(budget_bytes);
     s->max_sweeps = o.max_sweeps > 0 ? o.max_sweeps : 100;

@@ -151,6 +151,8 @@ def test_server_argument_errors():
     assert lib.svdb_server_create(C.byref(h), 1 << 20, 0, None) == -3
     o = svdb.make_opts(precision=1)
     assert lib.svdb_server_create(C.byref(h), 1 << 20, 4, C.byref(o)) == svdb.ERR_UNSUPPORTED
+    o = svdb.make_opts(precondition=2)   # the server's QR does not pivot
+    assert lib.svdb_server_create(C.byref(h), 1 << 20, 4, C.byref(o)) == svdb.ERR_UNSUPPORTED
     assert lib.svdb_server_submit(None, svdb.R64, 8, 4, 0x1000, 8, 0x2000, None, 8, None, 4,
                                   0.0, 0x3000, None) == -1
     assert lib.svdb_server_poll(None, None, None, None, 0, 0) == -1
@@ -171,6 +173,16 @@ def test_precondition_option_in_plan():
         svdb.plan(torch.complex128, 64, 64, precondition=1)
     with pytest.raises(svdb.SvdbError):
         svdb.plan(torch.float64, 2048, 100, precondition=1)
+    # column pivoting (precondition 2) only where the register QR runs
+    assert svdb.plan(torch.float64, 64, 64, precondition=2)[0] == svdb.PATH_RESIDENT
+    assert svdb.plan(torch.float32, 100, 40, precondition=2)[0] == svdb.PATH_RESIDENT
+    for dt, m, n in [(torch.float64, 256, 256), (torch.float64, 1000, 16),
+                     (torch.complex128, 64, 64)]:
+        with pytest.raises(svdb.SvdbError) as e:
+            svdb.plan(dt, m, n, precondition=2)
+        assert e.value.code == svdb.ERR_UNSUPPORTED
+    with pytest.raises(svdb.SvdbError):
+        svdb.plan(torch.float64, 64, 64, precondition=3)
     # waves per matrix the register layout of 64 columns cannot take are
     # refused by the plan, before any launch
     assert svdb.plan(torch.float64, 64, 64, waves=4)[2] == 256

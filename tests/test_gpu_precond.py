@@ -116,24 +116,27 @@ def test_precond_mixed_workload_sample():
         say(f"  {g.m}x{g.n}: sweeps gpu {sw.mean():.2f} oracle on A {swr.mean():.2f}")
 
 
-def test_precond_sweeps_match_the_oracle_pipeline():
-    """The resident path follows the oracle's preconditioned driver (pivoted
-    QR, second QR, Alg. 2 on R2^T): same SVD, and sweep counts within one of
-    the oracle's on every matrix of a workload sample (rounding can move a
-    pair across the threshold, never the whole schedule)."""
+@pytest.mark.parametrize("pc", [-1, 2])
+def test_precond_sweeps_match_the_oracle_pipeline(pc):
+    """The resident path follows the oracle's preconditioned driver (QR,
+    without column pivoting by default and with it for precondition 2,
+    second QR, Alg. 2 on R2^T): same SVD, and sweep counts within one of the
+    oracle's on every matrix of a workload sample (rounding can move a pair
+    across the threshold, never the whole schedule)."""
     import oracle
     groups = gen.mixed_64_128x32(batch=400)
     for g in groups:
         A = g.A[::8]
-        S, U, V, info, sw = run_gpu(A)
-        Sr, Ur, Vr, swr, infor = oracle.precond_gesvj_batch(A)
-        compare_with_oracle(A, S, U, V, info, Sr, infor, label=f"pipeline {g.m}x{g.n}")
-        say(f"  {g.m}x{g.n}: sweeps gpu {sw.mean():.2f} oracle pipeline {swr.mean():.2f}")
+        S, U, V, info, sw = run_gpu(A, precondition=pc)
+        Sr, Ur, Vr, swr, infor = oracle.precond_gesvj_batch(A, pivot=pc == 2)
+        compare_with_oracle(A, S, U, V, info, Sr, infor, label=f"pipeline {g.m}x{g.n} pc {pc}")
+        say(f"  {g.m}x{g.n} pc {pc}: sweeps gpu {sw.mean():.2f} oracle pipeline {swr.mean():.2f}")
         assert np.all(np.abs(sw - swr) <= 1), (sw.tolist(), swr.tolist())
 
 
-@pytest.mark.parametrize("m,n", [(33, 33), (48, 40), (64, 64), (100, 64), (256, 50)])
-def test_precond_v_from_triangular_solve(m, n):
+@pytest.mark.parametrize("pc", [1, 2])
+@pytest.mark.parametrize("m,n", [(33, 33), (48, 40), (64, 64), (100, 64), (160, 50)])
+def test_precond_v_from_triangular_solve(m, n, pc):
     """For 32 < n <= 64 the Jacobi on X = R2^T accumulates no rotations:
     J = X^-1 U_x diag(S) comes from a triangular solve, and only matrices
     whose J fails the orthogonality check run the Jacobi again with J
@@ -149,11 +152,11 @@ def test_precond_v_from_triangular_solve(m, n):
     A[5][:, n - 1] = 0.0
     A[6][:, :] = np.outer(A[6][:, 0], np.arange(1, n + 1))   # rank one
     A[7][:, n // 2:] = A[7][:, :n - n // 2] * 3.0             # rank n - n // 2
-    say(f"[precond nv {m}x{n}]")
-    S, U, V, info, sw = run_gpu(A, precondition=1)
+    say(f"[precond nv {m}x{n} pc {pc}]")
+    S, U, V, info, sw = run_gpu(A, precondition=pc)
     Sr, Ur, Vr, swr, infor = oracle_batch(A)
     compare_with_oracle(A, S, U, V, info, Sr, infor, label=f"precond nv {m}x{n}")
-    S1, U1, V1, info1, sw1 = run_gpu(A, precondition=1, compute_v=False)
+    S1, U1, V1, info1, sw1 = run_gpu(A, precondition=pc, compute_v=False)
     assert V1 is None
     assert np.array_equal(S, S1) and np.array_equal(U, U1)
     assert np.array_equal(info, info1) and np.array_equal(sw, sw1)

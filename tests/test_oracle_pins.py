@@ -417,35 +417,37 @@ def pin_batch_driver():
 
 
 def pin_precond():
-    """The preconditioned driver (pivoted QR, second QR, Alg. 2 on R2^T)
-    returns an SVD of A itself: sigma as LAPACK's, U S V^T = A, orthonormal
-    factors, with columns of A given in scrambled scale so that the pivot
-    order is not the identity; on graded matrices it needs fewer sweeps than
-    Alg. 2 on A; on a scrambled diagonal matrix R2^T is diagonal, so one
-    sweep with no rotation suffices and V is a signed permutation."""
-    rng = gen.rng_for(22, 0)
-    for m, n in [(64, 64), (128, 32), (17, 9), (5, 1)]:
-        for kind in ("gauss", "geo"):
-            A = gen.family(rng, kind, m, n, 1e10)
-            A = A[:, rng.permutation(n)] * (2.0 ** rng.integers(-20, 20, n))
-            S, U, V, sw, info = oracle.precond_gesvj(A)
-            ref = np.linalg.svd(A, compute_uv=False)
-            assert info == 0
-            assert sigma_err(S, ref) <= 1e-14, (m, n, kind)
-            assert recon_err(A, S, U, V) <= 1e-13 * n
-            assert orth_err(U) <= 1e-13 * n and orth_err(V) <= 1e-13 * n
-            if kind == "geo" and n >= 32:
-                assert sw < oracle.gesvj(A)[3]
-    d = np.array([3.0, -7.0, 0.5, 11.0, 2.0])
-    A = np.zeros((7, 5))
-    A[:5, :5] = np.diag(d)
-    S, U, V, sw, info = oracle.precond_gesvj(A)
-    assert info == 0 and sw == 1
-    assert np.array_equal(S, np.sort(np.abs(d))[::-1])
-    assert np.array_equal(np.abs(V), np.abs(V).round()) and np.allclose(np.abs(V).sum(0), 1)
-    assert recon_err(A, S, U, V) <= 1e-15
-    A[2, 3] = np.nan
-    assert oracle.precond_gesvj(A)[4] == 2
+    """The preconditioned driver (QR with or without column pivoting, second
+    QR, Alg. 2 on R2^T) returns an SVD of A itself: sigma as LAPACK's,
+    U S V^T = A, orthonormal factors, with columns of A given in scrambled
+    scale so that the pivot order is not the identity; on graded matrices it
+    needs fewer sweeps than Alg. 2 on A; on a scrambled diagonal matrix R2^T
+    is diagonal, so one sweep with no rotation suffices and V is a signed
+    permutation."""
+    for pivot in (True, False):
+        rng = gen.rng_for(22, 0)
+        for m, n in [(64, 64), (128, 32), (17, 9), (5, 1)]:
+            for kind in ("gauss", "geo"):
+                A = gen.family(rng, kind, m, n, 1e10)
+                A = A[:, rng.permutation(n)] * (2.0 ** rng.integers(-20, 20, n))
+                S, U, V, sw, info = oracle.precond_gesvj(A, pivot=pivot)
+                ref = np.linalg.svd(A, compute_uv=False)
+                assert info == 0
+                assert sigma_err(S, ref) <= 1e-14, (m, n, kind, pivot)
+                assert recon_err(A, S, U, V) <= 1e-13 * n
+                assert orth_err(U) <= 1e-13 * n and orth_err(V) <= 1e-13 * n
+                if kind == "geo" and n >= 32:
+                    assert sw < oracle.gesvj(A)[3]
+        d = np.array([3.0, -7.0, 0.5, 11.0, 2.0])
+        A = np.zeros((7, 5))
+        A[:5, :5] = np.diag(d)
+        S, U, V, sw, info = oracle.precond_gesvj(A, pivot=pivot)
+        assert info == 0 and sw == 1
+        assert np.array_equal(S, np.sort(np.abs(d))[::-1])
+        assert np.array_equal(np.abs(V), np.abs(V).round()) and np.allclose(np.abs(V).sum(0), 1)
+        assert recon_err(A, S, U, V) <= 1e-15
+        A[2, 3] = np.nan
+        assert oracle.precond_gesvj(A, pivot=pivot)[4] == 2
 
 
 PINS = {
