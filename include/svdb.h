@@ -25,10 +25,15 @@
  *    resident and QR-preconditioned resident paths are fully asynchronous.
  *    The block method (BLOCKED path, the mixed-precision mode, the wide and
  *    tall preconditioned paths that end in it, and svdb_svd_batched) runs
- *    one launch per round-robin iteration and waits on the host for the
- *    count of unconverged matrices after every sweep: those calls return
- *    only when their sweeps are done (the finalisation is still
- *    asynchronous), and cannot be captured into a HIP graph.
+ *    one launch per round-robin iteration; how its sweeps end is chosen by
+ *    opts->persistent.  With 0 (default) the host waits for the count of
+ *    unconverged matrices after every sweep, so the call returns only when
+ *    its sweeps are done.  With 1, or when `stream` is being captured, the
+ *    launches of all max_sweeps sweeps are queued and the count stays on
+ *    the device: the call returns at once, nothing waits on the host, and
+ *    svdb_svd_strided_batched can be captured into a HIP graph
+ *    (svdb_svd_batched stages its descriptors through pinned host memory
+ *    and is not meant for capture).
  *  - Return value: 0 on success; -k when argument k (1-based) is invalid,
  *    detected on the host before anything is launched; SVDB_ERR_UNSUPPORTED
  *    when a valid request is outside what this build implements;
@@ -94,12 +99,14 @@ typedef struct {
                          "Other Performance Considerations"; FP32 input is
                          widened and runs the FP64 kernels with its own
                          threshold, then the results are narrowed).  n <= 64
-                         and m <= 256 (m n <= 8192): A P = Q1 R1 (P = I
-                         unless 2), R1^T = Q2 R2, the resident kernel on
-                         R2^T, U = Q1 U_x; V = P Q2 J, or for 32 < n <= 64
-                         V = P R1^-1 U_x diag(S) by back substitution, kept
-                         where its columns are orthonormal to 2^-46 n (else
-                         the rotations are accumulated).  n <= 64 and larger
+                         and m <= 256 (m n <= 8192): A P = Q1 R1, R1^T =
+                         Q2 R2, the resident kernel on R2^T, U = Q1 U_x.
+                         For 32 < n <= 64 V = P R1^-1 U_x diag(S) by back
+                         substitution, kept where the largest row sum of
+                         |V^T V - I| is at most 2^-49 n (else the rotations
+                         are accumulated), with column pivoting in the
+                         first QR (the accuracy of that route needs it);
+                         for n <= 32 V = Q2 J and P = I.  n <= 64 and larger
                          m (AUTO: m <= 1024; 1: m <= 4096): A = Q R, the
                          resident kernel on R^T, U = Q J.  n > 64 (m <=
                          1024): A = Q1 R1, R1^T = Q2 R2 (blocked QRs), the
@@ -109,11 +116,11 @@ typedef struct {
                          (there the QRs cost more than the sweeps they
                          save); 0: off; 1: on (AUTO, RESIDENT or BLOCKED
                          path; SVDB_ERR_UNSUPPORTED where it does not
-                         apply); 2: on with column pivoting in the first QR
-                         (Businger-Golub, as LAPACK's xGEQP3; n <= 64 and
-                         m n <= 8192 only, SVDB_ERR_UNSUPPORTED elsewhere
-                         and for the server).  The sweeps count is that of
-                         the iteration on the triangular factor.          */
+                         apply); 2: as 1 with column pivoting in the first
+                         QR at every n (Businger-Golub, as LAPACK's xGEQP3;
+                         n <= 64 and m n <= 8192 only, SVDB_ERR_UNSUPPORTED
+                         elsewhere and for the server).  The sweeps count is
+                         that of the iteration on the triangular factor.  */
     int inner_sweeps; /* block method: sweeps of Alg. 1 per block-pair
                          solve ("Inexact Hermitian Eigendecomposition").  0
                          (default, tuned): one (Design 2) when the matrix
@@ -122,12 +129,16 @@ typedef struct {
                          or three (FP32); k > 0: at most k, stopping at a
                          sweep that rotates nothing; < 0: to convergence (at
                          most 100).                                          */
-    int persistent;   /* block method: must be 0 (default): one launch per
-                         round-robin iteration, the host waiting for the
-                         count of unconverged matrices after every sweep.
-                         1 (every sweep in one cooperative launch with grid
-                         barriers) is disabled in this version and returns
-                         SVDB_ERR_UNSUPPORTED.                               */
+    int persistent;   /* block method, sweep control.  0 (default): after
+                         every sweep the host waits for the count of
+                         unconverged matrices and stops at zero.  Nonzero:
+                         the launches of all max_sweeps sweeps are queued on
+                         the stream and the count stays on the device; once
+                         no matrix is left, every later launch returns at
+                         once (a few microseconds each).  Same results, bit
+                         for bit; the call returns before the work is done
+                         and can be captured into a HIP graph.  Chosen
+                         automatically when `stream` is capturing.        */
     double inner_tol_start; /* block method: the dynamic
                          tolerance of the inner eigensolver ("Inexact
                          Hermitian Eigendecomposition", subsection

@@ -73,11 +73,6 @@ struct Plan {
     bool via64 = false;         // FP32 input on an FP64 preconditioned path
 };
 
-// The cooperative single-launch form of the block method is switched off:
-// it stalled on the GPU in testing and the cause is not established.
-const char *const kPersistentOff =
-    "persistent = 1 (one cooperative launch for all sweeps) is disabled in this version";
-
 svdb_opts_t resolve_opts(const svdb_opts_t *o)
 {
     svdb_opts_t r;
@@ -142,7 +137,6 @@ int make_plan(svdb_dtype_t dt, int m, int n, const svdb_opts_t &o, Plan *p)
         if (!(o.inner_tol_rate > 0.0 && o.inner_tol_rate < 1.0) || !isfinite(o.inner_tol_start))
             return fail(SVDB_ERR_UNSUPPORTED, "dynamic inner tolerance: rate must be in (0, 1)");
     }
-    if (o.persistent) return fail(SVDB_ERR_UNSUPPORTED, kPersistentOff);
     int path = o.path;
     int rN = 0, rR = 0, rW = 0;
     // QR preconditioning of real matrices (FP32 input runs it in FP64): AUTO
@@ -603,7 +597,6 @@ int svdb_svd_batched(svdb_dtype_t dtype, int batch, const int *m, const int *n,
         return fail(SVDB_ERR_UNSUPPORTED, "uneven batches run in the working precision only");
     if (o.inner_tol_start > 0.0 && !(o.inner_tol_rate > 0.0 && o.inner_tol_rate < 1.0))
         return fail(SVDB_ERR_UNSUPPORTED, "dynamic inner tolerance: rate must be in (0, 1)");
-    if (o.persistent) return fail(SVDB_ERR_UNSUPPORTED, kPersistentOff);
     const size_t need = svdb_batched_workspace_size(dtype, batch, m, n, &o);
     if (!workspace || ws_bytes < need)
         return fail(-14, "workspace too small: need %zu bytes", need);

@@ -714,11 +714,11 @@ template <class T, bool CX, int NB>
 __global__ __launch_bounds__(kBT) void blk_iter(int m, int np, int l, int it,
                                                 typename Elem<T, CX>::type *W,
                                                 typename Elem<T, CX>::type *Vw, BlkState *st,
-                                                double tol, int inner)
+                                                double tol, int inner, const int *stop)
 {
     __shared__ IterShared<T, CX, NB> s;
     const int b = blockIdx.x / (l / 2), pair = blockIdx.x % (l / 2);
-    if (!st[b].active) return;
+    if ((stop && *stop) || !st[b].active) return;
     iter_body<T, CX, NB>(s, m, np, l, it, pair, W + (size_t)b * m * np, Vw + (size_t)b * np * np,
                          st + b, tol, inner);
 }
@@ -744,10 +744,10 @@ __host__ __device__ __forceinline__ double inner_tol(double tol, double t0, doub
 // masking a done matrix is retired; without, every matrix stays active
 // until the whole batch is done.  *pending counts the matrices not done.
 __global__ void blk_sweep_end(int batch, BlkState *st, int *pending, int masking, int phase32,
-                              double tol, double t0, double rate)
+                              double tol, double t0, double rate, const int *stop)
 {
     const int b = blockIdx.x * blockDim.x + threadIdx.x;
-    if (b >= batch) return;
+    if (b >= batch || (stop && *stop)) return;
     BlkState &s = st[b];
     if (!s.active) return;
     if (!s.done) {
@@ -765,6 +765,18 @@ __global__ void blk_sweep_end(int batch, BlkState *st, int *pending, int masking
     if (masking && s.done) s.active = 0;
 }
 
+// Sweep control of the queued form: ctl[0] counts the matrices still
+// sweeping after a sweep (round), ctl[1] is set once that count is zero, and
+// every later launch of the call returns at once.  The count starts from
+// zero for the next sweep.
+__global__ void sweep_close(int *ctl)
+{
+    if (threadIdx.x == 0) {
+        if (ctl[0] == 0) ctl[1] = 1;
+        ctl[0] = 0;
+    }
+}
+
 // Mark every matrix with finite input active again (start of the FP64
 // refinement); the FP32 phase's sweep count moves to sweeps32.
 __global__ void blk_rearm(int batch, BlkState *st, int *sweeps32)
@@ -773,173 +785,6 @@ __global__ void blk_rearm(int batch, BlkState *st, int *sweeps32)
     if (b >= batch) return;
     sweeps32[b] = st[b].sweeps;
     state_reset(st[b], st[b].bad);
-}
-
-// ---------------------------------------------------------------------------
-// Sweep control on the device.  One cooperative launch (every workgroup
-// resident) runs all the sweeps of a batch: a phase is one round-robin
-// iteration, whose (matrix, block pair) items the workgroups claim from a
-// counter, largest matrices first; a grid barrier ends the phase, the
-// matrices whose sweep ends there are closed (converged, capped or still
-// sweeping), another barrier publishes that, and the launch ends once no
-// matrix is still sweeping.  The host never waits, so the whole call stays
-// asynchronous on its stream.  The barrier waits are bounded by a watchdog
-// on the device's wall clock: if it ever fires, every workgroup leaves and
-// the unfinished matrices report info 3.
-// ---------------------------------------------------------------------------
-struct PersistCtl {
-    unsigned bar;     // grid-barrier arrivals (monotonic within a launch)
-    int remaining;    // matrices still sweeping
-    int next[2];      // item counters of even and odd phases
-    int abort;        // the watchdog fired (kept across the launches of a call)
-    int pad[3];
-};
-constexpr int kCtlInts = (int)(sizeof(PersistCtl) / sizeof(int));
-constexpr int kCtlLaunchInts = 4;   // the fields a launch starts from zero
-
-// Grid barrier over the workgroups of a cooperative launch; `target` is the
-// arrival count that completes it.  Returns false if the watchdog fired.
-__device__ bool grid_sync(PersistCtl *ctl, unsigned target, long long limit)
-{
-    __shared__ int s_ok;
-    __threadfence();   // release: this workgroup's writes, at device scope
-    __syncthreads();
-    if (threadIdx.x == 0) {
-        __hip_atomic_fetch_add(&ctl->bar, 1u, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_AGENT);
-        const long long t0 = wall_clock64();
-        int ok = 1;
-        while (__hip_atomic_load(&ctl->bar, __ATOMIC_ACQUIRE, __HIP_MEMORY_SCOPE_AGENT) < target) {
-            if (__hip_atomic_load(&ctl->abort, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT)) {
-                ok = 0;
-                break;
-            }
-            if (wall_clock64() - t0 > limit) {
-                __hip_atomic_store(&ctl->abort, 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-                ok = 0;
-                break;
-            }
-            __builtin_amdgcn_s_sleep(2);
-        }
-        s_ok = ok;
-    }
-    __syncthreads();
-    __threadfence();   // acquire: the other workgroups' writes
-    return s_ok != 0;
-}
-
-// End of a sweep of one matrix: a sweep without rotation converges it
-// (`phase32`, the FP32 phase of the mixed mode: so does a largest pair
-// cosine of at most kSwitchCos); one that reaches max_sweeps stops
-// unconverged.  With masking a converged matrix is retired; without, it
-// keeps being swept until the whole batch has stopped.  Returns true when
-// the matrix stopped sweeping at this sweep end.
-// With the dynamic inner tolerance (t0 > tol) a sweep converges a matrix
-// only if it ran at the final threshold tol.
-__device__ __forceinline__ bool close_sweep(BlkState &s, int max_sweeps, int masking, int phase32,
-                                            double tol = 0.0, double t0 = 0.0, double rate = 0.0)
-{
-    if (!s.active) return false;
-    bool stopped = false;
-    if (!s.done) {
-        const bool at_tol = inner_tol(tol, t0, rate, s.sweeps) <= tol;
-        s.sweeps += 1;
-        const double mc = __longlong_as_double((long long)s.maxcos);
-        bool fin = !s.rotated && at_tol;
-        if (phase32 && fp32_phase_done(mc, s.prevcos, s.sweeps)) fin = true;
-        s.prevcos = mc;
-        if (fin) {
-            s.done = 1;
-            stopped = true;
-        } else if (s.sweeps >= max_sweeps) {
-            s.active = 0;
-            stopped = true;
-        }
-    }
-    s.rotated = 0;
-    s.maxcos = 0ull;
-    if (masking && s.done) s.active = 0;
-    return stopped;
-}
-
-// The phase loop of a persistent launch.  item(w, itg) runs work item w of
-// phase itg (every thread of the workgroup calls it with the same w);
-// ends(itg) says whether any sweep can end at phase itg (uniform over the
-// grid); end_of(b, itg) closes matrix b's sweep if it ends there.
-template <class ItemFn, class EndsFn, class EndFn>
-__device__ void persist_loop(PersistCtl *ctl, int nitems, int count, int max_phases,
-                             long long limit, ItemFn item, EndsFn ends, EndFn end_of)
-{
-    __shared__ int s_w;
-    const unsigned G = gridDim.x;
-    unsigned nbar = 0;
-    for (int itg = 0; itg < max_phases; itg++) {
-        // the other counter was last claimed from in the previous phase,
-        // which every workgroup has left; it serves the next phase
-        if (blockIdx.x == 0 && threadIdx.x == 0)
-            __hip_atomic_store(&ctl->next[(itg + 1) & 1], 0, __ATOMIC_RELAXED,
-                               __HIP_MEMORY_SCOPE_AGENT);
-        for (;;) {
-            if (threadIdx.x == 0) s_w = atomicAdd(&ctl->next[itg & 1], 1);
-            __syncthreads();
-            const int w = s_w;
-            __syncthreads();
-            if (w >= nitems) break;
-            item(w, itg);
-        }
-        if (!grid_sync(ctl, ++nbar * G, limit)) return;
-        if (!ends(itg)) continue;
-        for (int b = blockIdx.x * blockDim.x + threadIdx.x; b < count; b += G * blockDim.x)
-            if (end_of(b, itg)) atomicSub(&ctl->remaining, 1);
-        if (!grid_sync(ctl, ++nbar * G, limit)) return;
-        if (__hip_atomic_load(&ctl->remaining, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) <= 0)
-            return;
-    }
-}
-
-// Uniform batch: matrix b's W at W + b m np, V at Vw + b np np, l block
-// columns; one item per (matrix, block pair).
-template <class T, bool CX, int NB>
-__global__ __launch_bounds__(kBT) void blk_persist(int batch, int m, int np, int l,
-                                                   typename Elem<T, CX>::type *W,
-                                                   typename Elem<T, CX>::type *Vw,
-                                                   BlkState *st, double tol, int inner,
-                                                   double t0, double rate, int max_sweeps,
-                                                   int masking, int phase32, PersistCtl *ctl,
-                                                   long long limit)
-{
-    __shared__ IterShared<T, CX, NB> s;
-    const int pairs = l / 2;
-    persist_loop(
-        ctl, batch * pairs, batch, max_sweeps * (l - 1), limit,
-        [&](int w, int itg) {
-            const int b = w / pairs, pair = w % pairs;
-            if (!st[b].active) return;
-            iter_body<T, CX, NB>(s, m, np, l, itg % (l - 1), pair, W + (size_t)b * m * np,
-                                 Vw + (size_t)b * np * np, st + b,
-                                 inner_tol(tol, t0, rate, st[b].sweeps), inner);
-        },
-        [&](int itg) { return (itg + 1) % (l - 1) == 0; },
-        [&](int b, int) {
-            return close_sweep(st[b], max_sweeps, masking, phase32, tol, t0, rate);
-        });
-}
-
-// Counts the matrices that are sweeping (at the start of a persistent launch).
-__global__ void count_active(int count, const BlkState *st, PersistCtl *ctl)
-{
-    const int b = blockIdx.x * blockDim.x + threadIdx.x;
-    if (b < count && st[b].active) atomicAdd(&ctl->remaining, 1);
-}
-
-// Unfinished matrices of a launch whose watchdog fired report info 3 (after
-// the finalisation, which wrote 0 or 1).  info: uniform batch, or NULL with
-// the descriptors' info pointers.
-__global__ void mark_aborted(int count, const BlkState *st, const PersistCtl *ctl, int *info,
-                             const VbDesc *d)
-{
-    const int b = blockIdx.x * blockDim.x + threadIdx.x;
-    if (b >= count || !ctl->abort) return;
-    if (!st[b].done && !st[b].bad) *(info ? info + b : d[b].info) = 3;
 }
 
 // sigma_c = ||w_c|| (FP64 sums, power-of-two scaling), stable descending
@@ -1215,92 +1060,82 @@ hipError_t pinned_counter(int **out)
     return hipSuccess;
 }
 
-// Resident workgroups of a kernel on the current device (its occupancy times
-// the compute units), and the watchdog limit of the persistent launches in
-// wall-clock ticks (20 s, far beyond any phase), cached per device.
-struct DeviceLimits {
-    int cus = 0;
-    long long watchdog = 0;
-};
-
-hipError_t device_limits(const void *fn, int *resident, long long *watchdog)
+// The queued sweep control is used when asked for, and whenever `stream`
+// is being captured into a graph (the host-closed loop cannot wait there).
+bool queued_sweeps(int persistent, hipStream_t stream)
 {
-    static std::mutex mu;
-    static std::map<int, DeviceLimits> dev_cache;
-    static std::map<std::pair<const void *, int>, int> occ_cache;
-    int dev = 0;
-    hipError_t e = hipGetDevice(&dev);
-    if (e != hipSuccess) return e;
-    std::lock_guard<std::mutex> lk(mu);
-    auto it = dev_cache.find(dev);
-    if (it == dev_cache.end()) {
-        DeviceLimits L;
-        int khz = 0;
-        e = hipDeviceGetAttribute(&L.cus, hipDeviceAttributeMultiprocessorCount, dev);
-        if (e == hipSuccess) e = hipDeviceGetAttribute(&khz, hipDeviceAttributeWallClockRate, dev);
-        if (e != hipSuccess) return e;
-        L.watchdog = (long long)(khz > 0 ? khz : 100000) * 1000LL * 20;
-        it = dev_cache.emplace(dev, L).first;
-    }
-    auto oc = occ_cache.find({fn, dev});
-    if (oc == occ_cache.end()) {
-        int occ = 0;
-        e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&occ, fn, kBT, 0);
-        if (e != hipSuccess) return e;
-        oc = occ_cache.emplace(std::make_pair(fn, dev), occ).first;
-    }
-    *resident = oc->second * it->second.cus;
-    *watchdog = it->second.watchdog;
-    return *resident > 0 ? hipSuccess : hipErrorInvalidConfiguration;
+    hipStreamCaptureStatus cs = hipStreamCaptureStatusNone;
+    if (hipStreamIsCapturing(stream, &cs) != hipSuccess) cs = hipStreamCaptureStatusNone;
+    return persistent != 0 || cs == hipStreamCaptureStatusActive;
 }
 
 template <class T, bool CX>
 void launch_iter(int nb, unsigned grid, hipStream_t stream, int m, int np, int l, int it,
                  typename Elem<T, CX>::type *W, typename Elem<T, CX>::type *Vw, BlkState *st,
-                 double tol, int inner)
+                 double tol, int inner, const int *stop)
 {
     if constexpr (CX) {
         hipLaunchKernelGGL((blk_iter<T, true, 16>), dim3(grid), dim3(kBT), 0, stream, m, np, l,
-                           it, W, Vw, st, tol, inner);
+                           it, W, Vw, st, tol, inner, stop);
         (void)nb;
     } else {
         if (nb == 8)
             hipLaunchKernelGGL((blk_iter<T, false, 8>), dim3(grid), dim3(kBT), 0, stream, m, np,
-                               l, it, W, Vw, st, tol, inner);
+                               l, it, W, Vw, st, tol, inner, stop);
         else if (nb == 16)
             hipLaunchKernelGGL((blk_iter<T, false, 16>), dim3(grid), dim3(kBT), 0, stream, m, np,
-                               l, it, W, Vw, st, tol, inner);
+                               l, it, W, Vw, st, tol, inner, stop);
         else
             hipLaunchKernelGGL((blk_iter<T, false, 32>), dim3(grid), dim3(kBT), 0, stream, m, np,
-                               l, it, W, Vw, st, tol, inner);
+                               l, it, W, Vw, st, tol, inner, stop);
     }
 }
 
-// Sweeps with a host-side loop: one launch per round-robin iteration, and a
-// host wait for the count of pending matrices after every sweep.  Kept as
-// the per-iteration form of the block method (svdb_opts_t.persistent = 0);
-// it is synchronous.
+// Sweeps of a uniform batch, one launch per round-robin iteration.
+// Host-closed form (queued = false): after every sweep the host waits for
+// the count of pending matrices and stops once it is zero; the call is
+// synchronous.  Queued form (queued = true): the launches of all max_sweeps
+// sweeps go onto the stream at once and the count stays on the device
+// (sweep_close); after the sweep that leaves no matrix pending, every later
+// launch returns at once.  Nothing waits on the host and nothing is copied
+// to it, so the call can be captured in a HIP graph; the price is the
+// no-op launches after convergence.  Both forms take the same decisions and
+// give the same bits.  ctl: two ints of the workspace.
 template <class T, bool CX>
 hipError_t run_sweeps_host(int batch, int m, int np, int nb, typename Elem<T, CX>::type *W,
-                           typename Elem<T, CX>::type *Vw, BlkState *st, int *pending,
+                           typename Elem<T, CX>::type *Vw, BlkState *st, int *ctl,
                            double tol, int max_sweeps, int masking, int phase32, int inner,
-                           hipStream_t stream, double t0, double rate)
+                           hipStream_t stream, double t0, double rate, bool queued)
 {
     const int l = np / nb;
+    const unsigned grid = (unsigned)batch * (unsigned)(l / 2);
+    const unsigned egrid = (unsigned)((batch + 255) / 256);
+    if (queued) {
+        hipError_t e = launch_fill_int(ctl, 2, 0, stream);
+        if (e != hipSuccess) return e;
+        for (int sw = 0; sw < max_sweeps; sw++) {
+            const double ts = inner_tol(tol, t0, rate, sw);
+            for (int it = 0; it < l - 1; it++)
+                launch_iter<T, CX>(nb, grid, stream, m, np, l, it, W, Vw, st, ts, inner, ctl + 1);
+            hipLaunchKernelGGL(blk_sweep_end, dim3(egrid), dim3(256), 0, stream, batch, st, ctl,
+                               masking, phase32, tol, t0, rate, (const int *)(ctl + 1));
+            hipLaunchKernelGGL(sweep_close, dim3(1), dim3(64), 0, stream, ctl);
+        }
+        return hipGetLastError();
+    }
     int *host_count;
     hipError_t e = pinned_counter(&host_count);
     if (e != hipSuccess) return e;
-    const unsigned grid = (unsigned)batch * (unsigned)(l / 2);
     for (int sw = 0; sw < max_sweeps; sw++) {
         // every matrix still sweeping is in its sweep sw
         const double ts = inner_tol(tol, t0, rate, sw);
         for (int it = 0; it < l - 1; it++)
-            launch_iter<T, CX>(nb, grid, stream, m, np, l, it, W, Vw, st, ts, inner);
-        e = hipMemsetAsync(pending, 0, sizeof(int), stream);
+            launch_iter<T, CX>(nb, grid, stream, m, np, l, it, W, Vw, st, ts, inner, nullptr);
+        e = hipMemsetAsync(ctl, 0, sizeof(int), stream);
         if (e != hipSuccess) return e;
-        hipLaunchKernelGGL(blk_sweep_end, dim3((batch + 255) / 256), dim3(256), 0, stream, batch,
-                           st, pending, masking, phase32, tol, t0, rate);
-        e = hipMemcpyAsync(host_count, pending, sizeof(int), hipMemcpyDeviceToHost, stream);
+        hipLaunchKernelGGL(blk_sweep_end, dim3(egrid), dim3(256), 0, stream, batch, st, ctl,
+                           masking, phase32, tol, t0, rate, (const int *)nullptr);
+        e = hipMemcpyAsync(host_count, ctl, sizeof(int), hipMemcpyDeviceToHost, stream);
         if (e != hipSuccess) return e;
         e = hipStreamSynchronize(stream);
         if (e != hipSuccess) return e;
@@ -1309,54 +1144,18 @@ hipError_t run_sweeps_host(int batch, int m, int np, int nb, typename Elem<T, CX
     return hipGetLastError();
 }
 
-template <class T, bool CX>
-using PersistFn = void (*)(int, int, int, int, typename Elem<T, CX>::type *,
-                           typename Elem<T, CX>::type *, BlkState *, double, int, double, double,
-                           int, int, int, PersistCtl *, long long);
-
-template <class T, bool CX>
-PersistFn<T, CX> persist_kernel(int nb)
-{
-    if constexpr (CX) {
-        (void)nb;
-        return blk_persist<T, true, 16>;
-    } else {
-        if (nb == 8) return blk_persist<T, false, 8>;
-        if (nb == 32) return blk_persist<T, false, 32>;
-        return blk_persist<T, false, 16>;
-    }
-}
-
-// All sweeps of a uniform batch in one persistent launch (nothing waits on
-// the host).  ctl: the control block in the workspace; its launch fields are
-// cleared here (by a kernel, so that the call can be captured in a graph).
+// Sweep control of the block method: persistent = 0 closes each sweep on
+// the host, 1 queues every sweep with the count on the device (see
+// run_sweeps_host).  ctl: the control block in the workspace.
 template <class T, bool CX>
 hipError_t run_sweeps(int batch, int m, int np, int nb, typename Elem<T, CX>::type *W,
-                      typename Elem<T, CX>::type *Vw, BlkState *st, PersistCtl *ctl, double tol,
+                      typename Elem<T, CX>::type *Vw, BlkState *st, int *ctl, double tol,
                       int max_sweeps, int masking, int phase32, int inner, int persistent,
                       hipStream_t stream, double t0 = 0.0, double rate = 0.0)
 {
-    if (!persistent)
-        return run_sweeps_host<T, CX>(batch, m, np, nb, W, Vw, st, (int *)ctl, tol, max_sweeps,
-                                      masking, phase32, inner, stream, t0, rate);
-    int l = np / nb;
-    hipError_t e = launch_fill_int((int *)ctl, kCtlLaunchInts, 0, stream);
-    if (e != hipSuccess) return e;
-    hipLaunchKernelGGL(count_active, dim3((batch + 255) / 256), dim3(256), 0, stream, batch,
-                       (const BlkState *)st, ctl);
-    e = hipGetLastError();
-    if (e != hipSuccess) return e;
-    PersistFn<T, CX> fn = persist_kernel<T, CX>(nb);
-    int resident = 0;
-    long long limit = 0;
-    e = device_limits((const void *)fn, &resident, &limit);
-    if (e != hipSuccess) return e;
-    const int items = batch * (l / 2);
-    const int grid = items < resident ? items : resident;
-    void *args[] = {&batch, &m, &np, &l, &W, &Vw, &st, &tol, &inner, &t0, &rate, &max_sweeps,
-                    &masking, &phase32, &ctl, &limit};
-    return hipLaunchCooperativeKernel((const void *)fn, dim3((unsigned)(grid > 0 ? grid : 1)),
-                                      dim3(kBT), args, 0, stream);
+    return run_sweeps_host<T, CX>(batch, m, np, nb, W, Vw, st, ctl, tol, max_sweeps,
+                                  masking, phase32, inner, stream, t0, rate,
+                                  queued_sweeps(persistent, stream));
 }
 
 // Workspace carving; the same order as blocked_workspace_bytes.
@@ -1365,7 +1164,7 @@ struct WsLayout {
     double *Q, *X;
     BlkState *st;
     int *sw32;
-    PersistCtl *ctl;   // sweep control (the host loop's pending count shares it)
+    int *ctl;          // sweep control: the count of pending matrices and the stop word
 };
 
 WsLayout carve(void *ws, int batch, int m, int n, int np, size_t elt, bool mixed)
@@ -1390,7 +1189,7 @@ WsLayout carve(void *ws, int batch, int m, int n, int np, size_t elt, bool mixed
     p += align256((size_t)batch * sizeof(BlkState));
     L.sw32 = (int *)p;
     p += align256((size_t)batch * sizeof(int));
-    L.ctl = (PersistCtl *)p;
+    L.ctl = (int *)p;
     return L;
 }
 
@@ -1412,8 +1211,7 @@ hipError_t launch_blocked(int batch, int m, int n, int nb, const typename Elem<T
     const int np = blocked_np(n, nb);
     WsLayout L = carve(ws, batch, m, n, np, sizeof(E), false);
     E *W = (E *)L.W, *Vw = (E *)L.Vw;
-    hipError_t e = persistent ? launch_fill_int((int *)L.ctl, kCtlInts, 0, stream) : hipSuccess;
-    if (e != hipSuccess) return e;
+    hipError_t e;
     hipLaunchKernelGGL((blk_init<E, E>), dim3(batch), dim3(kBT), 0, stream, m, n, np, A, lda, sA,
                        W, Vw, L.st);
     e = hipGetLastError();
@@ -1425,10 +1223,6 @@ hipError_t launch_blocked(int batch, int m, int n, int nb, const typename Elem<T
     hipLaunchKernelGGL((blk_finalize<E, E>), dim3(batch), dim3(kBT), lds, stream, m, n, np,
                        (const E *)W, (const E *)Vw, (const BlkState *)L.st, (const int *)nullptr,
                        S, sS, U, ldu, sU, V, ldv, sV, info, sweeps);
-    if (persistent)
-        hipLaunchKernelGGL(mark_aborted, dim3((batch + 255) / 256), dim3(256), 0, stream, batch,
-                           (const BlkState *)L.st, (const PersistCtl *)L.ctl, info,
-                           (const VbDesc *)nullptr);
     return hipGetLastError();
 }
 
@@ -1456,10 +1250,11 @@ __global__ __launch_bounds__(kBT) void vb_init(const VbDesc *d, const int *idx, 
 template <class T, bool CX>
 __global__ __launch_bounds__(kBT) void vb_iter(const VbDesc *d, const int2 *work, int itg,
                                                void *base, BlkState *st, double tol, int inner,
-                                               double t0, double rate)
+                                               double t0, double rate, const int *stop)
 {
     using E = typename Elem<T, CX>::type;
     __shared__ IterShared<T, CX, kVbNb> s;
+    if (stop && *stop) return;
     const int2 w = work[blockIdx.x];
     if (!st[w.x].active) return;
     const VbDesc &D = d[w.x];
@@ -1474,10 +1269,11 @@ __global__ __launch_bounds__(kBT) void vb_iter(const VbDesc *d, const int2 *work
 // that reaches max_sweeps unconverged stops (info 1).  With `pending`, counts
 // the matrices still sweeping.
 __global__ void vb_sweep_end(int count, const VbDesc *d, int itg, BlkState *st, int max_sweeps,
-                             int masking, int *pending, double tol, double t0, double rate)
+                             int masking, int *pending, double tol, double t0, double rate,
+                             const int *stop)
 {
     const int b = blockIdx.x * blockDim.x + threadIdx.x;
-    if (b >= count) return;
+    if (b >= count || (stop && *stop)) return;
     BlkState &s = st[b];
     if (s.active && (itg - d[b].it0 + 1) % (d[b].l - 1) == 0) {
         if (!s.done) {
@@ -1521,41 +1317,6 @@ __global__ __launch_bounds__(kBT) void vb_finalize(const VbDesc *d, const int *i
     const E *Wb = (const E *)base;
     finalize_body<E, E>(D.m, D.n, D.np, Wb + D.woff, Wb + D.voff, st[b], 0, (RealOf<E> *)D.S,
                         (E *)D.U, D.ldu, (E *)D.V, D.ldv, D.info, D.sweeps);
-}
-
-// Uneven batch, all sweeps in one cooperative launch: the work table lists
-// (matrix, block pair) largest matrices first; matrix b runs iteration
-// (itg - it0_b) mod (l_b - 1) at phase itg and closes a sweep at its own
-// boundary, so a small matrix completes several sweeps while a large one
-// completes one.
-template <class T, bool CX>
-__global__ __launch_bounds__(kBT) void vb_persist(const VbDesc *d, const int2 *work, int nwork,
-                                                  int count, int lmax, void *base, BlkState *st,
-                                                  double tol, int inner, double t0, double rate,
-                                                  int max_sweeps, int masking, PersistCtl *ctl,
-                                                  long long limit)
-{
-    using E = typename Elem<T, CX>::type;
-    __shared__ IterShared<T, CX, kVbNb> s;
-    E *Wb = (E *)base;
-    persist_loop(
-        ctl, nwork, count, max_sweeps * (lmax - 1), limit,
-        [&](int w, int itg) {
-            const int2 wk = work[w];
-            if (!st[wk.x].active) return;
-            const VbDesc &D = d[wk.x];
-            iter_body<T, CX, kVbNb>(s, D.m, D.np, D.l, (itg - D.it0) % (D.l - 1), wk.y,
-                                    Wb + D.woff, Wb + D.voff, st + wk.x,
-                                    inner_tol(tol, t0, rate, st[wk.x].sweeps),
-                                    inner != 0 ? inner : D.inner);
-        },
-        [&](int) { return true; },
-        [&](int b, int itg) {
-            if (!st[b].active) return false;
-            const VbDesc &D = d[b];
-            if ((itg - D.it0 + 1) % (D.l - 1) != 0) return false;
-            return close_sweep(st[b], max_sweeps, masking, 0, tol, t0, rate);
-        });
 }
 
 struct VbLayout {
@@ -1657,10 +1418,10 @@ hipError_t vb_staging_release(Staging *st, hipStream_t stream)
 template <class T, bool CX>
 void vb_launch_iter_t(const VbDesc *d, const int2 *work, int nwork, int itg, void *base,
                       BlkState *st, double tol, int inner, double t0, double rate,
-                      hipStream_t stream)
+                      hipStream_t stream, const int *stop)
 {
     hipLaunchKernelGGL((vb_iter<T, CX>), dim3((unsigned)nwork), dim3(kBT), 0, stream, d, work, itg,
-                       base, st, tol, inner, t0, rate);
+                       base, st, tol, inner, t0, rate, stop);
 }
 
 template <class E>
@@ -1696,31 +1457,37 @@ void vb_launch_init(int dtype, const VbDesc *d, const int *idx, int count, void 
 }
 
 void vb_launch_iter(int dtype, const VbDesc *d, const int2 *work, int nwork, int itg, void *base,
-                    void *st, double tol, hipStream_t stream, int inner, double t0, double rate)
+                    void *st, double tol, hipStream_t stream, int inner, double t0, double rate,
+                    const int *stop)
 {
     BlkState *S = (BlkState *)st;
     switch (dtype) {
     case 0:
-        vb_launch_iter_t<float, false>(d, work, nwork, itg, base, S, tol, inner, t0, rate, stream);
+        vb_launch_iter_t<float, false>(d, work, nwork, itg, base, S, tol, inner, t0, rate, stream,
+                                        stop);
         break;
     case 1:
-        vb_launch_iter_t<double, false>(d, work, nwork, itg, base, S, tol, inner, t0, rate, stream);
+        vb_launch_iter_t<double, false>(d, work, nwork, itg, base, S, tol, inner, t0, rate, stream,
+                                        stop);
         break;
     case 2:
-        vb_launch_iter_t<float, true>(d, work, nwork, itg, base, S, tol, inner, t0, rate, stream);
+        vb_launch_iter_t<float, true>(d, work, nwork, itg, base, S, tol, inner, t0, rate, stream,
+                                        stop);
         break;
     default:
-        vb_launch_iter_t<double, true>(d, work, nwork, itg, base, S, tol, inner, t0, rate, stream);
+        vb_launch_iter_t<double, true>(d, work, nwork, itg, base, S, tol, inner, t0, rate, stream,
+                                        stop);
         break;
     }
 }
 
 void vb_launch_sweep_end(int count, const VbDesc *d, int itg, void *st, int max_sweeps,
                          int masking, int *pending, hipStream_t stream, double tol, double t0,
-                         double rate)
+                         double rate, const int *stop)
 {
     hipLaunchKernelGGL(vb_sweep_end, dim3((unsigned)((count + 255) / 256)), dim3(256), 0, stream,
-                       count, d, itg, (BlkState *)st, max_sweeps, masking, pending, tol, t0, rate);
+                       count, d, itg, (BlkState *)st, max_sweeps, masking, pending, tol, t0, rate,
+                       stop);
 }
 
 void vb_launch_collect(int count, const void *st, int *flags, hipStream_t stream)
@@ -1812,67 +1579,44 @@ hipError_t launch_vb(int dtype, size_t elt, int batch, const int *m, const int *
     const hipError_t er = vb_staging_release(stg, stream);
     if (e != hipSuccess) return e;
     if (er != hipSuccess) return er;
-    PersistCtl *ctl = (PersistCtl *)L.pending;
-    if (persistent) {
-        e = launch_fill_int((int *)ctl, kCtlInts, 0, stream);
-        if (e != hipSuccess) return e;
-    }
     vb_launch_init(dtype, L.desc, nullptr, batch, L.base, L.st, stream);
     e = hipGetLastError();
     if (e != hipSuccess) return e;
+    // a round is lmax - 1 launches of the iteration (matrices with fewer
+    // block columns close sweeps inside it); the matrices still sweeping are
+    // counted at its end.  persistent = 0: the host reads the count after
+    // every round and stops at zero.  1 (queued): every round goes onto the
+    // stream, the count stays on the device and, once it is zero, the later
+    // launches return at once (see run_sweeps_host).
+    int *ctl = (int *)L.pending;
+    int *host_count = nullptr;
+    persistent = queued_sweeps(persistent, stream);
     if (persistent) {
-        hipLaunchKernelGGL(count_active, dim3((batch + 255) / 256), dim3(256), 0, stream, batch,
-                           (const BlkState *)L.st, ctl);
-        e = hipGetLastError();
-        if (e == hipSuccess && nwork) {
-            using VbFn = void (*)(const VbDesc *, const int2 *, int, int, int, void *, BlkState *,
-                                  double, int, double, double, int, int, PersistCtl *, long long);
-            VbFn fn = dtype == 0   ? vb_persist<float, false>
-                      : dtype == 1 ? vb_persist<double, false>
-                      : dtype == 2 ? vb_persist<float, true>
-                                   : vb_persist<double, true>;
-            int resident = 0;
-            long long limit = 0;
-            e = device_limits((const void *)fn, &resident, &limit);
-            int nw = (int)nwork;
-            const int grid = nw < resident ? nw : resident;
-            const VbDesc *dd = L.desc;
-            const int2 *ww = L.work;
-            void *base = L.base;
-            BlkState *stp = L.st;
-            void *args[] = {&dd, &ww, &nw, &batch, &lmax, &base, &stp, &tol, &inner, &t0, &rate,
-                            &max_sweeps, &masking, &ctl, &limit};
-            if (e == hipSuccess)
-                e = hipLaunchCooperativeKernel((const void *)fn, dim3((unsigned)grid), dim3(kBT),
-                                               args, 0, stream);
-        } else if (e == hipSuccess) {
-            // no block pairs (every n is 0): close the single sweep of each
-            vb_launch_sweep_end(batch, L.desc, 0, L.st, max_sweeps, masking, nullptr, stream);
-            e = hipGetLastError();
-        }
-        if (e != hipSuccess) return e;
-        vb_launch_finalize(dtype, L.desc, nullptr, batch, maxn, L.base, L.st, stream);
-        hipLaunchKernelGGL(mark_aborted, dim3((batch + 255) / 256), dim3(256), 0, stream, batch,
-                           (const BlkState *)L.st, (const PersistCtl *)ctl, (int *)nullptr,
-                           (const VbDesc *)L.desc);
-        return hipGetLastError();
+        e = launch_fill_int(ctl, 2, 0, stream);
+    } else {
+        e = pinned_counter(&host_count);
     }
-    int *host_count;
-    e = pinned_counter(&host_count);
     if (e != hipSuccess) return e;
+    const int *stop = persistent ? ctl + 1 : nullptr;
     int itg = 0;
     for (int round = 0; round < max_sweeps; round++) {
-        e = hipMemsetAsync(L.pending, 0, sizeof(int), stream);
-        if (e != hipSuccess) return e;
+        if (!persistent) {
+            e = hipMemsetAsync(ctl, 0, sizeof(int), stream);
+            if (e != hipSuccess) return e;
+        }
         for (int k = 0; k < lmax - 1; k++, itg++) {
             if (nwork)
                 vb_launch_iter(dtype, L.desc, L.work, (int)nwork, itg, L.base, L.st, tol, stream,
-                               inner, t0, rate);
+                               inner, t0, rate, stop);
             vb_launch_sweep_end(batch, L.desc, itg, L.st, max_sweeps, masking,
-                                k == lmax - 2 ? L.pending : (int *)nullptr, stream, tol, t0,
-                                rate);
+                                k == lmax - 2 ? ctl : (int *)nullptr, stream, tol, t0, rate,
+                                stop);
         }
-        e = hipMemcpyAsync(host_count, L.pending, sizeof(int), hipMemcpyDeviceToHost, stream);
+        if (persistent) {
+            hipLaunchKernelGGL(sweep_close, dim3(1), dim3(64), 0, stream, ctl);
+            continue;
+        }
+        e = hipMemcpyAsync(host_count, ctl, sizeof(int), hipMemcpyDeviceToHost, stream);
         if (e != hipSuccess) return e;
         e = hipStreamSynchronize(stream);
         if (e != hipSuccess) return e;
@@ -1973,8 +1717,7 @@ hipError_t launch_blocked_mixed_d(int batch, int m, int n, int nb, const double 
     WsLayout L = carve(ws, batch, m, n, np, sizeof(double), true);
     double *W = (double *)L.W, *Vw = (double *)L.Vw;
     float *W32 = (float *)L.W32, *V32 = (float *)L.V32;
-    hipError_t e = persistent ? launch_fill_int((int *)L.ctl, kCtlInts, 0, stream) : hipSuccess;
-    if (e != hipSuccess) return e;
+    hipError_t e;
     hipLaunchKernelGGL((blk_init<double, float>), dim3(batch), dim3(kBT), 0, stream, m, n, np, A,
                        lda, sA, W32, V32, L.st);
     e = hipGetLastError();
@@ -2020,10 +1763,6 @@ hipError_t launch_blocked_mixed_d(int batch, int m, int n, int nb, const double 
     hipLaunchKernelGGL((blk_finalize<double, double>), dim3(batch), dim3(kBT), lds, stream, m, n,
                        np, (const double *)W, (const double *)Vw, (const BlkState *)L.st,
                        (const int *)L.sw32, S, sS, U, ldu, sU, V, ldv, sV, info, sweeps);
-    if (persistent)
-        hipLaunchKernelGGL(mark_aborted, dim3((batch + 255) / 256), dim3(256), 0, stream, batch,
-                           (const BlkState *)L.st, (const PersistCtl *)L.ctl, info,
-                           (const VbDesc *)nullptr);
     return hipGetLastError();
 }
 

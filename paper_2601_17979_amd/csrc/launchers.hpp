@@ -154,12 +154,13 @@ struct VbDesc {
 void vb_launch_init(int dtype, const VbDesc *d, const int *idx, int count, void *base, void *st,
                     hipStream_t stream);
 // t0, rate: the dynamic inner tolerance (t0 <= tol: tol in every sweep).
+// stop: NULL, or a device word; once it is nonzero the launch does nothing.
 void vb_launch_iter(int dtype, const VbDesc *d, const int2 *work, int nwork, int itg, void *base,
                     void *st, double tol, hipStream_t stream, int inner = 0, double t0 = 0.0,
-                    double rate = 0.0);
+                    double rate = 0.0, const int *stop = nullptr);
 void vb_launch_sweep_end(int count, const VbDesc *d, int itg, void *st, int max_sweeps,
                          int masking, int *pending, hipStream_t stream, double tol = 0.0,
-                         double t0 = 0.0, double rate = 0.0);
+                         double t0 = 0.0, double rate = 0.0, const int *stop = nullptr);
 void vb_launch_collect(int count, const void *st, int *flags, hipStream_t stream);
 void vb_launch_mark_empty(int count, void *st, hipStream_t stream);
 void vb_launch_finalize(int dtype, const VbDesc *d, const int *idx, int count, int maxn,

@@ -342,8 +342,10 @@ __global__ __launch_bounds__(kQT) void apply_q_d(int m, int n, const double *__r
 // implementations", cites it).  Neither the rotations of the Jacobi nor Q2
 // are applied.  The product is accurate when U_x S is the one-sided Jacobi's
 // (column-wise backward stable) iterate and R1 is well conditioned up to row
-// scaling; it is kept only if ||J^T J - I||_F <= thr for J = R1^-1 U_x S,
-// else flag[b] = 1 asks for the V-accumulating Jacobi on this matrix.
+// scaling (R1 from the column-pivoted QR, whose rows are graded); it is kept
+// only if the largest row sum of |J^T J - I| is at most thr for
+// J = R1^-1 U_x S, else flag[b] = 1 asks for the V-accumulating Jacobi on
+// this matrix.
 //
 // One wave per matrix (n <= 64), column c of J in lane c.  R1 = X1^T (X1 n x
 // n, ld n, lower triangular) is staged in LDS as a packed upper triangle,
@@ -451,7 +453,7 @@ __global__ __launch_bounds__(64, 2) void solve_r1_d(int n, const double *__restr
             __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
         }
     }
-    // ---- ||J^T J - I||_F on the matrix cores --------------------------------
+    // ---- J^T J on the matrix cores --------------------------------------------
     // operand of 16-column block P at row step s: lane l supplies
     // J(4 s + l / 16, 16 P + l % 16), as A (transposed) and as B; result
     // register v of lane l is entry (4 v + l / 16, l % 16) of the block
@@ -480,7 +482,16 @@ __global__ __launch_bounds__(64, 2) void solve_r1_d(int n, const double *__restr
                     acc[t] = __builtin_amdgcn_mfma_f64_16x16x4f64(o[P], o[Q], acc[t], 0, 0, 0);
         }
     }
-    double err = 0.0;
+    // the largest row sum of |J^T J - I| (the 1-norm of this symmetric
+    // matrix, the paper's orthogonality measure times n), summed in a fixed
+    // order so that the decision is reproducible; FP32 suffices for a test
+    // against thr.  NaN or Inf anywhere fails it.
+    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+    __builtin_amdgcn_wave_barrier();
+    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+    constexpr int kE = N + 1;
+    static_assert(N * kE * sizeof(float) <= kR * sizeof(double), "|E| fits the triangle's memory");
+    float *ea = reinterpret_cast<float *>(sm);
     {
         int t = 0;
 #pragma unroll
@@ -491,12 +502,20 @@ __global__ __launch_bounds__(64, 2) void solve_r1_d(int n, const double *__restr
                 for (int v = 0; v < 4; v++) {
                     const int i = 16 * P + 4 * v + l4, j = 16 * Q + l16;
                     const double e = acc[t][v] - (i == j ? 1.0 : 0.0);
-                    const double w = P == Q ? 1.0 : 2.0;   // the lower blocks mirror these
-                    err = (i < n && j < n) ? fma(w * e, e, err) : err;
+                    const float ae = (i < n && j < n) ? (float)fabs(e) : 0.0f;
+                    ea[i * kE + j] = ae;
+                    if (P != Q) ea[j * kE + i] = ae;
                 }
     }
-    err = wave_sum(err);
-    if (c == 0) flag[b] = !(sqrt(err) <= thr);
+    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+    __builtin_amdgcn_wave_barrier();
+    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+    float rs = 0.0f;
+#pragma unroll 8
+    for (int k = 0; k < N; k++) rs += ea[c * kE + k];
+    const bool bad = !(rs <= (float)thr);
+    const bool any_bad = __any(bad);
+    if (c == 0) flag[b] = any_bad ? 1 : 0;
 }
 
 // rows per lane (power of two) and columns per group for an m x n matrix
@@ -1056,8 +1075,12 @@ hipError_t launch_precond_d(int batch, int m, int n, int ns, const double *A, in
     PrecondWs w;
     precond_carve(batch, m, n, ws, &w);
     const long long snn = (long long)n * n;
-    // A P = Q1 R1 (reflectors only when U is wanted, P only when V is and the
-    // QR pivots; P = I otherwise, as in the paper's QR step)
+    // A P = Q1 R1 (reflectors only when U is wanted, P only when V is).  The
+    // QR pivots where V comes from the back substitution with R1, whose
+    // accuracy needs the row grading that pivoting gives R1, and when asked
+    // to; elsewhere P = I, as in the paper's QR step
+    const bool nv = resident_nv_supported(n, n);
+    pivot = pivot || nv;
     int *perm = pivot && V ? w.perm : nullptr;
     hipError_t e = pivot ? launch_qr_d<true>(batch, m, n, A, lda, sA, w.X1, U ? w.Vq1 : nullptr,
                                              w.tau1, perm, stream)
@@ -1073,7 +1096,6 @@ hipError_t launch_precond_d(int batch, int m, int n, int ns, const double *A, in
     // comes from a back substitution; matrices whose V fails the
     // orthogonality check run the Jacobi again with J accumulated, and only
     // they get V = P Q2 J.
-    const bool nv = resident_nv_supported(n, n);
     if (nv) {
         e = launch_resident_d(batch, n, n, ns, w.X2, n, snn, S, sS, w.Ux, n, snn, nullptr, n, snn,
                               tol, max_sweeps, info, sweeps, stream, true, nullptr);
@@ -1081,7 +1103,7 @@ hipError_t launch_precond_d(int batch, int m, int n, int ns, const double *A, in
             hipLaunchKernelGGL(solve_r1_d<64>, dim3(batch), dim3(64), 0, stream, n,
                                (const double *)w.X1, (const double *)w.Ux, (const double *)S, sS,
                                (const int *)perm, V, ldv, sV, w.flag, (const int *)info,
-                               0x1p-46 * n);
+                               0x1p-49 * n);
             e = hipGetLastError();
             if (e == hipSuccess)
                 e = launch_resident_d(batch, n, n, ns, w.X2, n, snn, S, sS, w.Ux, n, snn, w.J, n,

@@ -196,17 +196,20 @@ def test_precondition_option_in_plan():
 
 
 
-def test_persistent_launch_is_refused():
-    """The single cooperative launch of the block method is switched off:
-    asking for it is an unsupported request (refused on the host, before
-    anything is launched), and the default is the per-iteration form."""
+def test_queued_sweep_control_is_an_option():
+    """The block method's sweep control: the host-closed loop is the default
+    and the queued form (persistent = 1) is accepted on every path of the
+    plan, uniform and uneven."""
     o = svdb.Opts()
     svdb.lib().svdb_opts_default(C.byref(o))
     assert o.persistent == 0
     assert svdb.plan(torch.float64, 256, 256)[0] == svdb.PATH_BLOCKED
-    with pytest.raises(svdb.SvdbError) as e:
-        svdb.plan(torch.float64, 256, 256, persistent=True)
-    assert e.value.code == svdb.ERR_UNSUPPORTED and "disabled" in str(e.value)
+    assert svdb.plan(torch.float64, 256, 256, persistent=True) == svdb.plan(torch.float64, 256,
+                                                                            256)
+    assert svdb.plan(torch.complex64, 40, 30, persistent=True)[0] == svdb.PATH_BLOCKED
+    ms, ns = (C.c_int * 2)(8, 40), (C.c_int * 2)(4, 30)
+    assert svdb.lib().svdb_batched_workspace_size(
+        svdb.C128, 2, ms, ns, C.byref(svdb.make_opts(persistent=True))) > 0
 
 
 def test_noalloc_refusals_before_any_launch():

@@ -1,11 +1,14 @@
-"""Sweep control on the device: the block method runs every sweep of a
-batch in one cooperative launch (grid barriers between round-robin
-iterations, the convergence test on the device), so svdb_svd_strided_batched
-and svdb_svd_batched return before the work is done.
+"""Sweep control on the device (svdb_opts_t.persistent = 1): the block
+method queues the launches of every sweep up to max_sweeps, the count of
+unconverged matrices stays on the device, and the launches after the sweep
+that leaves none return at once.  svdb_svd_strided_batched and
+svdb_svd_batched then return before the work is done, and the strided call
+can be captured into a HIP graph (a capturing stream selects this form by
+itself).
 
-The persistent launch takes the same convergence decisions as the
-per-iteration launches with a host-side loop (svdb_opts_t.persistent = 0),
-so the two agree bit for bit; both are checked against the oracle as well.
+The queued form takes the same convergence decisions as the host-closed
+loop (persistent = 0), so the two agree bit for bit; both are checked
+against the oracle as well.
 """
 import time
 
@@ -17,13 +20,6 @@ from workloads import gen
 from gpu_util import compare_with_oracle, run_gpu, say
 
 pytestmark = pytest.mark.gpu
-
-# The cooperative single-launch form stalled on the GPU (the complex128 9 x 9
-# case of test_gpu_complex.py did not finish within 150 s) and its cause is
-# not established, so the library refuses persistent = 1; these tests stay
-# in the tree, skipped, until it is.
-OFF = pytest.mark.skip(reason="persistent launch disabled: it stalled on the GPU, cause unknown")
-
 
 def _batch(m, n, count, seed, cx=False, kinds=("gauss", "geo", "random")):
     return np.stack([gen.family(gen.rng_for(seed, k), kinds[k % len(kinds)], m, n, 1e6,
@@ -45,15 +41,14 @@ CASES = [
 ]
 
 
-@OFF
 @pytest.mark.parametrize("label,npdt,tdt,shape,nb,kw", CASES, ids=[c[0] for c in CASES])
-def test_persistent_equals_per_iteration_launches(label, npdt, tdt, shape, nb, kw):
+def test_queued_equals_host_closed_sweeps(label, npdt, tdt, shape, nb, kw):
     import torch
     m, n = shape
     cx = npdt in (np.complex64, np.complex128)
     A = _batch(m, n, 7, 6100 + m + n, cx=cx).astype(npdt)
     A[3] *= 0.0   # a zero matrix converges at once and is retired early
-    say(f"[persistent {label} {m}x{n}]")
+    say(f"[queued {label} {m}x{n}]")
     common = dict(dtype=getattr(torch, tdt), path="blocked", nb=nb, precondition=0, **kw)
     P = run_gpu(A, persistent=True, **common)
     H = run_gpu(A, persistent=False, **common)
@@ -70,9 +65,8 @@ def test_persistent_equals_per_iteration_launches(label, npdt, tdt, shape, nb, k
                         P[3], Sr, infor, dtype=npdt, label=label)
 
 
-@OFF
 @pytest.mark.parametrize("dt", ["f64", "c128", "f32"])
-def test_uneven_persistent_equals_per_iteration_launches(dt):
+def test_uneven_queued_equals_host_closed_sweeps(dt):
     import torch
     from paper_2601_17979_amd import svdb
     cx = dt == "c128"
@@ -95,7 +89,7 @@ def test_uneven_persistent_equals_per_iteration_launches(dt):
             assert np.array_equal(out[True][j][k], out[False][j][k]), (dt, k, j)
     assert np.array_equal(out[True][3], out[False][3])
     assert np.array_equal(out[True][4], out[False][4])
-    say(f"[uneven persistent {dt}] sweeps {out[True][4].tolist()}")
+    say(f"[uneven queued {dt}] sweeps {out[True][4].tolist()}")
     for k, A in enumerate(mats):
         if min(A.shape) == 0:
             assert out[True][3][k] == 0
@@ -112,7 +106,6 @@ def test_uneven_persistent_equals_per_iteration_launches(dt):
                             label=f"uneven {dt} #{k} {A.shape}")
 
 
-@OFF
 def test_calls_return_before_the_work_is_done():
     """The strided and the mixed-shape calls only enqueue work: each returns
     long before its stream has finished (the per-iteration form waits on the
@@ -122,8 +115,9 @@ def test_calls_return_before_the_work_is_done():
     A = _batch(256, 256, 64, 6300, kinds=("geo",))
     Ag = svdb.col_major(torch.from_numpy(np.repeat(A, 16, axis=0)).cuda())
     mats = [Ag[k] for k in range(256)]
-    call = svdb.BatchedCall(mats)
-    for label, fn in (("strided", lambda: svdb.svd(Ag, path="blocked", precondition=0)),
+    call = svdb.BatchedCall(mats, persistent=True)
+    for label, fn in (("strided", lambda: svdb.svd(Ag, path="blocked", precondition=0,
+                                                   persistent=True)),
                       ("batched", call)):
         fn()
         torch.cuda.synchronize()
@@ -137,11 +131,11 @@ def test_calls_return_before_the_work_is_done():
         assert t_all > 0.02 and t_host < 0.25 * t_all, (label, t_host, t_all)
 
 
-@OFF
 def test_strided_call_replays_from_a_graph():
-    """The whole strided call (workspace clears by kernels, init, the
-    persistent sweeps, finalisation) captured in a HIP graph: every replay,
-    with other work and a new input in between, equals the eager call."""
+    """The whole strided call (workspace clears by kernels, init, the queued
+    sweeps, finalisation) captured in a HIP graph: every replay, with other
+    work and a new input in between, equals the eager call (which closes its
+    sweeps on the host)."""
     import torch
     from paper_2601_17979_amd import svdb
     m, n, b = 130, 96, 24

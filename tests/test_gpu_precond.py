@@ -119,16 +119,17 @@ def test_precond_mixed_workload_sample():
 @pytest.mark.parametrize("pc", [-1, 2])
 def test_precond_sweeps_match_the_oracle_pipeline(pc):
     """The resident path follows the oracle's preconditioned driver (QR,
-    without column pivoting by default and with it for precondition 2,
-    second QR, Alg. 2 on R2^T): same SVD, and sweep counts within one of the
-    oracle's on every matrix of a workload sample (rounding can move a pair
-    across the threshold, never the whole schedule)."""
+    with column pivoting for 32 < n <= 64 and, with precondition 2, at every
+    n, second QR, Alg. 2 on R2^T): same SVD, and sweep counts within one of
+    the oracle's on every matrix of a workload sample (rounding can move a
+    pair across the threshold, never the whole schedule)."""
     import oracle
     groups = gen.mixed_64_128x32(batch=400)
     for g in groups:
         A = g.A[::8]
         S, U, V, info, sw = run_gpu(A, precondition=pc)
-        Sr, Ur, Vr, swr, infor = oracle.precond_gesvj_batch(A, pivot=pc == 2)
+        pivot = pc == 2 or 32 < g.n <= 64
+        Sr, Ur, Vr, swr, infor = oracle.precond_gesvj_batch(A, pivot=pivot)
         compare_with_oracle(A, S, U, V, info, Sr, infor, label=f"pipeline {g.m}x{g.n} pc {pc}")
         say(f"  {g.m}x{g.n} pc {pc}: sweeps gpu {sw.mean():.2f} oracle pipeline {swr.mean():.2f}")
         assert np.all(np.abs(sw - swr) <= 1), (sw.tolist(), swr.tolist())
