@@ -134,137 +134,235 @@ __global__ __launch_bounds__(kQT) void qr_house_d(int m, int n, const double *__
         nrm[c] = PIV ? row_sum16(t) : 0.0;
         nref[c] = nrm[c];
     }
-    for (int j = 0; j < n && finite; j++) {
-        int p = j;   // the column taken at step j
-        if (PIV) {
-            double best = -1.0;
-            int bc = n;
+    if constexpr (PIV) {
+        for (int j = 0; j < n && finite; j++) {
+            int p = j;   // the column taken at step j
+            if (PIV) {
+                double best = -1.0;
+                int bc = n;
+#pragma unroll
+                for (int c = 0; c < CPG; c++) {
+                    const int col = grp + 16 * c;
+                    if (col < n && !((done >> c) & 1u) && nrm[c] > best) {
+                        best = nrm[c];
+                        bc = col;
+                    }
+                }
+                if (gl == 0) {
+                    s_cn[grp] = best;
+                    s_cc[grp] = bc;
+                }
+                __syncthreads();
+                // lane x of every row of 16 takes candidate x; a rotation
+                // butterfly leaves the largest (norm first, then lowest column:
+                // a total order) in all 16 lanes
+                best = s_cn[gl];
+                p = s_cc[gl];
+                arg_max_step<8>(best, p);
+                arg_max_step<4>(best, p);
+                arg_max_step<2>(best, p);
+                arg_max_step<1>(best, p);
+                if (tid == 0) s_step[p] = j;
+            }
+            double *vb = vbuf[j & 1];
+            if (grp == (p & 15)) {
+                const int cp = p >> 4;
+                double x[RPL];
+#pragma unroll
+                for (int r = 0; r < RPL; r++) {
+                    x[r] = h[0][r];
+#pragma unroll
+                    for (int c = 1; c < CPG; c++) x[r] = c == cp ? h[c][r] : x[r];
+                }
+                double s = 0.0, a = 0.0;
+#pragma unroll
+                for (int r = 0; r < RPL; r++) {
+                    const int row = gl + 16 * r;
+                    s = row > j ? fma(x[r], x[r], s) : s;
+                    a = row == j ? x[r] : a;
+                }
+                s = row_sum16(s);
+                const double alpha = row_sum16(a);   // one nonzero term: exact
+                double beta = alpha, tau = 0.0, scal = 0.0;
+                if (s > 0.0) {
+                    const double nrmj = sqrt(fma(alpha, alpha, s));
+                    beta = alpha >= 0.0 ? -nrmj : nrmj;
+                    tau = (beta - alpha) / beta;
+                    scal = 1.0 / (alpha - beta);
+                }
+#pragma unroll
+                for (int r = 0; r < RPL; r++) {
+                    const int row = gl + 16 * r;
+                    const double v = row == j ? 1.0 : (row > j ? x[r] * scal : 0.0);
+                    vb[row] = v;
+                    x[r] = row == j ? beta : (row > j ? v : x[r]);
+                }
+#pragma unroll
+                for (int c = 0; c < CPG; c++)
+#pragma unroll
+                    for (int r = 0; r < RPL; r++) h[c][r] = c == cp ? x[r] : h[c][r];
+                if (PIV) done |= 1u << cp;
+                if (gl == 0) s_tau[j] = tau;
+            }
+            __syncthreads();
+            const double tau = s_tau[j];
+            double v[RPL];
+#pragma unroll
+            for (int r = 0; r < RPL; r++) v[r] = vb[gl + 16 * r];
 #pragma unroll
             for (int c = 0; c < CPG; c++) {
                 const int col = grp + 16 * c;
-                if (col < n && !((done >> c) & 1u) && nrm[c] > best) {
-                    best = nrm[c];
-                    bc = col;
+                const bool open = PIV ? (col < n && !((done >> c) & 1u)) : (col > j && col < n);
+                if (open) {   // uniform in the group
+                    if (tau != 0.0) {
+                        double w = 0.0;
+#pragma unroll
+                        for (int r = 0; r < RPL; r++) w = fma(v[r], h[c][r], w);
+                        w = row_sum16(w) * tau;
+#pragma unroll
+                        for (int r = 0; r < RPL; r++) h[c][r] = fma(-w, v[r], h[c][r]);
+                    }
+                    if (PIV) {
+                        // R(j, col) sits in lane j mod 16 of the group, slot j / 16
+                        double rj = h[c][0];
+#pragma unroll
+                        for (int r = 1; r < RPL; r++) rj = r == (j >> 4) ? h[c][r] : rj;
+                        rj = __shfl(rj, (lane & 48) | (j & 15), 64);
+                        double nn = fmax(fma(-rj, rj, nrm[c]), 0.0);
+                        if (nn <= 0x1p-26 * nref[c]) {   // uniform in the group
+                            double t = 0.0;
+#pragma unroll
+                            for (int r = 0; r < RPL; r++) {
+                                const int row = gl + 16 * r;
+                                t = row > j ? fma(h[c][r], h[c][r], t) : t;
+                            }
+                            nn = row_sum16(t);
+                            nref[c] = nn;
+                        }
+                        nrm[c] = nn;
+                    }
                 }
             }
-            if (gl == 0) {
-                s_cn[grp] = best;
-                s_cc[grp] = bc;
-            }
-            __syncthreads();
-            // lane x of every row of 16 takes candidate x; a rotation
-            // butterfly leaves the largest (norm first, then lowest column:
-            // a total order) in all 16 lanes
-            best = s_cn[gl];
-            p = s_cc[gl];
-            arg_max_step<8>(best, p);
-            arg_max_step<4>(best, p);
-            arg_max_step<2>(best, p);
-            arg_max_step<1>(best, p);
-            if (tid == 0) s_step[p] = j;
-        }
-        double *vb = vbuf[j & 1];
-        if (grp == (p & 15)) {
-            const int cp = p >> 4;
-            double x[RPL];
-#pragma unroll
-            for (int r = 0; r < RPL; r++) {
-                x[r] = h[0][r];
-#pragma unroll
-                for (int c = 1; c < CPG; c++) x[r] = c == cp ? h[c][r] : x[r];
-            }
-            double s = 0.0, a = 0.0;
-#pragma unroll
-            for (int r = 0; r < RPL; r++) {
-                const int row = gl + 16 * r;
-                s = row > j ? fma(x[r], x[r], s) : s;
-                a = row == j ? x[r] : a;
-            }
-            s = row_sum16(s);
-            const double alpha = row_sum16(a);   // one nonzero term: exact
-            double beta = alpha, tau = 0.0, scal = 0.0;
-            if (s > 0.0) {
-                const double nrmj = sqrt(fma(alpha, alpha, s));
-                beta = alpha >= 0.0 ? -nrmj : nrmj;
-                tau = (beta - alpha) / beta;
-                scal = 1.0 / (alpha - beta);
-            }
-#pragma unroll
-            for (int r = 0; r < RPL; r++) {
-                const int row = gl + 16 * r;
-                const double v = row == j ? 1.0 : (row > j ? x[r] * scal : 0.0);
-                vb[row] = v;
-                x[r] = row == j ? beta : (row > j ? v : x[r]);
-            }
-#pragma unroll
-            for (int c = 0; c < CPG; c++)
-#pragma unroll
-                for (int r = 0; r < RPL; r++) h[c][r] = c == cp ? x[r] : h[c][r];
-            if (PIV) done |= 1u << cp;
-            if (gl == 0) s_tau[j] = tau;
         }
         __syncthreads();
-        const double tau = s_tau[j];
-        double v[RPL];
-#pragma unroll
-        for (int r = 0; r < RPL; r++) v[r] = vb[gl + 16 * r];
+        // X = R^T / scale: X(k, row) = R(row, k) for row <= k, zero above the
+        // diagonal of X, where k is the step of the column; the reflectors as
+        // full columns, in step order
+        X += (size_t)b * n * n;
+        const double inv = 1.0 / scale;
+        if (Vq) Vq += (size_t)b * m * n;
 #pragma unroll
         for (int c = 0; c < CPG; c++) {
             const int col = grp + 16 * c;
-            const bool open = PIV ? (col < n && !((done >> c) & 1u)) : (col > j && col < n);
-            if (open) {   // uniform in the group
-                if (tau != 0.0) {
-                    double w = 0.0;
+            if (col >= n) continue;
+            const int k = PIV && finite ? s_step[col] : col;
 #pragma unroll
-                    for (int r = 0; r < RPL; r++) w = fma(v[r], h[c][r], w);
-                    w = row_sum16(w) * tau;
+            for (int r = 0; r < RPL; r++) {
+                const int row = gl + 16 * r;
+                if (row >= m) continue;
+                const double x = h[c][r];
+                if (row < n)
+                    X[(size_t)row * n + k] = !finite ? __builtin_nan("") : (row <= k ? x * inv : 0.0);
+                if (Vq) Vq[(size_t)k * m + row] = row > k ? x : (row == k ? 1.0 : 0.0);
+            }
+            if (PIV && perm_out && gl == 0) perm_out[(size_t)b * n + k] = col;
+        }
+    } else {
+        // Without pivoting step j takes column j, held in slot j / 16; with
+        // the slot loop unrolled the slot is known where the column is read.
+        // The column is final at its step (its rows above j were finished by
+        // earlier steps), so its owner group writes it out after the barrier
+        // (X = R^T, the reflector as a full column) and keeps nothing of it.
+        X += (size_t)b * n * n;
+        const double inv = 1.0 / scale;
+        if (Vq) Vq += (size_t)b * m * n;
+        auto step = [&](int j, int cp) __attribute__((always_inline)) {
+            double *vb = vbuf[j & 1];
+            const bool owner = grp == (j & 15);
+            double x[RPL];   // owner: the finished column (R above, beta, v below)
+            if (owner) {
 #pragma unroll
-                    for (int r = 0; r < RPL; r++) h[c][r] = fma(-w, v[r], h[c][r]);
+                for (int r = 0; r < RPL; r++) {
+                    x[r] = h[0][r];
+#pragma unroll
+                    for (int c = 1; c < CPG; c++) x[r] = c == cp ? h[c][r] : x[r];
                 }
-                if (PIV) {
-                    // R(j, col) sits in lane j mod 16 of the group, slot j / 16
-                    double rj = h[c][0];
+                double s = 0.0, a = 0.0;
 #pragma unroll
-                    for (int r = 1; r < RPL; r++) rj = r == (j >> 4) ? h[c][r] : rj;
-                    rj = __shfl(rj, (lane & 48) | (j & 15), 64);
-                    double nn = fmax(fma(-rj, rj, nrm[c]), 0.0);
-                    if (nn <= 0x1p-26 * nref[c]) {   // uniform in the group
-                        double t = 0.0;
+                for (int r = 0; r < RPL; r++) {
+                    const int row = gl + 16 * r;
+                    s = row > j ? fma(x[r], x[r], s) : s;
+                    a = row == j ? x[r] : a;
+                }
+                s = row_sum16(s);
+                const double alpha = row_sum16(a);   // one nonzero term: exact
+                double beta = alpha, tau = 0.0, scal = 0.0;
+                if (s > 0.0) {
+                    const double nrmj = sqrt(fma(alpha, alpha, s));
+                    beta = alpha >= 0.0 ? -nrmj : nrmj;
+                    tau = (beta - alpha) / beta;
+                    scal = 1.0 / (alpha - beta);
+                }
 #pragma unroll
-                        for (int r = 0; r < RPL; r++) {
-                            const int row = gl + 16 * r;
-                            t = row > j ? fma(h[c][r], h[c][r], t) : t;
-                        }
-                        nn = row_sum16(t);
-                        nref[c] = nn;
+                for (int r = 0; r < RPL; r++) {
+                    const int row = gl + 16 * r;
+                    const double v = row == j ? 1.0 : (row > j ? x[r] * scal : 0.0);
+                    vb[row] = v;
+                    x[r] = row == j ? beta : (row > j ? v : x[r]);
+                }
+                if (gl == 0) s_tau[j] = tau;
+            }
+            __syncthreads();
+            // the owner's stores, off the path to the barrier
+            if (owner) {
+#pragma unroll
+                for (int r = 0; r < RPL; r++) {
+                    const int row = gl + 16 * r;
+                    if (row < n) X[(size_t)row * n + j] = row <= j ? x[r] * inv : 0.0;
+                    if (Vq && row < m) Vq[(size_t)j * m + row] = row > j ? x[r] : (row == j ? 1.0 : 0.0);
+                }
+            }
+            const double tau = s_tau[j];
+            double v[RPL];
+#pragma unroll
+            for (int r = 0; r < RPL; r++) v[r] = vb[gl + 16 * r];
+#pragma unroll
+            for (int c = 0; c < CPG; c++) {
+                const int col = grp + 16 * c;
+                if (col > j && col < n) {   // uniform in the group
+                    if (tau != 0.0) {
+                        double w = 0.0;
+#pragma unroll
+                        for (int r = 0; r < RPL; r++) w = fma(v[r], h[c][r], w);
+                        w = row_sum16(w) * tau;
+#pragma unroll
+                        for (int r = 0; r < RPL; r++) h[c][r] = fma(-w, v[r], h[c][r]);
                     }
-                    nrm[c] = nn;
+                }
+            }
+        };
+        if (finite) {
+#pragma unroll
+            for (int cp = 0; cp < CPG; cp++)
+                for (int jj = 0; jj < 16; jj++) {
+                    const int j = 16 * cp + jj;
+                    if (j >= n) break;
+                    step(j, cp);
+                }
+        } else {
+            // a non-finite input turns X into NaN, which the Jacobi kernel
+            // reports (info 2); nothing else is read
+#pragma unroll
+            for (int c = 0; c < CPG; c++) {
+                const int col = grp + 16 * c;
+                if (col >= n) continue;
+#pragma unroll
+                for (int r = 0; r < RPL; r++) {
+                    const int row = gl + 16 * r;
+                    if (row < n) X[(size_t)row * n + col] = __builtin_nan("");
                 }
             }
         }
-    }
-    __syncthreads();
-    // X = R^T / scale: X(k, row) = R(row, k) for row <= k, zero above the
-    // diagonal of X, where k is the step of the column; the reflectors as
-    // full columns, in step order
-    X += (size_t)b * n * n;
-    const double inv = 1.0 / scale;
-    if (Vq) Vq += (size_t)b * m * n;
-#pragma unroll
-    for (int c = 0; c < CPG; c++) {
-        const int col = grp + 16 * c;
-        if (col >= n) continue;
-        const int k = PIV && finite ? s_step[col] : col;
-#pragma unroll
-        for (int r = 0; r < RPL; r++) {
-            const int row = gl + 16 * r;
-            if (row >= m) continue;
-            const double x = h[c][r];
-            if (row < n)
-                X[(size_t)row * n + k] = !finite ? __builtin_nan("") : (row <= k ? x * inv : 0.0);
-            if (Vq) Vq[(size_t)k * m + row] = row > k ? x : (row == k ? 1.0 : 0.0);
-        }
-        if (PIV && perm_out && gl == 0) perm_out[(size_t)b * n + k] = col;
     }
     if (Vq && tid < n) tau_out[(size_t)b * n + tid] = finite ? s_tau[tid] : 0.0;
 }
