@@ -710,8 +710,22 @@ __device__ __forceinline__ void iter_body(IterShared<T, CX, NB> &s, int m, int n
     }
 }
 
+// Resident waves per SIMD the iteration kernels are compiled for.  The
+// kernel is bound by the latency of its barrier chain (chunked Gram, inner
+// sweep, update), so more resident workgroups pay: measured on 800 256x256
+// FP64 matrices, five waves instead of the four that the unconstrained
+// register allocation allowed took a call from 184 to 170 ms (22.9 sweeps,
+// all-FP64) and 72 to 68.5 ms (7.9 sweeps, QR-preconditioned); FP32 at six
+// or eight waves spills and is slower.  nb = 8 fits eight without spills;
+// the complex and nb = 32 instances are bound to two by their LDS.
 template <class T, bool CX, int NB>
-__global__ __launch_bounds__(kBT) void blk_iter(int m, int np, int l, int it,
+constexpr int blk_waves()
+{
+    return (CX || NB == 32) ? 2 : (NB == 8 ? 8 : 5);
+}
+
+template <class T, bool CX, int NB>
+__global__ __launch_bounds__(kBT, (blk_waves<T, CX, NB>())) void blk_iter(int m, int np, int l, int it,
                                                 typename Elem<T, CX>::type *W,
                                                 typename Elem<T, CX>::type *Vw, BlkState *st,
                                                 double tol, int inner, const int *stop)
@@ -1248,7 +1262,7 @@ __global__ __launch_bounds__(kBT) void vb_init(const VbDesc *d, const int *idx, 
 }
 
 template <class T, bool CX>
-__global__ __launch_bounds__(kBT) void vb_iter(const VbDesc *d, const int2 *work, int itg,
+__global__ __launch_bounds__(kBT, (blk_waves<T, CX, kVbNb>())) void vb_iter(const VbDesc *d, const int2 *work, int itg,
                                                void *base, BlkState *st, double tol, int inner,
                                                double t0, double rate, const int *stop)
 {
