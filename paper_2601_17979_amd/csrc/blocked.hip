@@ -46,7 +46,10 @@ typedef double double4v __attribute__((ext_vector_type(4)));
 typedef float float4v __attribute__((ext_vector_type(4)));
 
 constexpr int kBT = 256;   // threads per workgroup
-constexpr int kCH = 64;    // rows per streamed chunk
+// rows per streamed chunk: 64, or 32 for complex data, whose real form is
+// twice as wide (this keeps the workgroup's LDS within a third of a CU's)
+template <bool CX>
+constexpr int chunk_rows() { return CX ? 32 : 64; }
 constexpr int kVbNb = 16;  // block width of uneven batches
 
 // The FP32 phase of the mixed mode hands over to FP64 once the largest pair
@@ -247,10 +250,10 @@ __host__ __device__ inline int inner_sweeps_of(int inner, int l, int m, int np, 
 
 template <class T, bool CX, int NB>
 struct IterShared {
-    static constexpr int N2 = 2 * NB, NR = (CX ? 2 : 1) * N2;
+    static constexpr int N2 = 2 * NB, NR = (CX ? 2 : 1) * N2, CH = chunk_rows<CX>();
     union {
-        T xs[NR][kCH + 1];            // row chunk [Xr (Xi)], column major
-        double R[NR][NR + 1];         // real Gram matrix (the real G itself)
+        T xs[NR][CH + 1];             // row chunk [Xr (Xi)], column major
+        double R[CX ? 1 : NR][CX ? 1 : NR + 1];   // real: the Gram matrix G itself
     } u;
     double Gr[CX ? N2 : 1][N2 + 1];   // complex G: real and imaginary parts
     double Gi[CX ? N2 : 1][N2 + 1];
@@ -285,17 +288,18 @@ struct InnerBlocks {
     }
 };
 
-// Per-thread share of one chunk (kCH rows x 2nb columns) held in registers so
+// Per-thread share of one chunk (CH rows x 2nb columns) held in registers so
 // that the next chunk's global loads overlap the current chunk's MFMAs.
 template <class E, int NB>
 struct ChunkRegs {
-    static constexpr int K = 2 * NB * kCH / kBT;
+    static constexpr int CH = chunk_rows<EOps<E>::cx>();
+    static constexpr int K = 2 * NB * CH / kBT;
     E v[K];
 };
 
-// Loads rows [r0, r0 + kCH) of block columns p, q of the rows x np matrix X
+// Loads rows [r0, r0 + CH) of block columns p, q of the rows x np matrix X
 // (zero beyond `rows`).  Element k of thread t is chunk entry
-// idx = t + k kBT: column idx / kCH, row idx % kCH (coalesced columns).
+// idx = t + k kBT: column idx / CH, row idx % CH (coalesced columns).
 template <class E, int NB>
 __device__ __forceinline__ void chunk_load(ChunkRegs<E, NB> &Rg, const E *X, int rows, int r0,
                                            int p, int q)
@@ -304,7 +308,7 @@ __device__ __forceinline__ void chunk_load(ChunkRegs<E, NB> &Rg, const E *X, int
 #pragma unroll
     for (int k = 0; k < ChunkRegs<E, NB>::K; k++) {
         const int idx = tid + k * kBT;
-        const int c = idx / kCH, r = idx % kCH;
+        const int c = idx / ChunkRegs<E, NB>::CH, r = idx % ChunkRegs<E, NB>::CH;
         const int gc = c < NB ? p * NB + c : q * NB + (c - NB);
         const int gr = r0 + r;
         Rg.v[k] = gr < rows ? X[(size_t)gc * rows + gr] : EOps<E>::make(0.0, 0.0);
@@ -319,7 +323,7 @@ __device__ __forceinline__ void chunk_to_lds(IterShared<T, CX, NB> &s, const Chu
 #pragma unroll
     for (int k = 0; k < ChunkRegs<E, NB>::K; k++) {
         const int idx = tid + k * kBT;
-        const int c = idx / kCH, r = idx % kCH;
+        const int c = idx / ChunkRegs<E, NB>::CH, r = idx % ChunkRegs<E, NB>::CH;
         if constexpr (CX) {
             s.u.xs[c][r] = Rg.v[k].x;
             s.u.xs[c + N2][r] = Rg.v[k].y;
@@ -329,7 +333,7 @@ __device__ __forceinline__ void chunk_to_lds(IterShared<T, CX, NB> &s, const Chu
     }
 }
 
-// Stores the chunk held in s.u.xs to rows [r0, r0 + kCH) of X.
+// Stores the chunk held in s.u.xs to rows [r0, r0 + CH) of X.
 template <class T, bool CX, int NB, class E>
 __device__ __forceinline__ void chunk_store(const IterShared<T, CX, NB> &s, E *X, int rows, int r0,
                                             int p, int q)
@@ -339,7 +343,7 @@ __device__ __forceinline__ void chunk_store(const IterShared<T, CX, NB> &s, E *X
 #pragma unroll
     for (int k = 0; k < ChunkRegs<E, NB>::K; k++) {
         const int idx = tid + k * kBT;
-        const int c = idx / kCH, r = idx % kCH;
+        const int c = idx / ChunkRegs<E, NB>::CH, r = idx % ChunkRegs<E, NB>::CH;
         const int gc = c < NB ? p * NB + c : q * NB + (c - NB);
         if (r0 + r < rows) {
             E y;
@@ -378,18 +382,18 @@ template <class T, bool CX, int NB, class E>
 __device__ __forceinline__ void update_block_columns(IterShared<T, CX, NB> &s, E *X, int rows,
                                                      int p, int q)
 {
-    constexpr int NR = IterShared<T, CX, NB>::NR;
-    constexpr int TR = kCH / 16, TC = NR / 16, TILES = TR * TC, TPW = TILES / 4;
+    constexpr int NR = IterShared<T, CX, NB>::NR, CH = IterShared<T, CX, NB>::CH;
+    constexpr int TR = CH / 16, TC = NR / 16, TILES = TR * TC, TPW = TILES / 4;
     static_assert(TILES % 4 == 0, "tiles per wave");
     const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
     const int li = lane & 15, lk = lane >> 4;
     ChunkRegs<E, NB> Rg;
     chunk_load<E, NB>(Rg, X, rows, 0, p, q);
-    for (int r0 = 0; r0 < rows; r0 += kCH) {
+    for (int r0 = 0; r0 < rows; r0 += CH) {
         __syncthreads();                      // xs free (previous chunk stored)
         chunk_to_lds<T, CX, NB, E>(s, Rg);
         __syncthreads();
-        if (r0 + kCH < rows) chunk_load<E, NB>(Rg, X, rows, r0 + kCH, p, q);
+        if (r0 + CH < rows) chunk_load<E, NB>(Rg, X, rows, r0 + CH, p, q);
         typename Mfma<T>::acc_t acc[TPW];
 #pragma unroll
         for (int t = 0; t < TPW; t++) {
@@ -600,6 +604,23 @@ __device__ __forceinline__ double inner_sweep_cx(IterShared<T, true, NB> &s, dou
 
 // One block pair (pair `pair` of round-robin iteration `it` over l block
 // columns) of one matrix: steps 1-3 above.  W, Vw, stb: this matrix's.
+// Real Gram tile (ti TC + tj) that wave `wave` computes as its g-th.  Real:
+// tiles wave, wave + 4, ...  Complex (TC = 4, NB = 16): the wave with
+// (A, C) = (wave / 2, wave % 2) takes the tiles (A, C), (A + 2, C + 2),
+// (A, C + 2), (A + 2, C) of the real form, whose sums and differences are
+// block (A, C) of Gr and Gi.
+template <bool CX, int TC>
+__device__ __forceinline__ int gram_tile(int wave, int g)
+{
+    if constexpr (CX) {
+        const int A = wave >> 1, C = wave & 1;
+        const int ti = A + (g == 1 || g == 3 ? 2 : 0), tj = C + (g == 1 || g == 2 ? 2 : 0);
+        return ti * TC + tj;
+    } else {
+        return wave + 4 * g;
+    }
+}
+
 template <class T, bool CX, int NB>
 __device__ __forceinline__ void iter_body(IterShared<T, CX, NB> &s, int m, int np, int l, int it,
                                           int pair, typename Elem<T, CX>::type *W,
@@ -608,9 +629,10 @@ __device__ __forceinline__ void iter_body(IterShared<T, CX, NB> &s, int m, int n
 {
     using E = typename Elem<T, CX>::type;
     using Sh = IterShared<T, CX, NB>;
-    constexpr int N2 = Sh::N2, NR = Sh::NR;
+    constexpr int N2 = Sh::N2, NR = Sh::NR, CH = Sh::CH;
     constexpr int TC = NR / 16, GT = TC * TC;   // real Gram output tiles
     constexpr int GPW = (GT + 3) / 4;           // tiles per wave
+    static_assert(!CX || GPW == 4, "complex: a wave holds the four tiles of one block of G");
     const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
     const int li = lane & 15, lk = lane >> 4;
     int p, q;
@@ -623,18 +645,18 @@ __device__ __forceinline__ void iter_body(IterShared<T, CX, NB> &s, int m, int n
     {
         ChunkRegs<E, NB> Rg;
         chunk_load<E, NB>(Rg, W, m, 0, p, q);
-        for (int r0 = 0; r0 < m; r0 += kCH) {
+        for (int r0 = 0; r0 < m; r0 += CH) {
             __syncthreads();
             chunk_to_lds<T, CX, NB, E>(s, Rg);
             __syncthreads();
-            if (r0 + kCH < m) chunk_load<E, NB>(Rg, W, m, r0 + kCH, p, q);
+            if (r0 + CH < m) chunk_load<E, NB>(Rg, W, m, r0 + CH, p, q);
 #pragma unroll
             for (int g = 0; g < GPW; g++) {
-                const int tile = wave + 4 * g;
+                const int tile = gram_tile<CX, TC>(wave, g);
                 if (tile < GT) {
                     const int ti = tile / TC, tj = tile % TC;
 #pragma unroll
-                    for (int k0 = 0; k0 < kCH; k0 += 4) {
+                    for (int k0 = 0; k0 < CH; k0 += 4) {
                         const T a = s.u.xs[16 * ti + li][k0 + lk];    // X^T[i][k]
                         const T bb = s.u.xs[16 * tj + li][k0 + lk];   // X[k][j]
                         acc[g] = Mfma<T>::op(a, bb, acc[g]);
@@ -644,23 +666,27 @@ __device__ __forceinline__ void iter_body(IterShared<T, CX, NB> &s, int m, int n
         }
     }
     __syncthreads();                            // xs is dead, R takes its place
-#pragma unroll
-    for (int g = 0; g < GPW; g++) {
-        const int tile = wave + 4 * g;
-        if (tile < GT) {
-            const int ti = tile / TC, tj = tile % TC;
-#pragma unroll
-            for (int v = 0; v < 4; v++)
-                s.u.R[16 * ti + Mfma<T>::row(lane, v)][16 * tj + li] = (double)acc[g][v];
-        }
-    }
     if constexpr (CX) {
-        __syncthreads();
-        for (int idx = tid; idx < N2 * N2; idx += kBT) {
-            const int a = idx / N2, c = idx % N2;
-            s.Gr[a][c] = s.u.R[a][c] + s.u.R[a + N2][c + N2];
-            s.Gi[a][c] = s.u.R[a][c + N2] - s.u.R[a + N2][c];
-            s.Ji[a][c] = 0.0;
+        // G = X^H X from the real form R = [Xr Xi]^T [Xr Xi]: Gr = R11 + R22,
+        // Gi = R12 - R21; this wave holds the four tiles of block (A, C)
+        const int A = wave >> 1, C = wave & 1;
+#pragma unroll
+        for (int v = 0; v < 4; v++) {
+            const int row = 16 * A + Mfma<T>::row(lane, v), col = 16 * C + li;
+            s.Gr[row][col] = (double)acc[0][v] + (double)acc[1][v];
+            s.Gi[row][col] = (double)acc[2][v] - (double)acc[3][v];
+        }
+        for (int idx = tid; idx < N2 * N2; idx += kBT) s.Ji[idx / N2][idx % N2] = 0.0;
+    } else {
+#pragma unroll
+        for (int g = 0; g < GPW; g++) {
+            const int tile = wave + 4 * g;
+            if (tile < GT) {
+                const int ti = tile / TC, tj = tile % TC;
+#pragma unroll
+                for (int v = 0; v < 4; v++)
+                    s.u.R[16 * ti + Mfma<T>::row(lane, v)][16 * tj + li] = (double)acc[g][v];
+            }
         }
     }
     for (int idx = tid; idx < N2 * N2; idx += kBT) s.Jr[idx / N2][idx % N2] = (idx / N2 == idx % N2);
@@ -717,11 +743,12 @@ __device__ __forceinline__ void iter_body(IterShared<T, CX, NB> &s, int m, int n
 // register allocation allowed took a call from 184 to 170 ms (22.9 sweeps,
 // all-FP64) and 72 to 68.5 ms (7.9 sweeps, QR-preconditioned); FP32 at six
 // or eight waves spills and is slower.  nb = 8 fits eight without spills;
-// the complex and nb = 32 instances are bound to two by their LDS.
+// complex data (32-row chunks, no real Gram in LDS: 52 KB) three, nb = 32
+// two (its LDS).
 template <class T, bool CX, int NB>
 constexpr int blk_waves()
 {
-    return (CX || NB == 32) ? 2 : (NB == 8 ? 8 : 5);
+    return CX ? 3 : (NB == 32 ? 2 : (NB == 8 ? 8 : 5));
 }
 
 template <class T, bool CX, int NB>
