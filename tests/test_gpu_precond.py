@@ -37,6 +37,20 @@ def test_precond_vs_oracle(m, n, path):
     say(f"  sweeps gpu {sw.tolist()} oracle {swr.tolist()}")
 
 
+@pytest.mark.parametrize("m,n", [(1, 1), (2, 2), (7, 3), (16, 16), (17, 9), (30, 20), (32, 32),
+                                 (40, 24), (50, 37), (64, 64), (64, 40)])
+def test_precond_pivoted_vs_oracle(m, n):
+    """Column pivoting at every n (precondition 2); up to 64 rows the pivoted
+    QR runs one wave per matrix with one column per lane (every row-block
+    count), beyond it the register QR of 16-lane groups."""
+    A = _batch((m, n), 8, seed=8300 + 7 * m + n)
+    A[3] = _batch((m, n), 1, seed=8400 + m, kinds=("geo",), kappa=1e12)[0]
+    say(f"[precond pivoted {m}x{n}]")
+    S, U, V, info, sw = run_gpu(A, precondition=2)
+    Sr, Ur, Vr, swr, infor = oracle_batch(A)
+    compare_with_oracle(A, S, U, V, info, Sr, infor, label=f"pivoted {m}x{n}")
+
+
 def test_precond_is_the_auto_default_and_saves_sweeps():
     """AUTO uses the preconditioned path where it applies; on graded
     (geometric kappa 1e6) matrices it needs fewer sweeps than the iteration
@@ -68,13 +82,14 @@ def test_precond_optional_outputs(want):
             assert np.linalg.norm(V[k].T @ V[k] - np.eye(32)) <= 1e-13 * 32
 
 
-def test_precond_edge_cases():
+@pytest.mark.parametrize("m,n,pc", [(40, 24, 1), (40, 24, 2), (64, 64, 1), (100, 64, 2)])
+def test_precond_edge_cases(m, n, pc):
     """Zero and rank-deficient matrices, extreme scales, and non-finite input
-    (info 2, outputs untouched)."""
+    (info 2, outputs untouched), through the unpivoted and both pivoted QR
+    kernels."""
     import torch
     from paper_2601_17979_amd import svdb
-    m, n = 40, 24
-    A = _batch((m, n), 6, seed=8500)
+    A = _batch((m, n), 6, seed=8500 + m + n)
     A[0] = 0.0
     A[1][:, 3] = 0.0
     A[1][:, 7] = A[1][:, 5]
@@ -88,7 +103,8 @@ def test_precond_edge_cases():
            svdb.empty_col_major(6, n, n, torch.float64, "cuda").fill_(7.0),
            torch.empty(6, dtype=torch.int32, device="cuda"),
            torch.empty(6, dtype=torch.int32, device="cuda"))
-    svdb.svd(Ag, out=out, precondition=1)
+    say(f"[precond edge {m}x{n} pc {pc}]")
+    svdb.svd(Ag, out=out, precondition=pc)
     torch.cuda.synchronize()
     S, U, V, info, sw = (x.cpu().numpy() for x in out)
     assert info[2] == 2 and info[3] == 2
