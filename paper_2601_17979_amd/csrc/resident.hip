@@ -162,20 +162,10 @@ __device__ __forceinline__ double rsq_nr(double x)
     return y;
 }
 
-// Column ids in the top and bottom seat q at iteration `it` (see rr_pair).
-__device__ __forceinline__ void rr_seats(int l, int it, int q, int &ct, int &cb)
+// Byte offset of a double in an array indexed by column id.
+__device__ __forceinline__ double &at_off(double *base, int off)
 {
-    const int k = l >> 1, ring = l - 1;
-    if (q == 0) {
-        ct = 0;
-    } else {
-        int y = (q - 1) - it;
-        y += (y < 0) ? ring : 0;
-        ct = rr_initial(y, k);
-    }
-    int y = (2 * k - 2 - q) - it;
-    y += (y < 0) ? ring : 0;
-    cb = rr_initial(y, k);
+    return *reinterpret_cast<double *>(reinterpret_cast<char *>(base) + off);
 }
 
 template <int N, int R, int NS>
@@ -188,6 +178,12 @@ struct Shared {
     double xch[2][NS][2][R][64];      // columns leaving each wave (top, bottom)
     double sig[N];
     int rank[N];
+    // 8 x the column id initially at ring position y mod (N - 1), for
+    // y < 2 (N - 1) (rr_initial): the top seat q > 0 holds at iteration it
+    // the column that started at ring position q - 1 - it (mod N - 1), the
+    // bottom seat q the one from N - 2 - q - it, so one table read with a
+    // nonnegative index gives either
+    int ring[2 * N];
     double amax[NS];
     int bad[NS];
     int flag;
@@ -275,6 +271,7 @@ __global__ __launch_bounds__(64 * NS, res_waves_per_eu(N, RW, NS, NV)) void resi
         sh.bad[wave] = bad;
     }
     if (threadIdx.x < N) sh.d[threadIdx.x] = 1.0;
+    for (int y = threadIdx.x; y < 2 * (N - 1); y += 64 * NS) sh.ring[y] = 8 * rr_initial(y % (N - 1), K);
     if (threadIdx.x == 0) sh.flag = 0;
     __syncthreads();
     for (int w = 0; w < NS; w++) {
@@ -303,6 +300,10 @@ __global__ __launch_bounds__(64 * NS, res_waves_per_eu(N, RW, NS, NV)) void resi
 
     double *buf = sh.buf[wave];
     double2 *cs = sh.cs[wave];
+    // ring positions of this lane's top and bottom seat at iteration 0, one
+    // ring length up (seat 0 of the top row never moves: column 0)
+    const int qs = q0 + qloc;
+    const int pt = (qs == 0 ? 0 : qs - 1) + (N - 1), pb = (N - 2 - qs) + (N - 1);
     int sweeps = 0, converged = 0, par = 0;
     while (true) {
         // ---- fold the scale factors back in; exact squared norms ------------
@@ -361,6 +362,10 @@ __global__ __launch_bounds__(64 * NS, res_waves_per_eu(N, RW, NS, NV)) void resi
         sweeps++;
 #pragma unroll 1
         for (int it = 0; it < N - 1; it++) {
+            // columns of this lane's pair (byte offsets), read ahead of the
+            // Gram entries that they do not depend on
+            const int rt = sh.ring[pt - it], ob = sh.ring[pb - it];
+            const int ot = qs == 0 ? 0 : rt;
             // ---- Gram entries of this wave's pairs --------------------------
             double g[KG];
 #pragma unroll
@@ -371,12 +376,10 @@ __global__ __launch_bounds__(64 * NS, res_waves_per_eu(N, RW, NS, NV)) void resi
             }
             const double gs = reduce_pairs<KG, OpSum, PK>(g, buf);
             // ---- rotate-or-skip and the rotation, one pair per lane group ---
-            int ct, cb;
-            rr_seats(N, it, q0 + qloc, ct, cb);
-            const double dt = sh.d[ct], db = sh.d[cb];
+            const double dt = at_off(sh.d, ot), db = at_off(sh.d, ob);
             const double gam = gs * dt * db;            // true g_ij
-            const bool top_is_i = ct < cb;              // pair (i, j), i < j
-            const double gt = sh.nrm[ct], gb = sh.nrm[cb];
+            const bool top_is_i = ot < ob;              // pair (i, j), i < j
+            const double gt = at_off(sh.nrm, ot), gb = at_off(sh.nrm, ob);
             const double gi = top_is_i ? gt : gb, gj = top_is_i ? gb : gt;
             const double ag = fabs(gam);
             // |g_ij| >= tol sqrt(g_ii) sqrt(g_jj), squared unless the product
@@ -404,10 +407,10 @@ __global__ __launch_bounds__(64 * NS, res_waves_per_eu(N, RW, NS, NV)) void resi
                 mut = sg * r;
                 mub = -sg * rcp_nr(r);
                 if (x < Q) {
-                    sh.nrm[top_is_i ? ct : cb] = fma(tt, ag, gi);
-                    sh.nrm[top_is_i ? cb : ct] = fma(-tt, ag, gj);
-                    sh.d[ct] = c * dt;
-                    sh.d[cb] = c * db;
+                    at_off(sh.nrm, top_is_i ? ot : ob) = fma(tt, ag, gi);
+                    at_off(sh.nrm, top_is_i ? ob : ot) = fma(-tt, ag, gj);
+                    at_off(sh.d, ot) = c * dt;
+                    at_off(sh.d, ob) = c * db;
                 }
             }
             if (x < Q) cs[qloc] = make_double2(mut, mub);
