@@ -92,15 +92,15 @@ template <int ROR>
 __device__ __forceinline__ double row_ror16(double v)
 {
     constexpr int ctrl = 0x120 + ROR;
-    const int lo = __builtin_amdgcn_update_dpp(0, __double2loint(v), ctrl, 0xF, 0xF, false);
-    const int hi = __builtin_amdgcn_update_dpp(0, __double2hiint(v), ctrl, 0xF, 0xF, false);
+    const int lo = __builtin_amdgcn_mov_dpp(__double2loint(v), ctrl, 0xF, 0xF, false);
+    const int hi = __builtin_amdgcn_mov_dpp(__double2hiint(v), ctrl, 0xF, 0xF, false);
     return __hiloint2double(hi, lo);
 }
 
 template <int ROR>
 __device__ __forceinline__ int row_ror16i(int v)
 {
-    return __builtin_amdgcn_update_dpp(0, v, 0x120 + ROR, 0xF, 0xF, false);
+    return __builtin_amdgcn_mov_dpp(v, 0x120 + ROR, 0xF, 0xF, false);
 }
 
 // Power-of-two scale that brings max|a| into [1, 2): multiplying by it is

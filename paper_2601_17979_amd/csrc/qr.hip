@@ -416,8 +416,8 @@ __device__ __forceinline__ long long key_of(int lo, int hi)
 template <int ROR>
 __device__ __forceinline__ long long row_ror16_key(long long v)
 {
-    const int lo = __builtin_amdgcn_update_dpp(0, (int)v, 0x120 + ROR, 0xF, 0xF, false);
-    const int hi = __builtin_amdgcn_update_dpp(0, (int)(v >> 32), 0x120 + ROR, 0xF, 0xF, false);
+    const int lo = __builtin_amdgcn_mov_dpp((int)v, 0x120 + ROR, 0xF, 0xF, false);
+    const int hi = __builtin_amdgcn_mov_dpp((int)(v >> 32), 0x120 + ROR, 0xF, 0xF, false);
     return key_of(lo, hi);
 }
 

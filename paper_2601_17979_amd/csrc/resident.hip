@@ -75,8 +75,8 @@ __device__ __forceinline__ double row_ror(double v)
 {
     // value of lane (x + ROR) mod 16 of the same row of 16 lanes
     constexpr int ctrl = 0x120 + ROR;
-    int lo = __builtin_amdgcn_update_dpp(0, __double2loint(v), ctrl, 0xF, 0xF, false);
-    int hi = __builtin_amdgcn_update_dpp(0, __double2hiint(v), ctrl, 0xF, 0xF, false);
+    int lo = __builtin_amdgcn_mov_dpp(__double2loint(v), ctrl, 0xF, 0xF, false);
+    int hi = __builtin_amdgcn_mov_dpp(__double2hiint(v), ctrl, 0xF, 0xF, false);
     return __hiloint2double(hi, lo);
 }
 
@@ -304,6 +304,10 @@ __global__ __launch_bounds__(64 * NS, res_waves_per_eu(N, RW, NS, NV)) void resi
     // ring length up (seat 0 of the top row never moves: column 0)
     const int qs = q0 + qloc;
     const int pt = (qs == 0 ? 0 : qs - 1) + (N - 1), pb = (N - 2 - qs) + (N - 1);
+    // this wave's columns 2 q0 .. in the factor and norm arrays (one base
+    // address, constant offsets)
+    double *const dw = sh.d + 2 * q0;
+    double *const nw = sh.nrm + 2 * q0;
     int sweeps = 0, converged = 0, par = 0;
     while (true) {
         // ---- fold the scale factors back in; exact squared norms ------------
@@ -320,7 +324,7 @@ __global__ __launch_bounds__(64 * NS, res_waves_per_eu(N, RW, NS, NV)) void resi
 #pragma unroll
                     for (int k = 0; k < KC; k++) {
                         const int q = h0 + k;
-                        const double dq = sh.d[2 * (q0 + q) + side];
+                        const double dq = dw[2 * q + side];
                         double(&X)[R] = side ? B[q] : T[q];
                         p[k] = 0.0;
 #pragma unroll
@@ -348,7 +352,7 @@ __global__ __launch_bounds__(64 * NS, res_waves_per_eu(N, RW, NS, NV)) void resi
                 const bool wl = !PK || lane < 32;   // lanes of W rows
 #pragma unroll
                 for (int q = 0; q < KG; q++) {
-                    const double2 nn = *reinterpret_cast<const double2 *>(&sh.nrm[2 * (q0 + q)]);
+                    const double2 nn = *reinterpret_cast<const double2 *>(&nw[2 * q]);
 #pragma unroll
                     for (int t = 0; t < WS; t++) {
                         T[q][t] = (wl && nn.x == 0.0) ? 0.0 : T[q][t];
