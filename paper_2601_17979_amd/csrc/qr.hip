@@ -797,7 +797,12 @@ __global__ __launch_bounds__(64, 2) void solve_r1_d(int n, const double *__restr
         double *col = sm + rp_off(c);
         double x[N];
 #pragma unroll
-        for (int k = 0; k < N; k++) x[k] = X1[(size_t)(k < n ? k : n - 1) * n + cc];   // R1(k, c)
+        for (int k = 0; k < N; k++) {
+            // R1(k, c); lanes below the diagonal (c < k, bound for the sink)
+            // read R1(k, k), so that a row's loads touch only its upper part
+            const int kk = k < n ? k : n - 1;
+            x[k] = X1[(size_t)kk * n + (cc > kk ? cc : kk)];
+        }
 #pragma unroll
         for (int k = 0; k < N; k++) {
             double *dst = k <= c ? col + k : s_sink + c;
