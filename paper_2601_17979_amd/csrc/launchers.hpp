@@ -19,13 +19,16 @@ hipError_t launch_plain_d(int batch, int m, int n, const double *A, int lda, lon
 bool resident_config(int m, int n, int ns, int *N, int *R, int *NS);
 // nv: iterate on W alone (no V rows; V is not written), for m <= 64 and
 // 32 < n <= 64 (resident_nv_supported).  only: NULL or per-matrix flags,
-// matrices with flag 0 are skipped.
+// matrices with flag 0 are skipped.  lower: A is lower triangular (the
+// transposed triangular factor of the QR pre-processing); the entries above
+// its diagonal are taken as zero without being read.
 bool resident_nv_supported(int m, int n);
 hipError_t launch_resident_d(int batch, int m, int n, int ns, const double *A, int lda,
                              long long sA, double *S, long long sS, double *U, int ldu,
                              long long sU, double *V, int ldv, long long sV, double tol,
                              int max_sweeps, int *info, int *sweeps, hipStream_t stream,
-                             bool nv = false, const int *only = nullptr);
+                             bool nv = false, const int *only = nullptr,
+                             bool lower = false);
 
 // qr.hip: QR preconditioning (A P = Q1 R1, R1^T = Q2 R2, the resident Jacobi
 // on R2^T; P = I unless pivot).

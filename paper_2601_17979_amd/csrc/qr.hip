@@ -79,11 +79,12 @@ __device__ __forceinline__ void arg_max_step(double &nrm, int &col)
 // (the safeguard of xGEQP3; the norms only steer the pivot order, the
 // factorisation is exact for any order).  R, V and tau come out in step
 // order; perm_out[k] is the column of A taken at step k, so that A P = Q R
-// with P e_k = e_perm[k].
+// with P e_k = e_perm[k].  lower: A is lower triangular (the transposed
+// factor of a first QR); its upper part is taken as zero without being read.
 template <int RPL, int CPG, bool PIV>
 __global__ __launch_bounds__(kQT) void qr_house_d(int m, int n, const double *__restrict__ A,
                                                   int lda, long long sA, double *X, double *Vq,
-                                                  double *tau_out, int *perm_out)
+                                                  double *tau_out, int *perm_out, int lower)
 {
     __shared__ double vbuf[2][16 * RPL];
     __shared__ double s_tau[64];
@@ -103,7 +104,9 @@ __global__ __launch_bounds__(kQT) void qr_house_d(int m, int n, const double *__
 #pragma unroll
         for (int r = 0; r < RPL; r++) {
             const int row = gl + 16 * r, col = grp + 16 * c;
-            const double a = (row < m && col < n) ? A[(size_t)col * lda + row] : 0.0;
+            const double a = (row < m && col < n && (!lower || row >= col))
+                                 ? A[(size_t)col * lda + row]
+                                 : 0.0;
             bad |= !isfinite(a);
             amax = fmax(amax, fabs(a));
             h[c][r] = a;
@@ -692,7 +695,21 @@ __global__ __launch_bounds__(kQT) void apply_q_d(int m, int n, const double *__r
     Vq += (size_t)b * m * n;
     Y += (size_t)b * n * n;
     U += (size_t)b * sU;
-    for (int idx = tid; idx < m * n; idx += kQT) Vl[idx] = Vq[idx];
+    // the reflectors are zero above the diagonal: those entries are not read
+    {
+        int col = tid / m, row = tid - col * m;
+        constexpr int kStep = kQT;
+        const int dc = kStep / m, dr = kStep - dc * m;
+        for (int idx = tid; idx < m * n; idx += kStep) {
+            Vl[idx] = row >= col ? Vq[idx] : 0.0;
+            row += dr;
+            col += dc;
+            if (row >= m) {
+                row -= m;
+                col++;
+            }
+        }
+    }
     if (tid < n) s_tau[tid] = tau[(size_t)b * n + tid];
     double u[CPG][RPL];
 #pragma unroll
@@ -1423,7 +1440,8 @@ size_t big_head_bytes(int batch, int m, int n)
 
 template <bool PIV>
 hipError_t launch_qr_d(int batch, int m, int n, const double *A, int lda, long long sA,
-                       double *X, double *Vq, double *tau, int *perm, hipStream_t stream)
+                       double *X, double *Vq, double *tau, int *perm, hipStream_t stream,
+                       bool lower = false)
 {
     // The pivoted QR with m <= 64 runs one wave per matrix, one column per
     // lane; without pivoting the register QR of 16-lane groups, whose steps
@@ -1447,7 +1465,7 @@ hipError_t launch_qr_d(int batch, int m, int n, const double *A, int lda, long l
 #define SVDB_QR(RP, CP)                                                                        \
     if (rpl == RP && cpg == CP)                                                                \
         hipLaunchKernelGGL((qr_house_d<RP, CP, PIV>), dim3(batch), dim3(kQT), 0, stream, m, n, \
-                           A, lda, sA, X, Vq, tau, perm);
+                           A, lda, sA, X, Vq, tau, perm, lower ? 1 : 0);
 #define SVDB_QR_ROW(RP) SVDB_QR(RP, 1) SVDB_QR(RP, 2) SVDB_QR(RP, 3) SVDB_QR(RP, 4)
     SVDB_QR_ROW(1)
     SVDB_QR_ROW(2)
@@ -1513,7 +1531,7 @@ hipError_t launch_precond_d(int batch, int m, int n, int ns, const double *A, in
     if (e != hipSuccess) return e;
     // R1^T = Q2 R2 (reflectors only when V is wanted)
     e = launch_qr_d<false>(batch, n, n, w.X1, n, snn, w.X2, V ? w.Vq2 : nullptr, w.tau2, nullptr,
-                           stream);
+                           stream, true);
     if (e != hipSuccess) return e;
     // Jacobi on X = R2^T: its left vectors U_x feed U, its rotations J feed V.
     // For 32 < n <= 64 it iterates on W alone and V = P R1^-1 U_x diag(S)
@@ -1522,7 +1540,7 @@ hipError_t launch_precond_d(int batch, int m, int n, int ns, const double *A, in
     // they get V = P Q2 J.
     if (nv) {
         e = launch_resident_d(batch, n, n, ns, w.X2, n, snn, S, sS, w.Ux, n, snn, nullptr, n, snn,
-                              tol, max_sweeps, info, sweeps, stream, true, nullptr);
+                              tol, max_sweeps, info, sweeps, stream, true, nullptr, true);
         if (e == hipSuccess && V) {
             hipLaunchKernelGGL(solve_r1_d<64>, dim3(batch), dim3(64), 0, stream, n,
                                (const double *)w.X1, (const double *)w.Ux, (const double *)S, sS,
@@ -1531,11 +1549,13 @@ hipError_t launch_precond_d(int batch, int m, int n, int ns, const double *A, in
             e = hipGetLastError();
             if (e == hipSuccess)
                 e = launch_resident_d(batch, n, n, ns, w.X2, n, snn, S, sS, w.Ux, n, snn, w.J, n,
-                                      snn, tol, max_sweeps, info, sweeps, stream, false, w.flag);
+                                      snn, tol, max_sweeps, info, sweeps, stream, false, w.flag,
+                                      true);
         }
     } else {
         e = launch_resident_d(batch, n, n, ns, w.X2, n, snn, S, sS, U ? w.Ux : nullptr, n, snn,
-                              V ? w.J : nullptr, n, snn, tol, max_sweeps, info, sweeps, stream);
+                              V ? w.J : nullptr, n, snn, tol, max_sweeps, info, sweeps, stream,
+                              false, nullptr, true);
     }
     if (e != hipSuccess) return e;
     if (U) {

@@ -209,11 +209,12 @@ constexpr int res_waves_per_eu(int N, int RW, int NS, bool NV = false)
 // writes S and U; the caller forms V from W (for the triangular X of the QR
 // pre-processing, J = X^-1 W).  only: NULL, or a per-matrix flag; matrices
 // whose flag is 0 are skipped (the rerun of the ones a cheaper path left).
+// lower: A is lower triangular, its upper part is not read (zeros).
 template <int N, int RW, int NS, bool NV = false>
 __global__ __launch_bounds__(64 * NS, res_waves_per_eu(N, RW, NS, NV)) void resident_jacobi_d(
     int m, int n, const double *__restrict__ A, int lda, long long sA, double *S, long long sS,
     double *U, int ldu, long long sU, double *V, int ldv, long long sV, double tol,
-    int max_sweeps, int *info, int *sweeps_out, const int *only)
+    int max_sweeps, int *info, int *sweeps_out, const int *only, int lower)
 {
     constexpr bool PK = RW == 0;
     static_assert(!(PK && NV), "the packed layout keeps V");
@@ -251,8 +252,8 @@ __global__ __launch_bounds__(64 * NS, res_waves_per_eu(N, RW, NS, NV)) void resi
             const int s = 64 * t + lane;   // packed: m <= 32, lanes >= 32 read nothing
             double xt = 0.0, xb = 0.0;
             if (s < m) {
-                if (ct < n) xt = A[(size_t)ct * lda + s];
-                if (cb < n) xb = A[(size_t)cb * lda + s];
+                if (ct < n && (!lower || s >= ct)) xt = A[(size_t)ct * lda + s];
+                if (cb < n && (!lower || s >= cb)) xb = A[(size_t)cb * lda + s];
             }
             bad |= !isfinite(xt) | !isfinite(xb);
             amax = fmax(amax, fmax(fabs(xt), fabs(xb)));
@@ -632,11 +633,11 @@ template <int N, int R, int NS, bool NV = false>
 hipError_t launch_one(int batch, int m, int n, const double *A, int lda, long long sA, double *S,
                       long long sS, double *U, int ldu, long long sU, double *V, int ldv,
                       long long sV, double tol, int max_sweeps, int *info, int *sweeps,
-                      hipStream_t stream, const int *only)
+                      hipStream_t stream, const int *only, bool lower)
 {
     hipLaunchKernelGGL((resident_jacobi_d<N, R, NS, NV>), dim3(batch), dim3(64 * NS), 0, stream,
                        m, n, A, lda, sA, S, sS, U, ldu, sU, V, ldv, sV, tol, max_sweeps, info,
-                       sweeps, only);
+                       sweeps, only, lower ? 1 : 0);
     return hipGetLastError();
 }
 
@@ -678,7 +679,7 @@ hipError_t launch_resident_d(int batch, int m, int n, int ns, const double *A, i
                              long long sA, double *S, long long sS, double *U, int ldu,
                              long long sU, double *V, int ldv, long long sV, double tol,
                              int max_sweeps, int *info, int *sweeps, hipStream_t stream,
-                             bool nv, const int *only)
+                             bool nv, const int *only, bool lower)
 {
     if (nv) {   // W alone: N = 64, one slot of W rows
         if (!resident_nv_supported(m, n)) return hipErrorInvalidValue;
@@ -686,15 +687,15 @@ hipError_t launch_resident_d(int batch, int m, int n, int ns, const double *A, i
         if (w == 1)
             return launch_one<64, 1, 1, true>(batch, m, n, A, lda, sA, S, sS, U, ldu, sU, nullptr,
                                               ldv, sV, tol, max_sweeps, info, sweeps, stream,
-                                              only);
+                                              only, lower);
         if (w == 2)
             return launch_one<64, 1, 2, true>(batch, m, n, A, lda, sA, S, sS, U, ldu, sU, nullptr,
                                               ldv, sV, tol, max_sweeps, info, sweeps, stream,
-                                              only);
+                                              only, lower);
         if (w == 4)
             return launch_one<64, 1, 4, true>(batch, m, n, A, lda, sA, S, sS, U, ldu, sU, nullptr,
                                               ldv, sV, tol, max_sweeps, info, sweeps, stream,
-                                              only);
+                                              only, lower);
         return hipErrorInvalidValue;
     }
     int N, RW, NS;
@@ -702,7 +703,7 @@ hipError_t launch_resident_d(int batch, int m, int n, int ns, const double *A, i
 #define SVDB_RES(NN, RR, WW)                                                                   \
     if (N == NN && RW == RR && NS == WW)                                                       \
         return launch_one<NN, RR, WW>(batch, m, n, A, lda, sA, S, sS, U, ldu, sU, V, ldv, sV,  \
-                                      tol, max_sweeps, info, sweeps, stream, only);
+                                      tol, max_sweeps, info, sweeps, stream, only, lower);
     SVDB_RES(16, 0, 1)
     SVDB_RES(16, 0, 2)
     SVDB_RES(32, 0, 1)
