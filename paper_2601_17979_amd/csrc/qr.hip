@@ -67,8 +67,9 @@ __device__ __forceinline__ void arg_max_step(double &nrm, int &col)
 // LAPACK's xGEQRF) and publishes it in LDS; after one barrier every group
 // applies it to its own trailing columns.  A is pre-scaled by a power of two
 // (max |a| in [1, 2)) so that no square overflows.  Outputs: X = R^T
-// (unscaled, n x n), and for the application of Q the reflectors as full
-// columns V (m x n: zeros above the diagonal, ones on it) with tau.
+// (unscaled, n x n; only its lower triangle is written, every reader takes
+// the upper one as zero), and for the application of Q the reflectors as
+// full columns V (m x n: zeros above the diagonal, ones on it) with tau.
 //
 // PIV: column pivoting as in LAPACK's xGEQP3 (Businger-Golub), the step-j
 // pivot being the open column of largest trailing norm (rows j..m-1; ties
@@ -248,9 +249,9 @@ __global__ __launch_bounds__(kQT) void qr_house_d(int m, int n, const double *__
             }
         }
         __syncthreads();
-        // X = R^T / scale: X(k, row) = R(row, k) for row <= k, zero above the
-        // diagonal of X, where k is the step of the column; the reflectors as
-        // full columns, in step order
+        // X = R^T / scale: X(k, row) = R(row, k) for row <= k (the lower
+        // triangle of X), where k is the step of the column; the reflectors
+        // as full columns, in step order
         X += (size_t)b * n * n;
         const double inv = 1.0 / scale;
         if (Vq) Vq += (size_t)b * m * n;
@@ -264,8 +265,8 @@ __global__ __launch_bounds__(kQT) void qr_house_d(int m, int n, const double *__
                 const int row = gl + 16 * r;
                 if (row >= m) continue;
                 const double x = h[c][r];
-                if (row < n)
-                    X[(size_t)row * n + k] = !finite ? __builtin_nan("") : (row <= k ? x * inv : 0.0);
+                if (row < n && (!finite || row <= k))
+                    X[(size_t)row * n + k] = finite ? x * inv : __builtin_nan("");
                 if (Vq) Vq[(size_t)k * m + row] = row > k ? x : (row == k ? 1.0 : 0.0);
             }
             if (PIV && perm_out && gl == 0) perm_out[(size_t)b * n + k] = col;
@@ -321,7 +322,7 @@ __global__ __launch_bounds__(kQT) void qr_house_d(int m, int n, const double *__
 #pragma unroll
                 for (int r = 0; r < RPL; r++) {
                     const int row = gl + 16 * r;
-                    if (row < n) X[(size_t)row * n + j] = row <= j ? x[r] * inv : 0.0;
+                    if (row <= j) X[(size_t)row * n + j] = x[r] * inv;
                     if (Vq && row < m) Vq[(size_t)j * m + row] = row > j ? x[r] : (row == j ? 1.0 : 0.0);
                 }
             }
@@ -633,8 +634,8 @@ __global__ __launch_bounds__(64, 2) void qr_lane_d(int m, int n, const double *_
             }
         }
     }
-    // X = R^T / scale: X(k, row) = R(row, k) for row <= k (zero above the
-    // diagonal of X), k the step of the lane's column
+    // X = R^T / scale: X(k, row) = R(row, k) for row <= k (the lower
+    // triangle of X), k the step of the lane's column
     const int k = finite ? step : c;
     const double inv = 1.0 / scale;
     X += (size_t)b * n * n;
@@ -644,8 +645,8 @@ __global__ __launch_bounds__(64, 2) void qr_lane_d(int m, int n, const double *_
 #pragma unroll
             for (int i = 0; i < 16; i++) {
                 const int row = 16 * B + i;
-                if (row >= n) continue;
-                const double r = row < k ? a[B][i] : (row == k ? beta_l : 0.0);
+                if (row >= n || (finite && row > k)) continue;
+                const double r = row < k ? a[B][i] : beta_l;
                 X[(size_t)row * n + k] = finite ? r * inv : __builtin_nan("");
             }
         if (PIV && perm_out) perm_out[(size_t)b * n + k] = c;
