@@ -69,7 +69,8 @@ __device__ __forceinline__ void arg_max_step(double &nrm, int &col)
 // (max |a| in [1, 2)) so that no square overflows.  Outputs: X = R^T
 // (unscaled, n x n; only its lower triangle is written, every reader takes
 // the upper one as zero), and for the application of Q the reflectors as
-// full columns V (m x n: zeros above the diagonal, ones on it) with tau.
+// columns of V (m x n: ones on the diagonal and the vectors below it; the
+// part above the diagonal, zero, is neither written nor read) with tau.
 //
 // PIV: column pivoting as in LAPACK's xGEQP3 (Businger-Golub), the step-j
 // pivot being the open column of largest trailing norm (rows j..m-1; ties
@@ -251,7 +252,7 @@ __global__ __launch_bounds__(kQT) void qr_house_d(int m, int n, const double *__
         __syncthreads();
         // X = R^T / scale: X(k, row) = R(row, k) for row <= k (the lower
         // triangle of X), where k is the step of the column; the reflectors
-        // as full columns, in step order
+        // from the diagonal down, in step order
         X += (size_t)b * n * n;
         const double inv = 1.0 / scale;
         if (Vq) Vq += (size_t)b * m * n;
@@ -267,7 +268,7 @@ __global__ __launch_bounds__(kQT) void qr_house_d(int m, int n, const double *__
                 const double x = h[c][r];
                 if (row < n && (!finite || row <= k))
                     X[(size_t)row * n + k] = finite ? x * inv : __builtin_nan("");
-                if (Vq) Vq[(size_t)k * m + row] = row > k ? x : (row == k ? 1.0 : 0.0);
+                if (Vq && row >= k) Vq[(size_t)k * m + row] = row > k ? x : 1.0;
             }
             if (PIV && perm_out && gl == 0) perm_out[(size_t)b * n + k] = col;
         }
@@ -323,7 +324,7 @@ __global__ __launch_bounds__(kQT) void qr_house_d(int m, int n, const double *__
                 for (int r = 0; r < RPL; r++) {
                     const int row = gl + 16 * r;
                     if (row <= j) X[(size_t)row * n + j] = x[r] * inv;
-                    if (Vq && row < m) Vq[(size_t)j * m + row] = row > j ? x[r] : (row == j ? 1.0 : 0.0);
+                    if (Vq && row < m && row >= j) Vq[(size_t)j * m + row] = row > j ? x[r] : 1.0;
                 }
             }
             const double tau = s_tau[j];
@@ -653,7 +654,7 @@ __global__ __launch_bounds__(64, 2) void qr_lane_d(int m, int n, const double *_
         if (Vq) tau_out[(size_t)b * n + k] = tau_l;
     }
     if (Vq && finite) {
-        // the reflectors as full columns, in step order
+        // the reflectors from the diagonal down, in step order
         Vq += (size_t)b * m * n;
 #pragma unroll
         for (int B = 0; B < MB; B++) {
@@ -668,16 +669,16 @@ __global__ __launch_bounds__(64, 2) void qr_lane_d(int m, int n, const double *_
 #pragma unroll
             for (int q = 0; q < 16; q++) {
                 const int kk = 4 * q + (c >> 4), row = 16 * B + (c & 15);
-                if (kk < n && row < m) Vq[(size_t)kk * m + row] = tile[kk][c & 15];
+                if (kk < n && row < m && row >= kk) Vq[(size_t)kk * m + row] = tile[kk][c & 15];
             }
             lane_sync_lds();
         }
     }
 }
 
-// U = Q [Y; 0] = H_0 ... H_{n-1} [Y; 0] (Y n x n, ld n), the reflectors
-// (full columns, in LDS) applied last to first to the register-held U; no
-// barrier after the reflectors are loaded.  With perm (m = n), row k of the
+// U = Q [Y; 0] = H_0 ... H_{n-1} [Y; 0] (Y n x n, ld n), the reflectors (in
+// LDS, zero above the diagonal) applied last to first to the register-held
+// U; no barrier after the reflectors are loaded.  With perm (m = n), row k of the
 // product is stored as row perm[k] of U.  Matrices with info 2 (non-finite
 // input) are left untouched.
 template <int RPL, int CPG>
