@@ -44,6 +44,60 @@ __device__ __forceinline__ double row_sum16(double v)
     return v;
 }
 
+template <int CTRL>
+__device__ __forceinline__ double dpp_d(double v)
+{
+    const int lo = __builtin_amdgcn_mov_dpp(__double2loint(v), CTRL, 0xF, 0xF, false);
+    const int hi = __builtin_amdgcn_mov_dpp(__double2hiint(v), CTRL, 0xF, 0xF, false);
+    return __hiloint2double(hi, lo);
+}
+
+// Value of lane SRC of this lane's row of 16 (ds_swizzle in its bit-mask
+// form: lane id & 16 | SRC within each half of the wave).
+template <int SRC>
+__device__ __forceinline__ double row_bcast16(double v)
+{
+    constexpr int pat = 0x10 | (SRC << 5);
+    const int lo = __builtin_amdgcn_ds_swizzle(__double2loint(v), pat);
+    const int hi = __builtin_amdgcn_ds_swizzle(__double2hiint(v), pat);
+    return __hiloint2double(hi, lo);
+}
+
+// Sums of w[0..3] over each row of 16 lanes, all four in every lane of the
+// row.  Each level halves the values a lane carries: lanes x and x + 8
+// exchange the pair the other keeps (columns 0, 1 below lane 8, 2, 3 above),
+// then mirrored lanes of each half-row exchange the other column, and the
+// quads sum the one left; quad k then holds the sum of column k, which is
+// broadcast from its first lane.  27 VALU instructions and 8 swizzles
+// against 48 for four separate row sums.
+__device__ __forceinline__ void row_sum16x4(double (&w)[4])
+{
+    const int x = threadIdx.x & 15;
+    const bool hi = (x & 8) != 0, up = (x & 4) != 0;
+    const double a0 = (hi ? w[2] : w[0]) + dpp_d<0x128>(hi ? w[0] : w[2]);   // row_ror:8
+    const double a1 = (hi ? w[3] : w[1]) + dpp_d<0x128>(hi ? w[1] : w[3]);
+    double c = (up ? a1 : a0) + dpp_d<0x141>(up ? a0 : a1);                  // row_half_mirror
+    c += dpp_d<0xB1>(c);                                                      // quad lanes ^ 1
+    c += dpp_d<0x4E>(c);                                                      // quad lanes ^ 2
+    w[0] = row_bcast16<0>(c);
+    w[1] = row_bcast16<4>(c);
+    w[2] = row_bcast16<8>(c);
+    w[3] = row_bcast16<12>(c);
+}
+
+// The same for two values: lanes x and x + 8 exchange the column the other
+// keeps (column 0 below lane 8, 1 above), then each half-row sums its own.
+__device__ __forceinline__ void row_sum16x2(double (&w)[2])
+{
+    const bool hi = (threadIdx.x & 8) != 0;
+    double c = (hi ? w[1] : w[0]) + dpp_d<0x128>(hi ? w[0] : w[1]);   // row_ror:8
+    c += dpp_d<0x141>(c);                                              // row_half_mirror
+    c += dpp_d<0xB1>(c);                                               // quad lanes ^ 1
+    c += dpp_d<0x4E>(c);                                               // quad lanes ^ 2
+    w[0] = row_bcast16<0>(c);
+    w[1] = row_bcast16<8>(c);
+}
+
 // One butterfly step of the pivot search over a row of 16 lanes: keeps the
 // larger of (norm, column) and its partner ROR lanes on, ordered by norm and
 // then by the lower column.
@@ -731,14 +785,36 @@ __global__ __launch_bounds__(kQT) void apply_q_d(int m, int n, const double *__r
             const int row = gl + 16 * r;
             v[r] = row < m ? Vl[(size_t)j * m + row] : 0.0;
         }
+        // the transposing row sums where they measured faster (U of 64x64
+        // and V of 32x32; not U of 128x32, RPL = 8)
+        if constexpr (CPG == 4 || (CPG == 2 && RPL <= 4)) {
+            double w[CPG];
 #pragma unroll
-        for (int c = 0; c < CPG; c++) {
-            double w = 0.0;
+            for (int c = 0; c < CPG; c++) {
+                w[c] = 0.0;
 #pragma unroll
-            for (int r = 0; r < RPL; r++) w = fma(v[r], u[c][r], w);
-            w = row_sum16(w) * t;
+                for (int r = 0; r < RPL; r++) w[c] = fma(v[r], u[c][r], w[c]);
+            }
+            if constexpr (CPG == 4)
+                row_sum16x4(w);
+            else
+                row_sum16x2(w);
 #pragma unroll
-            for (int r = 0; r < RPL; r++) u[c][r] = fma(-w, v[r], u[c][r]);
+            for (int c = 0; c < CPG; c++) {
+                const double f = w[c] * t;
+#pragma unroll
+                for (int r = 0; r < RPL; r++) u[c][r] = fma(-f, v[r], u[c][r]);
+            }
+        } else {
+#pragma unroll
+            for (int c = 0; c < CPG; c++) {
+                double w = 0.0;
+#pragma unroll
+                for (int r = 0; r < RPL; r++) w = fma(v[r], u[c][r], w);
+                w = row_sum16(w) * t;
+#pragma unroll
+                for (int r = 0; r < RPL; r++) u[c][r] = fma(-w, v[r], u[c][r]);
+            }
         }
     }
     if (perm) perm += (size_t)b * n;
