@@ -370,3 +370,46 @@ def test_auto_skips_qr_for_few_columns(m, n, qr):
         assert np.array_equal(x, y)
     Sr, _, _, _, infor = oracle_batch(A)
     compare_with_oracle(A, auto[0], auto[1], auto[2], auto[3], Sr, infor, label=f"auto {m}x{n}")
+
+
+@pytest.mark.parametrize("m,n,pc", [(64, 64, 1), (128, 32, 1), (48, 40, 2), (40, 24, 1)])
+def test_precond_ignores_stale_workspace(m, n, pc):
+    """The kernels of the preconditioned path hand each other triangular
+    factors and reflectors written and read only from the diagonal down; the
+    rest of the workspace is never read.  A workspace full of NaN bytes from
+    an earlier use must give the same bits as a zeroed one (rank-deficient
+    matrices included, whose V comes from the V-accumulating rerun)."""
+    import ctypes as C
+    import torch
+    from paper_2601_17979_amd import svdb
+    A = _batch((m, n), 6, seed=8600 + m + n)
+    A[2][:, 5] = 0.0
+    A[2][:, 7] = A[2][:, 6]
+    Ag = svdb.col_major(torch.from_numpy(A).cuda())
+    L = svdb.lib()
+    b, k = A.shape[0], min(m, n)
+    o = svdb.make_opts(precondition=pc)
+    ws_bytes = L.svdb_workspace_size(svdb.dtype_code(Ag.dtype), b, m, n, C.byref(o))
+    assert ws_bytes > 0
+    outs = []
+    for fill in (0, 255):
+        S = torch.empty((b, k), dtype=torch.float64, device="cuda")
+        U = svdb.empty_col_major(b, m, k, torch.float64, "cuda")
+        V = svdb.empty_col_major(b, n, k, torch.float64, "cuda")
+        info = torch.empty(b, dtype=torch.int32, device="cuda")
+        ws = torch.full((ws_bytes,), fill, dtype=torch.uint8, device="cuda")
+        say(f"[stale workspace {m}x{n} pc {pc} fill {fill}]")
+        rc = L.svdb_svd_strided_batched(
+            svdb.dtype_code(Ag.dtype), b, m, n, Ag.data_ptr(), Ag.stride(2), Ag.stride(0),
+            S.data_ptr(), S.stride(0), U.data_ptr(), U.stride(2), U.stride(0), V.data_ptr(),
+            V.stride(2), V.stride(0), 0.0, info.data_ptr(), ws.data_ptr(), ws_bytes, C.byref(o),
+            torch.cuda.current_stream().cuda_stream)
+        assert rc == 0, svdb.last_error()
+        torch.cuda.synchronize()
+        outs.append([x.cpu().numpy() for x in (S, U, V, info)])
+    for x0, x1 in zip(*outs):
+        assert np.array_equal(x0, x1)
+    assert np.all(outs[0][3] == 0)
+    Sr, _, _, _, infor = oracle_batch(A)
+    compare_with_oracle(A, outs[0][0], outs[0][1], outs[0][2], outs[0][3], Sr, infor,
+                        label=f"stale workspace {m}x{n}")
